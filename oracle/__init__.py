@@ -1,0 +1,230 @@
+"""FP64 CPU oracle (ctypes wrapper around ``oracle/oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: tests, the smoke check and the benchmark's CPU
+baseline leg may use it; the product package never imports it. It shares no
+code with the GPU library. See ``oracle.c`` for what each routine computes and
+which passage of the paper it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no FP contraction, OpenMP)."""
+    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "oracle_tti.c", "oracle_elastic.c")
+            if os.path.exists(os.path.join(_HERE, f))]
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+               "-Wall", *srcs, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        c_int, c_double = ctypes.c_int, ctypes.c_double
+        vp = ctypes.c_void_p
+        L.or_fornberg.argtypes = [c_int, c_int, _dp, c_double, _dp]
+        L.or_weights_d2.argtypes = [c_int, _dp]
+        L.or_weights_d1.argtypes = [c_int, _dp]
+        L.or_weights_d1_staggered.argtypes = [c_int, _dp]
+        L.or_trilinear.argtypes = [_dp, _dp, _dp, _ip, _ip, _dp]
+        L.or_damping.argtypes = [_ip, _dp, c_int, c_double, _dp]
+        L.or_damping.restype = None
+        L.or_laplacian.argtypes = [_ip, _dp, c_int, _dp, _dp]
+        L.or_acoustic_forward.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int, _dp,
+                                          c_double, c_int, _dp, _dp, c_int, _dp,
+                                          vp, vp, vp, vp, vp, vp]
+        L.or_acoustic_inject_increment.argtypes = [_ip, _dp, _dp, c_int, c_double, _dp, c_int,
+                                                   _dp, _dp, c_int, _dp]
+        L.or_acoustic_adjoint.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int, _dp,
+                                          c_double, c_int, _dp, _dp, c_int, _dp, _dp,
+                                          vp, vp, vp, vp]
+        L.or_misfit.argtypes = [c_int, c_int, _dp, _dp, vp]
+        L.or_misfit.restype = c_double
+        L.or_num_threads.restype = c_int
+        if hasattr(L, "or_tti_forward"):
+            L.or_tti_forward.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int,
+                                         _dp, _dp, _dp, _dp, _dp, c_double,
+                                         c_int, _dp, _dp, c_int, _dp, vp, vp, vp, vp, vp]
+        if hasattr(L, "or_elastic_forward"):
+            L.or_elastic_forward.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int,
+                                             _dp, _dp, _dp, c_double,
+                                             c_int, _dp, _dp, c_int, _dp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(st: int, what: str):
+    if st < 0:
+        raise RuntimeError(f"oracle {what} failed with status {st}")
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+def fornberg(m: int, x, x0: float) -> np.ndarray:
+    x = _f64(x)
+    out = np.zeros(len(x))
+    _check(lib().or_fornberg(m, len(x), x, float(x0), out), "fornberg")
+    return out
+
+
+def weights_d2(so: int) -> np.ndarray:
+    out = np.zeros(so // 2 + 1)
+    _check(lib().or_weights_d2(so, out), "weights_d2")
+    return out
+
+
+def weights_d1(so: int) -> np.ndarray:
+    out = np.zeros(so // 2)
+    _check(lib().or_weights_d1(so, out), "weights_d1")
+    return out
+
+
+def weights_d1_staggered(so: int) -> np.ndarray:
+    out = np.zeros(so // 2)
+    _check(lib().or_weights_d1_staggered(so, out), "weights_d1_staggered")
+    return out
+
+
+def trilinear(p, o, h, n):
+    """Return (nodes[k][3], weights[k]) of the non-zero trilinear corners."""
+    nodes = np.zeros((8, 3), dtype=np.int32)
+    w = np.zeros(8)
+    cnt = lib().or_trilinear(_f64(p), _f64(o), _f64(h), np.asarray(n, dtype=np.int32),
+                             nodes, w)
+    if cnt < 0:
+        raise ValueError("point outside the grid")
+    return nodes[:cnt].copy(), w[:cnt].copy()
+
+
+def damping(shape, spacing, nbl: int, vmax: float) -> np.ndarray:
+    out = np.zeros(shape)
+    lib().or_damping(np.asarray(shape, dtype=np.int32), _f64(spacing), int(nbl), float(vmax),
+                     out)
+    return out
+
+
+def laplacian(u: np.ndarray, spacing, so: int) -> np.ndarray:
+    u = _f64(u)
+    out = np.zeros_like(u)
+    _check(lib().or_laplacian(np.asarray(u.shape, dtype=np.int32), _f64(spacing), so, u, out),
+           "laplacian")
+    return out
+
+
+def acoustic_forward(shot, vp: Optional[np.ndarray] = None, src_wav=None, vmax_damp: float = 0.0,
+                     u0=None, u1=None, want_history: bool = False, nbl: Optional[int] = None,
+                     src_xyz=None, rec_xyz=None, nt: Optional[int] = None):
+    """Run the FP64 acoustic forward of a ``workloads.Shot``.
+
+    Returns dict(traces[nt][nrec], u_last, u_prev, history (optional)).
+    """
+    n = np.asarray(shot.shape, dtype=np.int32)
+    vp = _f64(shot.vp if vp is None else vp)
+    wav = _f64(shot.src_wav if src_wav is None else src_wav)
+    sx = _f64(shot.src_xyz if src_xyz is None else src_xyz)
+    rx = _f64(shot.rec_xyz if rec_xyz is None else rec_xyz)
+    nt = shot.nt if nt is None else nt
+    nsrc = sx.shape[0]
+    nrec = rx.shape[0]
+    traces = np.zeros((nt, nrec))
+    u_last = np.zeros(shot.shape)
+    u_prev = np.zeros(shot.shape)
+    hist = np.zeros((nt + 1,) + tuple(shot.shape)) if want_history else None
+    u0 = None if u0 is None else _f64(u0)
+    u1 = None if u1 is None else _f64(u1)
+    st = lib().or_acoustic_forward(n, _f64(shot.spacing), _f64(shot.origin), shot.space_order,
+                                   shot.nbl if nbl is None else nbl, float(shot.dt), nt, vp,
+                                   float(vmax_damp), nsrc, sx, wav, nrec, rx,
+                                   _ptr(u0), _ptr(u1), _ptr(traces), _ptr(u_last),
+                                   _ptr(u_prev), _ptr(hist))
+    _check(st, "acoustic_forward")
+    out = dict(traces=traces, u_last=u_last, u_prev=u_prev)
+    if want_history:
+        out["history"] = hist
+    return out
+
+
+def acoustic_inject_increment(shot, t: int, vp=None) -> np.ndarray:
+    out = np.zeros(shot.shape)
+    _check(lib().or_acoustic_inject_increment(
+        np.asarray(shot.shape, dtype=np.int32), _f64(shot.spacing), _f64(shot.origin),
+        shot.space_order, float(shot.dt), _f64(shot.vp if vp is None else vp),
+        shot.src_xyz.shape[0], _f64(shot.src_xyz), _f64(shot.src_wav), int(t), out),
+        "inject_increment")
+    return out
+
+
+def acoustic_adjoint(shot, res: np.ndarray, vp=None, vmax_damp: float = 0.0,
+                     u_hist: Optional[np.ndarray] = None, want_grad: bool = False,
+                     want_qhat: bool = True, nbl: Optional[int] = None):
+    """Adjoint run driven by data-space vector ``res[nt][nrec]``.
+
+    Returns dict(qhat[nt][nsrc], grad (if want_grad, needs u_hist), nu1).
+    """
+    n = np.asarray(shot.shape, dtype=np.int32)
+    vp = _f64(shot.vp if vp is None else vp)
+    nsrc = shot.src_xyz.shape[0]
+    nrec = shot.rec_xyz.shape[0]
+    res = _f64(res)
+    qhat = np.zeros((shot.nt, nsrc)) if want_qhat else None
+    grad = np.zeros(shot.shape) if want_grad else None
+    nu1 = np.zeros(shot.shape)
+    if want_grad:
+        if u_hist is None:
+            raise ValueError("gradient needs the forward history")
+        u_hist = _f64(u_hist)
+    st = lib().or_acoustic_adjoint(n, _f64(shot.spacing), _f64(shot.origin), shot.space_order,
+                                   shot.nbl if nbl is None else nbl, float(shot.dt), shot.nt, vp,
+                                   float(vmax_damp), nsrc, _f64(shot.src_xyz),
+                                   _f64(shot.src_wav), nrec, _f64(shot.rec_xyz), res,
+                                   _ptr(u_hist), _ptr(grad), _ptr(qhat), _ptr(nu1))
+    _check(st, "acoustic_adjoint")
+    return dict(qhat=qhat, grad=grad, nu1=nu1)
+
+
+def acoustic_gradient(shot, dobs: np.ndarray, vp=None, vmax_damp: float = 0.0):
+    """J(m) and dJ/dm (m = 1/vp^2) for J = 1/2 sum |P_r u^k - dobs^k|^2."""
+    fw = acoustic_forward(shot, vp=vp, vmax_damp=vmax_damp, want_history=True)
+    res = np.zeros_like(fw["traces"])
+    J = lib().or_misfit(shot.nt, shot.rec_xyz.shape[0], _f64(fw["traces"]), _f64(dobs),
+                        _ptr(res))
+    adj = acoustic_adjoint(shot, res, vp=vp, vmax_damp=vmax_damp,
+                           u_hist=fw["history"][:shot.nt], want_grad=True, want_qhat=False)
+    return float(J), adj["grad"], fw
+
+
+def misfit(d, dobs) -> float:
+    d = _f64(d)
+    dobs = _f64(dobs)
+    return float(lib().or_misfit(d.shape[0], d.shape[1], d, dobs, None))

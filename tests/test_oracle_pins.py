@@ -1,0 +1,312 @@
+"""Pins of the FP64 oracle against facts fixed by the mathematics or the
+literature, independent of the oracle's own code.
+
+Each test names the part of the oracle it pins and what a plausible mistake
+would break. All run on the CPU.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2010_10248_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_weights():
+    out = {}
+    with open(os.path.join(GOLD, "fd_weights.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            kind, so, *vals = line.split()
+            out[(kind, int(so))] = [float(Fraction(v)) for v in vals]
+    return out
+
+
+# --------------------------------------------------------------------------
+# FD weights (oracle or_fornberg / or_weights_*): literature rationals and
+# polynomial exactness to exactly the stated order.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,so", [("d2", 4), ("d2", 8), ("d2", 12), ("d1", 4), ("d1", 8),
+                                     ("d1s", 4), ("d1s", 8)])
+def test_fd_weights_match_fornberg_table(orc, kind, so):
+    gold = _golden_weights()[(kind, so)]
+    fn = {"d2": orc.weights_d2, "d1": orc.weights_d1, "d1s": orc.weights_d1_staggered}[kind]
+    w = fn(so)
+    np.testing.assert_allclose(w, gold, rtol=1e-13, atol=1e-15)
+
+
+def _apply(kind, w, p):
+    """Apply weights to x**p at 0 on unit spacing; return (approx, exact)."""
+    r = len(w) - 1 if kind == "d2" else len(w)
+    if kind == "d2":
+        s = w[0] * (0.0 ** p if p > 0 else 1.0)
+        for j in range(1, r + 1):
+            s += w[j] * (float(j) ** p + float(-j) ** p)
+        exact = 2.0 if p == 2 else 0.0
+    elif kind == "d1":
+        s = sum(w[j - 1] * (float(j) ** p - float(-j) ** p) for j in range(1, r + 1))
+        exact = 1.0 if p == 1 else 0.0
+    else:
+        s = sum(w[j] * ((j + 0.5) ** p - (-(j + 0.5)) ** p) for j in range(r))
+        exact = 1.0 if p == 1 else 0.0
+    return s, exact
+
+
+@pytest.mark.parametrize("so", [4, 8, 12])
+def test_fd_d2_exact_to_order(orc, so):
+    w = orc.weights_d2(so)
+    # Exact for every monomial of degree <= so + 1 ...
+    for p in range(0, so + 2):
+        s, e = _apply("d2", w, p)
+        assert abs(s - e) <= 1e-9 * max(1.0, (so / 2) ** p), (p, s, e)
+    # ... and not for degree so + 2 (so the order is exactly so).
+    s, e = _apply("d2", w, so + 2)
+    assert abs(s - e) > 1e-3
+
+
+@pytest.mark.parametrize("kind,so", [("d1", 4), ("d1", 8), ("d1s", 4), ("d1s", 8)])
+def test_fd_d1_exact_to_order(orc, kind, so):
+    w = orc.weights_d1(so) if kind == "d1" else orc.weights_d1_staggered(so)
+    for p in range(0, so + 1):
+        s, e = _apply(kind, w, p)
+        assert abs(s - e) <= 1e-9 * max(1.0, (so / 2 + 1) ** p), (p, s, e)
+    s, e = _apply(kind, w, so + 1)
+    assert abs(s - e) > 1e-4
+
+
+def test_laplacian_exact_on_quadratic(orc):
+    """L applied to a quadratic field away from the boundary equals its exact
+    Laplacian (pins axis scaling h_a^-2 and the symmetric offsets)."""
+    n = (20, 22, 24)
+    h = (10.0, 7.0, 5.0)
+    x, y, z = np.meshgrid(*[np.arange(k) * hh for k, hh in zip(n, h)], indexing="ij")
+    u = 0.3 * x * x - 1.1 * y * y + 0.7 * z * z + 2.0 * x * y - z + 5.0
+    for so in (4, 8):
+        r = so // 2
+        L = orc.laplacian(u, h, so)
+        inner = L[r:-r, r:-r, r:-r]
+        np.testing.assert_allclose(inner, 2 * (0.3 - 1.1 + 0.7), rtol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Trilinear weights (or_trilinear): reproduce affine functions exactly, sum
+# to one, drop zero corners, reject out-of-range points.
+# --------------------------------------------------------------------------
+def test_trilinear_reproduces_affine(orc):
+    rng = np.random.Generator(np.random.PCG64(1))
+    n = (11, 13, 17)
+    h = (10.0, 12.5, 8.0)
+    o = (-3.0, 5.0, 100.0)
+    for _ in range(200):
+        p = np.array([o[a] + rng.random() * (n[a] - 1) * h[a] for a in range(3)])
+        nodes, w = orc.trilinear(p, o, h, n)
+        assert abs(w.sum() - 1.0) < 1e-14
+        X = np.array([[o[a] + nd[a] * h[a] for a in range(3)] for nd in nodes])
+        f = lambda q: 2.0 * q[..., 0] - 3.0 * q[..., 1] + 0.5 * q[..., 2] + 7.0
+        assert abs((w * f(X)).sum() - f(p)) < 1e-9
+        # the bilinear term xy is reproduced too (tensor-product weights)
+        g = lambda q: q[..., 0] * q[..., 1] - q[..., 1] * q[..., 2]
+        assert abs((w * g(X)).sum() - g(p)) < 1e-7 * max(1.0, abs(g(p)))
+
+
+def test_trilinear_on_grid_and_edges(orc):
+    n = (5, 5, 5)
+    h = (1.0, 1.0, 1.0)
+    o = (0.0, 0.0, 0.0)
+    nodes, w = orc.trilinear([2.0, 3.0, 1.0], o, h, n)
+    assert nodes.tolist() == [[2, 3, 1]] and w.tolist() == [1.0]
+    nodes, w = orc.trilinear([4.0, 4.0, 4.0], o, h, n)  # upper corner exactly
+    assert nodes.tolist() == [[4, 4, 4]]
+    nodes, w = orc.trilinear([2.5, 3.0, 1.0], o, h, n)
+    assert sorted(nodes.tolist()) == [[2, 3, 1], [3, 3, 1]]
+    np.testing.assert_allclose(w, [0.5, 0.5])
+    with pytest.raises(ValueError):
+        orc.trilinear([4.0001, 1.0, 1.0], o, h, n)
+    with pytest.raises(ValueError):
+        orc.trilinear([-1e-9, 1.0, 1.0], o, h, n)
+
+
+# --------------------------------------------------------------------------
+# Damping profile: zero in the interior, quadratic in the layer, summed
+# over axes; 3 v ln(1/R)/(2 L) at the outer node.
+# --------------------------------------------------------------------------
+def test_damping_profile(orc):
+    n = (30, 30, 30)
+    h = (10.0, 10.0, 20.0)
+    nbl, vmax = 5, 2000.0
+    d = orc.damping(n, h, nbl, vmax)
+    assert np.all(d[nbl:-nbl, nbl:-nbl, nbl:-nbl] == 0.0)
+    d0x = 3 * vmax * math.log(1e3) / (2 * nbl * h[0])
+    assert d[0, 15, 15] == pytest.approx(d0x, rel=1e-14)
+    assert d[2, 15, 15] == pytest.approx(d0x * (3 / 5) ** 2, rel=1e-14)
+    assert d[29, 15, 15] == pytest.approx(d0x, rel=1e-14)
+    d0z = 3 * vmax * math.log(1e3) / (2 * nbl * h[2])
+    assert d[0, 15, 0] == pytest.approx(d0x + d0z, rel=1e-14)
+    assert np.all(orc.damping(n, h, 0, vmax) == 0.0)
+
+
+# --------------------------------------------------------------------------
+# Whole forward step.
+# --------------------------------------------------------------------------
+def _tiny(seed=3, n=(24, 26, 28), so=8, nt=40, nbl=4, nsrc=2, nrec=6, layered=True):
+    s = W.acoustic_scaled(seed, n, so, nt, nbl, nsrc=nsrc, nrec=nrec, layered=layered)
+    return s
+
+
+def test_zero_source_stays_exactly_zero(orc):
+    s = _tiny()
+    out = orc.acoustic_forward(s, src_wav=np.zeros_like(s.src_wav))
+    assert np.all(out["traces"] == 0.0)
+    assert np.all(out["u_last"] == 0.0) and np.all(out["u_prev"] == 0.0)
+
+
+def test_energy_conserved_without_damping(orc):
+    """With d = 0 and the source off after step n0, the discrete energy
+    E = sum (u^{n+1}-u^n)^2/c - <u^{n+1}, L u^n> is constant (L symmetric)."""
+    s = _tiny(nt=60, nbl=0)
+    wav = s.src_wav.copy()
+    wav[20:] = 0.0
+    out = orc.acoustic_forward(s, src_wav=wav, want_history=True)
+    H = out["history"]
+    c = s.dt ** 2 * s.vp ** 2
+    E = []
+    for k in range(22, 60):
+        du = H[k + 1] - H[k]
+        E.append(float(np.sum(du * du / c) - np.sum(H[k + 1] * orc.laplacian(H[k], s.spacing, 8))))
+    E = np.array(E)
+    assert abs(E[0]) > 0
+    assert np.max(np.abs(E - E[0])) / abs(E[0]) < 1e-12
+
+
+def test_energy_drift_detects_wrong_update(orc):
+    """Control: the same energy is not conserved when the damping layer is on,
+    so the conservation test above can fail."""
+    s = _tiny(nt=60, nbl=4)
+    wav = s.src_wav.copy()
+    wav[20:] = 0.0
+    out = orc.acoustic_forward(s, src_wav=wav, want_history=True)
+    H = out["history"]
+    c = s.dt ** 2 * s.vp ** 2
+    E = []
+    for k in (22, 59):
+        du = H[k + 1] - H[k]
+        E.append(float(np.sum(du * du / c) - np.sum(H[k + 1] * orc.laplacian(H[k], s.spacing, 8))))
+    assert abs(E[1] - E[0]) / abs(E[0]) > 1e-6
+
+
+def test_superposition(orc):
+    s = _tiny(nsrc=3)
+    full = orc.acoustic_forward(s)
+    acc_t = np.zeros_like(full["traces"])
+    acc_u = np.zeros_like(full["u_last"])
+    for k in range(3):
+        wav = np.zeros_like(s.src_wav)
+        wav[:, k] = s.src_wav[:, k]
+        o = orc.acoustic_forward(s, src_wav=wav)
+        acc_t += o["traces"]
+        acc_u += o["u_last"]
+    scale = np.abs(full["u_last"]).max()
+    assert np.abs(acc_u - full["u_last"]).max() <= 1e-12 * scale
+    assert np.abs(acc_t - full["traces"]).max() <= 1e-12 * np.abs(full["traces"]).max()
+
+
+def test_reciprocity_heterogeneous(orc):
+    """Swapping an off-grid source and receiver gives the same trace, for a
+    layered model with damping: the dt^2/m injection makes the discrete
+    Green's operator symmetric."""
+    s = _tiny(nsrc=1, nrec=1, nt=50)
+    a, b = s.src_xyz.copy(), s.rec_xyz.copy()
+    o1 = orc.acoustic_forward(s, src_xyz=a, rec_xyz=b)
+    o2 = orc.acoustic_forward(s, src_xyz=b, rec_xyz=a)
+    t1, t2 = o1["traces"][:, 0], o2["traces"][:, 0]
+    assert np.abs(t1).max() > 0
+    assert np.abs(t1 - t2).max() <= 1e-12 * np.abs(t1).max()
+
+
+def test_injection_increment_is_direct_scatter(orc):
+    """The source loop's increment on a zero grid equals W * dt^2 vp^2 * q
+    at each corner, summed over sources."""
+    s = _tiny(nsrc=2)
+    t = 7
+    inc = orc.acoustic_inject_increment(s, t)
+    ref = np.zeros(s.shape)
+    h = np.array(s.spacing)
+    for k in range(2):
+        xi = (s.src_xyz[k] - np.array(s.origin)) / h
+        i0 = np.floor(xi).astype(int)
+        f = xi - i0
+        for b in np.ndindex(2, 2, 2):
+            wgt = np.prod([f[a] if b[a] else 1 - f[a] for a in range(3)])
+            if wgt == 0:
+                continue
+            node = tuple(i0 + np.array(b))
+            ref[node] += wgt * s.dt ** 2 * s.vp[node] ** 2 * s.src_wav[t, k]
+    np.testing.assert_allclose(inc, ref, rtol=1e-13, atol=1e-300)
+
+
+def _power_iteration_rho(orc, n, h, so, vp, iters=300):
+    rng = np.random.Generator(np.random.PCG64(0))
+    x = rng.standard_normal(n)
+    c = vp ** 2
+    lam = 0.0
+    for _ in range(iters):
+        y = c * orc.laplacian(x, h, so)
+        lam = np.linalg.norm(y) / np.linalg.norm(x)
+        x = y / np.linalg.norm(y)
+    return lam
+
+
+@pytest.mark.parametrize("so,bound", [(4, 0.5), (8, 0.45286)])
+def test_stability_bound_closed_form(orc, so, bound):
+    """rho(c L) for constant vp approaches the closed-form symbol maximum
+    vp^2 * 3 |sum_j w_j (-1)^j| / h^2, which gives the CFL bound
+    vp dt / h <= 2/sqrt(3 |.|) (0.5 for SO4, 0.45286 for SO8)."""
+    n = (24, 24, 24)
+    h = (10.0, 10.0, 10.0)
+    vp = np.full(n, 1500.0)
+    rho = _power_iteration_rho(orc, n, h, so, vp)
+    w = orc.weights_d2(so)
+    sym = abs(w[0] + 2 * sum(w[j] * (-1) ** j for j in range(1, len(w))))
+    closed = 1500.0 ** 2 * 3 * sym / 100.0
+    assert rho <= closed * (1 + 1e-9)
+    assert rho >= 0.97 * closed
+    cfl = 2.0 / math.sqrt(3 * sym)
+    assert cfl == pytest.approx(bound, abs=2e-5)
+    # leapfrog is stable iff dt^2 rho <= 4: running just above the bound blows up
+    s = W.acoustic_scaled(5, n, so, 400, 0, nsrc=1, nrec=1, layered=False)
+    for fac, ok in ((0.98, True), (1.03, False)):
+        s.dt = fac * cfl * 10.0 / 1500.0
+        s.src_wav = W.ricker(10.0, s.nt, s.dt)[:, None]
+        u = orc.acoustic_forward(s)["u_last"]
+        assert (np.abs(u).max() < 1e3) == ok
+
+
+def test_green_function_homogeneous(orc):
+    """Homogeneous 3D Green's function: u = h^3 q(t - R/v) / (4 pi R) for the
+    un-normalised dt^2/m injection, checked before boundary reflections; the
+    error falls ~4x when h and dt are halved (second order in time)."""
+    def run(h, L=750.0, f0=10.0, v=1500.0, R=200.0, T=0.36):
+        n = int(round(L / h)) + 1
+        dt = 0.4 * h / v
+        nt = int(round(T / dt))
+        c = (n // 2) * h
+        src = np.array([[c, c, c]])
+        rec = np.array([[c + R, c, c], [c, c + 0.6 * R, c + 0.8 * R]])
+        wav = W.ricker(f0, nt, dt)[:, None]
+        s = W.Shot((n, n, n), (h, h, h), (0.0, 0.0, 0.0), 8, 0, dt, nt,
+                   np.full((n, n, n), v), src, wav, rec)
+        tr = orc.acoustic_forward(s)["traces"]
+        ana = h ** 3 * W.ricker(f0, nt, dt, t0=1.0 / f0 + R / v) / (4 * math.pi * R)
+        return [np.linalg.norm(tr[:, k] - ana) / np.linalg.norm(ana) for k in range(2)]
+
+    e10 = run(10.0)
+    e5 = run(5.0)
+    assert max(e10) < 0.03
+    for a, b in zip(e10, e5):
+        assert 3.5 < a / b < 4.5
