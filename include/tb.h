@@ -1,0 +1,203 @@
+/*
+ * tb.h — C ABI of the MI355X (gfx950) temporal-blocking wave-propagation
+ * library.
+ *
+ * The library implements the method of "Temporal blocking of
+ * finite-difference stencil operators with sparse off-the-grid sources"
+ * (Bisbas et al., arXiv 2010.10248): explicit finite-difference wave
+ * propagators whose sparse off-the-grid source injection and receiver
+ * interpolation are precomputed by an inspector (Section II-A) into
+ * grid-aligned per-point wavelets, so that wave-front temporal blocking
+ * (Section II-B) can advance several time steps per pass over memory.
+ *
+ * Conventions
+ *  - Every call returns a tb_status (TB_OK == 0, errors < 0); no C++
+ *    exception crosses this boundary. tb_last_error() returns a thread-local
+ *    text for the last failure on the calling thread.
+ *  - Grids are C-order [nx][ny][nz] float32 with z fastest. "Device" pointers
+ *    are HIP device memory on the current device; "host" pointers are
+ *    ordinary host memory, read during the call and not retained.
+ *  - Streams are passed as void* (a hipStream_t; NULL = the null stream).
+ *    Work is enqueued asynchronously; execution errors surface at the
+ *    caller's synchronisation.
+ *  - Handles are immutable after creation apart from internal caches that
+ *    are built under a lock; a handle may be used from several streams.
+ */
+#ifndef TB_H
+#define TB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tb_status;
+
+#define TB_OK 0
+#define TB_EINVAL (-1)       /* malformed argument                           */
+#define TB_EUNSUPPORTED (-2) /* physics / space order / option not built     */
+#define TB_EUNSTABLE (-3)    /* dt exceeds the discrete stability bound      */
+#define TB_ERANGE (-4)       /* a sparse coordinate lies outside the grid    */
+#define TB_ENOMEM (-5)       /* device or host allocation failed             */
+#define TB_EHIP (-6)         /* a HIP runtime call or kernel launch failed   */
+#define TB_EWORKSPACE (-7)   /* caller workspace / buffer too small          */
+
+#define TB_ACOUSTIC 0 /* isotropic acoustic, Section III-A                  */
+#define TB_TTI 1      /* pseudo-acoustic TTI, Section III-B                 */
+#define TB_ELASTIC 2  /* isotropic elastic velocity-stress, Section III-C  */
+
+#define TB_SCHED_SB 0 /* spatial blocking: one time step per pass (Fig. 4a) */
+#define TB_SCHED_TB 1 /* wave-front temporal blocking (Fig. 4b, Fig. 7)    */
+
+typedef struct tb_model tb_model;
+typedef struct tb_sparse tb_sparse;
+
+/*
+ * Model description (equation (acou) of Section III-A and Section IV-B).
+ *  shape       grid nodes per axis; the absorbing layers lie inside it.
+ *  spacing     h per axis in metres; origin in metres.
+ *  space_order 4 or 8 (centred Taylor weights, radius space_order/2).
+ *  nbl         absorbing-layer width in nodes (0 = no damping).
+ *  dt, nt      time step (s) and number of updates of a forward run.
+ *  damp_vmax   velocity used by the damping profile (<= 0: max(vp)).
+ *  vp          device float32 [nx][ny][nz] P velocity (m/s); read during the
+ *              call only (the library derives its own coefficient arrays).
+ *  epsilon, delta, theta, phi   TTI only (device float32 [nx][ny][nz]).
+ *  vs, rho     elastic only (device float32 [nx][ny][nz]).
+ */
+typedef struct {
+    int32_t physics;
+    int32_t shape[3];
+    double spacing[3];
+    double origin[3];
+    int32_t space_order;
+    int32_t nbl;
+    double dt;
+    int32_t nt;
+    double damp_vmax;
+    const float *vp;
+    const float *epsilon;
+    const float *delta;
+    const float *theta;
+    const float *phi;
+    const float *vs;
+    const float *rho;
+} tb_model_desc;
+
+/*
+ * Schedule of the time loop (Section II-B; the wave-front loop nest of the
+ * last listing). mode TB_SCHED_SB runs one step per pass; TB_SCHED_TB runs
+ * time_tile steps per pass with a wave-front along x and overlapped y-z
+ * halos. tile_y is the number of y rows one workgroup holds (16, 32 or 64),
+ * chunk_x the number of x planes one workgroup streams (0 = all of x).
+ * Passing NULL where a schedule is accepted selects the tuned default.
+ */
+typedef struct {
+    int32_t mode;
+    int32_t time_tile;
+    int32_t tile_y;
+    int32_t chunk_x;
+} tb_schedule;
+
+/* Workspace operations for tb_workspace_size. */
+#define TB_OP_FORWARD 0
+#define TB_OP_ADJOINT 1
+#define TB_OP_GRADIENT 2
+
+/*
+ * Create a model: validates the description, computes c = dt^2 vp^2 (FP64,
+ * rounded once to FP32) and the damping profile into library-owned device
+ * memory on the current device. Errors: TB_EINVAL, TB_EUNSUPPORTED (physics
+ * or space order), TB_EUNSTABLE (vp_max dt exceeds the leapfrog bound of the
+ * chosen weights), TB_ENOMEM, TB_EHIP. *out is NULL on failure.
+ */
+tb_status tb_create_model(const tb_model_desc *desc, tb_model **out);
+void tb_destroy_model(tb_model *m);
+
+/*
+ * Inspector (Section II-A; the empty-grid injection, mask/ID and
+ * decomposition listings). Host inputs: nsrc source coordinates
+ * src_xyz[nsrc][3] (m), their wavelets src_wavelet[nt][nsrc] (the value
+ * injected at t_n = n dt), and nrec receiver coordinates rec_xyz[nrec][3].
+ * Builds the unique affected-point set with ascending IDs, the decomposed
+ * per-point wavelets src_dcmp[nt][npts] (summed in FP64, rounded once to
+ * FP32) and the receiver mirror, and uploads them. Per-schedule tile lists
+ * are built lazily and cached in the handle. Errors: TB_ERANGE (a point
+ * outside [origin, origin + (n-1) h]), TB_EINVAL, TB_ENOMEM, TB_EHIP.
+ * nsrc or nrec may be 0 (the pointer may then be NULL).
+ */
+tb_status tb_inspect_sparse(const tb_model *m, int32_t nsrc, const double *src_xyz,
+                            const double *src_wavelet, int32_t nrec, const double *rec_xyz,
+                            tb_sparse **out);
+void tb_destroy_sparse(tb_sparse *s);
+
+/* Sizes of the inspector's products: unique source points, unique receiver
+ * points. */
+tb_status tb_sparse_counts(const tb_sparse *s, int32_t *npts, int32_t *nrid);
+
+/*
+ * Host-only inspector (no device memory touched), for checking the
+ * decomposition on a machine without a GPU. vp_host is float32
+ * [nx][ny][nz]. On input *npts holds the capacity of nodes[cap][3] and
+ * dcmp[nt][cap]; on return it holds the number of unique affected points
+ * (TB_EWORKSPACE if it exceeds the capacity; nothing else written then).
+ * nodes are listed in ascending raster order (their IDs); dcmp[n][id] =
+ * sum_s sum_corner W c(node) q_s(t_n) with c = dt^2 vp^2.
+ */
+tb_status tb_inspect_host(const int32_t shape[3], const double spacing[3], const double origin[3],
+                          double dt, int32_t nt, const float *vp_host, int32_t nsrc,
+                          const double *src_xyz, const double *src_wavelet, int32_t *npts,
+                          int32_t *nodes, float *dcmp);
+
+/* Bytes of caller workspace needed by an operation (TB_OP_*). */
+tb_status tb_workspace_size(const tb_model *m, const tb_sparse *s, const tb_schedule *sched,
+                            int32_t op, size_t *bytes);
+
+/*
+ * Forward propagation from zero initial conditions over nt steps (equation
+ * (acou); naive-order semantics of the first listing, computed in the order
+ * of the chosen schedule). Outputs (device, caller-owned, any may be NULL):
+ * rec_out[nt][nrec] with d^n = P_r u^n (so d^0 = 0), field_out = u^{nt} and
+ * field_prev_out = u^{nt-1} as [nx][ny][nz]. ws must hold
+ * tb_workspace_size(TB_OP_FORWARD) bytes of device memory.
+ * Errors: TB_EINVAL, TB_EWORKSPACE, TB_EUNSUPPORTED, TB_EHIP.
+ */
+tb_status tb_forward(const tb_model *m, const tb_sparse *s, const tb_schedule *sched, void *ws,
+                     size_t ws_bytes, float *rec_out, float *field_out, float *field_prev_out,
+                     void *stream);
+
+/*
+ * Exact discrete adjoint of the linear map q -> d of tb_forward (the same
+ * update run backward in time, driven by rec_in[nt][nrec] at the receiver
+ * points). Output src_out[nt][nsrc] (device). Used for the dot-product test
+ * and for imaging. Acoustic only.
+ */
+tb_status tb_adjoint(const tb_model *m, const tb_sparse *s, const tb_schedule *sched, void *ws,
+                     size_t ws_bytes, const float *rec_in, float *src_out, void *stream);
+
+/*
+ * Gradient of J = 1/2 sum_n |P_r u^n - d_obs^n|^2 with respect to the squared
+ * slowness m = 1/vp^2 (damping profile held fixed), by a forward run with
+ * checkpoints every checkpoint_every steps (0 = ceil(sqrt(nt))), recompute of
+ * each segment and the adjoint run with the imaging condition fused.
+ * d_obs[nt][nrec] device; grad_m [nx][ny][nz] device (overwritten);
+ * loss_out host (may be NULL; written after the call synchronises the
+ * stream). Acoustic only: TB_EUNSUPPORTED otherwise.
+ */
+tb_status tb_gradient(const tb_model *m, const tb_sparse *s, const tb_schedule *sched, void *ws,
+                      size_t ws_bytes, const float *d_obs, float *grad_m, double *loss_out,
+                      int32_t checkpoint_every, void *stream);
+
+/* Text of the last error on this thread ("" if none). */
+const char *tb_last_error(void);
+
+/* Library version string. */
+const char *tb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TB_H */

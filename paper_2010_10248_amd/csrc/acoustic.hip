@@ -1,0 +1,164 @@
+// Host launch code of the acoustic propagator and the small auxiliary kernels
+// (fill, trace reduction, unpadding, adjoint source assembly). The wave-front
+// kernel itself lives in acoustic_kernel.h.
+#include "acoustic_params.h"
+
+namespace tbw {
+namespace {
+
+__global__ void fill_kernel(float *p, size_t n, float v)
+{
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+// d[n][r] = sum_k W_rk rec_dcmp[row(n)][rid_k], corners in their fixed order.
+__global__ void trace_reduce_kernel(const float *__restrict__ rec_dcmp, int nrid, int nt,
+                                    const int *__restrict__ ptr, const int *__restrict__ id,
+                                    const float *__restrict__ w, int nrec, float *out, int reverse)
+{
+    const long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (g >= (long long)nt * nrec) return;
+    const int n = (int)(g / nrec), r = (int)(g % nrec);
+    const int rowi = reverse ? nt - 1 - n : n;
+    const float *src = rec_dcmp + (long long)rowi * nrid;
+    float acc = 0.0f;
+    for (int k = ptr[r]; k < ptr[r + 1]; k++) acc = __builtin_fmaf(w[k], src[id[k]], acc);
+    out[g] = acc;
+}
+
+__global__ void unpad_kernel(const float *__restrict__ src, float *__restrict__ dst, int nx,
+                             int ny, int nz, int nzp)
+{
+    const long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long total = (long long)nx * ny * nz;
+    if (g >= total) return;
+    const int zz = (int)(g % nz);
+    const long long xy = g / nz;
+    dst[g] = src[xy * nzp + zz];
+}
+
+// Adjoint source term: dcmp_out[tau][rid] = scale[rid] * sum W res[nt-1-tau][rec].
+__global__ void adj_inject_kernel(const float *__restrict__ res, int nt, int nrec, int nrid,
+                                  const int *__restrict__ rr_ptr, const int *__restrict__ rr_rec,
+                                  const float *__restrict__ rr_w,
+                                  const float *__restrict__ rid_scale, float *dcmp_out)
+{
+    const long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (g >= (long long)nt * nrid) return;
+    const int tau = (int)(g / nrid), rid = (int)(g % nrid);
+    const float *rv = res + (long long)(nt - 1 - tau) * nrec;
+    float acc = 0.0f;
+    for (int k = rr_ptr[rid]; k < rr_ptr[rid + 1]; k++)
+        acc = __builtin_fmaf(rr_w[k], rv[rr_rec[k]], acc);
+    dcmp_out[g] = rid_scale[rid] * acc;
+}
+
+}  // namespace
+
+tb_status launch_acoustic(const tb_model *m, const TileGeom &g, const TileLists &tl,
+                          const AcLaunch &a, hipStream_t st)
+{
+    AcParams p{};
+    p.u = a.u;
+    p.um = a.um;
+    p.c = m->d_c;
+    p.out0 = a.out0;
+    p.out1 = a.out1;
+    p.dx = m->d_damp;
+    p.dy = m->d_damp + m->n[0];
+    p.dz = m->d_damp + m->n[0] + m->n[1];
+    p.hdt = (float)(m->dt / 2.0);
+    // Centred second-derivative weights of order so (Fornberg), tabulated
+    // as exact rationals and scaled by h^-2 per axis.
+    static const double w4[3] = {-5.0 / 2.0, 4.0 / 3.0, -1.0 / 12.0};
+    static const double w8[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+    const double *w = m->so == 4 ? w4 : w8;
+    const double ihx = 1.0 / (m->h[0] * m->h[0]), ihy = 1.0 / (m->h[1] * m->h[1]),
+                 ihz = 1.0 / (m->h[2] * m->h[2]);
+    p.w0 = (float)(w[0] * (ihx + ihy + ihz));
+    for (int j = 0; j < 4; j++) {
+        const double wj = j < m->r ? w[j + 1] : 0.0;
+        p.wx[j] = (float)(wj * ihx);
+        p.wy[j] = (float)(wj * ihy);
+        p.wz[j] = (float)(wj * ihz);
+    }
+    p.nx = m->n[0];
+    p.ny = m->n[1];
+    p.nz = m->n[2];
+    p.nzp = m->nzp;
+    p.sx = (long long)m->n[1] * m->nzp;
+    p.tiles_y = g.tiles_y;
+    p.tiles_z = g.tiles_z;
+    p.chunk = g.chunk;
+    p.nblocks = g.nblocks();
+    p.src = tl.d_src;
+    p.src_off = tl.d_src_off;
+    p.dcmp = a.dcmp;
+    p.npts = a.npts;
+    p.n0 = a.n0;
+    p.rec = tl.d_rec;
+    p.rec_off = tl.d_rec_off;
+    p.rec_dcmp = a.rec_dcmp;
+    p.nrid = a.nrid;
+    hipError_t e = hipErrorInvalidValue;
+    if (m->r == 2) e = launch_acoustic_r2(p, g.T, g.BYE, g.nblocks(), st);
+    else if (m->r == 4) e = launch_acoustic_r4(p, g.T, g.BYE, g.nblocks(), st);
+    if (e != hipSuccess) {
+        set_error("acoustic kernel launch (R=%d T=%d BYE=%d) failed: %s", m->r, g.T, g.BYE,
+                  hipGetErrorString(e));
+        return TB_EHIP;
+    }
+    return TB_OK;
+}
+
+tb_status launch_fill(float *ptr, size_t n, float v, hipStream_t st)
+{
+    if (n == 0) return TB_OK;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, ptr, n, v);
+    TB_HIP(hipGetLastError());
+    return TB_OK;
+}
+
+tb_status launch_trace_reduce(const float *rec_dcmp, int nrid, int nt, const int *ptr,
+                              const int *id, const float *w, int nrec, float *out, int reverse,
+                              hipStream_t st)
+{
+    const long long total = (long long)nt * nrec;
+    if (total == 0) return TB_OK;
+    hipLaunchKernelGGL(trace_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       st, rec_dcmp, nrid, nt, ptr, id, w, nrec, out, reverse);
+    TB_HIP(hipGetLastError());
+    return TB_OK;
+}
+
+tb_status launch_unpad(const float *src, float *dst, int nx, int ny, int nz, int nzp,
+                       hipStream_t st)
+{
+    const long long total = (long long)nx * ny * nz;
+    if (nz == nzp) {
+        TB_HIP(hipMemcpyAsync(dst, src, total * sizeof(float), hipMemcpyDeviceToDevice, st));
+        return TB_OK;
+    }
+    hipLaunchKernelGGL(unpad_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, src,
+                       dst, nx, ny, nz, nzp);
+    TB_HIP(hipGetLastError());
+    return TB_OK;
+}
+
+tb_status launch_adj_inject(const float *res, int nt, int nrec, int nrid, const int *rr_ptr,
+                            const int *rr_rec, const float *rr_w, const float *rid_scale,
+                            float *dcmp_out, hipStream_t st)
+{
+    const long long total = (long long)nt * nrid;
+    if (total == 0) return TB_OK;
+    hipLaunchKernelGGL(adj_inject_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       res, nt, nrec, nrid, rr_ptr, rr_rec, rr_w, rid_scale, dcmp_out);
+    TB_HIP(hipGetLastError());
+    return TB_OK;
+}
+
+}  // namespace tbw

@@ -1,0 +1,38 @@
+// Kernel argument block of the acoustic wave-front kernels.
+#pragma once
+
+#include "tb_internal.h"
+
+namespace tbw {
+
+struct AcParams {
+    const float *__restrict__ u;   // u^n      [nx][ny][nzp]
+    const float *__restrict__ um;  // u^{n-1}
+    const float *__restrict__ c;   // dt^2 vp^2
+    float *out0;                   // u^{n+T}
+    float *out1;                   // u^{n+T-1} (T >= 2)
+    const float *__restrict__ dx;  // damping per axis
+    const float *__restrict__ dy;
+    const float *__restrict__ dz;
+    float hdt;  // dt / 2
+    float w0;   // centre weight, summed over the three axes
+    float wx[4], wy[4], wz[4];
+    int nx, ny, nz, nzp;
+    long long sx;  // plane stride ny * nzp
+    int tiles_y, tiles_z, chunk, nblocks;
+    const int4 *__restrict__ src;
+    const int *__restrict__ src_off;
+    const float *__restrict__ dcmp;
+    int npts, n0;
+    const int4 *__restrict__ rec;
+    const int *__restrict__ rec_off;
+    float *rec_dcmp;
+    int nrid;
+};
+
+// Launchers of the wave-front kernel for one stencil radius (one translation
+// unit per radius so the instantiations compile in parallel).
+hipError_t launch_acoustic_r2(const AcParams &p, int T, int BYE, int nblocks, hipStream_t st);
+hipError_t launch_acoustic_r4(const AcParams &p, int T, int BYE, int nblocks, hipStream_t st);
+
+}  // namespace tbw

@@ -1,0 +1,11 @@
+// Wave-front kernel instantiations for stencil radius 2 (space order 4).
+#include "acoustic_kernel.h"
+
+namespace tbw {
+
+hipError_t launch_acoustic_r2(const AcParams &p, int T, int BYE, int nblocks, hipStream_t st)
+{
+    return wf::launch_r<2>(p, T, BYE, nblocks, st);
+}
+
+}  // namespace tbw

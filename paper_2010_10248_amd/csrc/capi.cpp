@@ -1,0 +1,483 @@
+// C ABI of the temporal-blocking library: model and sparse handles, the
+// time loop of the forward and adjoint propagators (host side), status codes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "tb_internal.h"
+
+namespace tbw {
+const char *last_error();
+tb_status inspect_into(tb_sparse *s, int nsrc, const double *src_xyz, const double *wav, int nrec,
+                       const double *rec_xyz);
+}  // namespace tbw
+
+using namespace tbw;
+
+tb_model::~tb_model()
+{
+    if (d_c) (void)hipFree(d_c);
+    if (d_damp) (void)hipFree(d_damp);
+}
+
+tb_sparse::~tb_sparse()
+{
+    tiles.clear();
+    for (void *p : {(void *)d_dcmp, (void *)d_rc_ptr, (void *)d_rc_id, (void *)d_rc_w,
+                    (void *)d_sc_ptr, (void *)d_sc_id, (void *)d_sc_w, (void *)d_rr_ptr,
+                    (void *)d_rr_rec, (void *)d_rr_w, (void *)d_rid_scale})
+        if (p) (void)hipFree(p);
+}
+
+namespace {
+
+// Centred second-derivative weights (Fornberg rationals) for the stability
+// bound; the kernels tabulate the same rationals.
+const double *d2_weights(int so)
+{
+    static const double w4[3] = {-5.0 / 2.0, 4.0 / 3.0, -1.0 / 12.0};
+    static const double w8[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+    return so == 4 ? w4 : (so == 8 ? w8 : nullptr);
+}
+
+// Damping profile along one axis: d0 (k/nbl)^2 with k the depth into the
+// absorbing layer, d0 = 3 vmax ln(1/R) / (2 nbl h), R = 1e-3.
+void damping_axis(int n, int nbl, double h, double vmax, float *out)
+{
+    for (int i = 0; i < n; i++) {
+        double v = 0.0;
+        if (nbl > 0) {
+            int k = std::max(std::max(nbl - i, i - (n - 1 - nbl)), 0);
+            double d0 = 3.0 * vmax * std::log(1.0 / 1e-3) / (2.0 * nbl * h);
+            double q = (double)k / nbl;
+            v = d0 * q * q;
+        }
+        out[i] = (float)v;
+    }
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+template <class T>
+tb_status upload(T **dst, const std::vector<T> &src)
+{
+    size_t n = std::max<size_t>(src.size(), 1);
+    TB_HIP(hipMalloc(dst, n * sizeof(T)));
+    if (!src.empty()) TB_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    return TB_OK;
+}
+
+struct SchedChoice {
+    int T, BYE, chunk;
+};
+
+tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice *out)
+{
+    SchedChoice c{2, 32, 0};
+    if (s) {
+        if (s->mode == TB_SCHED_SB) c.T = 1;
+        else if (s->mode == TB_SCHED_TB) c.T = s->time_tile;
+        else {
+            set_error("schedule mode %d unknown", s->mode);
+            return TB_EINVAL;
+        }
+        if (s->tile_y) c.BYE = s->tile_y;
+        c.chunk = s->chunk_x;
+    } else {
+        // Tuned default for large grids: two steps per pass.
+        c.T = 2;
+        c.BYE = 32;
+        c.chunk = m->n[0] >= 256 ? 128 : 0;
+    }
+    if (c.T < 1 || c.T > 4) {
+        set_error("time_tile %d not in 1..4", c.T);
+        return TB_EUNSUPPORTED;
+    }
+    if (c.BYE != 16 && c.BYE != 32 && c.BYE != 64) {
+        set_error("tile_y %d not in {16, 32, 64}", c.BYE);
+        return TB_EUNSUPPORTED;
+    }
+    if (c.BYE - 2 * m->r * (c.T - 1) <= 0) {
+        set_error("tile_y %d too small for time_tile %d at radius %d", c.BYE, c.T, m->r);
+        return TB_EUNSUPPORTED;
+    }
+    if (c.chunk < 0) {
+        set_error("chunk_x %d negative", c.chunk);
+        return TB_EINVAL;
+    }
+    *out = c;
+    return TB_OK;
+}
+
+// Cached per-tile lists for (direction, T, BYE, chunk).
+tb_status get_lists(const tb_model *m, tb_sparse *s, int adjoint, const TileGeom &g,
+                    TileLists **out)
+{
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto key = std::make_tuple(adjoint, g.T, g.BYE, g.chunk);
+    auto it = s->tiles.find(key);
+    if (it != s->tiles.end()) {
+        *out = it->second.get();
+        return TB_OK;
+    }
+    auto tl = std::make_unique<TileLists>();
+    tb_status st = adjoint ? build_tile_lists(m, s->rid_nodes, s->src_nodes, g, tl.get())
+                           : build_tile_lists(m, s->src_nodes, s->rid_nodes, g, tl.get());
+    if (st) return st;
+    *out = tl.get();
+    s->tiles[key] = std::move(tl);
+    return TB_OK;
+}
+
+size_t field_bytes(const tb_model *m) { return align256(m->field_elems() * sizeof(float)); }
+
+// Run the propagation time loop: nt updates from zero state in F[0..3],
+// injecting dcmp rows 0..nt-1 at inj points and recording at the nrecp rec
+// points into rec_dcmp rows 1..nt (row 0, the zero initial level, is
+// cleared here). Returns the buffer indices of the last two levels.
+tb_status time_loop(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int adjoint,
+                    float *F[4], const float *dcmp, int ninj, float *rec_dcmp, int nrecp,
+                    int *cur_out, int *prev_out, hipStream_t st)
+{
+    const int nt = m->nt;
+    const size_t fe = m->field_elems();
+    tb_status rc;
+    for (int k = 0; k < 2; k++)
+        if ((rc = launch_fill(F[k], fe, 0.0f, st))) return rc;
+    if (nrecp > 0 && (rc = launch_fill(rec_dcmp, (size_t)nrecp, 0.0f, st))) return rc;
+    int cur = 0, prev = 1;
+    int n = 0;
+    while (n < nt) {
+        const int T = std::min(sc.T, nt - n);
+        TileGeom g = make_geom(m->r, T, sc.BYE, sc.chunk, m->n[0], m->n[1], m->n[2]);
+        TileLists *tl = nullptr;
+        if ((rc = get_lists(m, s, adjoint, g, &tl))) return rc;
+        AcLaunch a{};
+        a.u = F[cur];
+        a.um = F[prev];
+        a.n0 = n;
+        a.dcmp = dcmp;
+        a.npts = ninj;
+        a.rec_dcmp = rec_dcmp;
+        a.nrid = nrecp;
+        int f0 = -1, f1 = -1;
+        if (T == 1) {
+            a.out0 = F[prev];  // u^{n+1} overwrites u^{n-1} point by point
+            a.out1 = nullptr;
+        } else {
+            for (int k = 0; k < 4; k++)
+                if (k != cur && k != prev) (f0 < 0 ? f0 : f1) = k;
+            a.out0 = F[f0];
+            a.out1 = F[f1];
+        }
+        if ((rc = launch_acoustic(m, g, *tl, a, st))) return rc;
+        if (T == 1) {
+            std::swap(cur, prev);
+        } else {
+            cur = f0;
+            prev = f1;
+        }
+        n += T;
+    }
+    *cur_out = cur;
+    *prev_out = prev;
+    return TB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tb_last_error(void) { return tbw::last_error(); }
+
+const char *tb_version(void) { return "tbwave 0.1 (gfx950)"; }
+
+tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
+{
+    if (!out) {
+        set_error("tb_create_model: out is NULL");
+        return TB_EINVAL;
+    }
+    *out = nullptr;
+    if (!d) {
+        set_error("tb_create_model: desc is NULL");
+        return TB_EINVAL;
+    }
+    if (d->physics != TB_ACOUSTIC) {
+        set_error("physics %d is not built", d->physics);
+        return TB_EUNSUPPORTED;
+    }
+    if (d->space_order != 4 && d->space_order != 8) {
+        set_error("space order %d not supported (4 or 8)", d->space_order);
+        return TB_EUNSUPPORTED;
+    }
+    for (int a = 0; a < 3; a++) {
+        if (d->shape[a] < 1 || !(d->spacing[a] > 0.0) || !std::isfinite(d->origin[a])) {
+            set_error("shape/spacing/origin of axis %d invalid", a);
+            return TB_EINVAL;
+        }
+    }
+    if (!(d->dt > 0.0) || d->nt < 0 || d->nbl < 0 || !d->vp) {
+        set_error("dt, nt, nbl or vp invalid");
+        return TB_EINVAL;
+    }
+    const int nx = d->shape[0], ny = d->shape[1], nz = d->shape[2];
+    if ((long long)ny * nz > (1LL << 30) || (long long)nx * ny * nz > (1LL << 36)) {
+        set_error("grid too large");
+        return TB_EINVAL;
+    }
+    auto m = std::make_unique<tb_model>();
+    m->physics = d->physics;
+    std::memcpy(m->n, d->shape, sizeof m->n);
+    m->nzp = (nz + 3) & ~3;
+    std::memcpy(m->h, d->spacing, sizeof m->h);
+    std::memcpy(m->o, d->origin, sizeof m->o);
+    m->so = d->space_order;
+    m->r = d->space_order / 2;
+    m->nbl = d->nbl;
+    m->dt = d->dt;
+    m->nt = d->nt;
+    TB_HIP(hipGetDevice(&m->device));
+
+    const size_t N = (size_t)nx * ny * nz;
+    std::vector<float> vp(N);
+    TB_HIP(hipMemcpy(vp.data(), d->vp, N * sizeof(float), hipMemcpyDeviceToHost));
+    double vpmax = 0.0;
+    for (size_t i = 0; i < N; i++) {
+        if (!(vp[i] > 0.0f) || !std::isfinite(vp[i])) {
+            set_error("vp[%zu] = %g is not a positive finite velocity", i, (double)vp[i]);
+            return TB_EINVAL;
+        }
+        vpmax = std::max(vpmax, (double)vp[i]);
+    }
+    m->vmax = d->damp_vmax > 0.0 ? d->damp_vmax : vpmax;
+    // Leapfrog stability: dt^2 vp_max^2 * sum_a |symbol max| / h_a^2 <= 4.
+    const double *w = d2_weights(m->so);
+    double sym = w[0];
+    for (int j = 1; j <= m->r; j++) sym += 2.0 * w[j] * ((j & 1) ? -1.0 : 1.0);
+    sym = std::fabs(sym);
+    double rho = 0.0;
+    for (int a = 0; a < 3; a++) rho += sym / (m->h[a] * m->h[a]);
+    if (m->dt * m->dt * vpmax * vpmax * rho > 4.0) {
+        set_error("dt = %g exceeds the stability bound %g for vp_max = %g", m->dt,
+                  2.0 / (vpmax * std::sqrt(rho)), vpmax);
+        return TB_EUNSTABLE;
+    }
+    m->c64.resize(N);
+    std::vector<float> cpad(m->field_elems(), 0.0f);
+    for (size_t x = 0; x < (size_t)nx; x++)
+        for (size_t y = 0; y < (size_t)ny; y++)
+            for (size_t z = 0; z < (size_t)nz; z++) {
+                const size_t i = (x * ny + y) * nz + z;
+                const double v = (double)vp[i];
+                const double c = m->dt * m->dt * v * v;
+                m->c64[i] = c;
+                cpad[(x * ny + y) * m->nzp + z] = (float)c;
+            }
+    m->damp.assign((size_t)nx + ny + m->nzp, 0.0f);
+    damping_axis(nx, m->nbl, m->h[0], m->vmax, m->damp.data());
+    damping_axis(ny, m->nbl, m->h[1], m->vmax, m->damp.data() + nx);
+    damping_axis(nz, m->nbl, m->h[2], m->vmax, m->damp.data() + nx + ny);
+    TB_HIP(hipMalloc(&m->d_c, m->field_elems() * sizeof(float)));
+    TB_HIP(hipMemcpy(m->d_c, cpad.data(), cpad.size() * sizeof(float), hipMemcpyHostToDevice));
+    TB_HIP(hipMalloc(&m->d_damp, m->damp.size() * sizeof(float)));
+    TB_HIP(hipMemcpy(m->d_damp, m->damp.data(), m->damp.size() * sizeof(float),
+                     hipMemcpyHostToDevice));
+    *out = m.release();
+    return TB_OK;
+}
+
+void tb_destroy_model(tb_model *m) { delete m; }
+
+tb_status tb_inspect_sparse(const tb_model *m, int32_t nsrc, const double *src_xyz,
+                            const double *src_wavelet, int32_t nrec, const double *rec_xyz,
+                            tb_sparse **out)
+{
+    if (!out) {
+        set_error("tb_inspect_sparse: out is NULL");
+        return TB_EINVAL;
+    }
+    *out = nullptr;
+    if (!m || nsrc < 0 || nrec < 0 || (nsrc && (!src_xyz || (m->nt && !src_wavelet))) ||
+        (nrec && !rec_xyz)) {
+        set_error("tb_inspect_sparse: invalid argument");
+        return TB_EINVAL;
+    }
+    auto s = std::make_unique<tb_sparse>();
+    s->m = m;
+    tb_status st = inspect_into(s.get(), nsrc, src_xyz, src_wavelet, nrec, rec_xyz);
+    if (st) return st;
+    if ((st = upload(&s->d_dcmp, s->dcmp))) return st;
+    // Receiver read-out: per receiver corners (rid, W).
+    std::vector<float> rw(s->rc_w.begin(), s->rc_w.end());
+    if ((st = upload(&s->d_rc_ptr, s->rc_ptr)) || (st = upload(&s->d_rc_id, s->rc_id)) ||
+        (st = upload(&s->d_rc_w, rw)))
+        return st;
+    // Adjoint read-out at the sources: weights W alpha(node).
+    const int nx = m->n[0], ny = m->n[1], nz = m->n[2];
+    auto alpha_at = [&](int64_t r) {
+        const int z = (int)(r % nz), y = (int)((r / nz) % ny), x = (int)(r / ((int64_t)nz * ny));
+        const double d = (double)m->damp[x] + (double)m->damp[nx + y] + (double)m->damp[nx + ny + z];
+        return 1.0 + d * m->dt / 2.0;
+    };
+    (void)nx;
+    std::vector<float> sw(s->sc_w.size());
+    for (int p = 0; p < nsrc; p++)
+        for (int k = s->sc_ptr[p]; k < s->sc_ptr[p + 1]; k++)
+            sw[k] = (float)(s->sc_w[k] * alpha_at(s->src_nodes[s->sc_id[k]]));
+    if ((st = upload(&s->d_sc_ptr, s->sc_ptr)) || (st = upload(&s->d_sc_id, s->sc_id)) ||
+        (st = upload(&s->d_sc_w, sw)))
+        return st;
+    // Adjoint injection at receiver points: rid -> (receiver, W), scale c/alpha.
+    std::vector<int> cnt(s->nrid + 1, 0);
+    for (size_t k = 0; k < s->rc_id.size(); k++) cnt[s->rc_id[k] + 1]++;
+    for (int i = 0; i < s->nrid; i++) cnt[i + 1] += cnt[i];
+    std::vector<int> rr_rec(s->rc_id.size());
+    std::vector<float> rr_w(s->rc_id.size());
+    std::vector<int> fillp(cnt.begin(), cnt.end() - 1);
+    for (int r = 0; r < nrec; r++)
+        for (int k = s->rc_ptr[r]; k < s->rc_ptr[r + 1]; k++) {
+            const int pos = fillp[s->rc_id[k]]++;
+            rr_rec[pos] = r;
+            rr_w[pos] = (float)s->rc_w[k];
+        }
+    std::vector<float> scale(s->nrid);
+    for (int i = 0; i < s->nrid; i++)
+        scale[i] = (float)(m->c64[s->rid_nodes[i]] / alpha_at(s->rid_nodes[i]));
+    if ((st = upload(&s->d_rr_ptr, cnt)) || (st = upload(&s->d_rr_rec, rr_rec)) ||
+        (st = upload(&s->d_rr_w, rr_w)) || (st = upload(&s->d_rid_scale, scale)))
+        return st;
+    *out = s.release();
+    return TB_OK;
+}
+
+void tb_destroy_sparse(tb_sparse *s) { delete s; }
+
+tb_status tb_sparse_counts(const tb_sparse *s, int32_t *npts, int32_t *nrid)
+{
+    if (!s) {
+        set_error("tb_sparse_counts: NULL handle");
+        return TB_EINVAL;
+    }
+    if (npts) *npts = s->npts;
+    if (nrid) *nrid = s->nrid;
+    return TB_OK;
+}
+
+tb_status tb_workspace_size(const tb_model *m, const tb_sparse *s, const tb_schedule *sched,
+                            int32_t op, size_t *bytes)
+{
+    if (!m || !s || !bytes) {
+        set_error("tb_workspace_size: invalid argument");
+        return TB_EINVAL;
+    }
+    SchedChoice sc;
+    tb_status st = resolve_schedule(m, sched, &sc);
+    if (st) return st;
+    const size_t fb = field_bytes(m);
+    const size_t nt1 = (size_t)m->nt + 1;
+    switch (op) {
+    case TB_OP_FORWARD:
+        *bytes = 4 * fb + align256(nt1 * std::max(s->nrid, 1) * sizeof(float));
+        return TB_OK;
+    case TB_OP_ADJOINT:
+        *bytes = 4 * fb + align256(nt1 * std::max(s->npts, 1) * sizeof(float)) +
+                 align256((size_t)m->nt * std::max(s->nrid, 1) * sizeof(float));
+        return TB_OK;
+    default:
+        set_error("operation %d has no workspace query", op);
+        return TB_EUNSUPPORTED;
+    }
+}
+
+tb_status tb_forward(const tb_model *m, const tb_sparse *s_, const tb_schedule *sched, void *ws,
+                     size_t ws_bytes, float *rec_out, float *field_out, float *field_prev_out,
+                     void *stream)
+{
+    tb_sparse *s = const_cast<tb_sparse *>(s_);
+    if (!m || !s || s->m != m || !ws) {
+        set_error("tb_forward: invalid argument");
+        return TB_EINVAL;
+    }
+    SchedChoice sc;
+    tb_status st = resolve_schedule(m, sched, &sc);
+    if (st) return st;
+    size_t need = 0;
+    if ((st = tb_workspace_size(m, s, sched, TB_OP_FORWARD, &need))) return st;
+    if (ws_bytes < need) {
+        set_error("workspace %zu bytes < %zu needed", ws_bytes, need);
+        return TB_EWORKSPACE;
+    }
+    hipStream_t strm = (hipStream_t)stream;
+    const size_t fb = field_bytes(m);
+    char *base = (char *)ws;
+    float *F[4] = {(float *)base, (float *)(base + fb), (float *)(base + 2 * fb),
+                   (float *)(base + 3 * fb)};
+    float *rec_dcmp = (float *)(base + 4 * fb);
+    const int nrecp = s->nrid;
+    int cur = 0, prev = 1;
+    st = time_loop(m, s, sc, 0, F, s->d_dcmp, s->npts, rec_dcmp, nrecp, &cur, &prev, strm);
+    if (st) return st;
+    if (rec_out && s->nrec > 0 && m->nt > 0)
+        if ((st = launch_trace_reduce(rec_dcmp, s->nrid, m->nt, s->d_rc_ptr, s->d_rc_id,
+                                      s->d_rc_w, s->nrec, rec_out, 0, strm)))
+            return st;
+    if (field_out && (st = launch_unpad(F[cur], field_out, m->n[0], m->n[1], m->n[2], m->nzp, strm)))
+        return st;
+    if (field_prev_out &&
+        (st = launch_unpad(F[prev], field_prev_out, m->n[0], m->n[1], m->n[2], m->nzp, strm)))
+        return st;
+    return TB_OK;
+}
+
+tb_status tb_adjoint(const tb_model *m, const tb_sparse *s_, const tb_schedule *sched, void *ws,
+                     size_t ws_bytes, const float *rec_in, float *src_out, void *stream)
+{
+    tb_sparse *s = const_cast<tb_sparse *>(s_);
+    if (!m || !s || s->m != m || !ws || (s->nrec > 0 && m->nt > 0 && !rec_in)) {
+        set_error("tb_adjoint: invalid argument");
+        return TB_EINVAL;
+    }
+    SchedChoice sc;
+    tb_status st = resolve_schedule(m, sched, &sc);
+    if (st) return st;
+    size_t need = 0;
+    if ((st = tb_workspace_size(m, s, sched, TB_OP_ADJOINT, &need))) return st;
+    if (ws_bytes < need) {
+        set_error("workspace %zu bytes < %zu needed", ws_bytes, need);
+        return TB_EWORKSPACE;
+    }
+    hipStream_t strm = (hipStream_t)stream;
+    const size_t fb = field_bytes(m);
+    const size_t nt1 = (size_t)m->nt + 1;
+    char *base = (char *)ws;
+    float *F[4] = {(float *)base, (float *)(base + fb), (float *)(base + 2 * fb),
+                   (float *)(base + 3 * fb)};
+    float *rec_dcmp = (float *)(base + 4 * fb);  // recorded at source points
+    float *adj_dcmp = (float *)(base + 4 * fb + align256(nt1 * std::max(s->npts, 1) * sizeof(float)));
+    if (s->nrid > 0 && m->nt > 0)
+        if ((st = launch_adj_inject(rec_in, m->nt, s->nrec, s->nrid, s->d_rr_ptr, s->d_rr_rec,
+                                    s->d_rr_w, s->d_rid_scale, adj_dcmp, strm)))
+            return st;
+    int cur = 0, prev = 1;
+    st = time_loop(m, s, sc, 1, F, adj_dcmp, s->nrid, rec_dcmp, s->npts, &cur, &prev, strm);
+    if (st) return st;
+    // qhat^n = P_s (alpha nu^{n+1}); nu^{n+1} is adjoint level nt-1-n.
+    if (src_out && s->nsrc > 0 && m->nt > 0)
+        if ((st = launch_trace_reduce(rec_dcmp, s->npts, m->nt, s->d_sc_ptr, s->d_sc_id, s->d_sc_w,
+                                      s->nsrc, src_out, 1, strm)))
+            return st;
+    return TB_OK;
+}
+
+tb_status tb_gradient(const tb_model *m, const tb_sparse *s, const tb_schedule *sched, void *ws,
+                      size_t ws_bytes, const float *d_obs, float *grad_m, double *loss_out,
+                      int32_t checkpoint_every, void *stream)
+{
+    (void)m; (void)s; (void)sched; (void)ws; (void)ws_bytes; (void)d_obs; (void)grad_m;
+    (void)loss_out; (void)checkpoint_every; (void)stream;
+    set_error("tb_gradient is not built yet");
+    return TB_EUNSUPPORTED;
+}
+
+}  // extern "C"

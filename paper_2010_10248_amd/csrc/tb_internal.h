@@ -1,0 +1,144 @@
+// Internal host-side structures of the temporal-blocking library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/tb.h"
+
+namespace tbw {
+
+// Error reporting: thread-local text behind tb_last_error().
+void set_error(const char *fmt, ...);
+#define TB_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ::tbw::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),    \
+                             __FILE__, __LINE__);                                      \
+            return TB_EHIP;                                                            \
+        }                                                                              \
+    } while (0)
+
+// Workgroup z extent of the acoustic kernels: 16 lanes, 4 consecutive z each.
+constexpr int kTileZ = 64;
+constexpr int kLanesZ = 16;
+
+// Geometry of one schedule (shared by the binning and the launch code).
+struct TileGeom {
+    int R = 0, T = 1, BYE = 32;  // radius, steps per pass, y rows per workgroup
+    int HY = 0, HZ = 0;          // halo rows / halo columns (columns multiple of 4)
+    int OY = 0, OZ = 0;          // owned rows / owned columns per tile
+    int tiles_y = 0, tiles_z = 0, nchunks = 0, chunk = 0;
+    int nblocks() const { return tiles_y * tiles_z * nchunks; }
+};
+TileGeom make_geom(int R, int T, int BYE, int chunk, int nx, int ny, int nz);
+
+// Per-tile injection / recording lists in CSR form. Entry = {x, row, col, id}.
+struct TileLists {
+    int4 *d_src = nullptr;
+    int *d_src_off = nullptr;
+    int4 *d_rec = nullptr;
+    int *d_rec_off = nullptr;
+    int nsrc_entries = 0, nrec_entries = 0;
+    ~TileLists();
+};
+
+}  // namespace tbw
+
+struct tb_model {
+    int physics = TB_ACOUSTIC;
+    int n[3] = {0, 0, 0};
+    int nzp = 0;  // padded row length (multiple of 4)
+    double h[3] = {0, 0, 0}, o[3] = {0, 0, 0};
+    int so = 8, r = 4, nbl = 0;
+    double dt = 0;
+    int nt = 0;
+    double vmax = 0;  // velocity of the damping profile
+    int device = 0;
+    float *d_c = nullptr;     // dt^2 vp^2, [nx][ny][nzp]
+    float *d_damp = nullptr;  // d_x[nx] | d_y[ny] | d_z[nzp]
+    std::vector<double> c64;  // host copy of dt^2 vp^2 (FP64 from the FP32 vp)
+    std::vector<float> damp;  // host copy of the three tables
+    size_t field_elems() const { return (size_t)n[0] * n[1] * nzp; }
+    ~tb_model();
+};
+
+struct tb_sparse {
+    const tb_model *m = nullptr;
+    int nsrc = 0, nrec = 0, nt = 0;
+    // Source side (inspector, Section II-A): unique affected points.
+    int npts = 0;
+    std::vector<int64_t> src_nodes;  // raster index x*ny*nz + y*nz + z, ascending = SID
+    std::vector<float> dcmp;         // [nt][npts]
+    float *d_dcmp = nullptr;
+    // Per source: corners (sid, W) in corner order (adjoint read-out).
+    std::vector<int> sc_ptr, sc_id;
+    std::vector<double> sc_w;
+    // Receiver mirror: unique points and per-receiver corners (rid, W).
+    int nrid = 0;
+    std::vector<int64_t> rid_nodes;
+    std::vector<int> rc_ptr, rc_id;
+    std::vector<double> rc_w;
+    int *d_rc_ptr = nullptr, *d_rc_id = nullptr;
+    float *d_rc_w = nullptr;
+    // Adjoint: source read-out weights W * alpha(node), and receiver-point
+    // injection scale c/alpha at each rid.
+    int *d_sc_ptr = nullptr, *d_sc_id = nullptr;
+    float *d_sc_w = nullptr;
+    // For each rid: receivers hitting it and their weights (adjoint injection).
+    int *d_rr_ptr = nullptr, *d_rr_rec = nullptr;
+    float *d_rr_w = nullptr;
+    float *d_rid_scale = nullptr;  // (c/alpha)(rid node)
+    std::mutex mu;
+    std::map<std::tuple<int, int, int, int>, std::unique_ptr<tbw::TileLists>> tiles;
+    ~tb_sparse();
+};
+
+namespace tbw {
+
+// Host inspector: support, IDs and FP64 decomposition.
+struct Support {
+    std::vector<int64_t> nodes;  // unique raster indices, ascending
+    std::vector<int> ptr, id;    // per point: corners (index into nodes)
+    std::vector<double> w;       // corner weights
+};
+tb_status build_support(const int n[3], const double h[3], const double o[3], int npts_in,
+                        const double *xyz, Support *out);
+
+// Bin points into per-tile lists for a schedule geometry.
+// inj: points injected at every computed copy (extended region); rec: points
+// recorded from the owned copy only.
+tb_status build_tile_lists(const tb_model *m, const std::vector<int64_t> &inj,
+                           const std::vector<int64_t> &rec, const TileGeom &g, TileLists *out);
+
+// Kernel launchers (acoustic.hip).
+struct AcLaunch {
+    const float *u, *um;
+    float *out0, *out1;
+    int n0;  // time index of the first update of this pass
+    const float *dcmp;
+    int npts;
+    float *rec_dcmp;
+    int nrid;
+};
+tb_status launch_acoustic(const tb_model *m, const TileGeom &g, const TileLists &tl,
+                          const AcLaunch &a, hipStream_t st);
+tb_status launch_fill(float *p, size_t n, float v, hipStream_t st);
+tb_status launch_trace_reduce(const float *rec_dcmp, int nrid, int nt, const int *ptr,
+                              const int *id, const float *w, int nrec, float *out,
+                              int reverse, hipStream_t st);
+tb_status launch_unpad(const float *src, float *dst, int nx, int ny, int nz, int nzp,
+                       hipStream_t st);
+tb_status launch_adj_inject(const float *res, int nt, int nrec, int nrid, const int *rr_ptr,
+                            const int *rr_rec, const float *rr_w, const float *rid_scale,
+                            float *dcmp_out, hipStream_t st);
+
+}  // namespace tbw

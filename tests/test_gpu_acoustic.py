@@ -1,0 +1,180 @@
+"""GPU parity of the acoustic propagator: HIP path vs the FP64 oracle
+(relative L2 <= 1e-5 on traces and the last two wavefields), bit-identity of
+every temporally blocked schedule with the spatially blocked one, and the
+C-ABI error paths that need a device."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2010_10248_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _run(tb, prop, sched):
+    out = prop.forward(sched)
+    import torch
+
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+SCHEDS = [("sb", 1, 32, 0), ("sb", 1, 16, 24), ("tb", 2, 32, 0), ("tb", 2, 16, 0),
+          ("tb", 3, 32, 0), ("tb", 4, 32, 40), ("tb", 2, 32, 24), ("tb", 3, 32, 17)]
+
+
+def _check_case(torch_cuda, orc, shot, scheds=SCHEDS, tol=TOL):
+    from paper_2010_10248_amd import tb
+
+    ref = orc.acoustic_forward(shot)
+    prop = tb.Acoustic(shot)
+    base = None
+    for mode, T, by, ch in scheds:
+        if shot.space_order == 8 and T >= 4 and by < 32:
+            continue
+        sc = tb.schedule(mode, T, by, ch)
+        _say(f"case {shot.name} sched {sc}")
+        out = _run(tb, prop, sc)
+        e_tr = _rel(out["traces"], ref["traces"])
+        e_u = _rel(out["u_last"], ref["u_last"])
+        e_up = _rel(out["u_prev"], ref["u_prev"])
+        _say(f"  relL2 traces {e_tr:.3e} u {e_u:.3e} u_prev {e_up:.3e}")
+        assert e_tr <= tol and e_u <= tol and e_up <= tol, (sc, e_tr, e_u, e_up)
+        if base is None:
+            base = out
+        else:
+            for k in ("traces", "u_last", "u_prev"):
+                assert np.array_equal(out[k].view(np.uint32), base[k].view(np.uint32)), (sc, k)
+    prop.close()
+
+
+def test_parity_small_constant_so4(torch_cuda, orc):
+    """64^3, h=10 m, SO4, nbl 10, 100 steps, one off-grid Ricker, 32 receivers."""
+    _check_case(torch_cuda, orc, W.acoustic_small())
+
+
+def test_parity_two_layer_so8_ragged(torch_cuda, orc):
+    """SO8 two-layer model on a ragged grid (nz not a multiple of 4, nx not a
+    multiple of any chunk), several sources and a receiver line."""
+    s = W.acoustic_scaled(21, (61, 75, 70), 8, 60, 8, nsrc=3, nrec=24, layered=True)
+    _check_case(torch_cuda, orc, s)
+
+
+def test_sources_on_tile_boundaries(torch_cuda, orc):
+    """Sources and receivers placed on the y/z tile seams and x-chunk seams of
+    the schedules, where a halo copy must receive the same injection (the
+    violation of the paper's Fig. 4b)."""
+    s = W.acoustic_scaled(5, (72, 96, 128), 8, 40, 6, nsrc=4, nrec=16, layered=True)
+    h = s.spacing[0]
+    # T=2, tile_y=32: owned rows per tile 24, halo 4; owned columns 56.
+    s.src_xyz[0] = np.array([23.5, 23.5, 55.5]) * h
+    s.src_xyz[1] = np.array([24.0, 47.7, 56.2]) * h
+    s.src_xyz[2] = np.array([39.9, 19.6, 59.9]) * h   # inside a y halo
+    s.src_xyz[3] = np.array([40.2, 72.1, 111.6]) * h
+    s.rec_xyz[:4] = s.src_xyz[:4] + 0.25 * h
+    _check_case(torch_cuda, orc, s, scheds=[("sb", 1, 32, 0), ("tb", 2, 32, 24), ("tb", 2, 32, 0),
+                                            ("tb", 3, 32, 40), ("tb", 4, 32, 0), ("tb", 2, 16, 17)])
+
+
+def test_zero_source_is_exactly_zero(torch_cuda):
+    from paper_2010_10248_amd import tb
+
+    s = W.acoustic_scaled(8, (40, 44, 48), 8, 30, 5, nsrc=2, nrec=8)
+    prop = tb.Acoustic(s, src_wav=np.zeros_like(s.src_wav))
+    for sc in (tb.schedule("sb"), tb.schedule("tb", 3, 32)):
+        out = _run(tb, prop, sc)
+        for k in ("traces", "u_last", "u_prev"):
+            assert np.all(out[k].view(np.uint32) == 0), (sc, k)
+    prop.close()
+
+
+def test_tiny_and_degenerate_grids(torch_cuda, orc):
+    """Grids smaller than one tile, a single plane of sources at the grid
+    edge (x = 0, z = nz-1) and nt = 1 / nt = T - 1."""
+    from paper_2010_10248_amd import tb
+
+    s = W.acoustic_scaled(9, (9, 13, 6), 4, 7, 0, nsrc=2, nrec=3, layered=False)
+    s.src_xyz[0] = [0.0, 40.0, 50.0]
+    s.src_xyz[1] = [80.0, 120.0, 50.0]
+    _check_case(torch_cuda, orc, s, scheds=[("sb", 1, 16, 0), ("tb", 2, 16, 0), ("tb", 3, 16, 4),
+                                            ("tb", 4, 32, 0)])
+    for nt in (1, 2):
+        s2 = W.acoustic_scaled(10, (20, 18, 24), 8, nt, 2, nsrc=1, nrec=2)
+        _check_case(torch_cuda, orc, s2, scheds=[("sb", 1, 32, 0), ("tb", 3, 32, 0)])
+
+
+def test_error_paths_on_device(torch_cuda):
+    import torch
+
+    from paper_2010_10248_amd import tb
+
+    s = W.acoustic_scaled(12, (24, 24, 24), 8, 10, 2, nsrc=1, nrec=2)
+    vp = torch.as_tensor(s.vp.astype(np.float32), device="cuda")
+    with pytest.raises(tb.TbError) as e:
+        tb.create_model(s.shape, s.spacing, s.origin, 8, 2, s.dt * 1.2, 10, vp)
+    assert e.value.status == tb.EUNSTABLE
+    m = tb.create_model(s.shape, s.spacing, s.origin, 8, 2, s.dt, 10, vp)
+    with pytest.raises(tb.TbError) as e:
+        tb.inspect_sparse(m, [[0.0, 0.0, 231.0]], s.src_wav, s.rec_xyz)
+    assert e.value.status == tb.ERANGE
+    sp = tb.inspect_sparse(m, s.src_xyz, s.src_wav, s.rec_xyz)
+    need = tb.workspace_size(m, sp, None)
+    ws = torch.empty(need - 1, dtype=torch.uint8, device="cuda")
+    rec = torch.empty((10, 2), device="cuda")
+    with pytest.raises(tb.TbError) as e:
+        tb.forward(m, sp, None, ws, rec)
+    assert e.value.status == tb.EWORKSPACE
+    with pytest.raises(tb.TbError) as e:
+        tb.forward(m, sp, tb.schedule("tb", 4, 16), torch.empty(need * 2, dtype=torch.uint8,
+                                                               device="cuda"), rec)
+    assert e.value.status == tb.EUNSUPPORTED
+    tb.destroy_sparse(sp)
+    tb.destroy_model(m)
+
+
+@pytest.mark.parametrize("so", [4, 8])
+def test_adjoint_dot_product_and_oracle(torch_cuda, orc, so):
+    import torch
+
+    from paper_2010_10248_amd import tb
+
+    s = W.acoustic_scaled(31, (40, 46, 52), so, 50, 5, nsrc=3, nrec=12, layered=True)
+    rng = np.random.Generator(np.random.PCG64(4))
+    q = rng.standard_normal(s.src_wav.shape)
+    dp = rng.standard_normal((s.nt, s.rec_xyz.shape[0]))
+    prop = tb.Acoustic(s, src_wav=q)
+    for sc in (tb.schedule("sb"), tb.schedule("tb", 2, 32), tb.schedule("tb", 3, 32, 20)):
+        _say(f"adjoint so{so} {sc}")
+        Fq = prop.forward(sc)["traces"].double().cpu().numpy()
+        FTd = prop.adjoint(torch.as_tensor(dp.astype(np.float32), device="cuda"), sc)
+        FTd = FTd.double().cpu().numpy()
+        lhs = float(np.sum(Fq * dp))
+        rhs = float(np.sum(q * FTd))
+        _say(f"  dot {lhs:.9e} {rhs:.9e} rel {abs(lhs - rhs) / abs(lhs):.2e}")
+        assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+        ref = orc.acoustic_adjoint(s, dp)["qhat"]
+        assert _rel(FTd, ref) <= TOL
+    prop.close()
