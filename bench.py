@@ -1,0 +1,198 @@
+"""Benchmark: GPts/s of the temporally blocked acoustic propagator against the
+spatially blocked one on the 512^3 SO8 two-layer workload (one MI355X).
+
+One step = one full forward shot: nt updates of the whole grid with fused
+off-grid injection of 8 sources and interpolation at 512 receivers, from
+resident inputs. Prints one JSON line (see the keys below).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GPts/s temporal- vs spatial-blocked (1 GPU, rel L2≤1e-5); shots/s + p99 latency"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_POINT_STEP = 16  # read u^n, u^{n-1}, c; write u^{n+1}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def rel_l2(a, b):
+    import numpy as np
+
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def time_forward(tb, prop, sched, steps, warmup, torch):
+    """Run warmup + timed forward shots; return (seconds, kernel stats, outputs)."""
+    ws = prop.workspace(sched)
+    nt = prop.shot.nt
+    rec = torch.empty((nt, prop.nrec), dtype=torch.float32, device="cuda")
+    u = torch.empty(prop.shot.shape, dtype=torch.float32, device="cuda")
+    up = torch.empty(prop.shot.shape, dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
+        tb.forward(prop.model, prop.sparse, sched, ws, rec, u, up)
+    torch.cuda.synchronize()
+    tb.kernel_timing(True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        tb.forward(prop.model, prop.sparse, sched, ws, rec, u, up)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, kms = tb.kernel_timing_read()
+    tb.kernel_timing(False)
+    return dt, launches, kms, rec, u, up
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--nt", type=int, default=1000)
+    ap.add_argument("--T", type=int, default=2)
+    ap.add_argument("--tile-y", type=int, default=32)
+    ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--sb-tile-y", type=int, default=32)
+    ap.add_argument("--sb-chunk", type=int, default=64)
+    ap.add_argument("--no-sb", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=24,
+                    help="steps of the full grid the FP64 oracle runs as the CPU sample")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(shots shard across GPUs without communication; see the design notes)",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2010_10248_amd import tb
+    from paper_2010_10248_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    shot = W.acoustic_two_layer(n=args.n, nt=args.nt)
+    N3 = int(np.prod(shot.shape))
+    log(f"workload: {shot.name}, {shot.src_xyz.shape[0]} sources, {shot.rec_xyz.shape[0]} receivers")
+    t0 = time.perf_counter()
+    prop = tb.Acoustic(shot)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    npts, nrid = tb.sparse_counts(prop.sparse)
+    log(f"model + inspector: {setup_s:.3f} s (npts {npts}, receiver points {nrid})")
+
+    tb_sched = tb.schedule("tb", args.T, args.tile_y, args.chunk)
+    sb_sched = tb.schedule("sb", 1, args.sb_tile_y, args.sb_chunk)
+
+    dt_tb, nl_tb, kms_tb, rec_tb, u_tb, up_tb = time_forward(tb, prop, tb_sched, args.steps,
+                                                            args.warmup, torch)
+    gpts_tb = N3 * shot.nt * args.steps / dt_tb / 1e9
+    log(f"TB {tb_sched}: {dt_tb / args.steps * 1e3:.2f} ms/shot, {gpts_tb:.1f} GPts/s, "
+        f"{nl_tb} kernel launches, {kms_tb / max(nl_tb, 1):.3f} ms each")
+
+    sb = None
+    if not args.no_sb:
+        dt_sb, nl_sb, kms_sb, rec_sb, u_sb, up_sb = time_forward(tb, prop, sb_sched, args.steps,
+                                                                args.warmup, torch)
+        gpts_sb = N3 * shot.nt * args.steps / dt_sb / 1e9
+        same = (torch.equal(rec_tb.view(torch.int32), rec_sb.view(torch.int32))
+                and torch.equal(u_tb.view(torch.int32), u_sb.view(torch.int32))
+                and torch.equal(up_tb.view(torch.int32), up_sb.view(torch.int32)))
+        sb = dict(value=round(gpts_sb, 2), ms_per_step=round(dt_sb / args.steps * 1e3, 3),
+                  kernel_ms_avg=round(kms_sb / max(nl_sb, 1), 4), schedule=repr(sb_sched),
+                  bitwise_equal_to_tb=bool(same))
+        log(f"SB {sb_sched}: {dt_sb / args.steps * 1e3:.2f} ms/shot, {gpts_sb:.1f} GPts/s; "
+            f"TB == SB bitwise: {same}")
+
+    # Dominant kernel: the wave-front propagation kernel. Algorithmic bytes
+    # per launch = 16 B x N^3 points x T steps.
+    steps_per_launch = shot.nt * args.steps / max(nl_tb, 1)
+    achieved = BYTES_PER_POINT_STEP * N3 * shot.nt * args.steps / (kms_tb * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    kernel=f"acoustic_wavefront<R=4,T={args.T},BYE={args.tile_y}>",
+                    kernel_ms_avg=round(kms_tb / max(nl_tb, 1), 4),
+                    steps_per_launch=round(steps_per_launch, 3),
+                    bytes_per_point_step=BYTES_PER_POINT_STEP)
+
+    cpu = None
+    parity = None
+    if not args.no_cpu:
+        import oracle
+
+        sample = W.acoustic_two_layer(n=args.n, nt=args.cpu_steps)
+        t0 = time.perf_counter()
+        ref = oracle.acoustic_forward(sample)
+        cpu_s = time.perf_counter() - t0
+        cores = oracle.num_threads()
+        cpu = dict(value=round(N3 * sample.nt / cpu_s / 1e9, 4), unit="GPts/s", cores=cores,
+                   kind="oracle", seconds=round(cpu_s, 2),
+                   sample=f"FP64 oracle, full {args.n}^3 grid, first {sample.nt} of {shot.nt} "
+                          f"steps (same sources/receivers)")
+        log(f"oracle: {cpu_s:.1f} s for {sample.nt} steps on {cores} threads")
+        sp = tb.Acoustic(sample)
+        errs = {}
+        for name, sc in (("tb", tb_sched), ("sb", sb_sched)):
+            o = sp.forward(sc)
+            torch.cuda.synchronize()
+            errs[name] = dict(traces=rel_l2(o["traces"].cpu().numpy(), ref["traces"]),
+                              u_last=rel_l2(o["u_last"].cpu().numpy(), ref["u_last"]),
+                              u_prev=rel_l2(o["u_prev"].cpu().numpy(), ref["u_prev"]))
+        sp.close()
+        parity = dict(steps=sample.nt, **{k: {kk: float(f"{vv:.3e}") for kk, vv in v.items()}
+                                          for k, v in errs.items()})
+        log(f"parity vs FP64 oracle at {sample.nt} steps: {parity}")
+
+    line = {
+        "metric": METRIC,
+        "value": round(gpts_tb, 2),
+        "unit": "GPts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt_tb / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"isotropic acoustic {args.n}^3, h=10 m, SO8, {shot.nt} steps, "
+                        f"two-layer vp 1500/4500, 8 off-grid Ricker sources, "
+                        f"{shot.rec_xyz.shape[0]} receivers, sponge 40",
+            "schedule": repr(tb_sched),
+            "effective_hbm_frac": round(gpts_tb * BYTES_PER_POINT_STEP / HBM_PEAK_GBS, 4),
+            "spatial_blocked": sb,
+            "tb_over_sb": round(gpts_tb / sb["value"], 3) if sb else None,
+            "parity_rel_l2": parity,
+            "inspector_s": round(setup_s, 3),
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    prop.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -90,8 +90,9 @@ typedef struct {
  * Schedule of the time loop (Section II-B; the wave-front loop nest of the
  * last listing). mode TB_SCHED_SB runs one step per pass; TB_SCHED_TB runs
  * time_tile steps per pass with a wave-front along x and overlapped y-z
- * halos. tile_y is the number of y rows one workgroup holds (16, 32 or 64),
- * chunk_x the number of x planes one workgroup streams (0 = all of x).
+ * halos. time_tile is 1..4 at space order 4 and 1..3 at space order 8.
+ * tile_y is the number of y rows one workgroup holds (16 or 32), chunk_x the
+ * number of x planes one workgroup streams (0 = all of x; at most 2048).
  * Passing NULL where a schedule is accepted selects the tuned default.
  */
 typedef struct {
@@ -189,6 +190,17 @@ tb_status tb_adjoint(const tb_model *m, const tb_sparse *s, const tb_schedule *s
 tb_status tb_gradient(const tb_model *m, const tb_sparse *s, const tb_schedule *sched, void *ws,
                       size_t ws_bytes, const float *d_obs, float *grad_m, double *loss_out,
                       int32_t checkpoint_every, void *stream);
+
+/*
+ * Kernel timing for measurement. While enabled, every propagation kernel
+ * launch made by this library (from any thread) is bracketed by HIP events on
+ * the stream it is launched on. tb_kernel_timing_read synchronises those
+ * events and returns the number of timed launches and their summed device
+ * time in milliseconds since the last enable, then keeps counting.
+ * Enabling resets the counters; disabling releases the events.
+ */
+tb_status tb_kernel_timing(int32_t enable);
+tb_status tb_kernel_timing_read(int32_t *launches, double *total_ms);
 
 /* Text of the last error on this thread ("" if none). */
 const char *tb_last_error(void);

@@ -64,6 +64,7 @@ tb_status launch_acoustic(const tb_model *m, const TileGeom &g, const TileLists 
     p.u = a.u;
     p.um = a.um;
     p.c = m->d_c;
+    p.zero = m->d_zero;
     p.out0 = a.out0;
     p.out1 = a.out1;
     p.dx = m->d_damp;
@@ -103,13 +104,84 @@ tb_status launch_acoustic(const tb_model *m, const TileGeom &g, const TileLists 
     p.rec_dcmp = a.rec_dcmp;
     p.nrid = a.nrid;
     hipError_t e = hipErrorInvalidValue;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (timing_enabled()) timing_begin(st, &ev0, &ev1);
     if (m->r == 2) e = launch_acoustic_r2(p, g.T, g.BYE, g.nblocks(), st);
     else if (m->r == 4) e = launch_acoustic_r4(p, g.T, g.BYE, g.nblocks(), st);
+    if (ev0) timing_end(st, ev0, ev1);
     if (e != hipSuccess) {
         set_error("acoustic kernel launch (R=%d T=%d BYE=%d) failed: %s", m->r, g.T, g.BYE,
                   hipGetErrorString(e));
         return TB_EHIP;
     }
+    return TB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Optional per-launch timing (tb_kernel_timing).
+namespace {
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_events;
+double g_done_ms = 0.0;
+int g_done_n = 0;
+}  // namespace
+
+bool timing_enabled()
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    return g_timing;
+}
+
+void timing_begin(hipStream_t st, hipEvent_t *a, hipEvent_t *b)
+{
+    if (hipEventCreate(a) != hipSuccess || hipEventCreate(b) != hipSuccess) {
+        *a = *b = nullptr;
+        return;
+    }
+    (void)hipEventRecord(*a, st);
+}
+
+void timing_end(hipStream_t st, hipEvent_t a, hipEvent_t b)
+{
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_events.emplace_back(a, b);
+}
+
+static void timing_drain(bool keep)
+{
+    for (auto &e : g_events) {
+        if (keep) {
+            (void)hipEventSynchronize(e.second);
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
+                g_done_ms += ms;
+                g_done_n++;
+            }
+        }
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+    }
+    g_events.clear();
+}
+
+tb_status kernel_timing(int enable)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    timing_drain(false);
+    g_done_ms = 0.0;
+    g_done_n = 0;
+    g_timing = enable != 0;
+    return TB_OK;
+}
+
+tb_status kernel_timing_read(int *n, double *ms)
+{
+    std::lock_guard<std::mutex> lk(g_tmu);
+    timing_drain(true);
+    if (n) *n = g_done_n;
+    if (ms) *ms = g_done_ms;
     return TB_OK;
 }
 

@@ -1,18 +1,18 @@
-// Isotropic acoustic propagator kernels for gfx950 (CDNA4).
+// Isotropic acoustic propagator kernel for gfx950 (CDNA4).
 //
 // One kernel template covers both schedules of the paper:
 //   T == 1  spatial blocking (Fig. 4a): one time step per pass over memory;
 //   T >= 2  wave-front temporal blocking (Section II-B, Fig. 7/8a and the
 //           final loop-nest listing): T steps per pass.
 //
-// A workgroup owns a y-z tile and streams along x. Stage s of the pipeline
+// A workgroup owns a y-z tile (BYE rows x 64 z; each lane holds 4
+// consecutive z as one float4) and streams along x. Stage s of the pipeline
 // holds the (2R+1)-plane window of time level n+s in registers (the x
-// neighbours), publishes its centre plane to LDS (the y neighbours) and
-// exchanges z neighbours inside 16-lane DPP rows (each lane holds 4
-// consecutive z as one float4, so a single row shift brings all R <= 4 z
-// neighbours). Stage s lags stage s-1 by R planes: the wave-front angle the
-// stencil radius imposes (Section II-B). The y-z tile carries an overlapped
-// halo of R(T-1) so the T stages need no exchange between workgroups.
+// neighbours) and publishes its centre plane to LDS, from where the y and z
+// neighbours are read. Stage s lags stage s-1 by R planes: the wave-front
+// angle the stencil radius imposes (Section II-B). The y-z tile carries an
+// overlapped halo of R(T-1), so the T stages need no exchange between
+// workgroups; an x-chunk carries the same halo along x.
 //
 // Injection follows the inspector's decomposition (Section II-A): the
 // per-tile list names every affected grid point in the workgroup's extended
@@ -24,6 +24,17 @@
 //
 // Every schedule evaluates the same per-point expression with the same
 // operation order, so all schedules give bit-identical fields.
+//
+// Throughput notes (the kernel is VALU-issue bound unless the per-point
+// instruction count is kept near the arithmetic of the stencil):
+//  * all field traffic uses buffer instructions whose descriptor is rebuilt
+//    per plane on the scalar unit; lanes outside the grid carry an offset
+//    past the end of the buffer, so their loads return 0 and their stores are
+//    dropped — no per-lane address arithmetic or masking;
+//  * inputs are loaded PD ticks ahead into a register ring, and the barrier
+//    fences LDS only, so the loads of later ticks stay in flight across it;
+//  * c = dt^2 vp^2 is zero outside the grid, so points outside the domain
+//    evaluate to +0 without masking.
 #pragma once
 
 #include <type_traits>
@@ -33,32 +44,45 @@
 namespace tbw {
 namespace wf {
 
-struct F4 {
-    float v[4];
-};
+typedef float f4v __attribute__((ext_vector_type(4)));
+using rsrc_t = __amdgpu_buffer_rsrc_t;
 
-__device__ __forceinline__ F4 tof4(float4 a) { return F4{{a.x, a.y, a.z, a.w}}; }
-__device__ __forceinline__ float4 tofloat4(const F4 &a)
+// Raw-buffer descriptor word 3 for gfx9-class parts (32-bit data format).
+constexpr int kRsrcWord3 = 0x00020000;
+// Byte offset beyond any buffer: loads return 0, stores are discarded.
+constexpr unsigned kNoLane = 0x80000000u;
+
+// LDS row stride in float4 (16 lanes + 2 ring columns + padding).
+constexpr int kLdsRow = 18;
+// Damping values of the chunk's x range (chunk plus halo) staged in LDS.
+constexpr int kDxCap = kMaxChunk + 32;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes)
 {
-    return make_float4(a.v[0], a.v[1], a.v[2], a.v[3]);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             kRsrcWord3);
 }
 
-__device__ __forceinline__ float4 ld4(const float *__restrict__ base, long long off, bool ok)
+__device__ __forceinline__ f4v bload(rsrc_t r, unsigned off)
 {
-    return ok ? *reinterpret_cast<const float4 *>(base + off) : make_float4(0.f, 0.f, 0.f, 0.f);
+    return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
 }
 
-// Lane l of a 16-lane DPP row receives lane l-1 (shr) or l+1 (shl); the lane
-// at the row edge keeps `old`.
-__device__ __forceinline__ float dpp_from_left(float old, float src)
+__device__ __forceinline__ void bstore(rsrc_t r, unsigned off, f4v v)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src),
-                                                      0x111, 0xF, 0xF, false));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v),
+                                           r, (int)off, 0, 0);
 }
-__device__ __forceinline__ float dpp_from_right(float old, float src)
+
+// Workgroup barrier that orders LDS only. __syncthreads() also fences global
+// memory, which makes the compiler wait for every outstanding global load
+// (the prefetches of later ticks included) at each barrier; the kernels here
+// never exchange global data inside a launch, so an LDS-scoped fence suffices.
+__device__ __forceinline__ void lds_barrier()
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src),
-                                                      0x101, 0xF, 0xF, false));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 template <int I, int N, class F>
@@ -71,41 +95,77 @@ __device__ __forceinline__ void static_for(F &&f)
 }
 
 // The per-point update shared by every schedule (fixed operation order):
-//   lap = w0 u + sum_{j=1..R} [wx_j (x-j + x+j) + wy_j (y-j + y+j) + wz_j (z-j + z+j)]
+//   lap = w0 u + sum_j wx_j (x-j + x+j) + sum_j wz_j (z-j + z+j) + sum_j wy_j (y-j + y+j)
 //   r   = c lap + (2u - beta u^{n-1});  r /= alpha where the damping is non-zero.
-template <int R>
+// Without damping (d == 0, beta == alpha == 1) the same expression is
+// evaluated by the fast path below with identical rounding.
+template <int R, bool DAMP>
 __device__ __forceinline__ float point_update(const AcParams &p, float ctr, const float *xm,
                                               const float *xp, const float *ym, const float *yp,
                                               const float *zm, const float *zp, float prev,
                                               float cc, float d)
 {
+    // x terms (register window) first, so LDS reads of the y/z neighbours
+    // overlap with arithmetic.
     float lap = p.w0 * ctr;
 #pragma unroll
-    for (int j = 0; j < R; j++) {
-        lap = __builtin_fmaf(p.wx[j], xm[j] + xp[j], lap);
-        lap = __builtin_fmaf(p.wy[j], ym[j] + yp[j], lap);
-        lap = __builtin_fmaf(p.wz[j], zm[j] + zp[j], lap);
+    for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wx[j], xm[j] + xp[j], lap);
+#pragma unroll
+    for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wz[j], zm[j] + zp[j], lap);
+#pragma unroll
+    for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wy[j], ym[j] + yp[j], lap);
+    if constexpr (DAMP) {
+        const float dd = d * p.hdt;
+        const float beta = 1.0f - dd;
+        float r = __builtin_fmaf(cc, lap, __builtin_fmaf(-beta, prev, 2.0f * ctr));
+        if (d != 0.0f) r = r / (1.0f + dd);
+        return r;
+    } else {
+        return __builtin_fmaf(cc, lap, __builtin_fmaf(-1.0f, prev, 2.0f * ctr));
     }
-    const float dd = d * p.hdt;
-    const float beta = 1.0f - dd;
-    float r = __builtin_fmaf(cc, lap, __builtin_fmaf(-beta, prev, 2.0f * ctr));
-    if (d != 0.0f) r = r / (1.0f + dd);
-    return r;
 }
 
-template <int R, int T, int BYE>
+// Side inputs of one tick. The HBM-bound ones are loaded PD ticks ahead into
+// a register ring; the ones the caches mostly serve (halo rings, c planes of
+// the later stages, read R*s ticks earlier by stage 0) one tick ahead.
+template <int T>
+struct FarIn {
+    f4v u;     // u^n at the newest plane i (enters the stage-0 window)
+    f4v um;    // u^{n-1} at the stage-0 centre plane
+    f4v c[T];  // c at every stage's centre plane
+};
+// Halo rings of stage 0 (z ring: lanes 0 and 15; y ring: threads < 2R*16),
+// mostly served by the caches: loaded right after a tick's barrier for the
+// next tick, a full tick ahead of their use, in a single register set.
+struct RingIn {
+    f4v rg;
+    f4v yr;
+};
+
+template <int R, int T, int BYE, int PD>
 __global__ void __launch_bounds__(kLanesZ *BYE) acoustic_wavefront(const AcParams p)
 {
-    constexpr int Q = 2 * R + 1;  // x window
+    constexpr int U = 2 * R + 1;  // window slots: the 2R+1 live planes
+    static_assert(U % PD == 0, "prefetch ring must divide the window");
     constexpr int HY = R * (T - 1);
     constexpr int HZ = ((R * (T - 1) + 3) / 4) * 4;
     constexpr int OY = BYE - 2 * HY;
     constexpr int OZ = kTileZ - 2 * HZ;
-    constexpr int LR = BYE + 2 * R;  // LDS rows per stage (with the y ring)
+    constexpr int LR = BYE + 2 * R;       // LDS rows per stage (with the y ring)
+    // LDS row: 16 lane columns, then the left and right z ring, padded to
+    // kLdsRow float4 (the row stride decides the bank mapping).
+    constexpr int LC = kLdsRow;
+    static_assert(LC >= kLanesZ + 2, "row must hold the lanes and the z ring");
+    constexpr int NTH = kLanesZ * BYE;
     static_assert(OY > 0 && OZ > 0, "tile too small for this depth");
     static_assert(R >= 1 && R <= 4, "radius must be 1..4");
 
-    __shared__ float4 sh[2][T][LR][kLanesZ];
+    __shared__ f4v sh[2][T][LR][LC];
+    __shared__ int2 s_src[kSrcCap];
+    __shared__ float s_val[kSrcCap][T];
+    __shared__ int2 s_rec[kRecCap];
+    __shared__ float s_recv[kRecCap][T];
+    __shared__ float s_dx[kDxCap];
 
     const int tid = threadIdx.x;
     const int zl = tid & (kLanesZ - 1);
@@ -127,217 +187,290 @@ __global__ void __launch_bounds__(kLanesZ *BYE) acoustic_wavefront(const AcParam
     const int xc1 = min(p.nx, xc0 + p.chunk);
     const int y = y0 + row, z = z0 + 4 * zl;
     const bool yin = (unsigned)y < (unsigned)p.ny;
-    const bool ldok = yin && z >= 0 && z < p.nzp;
-    const long long rowoff = (long long)y * p.nzp + z;
-    bool dm[4];
-    float dyz[4];
-#pragma unroll
-    for (int k = 0; k < 4; k++) {
-        dm[k] = yin && z + k >= 0 && z + k < p.nz;
-        dyz[k] = dm[k] ? p.dy[y] + p.dz[z + k] : 0.0f;
-    }
-    const bool own = row >= HY && row < HY + OY && zl >= HZ / 4 && zl < (HZ + OZ) / 4 && ldok;
-
-    // z ring of stage 0: lane 0 of each row holds z0-4..z0-1, lane 15 holds
+    const bool zin = z >= 0 && z < p.nzp;
+    const unsigned plane_bytes = (unsigned)(p.sx * 4);
+    // In-plane byte offsets (kNoLane for lanes outside the grid).
+    const unsigned off_c = (yin && zin) ? (unsigned)((y * p.nzp + z) * 4) : kNoLane;
+    const bool own = row >= HY && row < HY + OY && zl >= HZ / 4 && zl < (HZ + OZ) / 4;
+    const unsigned off_own = own ? off_c : kNoLane;
+    // z ring of stage 0: lane 0 of each row loads z0-4..z0-1, lane 15 loads
     // z0+64..z0+67 (one float4 covers the radius).
     const int zr = zl == 0 ? z - 4 : z + 4;
     const bool rgok = yin && (zl == 0 || zl == kLanesZ - 1) && zr >= 0 && zr < p.nzp;
-    const long long rgoff = (long long)y * p.nzp + zr;
+    const unsigned off_rg = rgok ? (unsigned)((y * p.nzp + zr) * 4) : kNoLane;
+    const int rg_col = zl == 0 ? kLanesZ : kLanesZ + 1;
+    const int col_l = zl == 0 ? kLanesZ : zl - 1;  // left z neighbour (or ring)
+    const int col_r = zl == kLanesZ - 1 ? kLanesZ + 1 : zl + 1;
+    const bool has_rg = zl == 0 || zl == kLanesZ - 1;
     // y ring of stage 0: rows y0-R..y0-1 and y0+BYE..y0+BYE+R-1.
     const bool has_yr = tid < 2 * R * kLanesZ;
-    const int rr = row;  // ring row index for threads with has_yr
-    const int yr = rr < R ? y0 - R + rr : y0 + BYE + rr - R;
-    const int yr_lds = rr < R ? rr : BYE + rr;
-    const bool yrok = has_yr && (unsigned)yr < (unsigned)p.ny && z >= 0 && z < p.nzp;
-    const long long yroff = (long long)yr * p.nzp + z;
+    const int yr = row < R ? y0 - R + row : y0 + BYE + row - R;
+    const int yr_lds = row < R ? row : BYE + row;
+    const bool yrok = has_yr && (unsigned)yr < (unsigned)p.ny && zin;
+    const unsigned off_yr = yrok ? (unsigned)((yr * p.nzp + z) * 4) : kNoLane;
 
-    // Clear the LDS planes so the unused ring rows of stages >= 1 hold zeros.
-    for (int k = tid; k < 2 * T * LR * kLanesZ; k += kLanesZ * BYE)
-        (&sh[0][0][0][0])[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    // Damping of this thread's points along y and z (zero outside the grid).
+    float dyz[4];
+    bool any_dyz = false;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const bool in = yin && z + k >= 0 && z + k < p.nz;
+        dyz[k] = in ? p.dy[y] + p.dz[z + k] : 0.0f;
+        any_dyz |= dyz[k] != 0.0f;
+    }
+    const bool wave_dyz = __builtin_amdgcn_ballot_w64(any_dyz) != 0;
 
-    // Per-stage x ranges and list cursors.
+    // Clear the LDS planes so the unused ring rows/columns stay zero.
+    for (int k = tid; k < 2 * T * LR * LC; k += NTH)
+        (&sh[0][0][0][0])[k] = f4v{0.f, 0.f, 0.f, 0.f};
+
+    // Per-stage x ranges; damping d_x over [xlo, xlo + nxd) staged in LDS.
     int lo[T], hi[T];
 #pragma unroll
     for (int s = 0; s < T; s++) {
         lo[s] = max(0, xc0 - R * (T - 1 - s));
         hi[s] = min(p.nx, xc1 + R * (T - 1 - s));
     }
-    const int sbeg = p.src_off[L], send = p.src_off[L + 1];
-    const int rbeg = p.rec_off[L], rend = p.rec_off[L + 1];
-    int scur[T], rcur[T];
+    const int xlo = lo[0];
+    const int nxd = hi[0] - lo[0];
+    for (int k = tid; k < nxd; k += NTH) s_dx[k] = p.dx[xlo + k];
+
+    // Stage this tile's injection list (with the decomposed wavelet values of
+    // this pass's T steps) and its receiver list in LDS. The host keeps every
+    // tile within the capacities (shorter x chunks otherwise).
+    const int sbeg = p.src_off[L], nsl = p.src_off[L + 1] - sbeg;
+    const int rbeg = p.rec_off[L], nrl = p.rec_off[L + 1] - rbeg;
+    for (int k = tid; k < nsl; k += NTH) {
+        const int2 e = p.src[sbeg + k];
+        s_src[k] = e;
+#pragma unroll
+        for (int s = 0; s < T; s++) s_val[k][s] = p.dcmp[(long long)(p.n0 + s) * p.npts + e.y];
+    }
+    for (int k = tid; k < nrl; k += NTH) s_rec[k] = p.rec[rbeg + k];
+    lds_barrier();
+    // Each lane walks its own entries (sorted by x) with one cursor per stage,
+    // so a tick costs one compare per stage unless this lane has a point on
+    // the stage's plane.
+    const int mykey = row * 16 + zl;
+    auto first_at = [&](const int2 *lst, int n, int x) {
+        const int want = tile_key(row, zl, x, 0);
+        int a = 0, b2 = n;
+        while (a < b2) {
+            const int mid = (a + b2) >> 1;
+            if (lst[mid].x < want) a = mid + 1;
+            else b2 = mid;
+        }
+        return a;
+    };
+    auto next_x = [&](const int2 *lst, int n, int k) {
+        return (k < n && (lst[k].x >> 18) == mykey) ? ((lst[k].x >> 2) & 0xffff) : 0x7fffffff;
+    };
+    int scur[T], snx[T], rcur[T], rnx[T];
 #pragma unroll
     for (int s = 0; s < T; s++) {
-        scur[s] = sbeg;
-        rcur[s] = rbeg;
+        scur[s] = nsl ? first_at(s_src, nsl, lo[s]) : 0;
+        snx[s] = next_x(s_src, nsl, scur[s]);
+        rcur[s] = nrl ? first_at(s_rec, nrl, lo[s]) : 0;
+        rnx[s] = next_x(s_rec, nrl, rcur[s]);
     }
 
-    F4 q[T][Q];
+    f4v q[T][U];
 #pragma unroll
     for (int s = 0; s < T; s++)
 #pragma unroll
-        for (int k = 0; k < Q; k++) q[s][k] = F4{{0.f, 0.f, 0.f, 0.f}};
+        for (int k = 0; k < U; k++) q[s][k] = f4v{0.f, 0.f, 0.f, 0.f};
 
     const int i0 = max(0, xc0 - R * T);
     const int ilast = xc1 - 1 + R * T;
 
-    // Prefetch registers for the tick about to run: the new plane of u^n, and
-    // at the stage-0 centre plane u^{n-1}, the z ring and the y ring; c at
-    // every stage's centre plane (stages >= 1 re-read planes stage 0 read R*s
-    // ticks earlier, which the caches still hold).
-    auto fetch = [&](int i, float4 &fu, float4 &fum, float4 (&fc)[T], float4 &frg,
-                     float4 &fyr) {
+    // Descriptor of plane x of a field (zero records outside [0, nx): every
+    // lane then reads 0).
+    auto plane = [&](const float *f, int x) {
+        const bool in = x >= 0 && x < p.nx;
+        return make_rsrc(f + (in ? (long long)x * p.sx : 0), in ? plane_bytes : 0u);
+    };
+    // Inputs of tick i: the newest plane i of u^n, u^{n-1} at the stage-0
+    // centre plane, c at every stage's centre plane (stages >= 1 re-read c
+    // planes stage 0 read R*s ticks earlier, which the caches still hold).
+    auto fetch_far = [&](int i, FarIn<T> &f) {
         const int c0 = i - R;
-        const bool pin = i < p.nx;  // i >= 0 always
-        const bool cin = c0 >= 0 && c0 < p.nx;
-        fu = ld4(p.u, (long long)i * p.sx + rowoff, ldok && pin);
-        fum = ld4(p.um, (long long)c0 * p.sx + rowoff, ldok && cin);
+        f.u = bload(plane(p.u, i), off_c);
+        f.um = bload(plane(p.um, c0), off_c);
 #pragma unroll
         for (int s = 0; s < T; s++) {
             const int cs = c0 - R * s;
-            fc[s] = ld4(p.c, (long long)cs * p.sx + rowoff, ldok && cs >= lo[s] && cs < hi[s]);
+            f.c[s] = bload(plane(p.c, (cs >= lo[s] && cs < hi[s]) ? cs : -1), off_c);
         }
-        frg = ld4(p.u, (long long)c0 * p.sx + rgoff, rgok && cin);
-        fyr = ld4(p.u, (long long)c0 * p.sx + yroff, yrok && cin);
     };
-    float4 pu, pum, pc[T], prg, pyr;
-    fetch(i0, pu, pum, pc, prg, pyr);
-    __syncthreads();
+    auto fetch_ring = [&](int i, RingIn &f) {
+        const rsrc_t ru = plane(p.u, i - R);
+        f.rg = bload(ru, off_rg);
+        f.yr = bload(ru, off_yr);
+    };
+    FarIn<T> pf[PD];
+    RingIn rgn;
+    static_for<0, PD>([&](auto KC) {
+        constexpr int k = decltype(KC)::value;
+        fetch_far(i0 + k, pf[k]);
+    });
+    fetch_ring(i0, rgn);
+    lds_barrier();
 
     int i = i0;
     int tick = 0;
     while (i <= ilast) {
-        static_for<0, Q>([&](auto PC) {
-            constexpr int P = decltype(PC)::value;
+        static_for<0, U>([&](auto PC) {
+            constexpr int P = PC.value;
+            constexpr int SLOT = P % PD;
+            constexpr int CTR = (P + R) % U;
+            constexpr int OLD = P % U;
+            constexpr int NEW = (P + 2 * R) % U;
             if (i > ilast) return;
-            const F4 cu = tof4(pu);
-            const F4 cum = tof4(pum);
-            float4 cc4[T];
-#pragma unroll
-            for (int s = 0; s < T; s++) cc4[s] = pc[s];
-            const float4 crg = prg;
-            const float4 cyr = pyr;
-            if (i + 1 <= ilast) fetch(i + 1, pu, pum, pc, prg, pyr);
-
-            constexpr int NEW = (P + 2 * R) % Q;
-            constexpr int CTR = (P + R) % Q;
-            constexpr int OLD = P % Q;
-            q[0][NEW] = cu;
+            const FarIn<T> &in = pf[SLOT];
+            q[0][NEW] = in.u;
             const int buf = tick & 1;
 #pragma unroll
-            for (int s = 0; s < T; s++) sh[buf][s][row + R][zl] = tofloat4(q[s][CTR]);
-            if (has_yr) sh[buf][0][yr_lds][zl] = cyr;
-            __syncthreads();
+            for (int s = 0; s < T; s++) sh[buf][s][row + R][zl] = q[s][CTR];
+            if (has_rg) sh[buf][0][row + R][rg_col] = rgn.rg;
+            if (has_yr) sh[buf][0][yr_lds][zl] = rgn.yr;
+            lds_barrier();
+            fetch_ring(i + 1, rgn);
 
             static_for<0, T>([&](auto SC) {
-                constexpr int s = decltype(SC)::value;
+                constexpr int s = SC.value;
                 const int cs = i - R * (s + 1);
-                F4 v = F4{{0.f, 0.f, 0.f, 0.f}};
+                f4v v = f4v{0.f, 0.f, 0.f, 0.f};
                 if (cs >= lo[s] && cs < hi[s]) {
-                    const F4 ctr = q[s][CTR];
-                    const F4 prev = (s == 0) ? cum : q[s > 0 ? s - 1 : 0][OLD];
-                    const F4 cf = tof4(cc4[s]);
-                    const F4 ring = (s == 0) ? tof4(crg) : F4{{0.f, 0.f, 0.f, 0.f}};
+                    const f4v ctr = q[s][CTR];
+                    const f4v prev = (s == 0) ? in.um : q[s > 0 ? s - 1 : 0][OLD];
+                    const f4v cf = in.c[s];
+                    const f4v zl4 = sh[buf][s][row + R][col_l];
+                    const f4v zr4 = sh[buf][s][row + R][col_r];
                     float zw[12];
 #pragma unroll
                     for (int k = 0; k < 4; k++) {
-                        zw[k] = dpp_from_left(ring.v[k], ctr.v[k]);
-                        zw[4 + k] = ctr.v[k];
-                        zw[8 + k] = dpp_from_right(ring.v[k], ctr.v[k]);
+                        zw[k] = zl4[k];
+                        zw[4 + k] = ctr[k];
+                        zw[8 + k] = zr4[k];
                     }
-                    F4 ym[R], yp[R];
+                    f4v ym[R], yp[R];
 #pragma unroll
                     for (int j = 1; j <= R; j++) {
-                        ym[j - 1] = tof4(sh[buf][s][row + R - j][zl]);
-                        yp[j - 1] = tof4(sh[buf][s][row + R + j][zl]);
+                        ym[j - 1] = sh[buf][s][row + R - j][zl];
+                        yp[j - 1] = sh[buf][s][row + R + j][zl];
                     }
-                    const float dxs = p.dx[cs];
+                    const float dxs = s_dx[cs - xlo];
+                    auto compute = [&](auto DC) {
+                        constexpr bool DAMP = decltype(DC)::value;
 #pragma unroll
-                    for (int k = 0; k < 4; k++) {
-                        float xm[R], xp[R], a[R], bb[R], zm[R], zp[R];
+                        for (int k = 0; k < 4; k++) {
+                            float xm[R], xp[R], a[R], bb[R], zm[R], zp[R];
 #pragma unroll
-                        for (int j = 1; j <= R; j++) {
-                            xm[j - 1] = q[s][(P + R - j) % Q].v[k];
-                            xp[j - 1] = q[s][(P + R + j) % Q].v[k];
-                            a[j - 1] = ym[j - 1].v[k];
-                            bb[j - 1] = yp[j - 1].v[k];
-                            zm[j - 1] = zw[4 + k - j];
-                            zp[j - 1] = zw[4 + k + j];
+                            for (int j = 1; j <= R; j++) {
+                                xm[j - 1] = q[s][(P + R - j) % U][k];
+                                xp[j - 1] = q[s][(P + R + j) % U][k];
+                                a[j - 1] = ym[j - 1][k];
+                                bb[j - 1] = yp[j - 1][k];
+                                zm[j - 1] = zw[4 + k - j];
+                                zp[j - 1] = zw[4 + k + j];
+                            }
+                            v[k] = point_update<R, DAMP>(p, ctr[k], xm, xp, a, bb, zm, zp,
+                                                         prev[k], cf[k], dxs + dyz[k]);
                         }
-                        v.v[k] = point_update<R>(p, ctr.v[k], xm, xp, a, bb, zm, zp, prev.v[k],
-                                                 cf.v[k], dxs + dyz[k]);
-                    }
+                    };
+                    if (dxs != 0.0f || wave_dyz) compute(std::true_type{});
+                    else compute(std::false_type{});
                     // Fused injection at every computed copy (per-tile list).
-                    if (sbeg < send) {
+                    if (snx[s] == cs) {
                         int kk = scur[s];
-                        while (kk < send && p.src[kk].x < cs) kk++;
+                        for (; kk < nsl && (s_src[kk].x >> 18) == mykey &&
+                               ((s_src[kk].x >> 2) & 0xffff) == cs;
+                             kk++) {
+                            const int k = s_src[kk].x & 3;
+                            const float add = s_val[kk][s];
+                            v[0] = k == 0 ? v[0] + add : v[0];
+                            v[1] = k == 1 ? v[1] + add : v[1];
+                            v[2] = k == 2 ? v[2] + add : v[2];
+                            v[3] = k == 3 ? v[3] + add : v[3];
+                        }
                         scur[s] = kk;
-                        for (; kk < send && p.src[kk].x == cs; kk++) {
-                            const int4 e = p.src[kk];
-                            if (e.y == row && (e.z >> 2) == zl) {
-                                const float add =
-                                    p.dcmp[(long long)(p.n0 + s) * p.npts + e.w];
-#pragma unroll
-                                for (int k = 0; k < 4; k++)
-                                    if ((e.z & 3) == k) v.v[k] += add;
-                            }
-                        }
+                        snx[s] = next_x(s_src, nsl, kk);
                     }
-#pragma unroll
-                    for (int k = 0; k < 4; k++)
-                        if (!dm[k]) v.v[k] = 0.0f;
-                    // Receiver points: owned copy only.
-                    if (rbeg < rend) {
+                    // Receiver points (owned copy only), buffered in LDS and
+                    // written out once at the end.
+                    if (rnx[s] == cs) {
                         int kk = rcur[s];
-                        while (kk < rend && p.rec[kk].x < cs) kk++;
-                        rcur[s] = kk;
-                        for (; kk < rend && p.rec[kk].x == cs; kk++) {
-                            const int4 e = p.rec[kk];
-                            if (e.y == row && (e.z >> 2) == zl) {
-                                float val = v.v[0];
-#pragma unroll
-                                for (int k = 1; k < 4; k++)
-                                    if ((e.z & 3) == k) val = v.v[k];
-                                p.rec_dcmp[(long long)(p.n0 + s + 1) * p.nrid + e.w] = val;
-                            }
+                        for (; kk < nrl && (s_rec[kk].x >> 18) == mykey &&
+                               ((s_rec[kk].x >> 2) & 0xffff) == cs;
+                             kk++) {
+                            const int k = s_rec[kk].x & 3;
+                            s_recv[kk][s] = k == 0 ? v[0] : k == 1 ? v[1] : k == 2 ? v[2] : v[3];
                         }
+                        rcur[s] = kk;
+                        rnx[s] = next_x(s_rec, nrl, kk);
                     }
                 }
                 if constexpr (s + 1 < T) {
                     q[s + 1 < T ? s + 1 : 0][NEW] = v;
                 } else {
-                    if (cs >= xc0 && cs < xc1 && own) {
-                        const long long off = (long long)cs * p.sx + rowoff;
-                        *reinterpret_cast<float4 *>(p.out0 + off) = tofloat4(v);
-                        if constexpr (T > 1)
-                            *reinterpret_cast<float4 *>(p.out1 + off) = tofloat4(q[s][CTR]);
-                    }
+                    const bool st_in = cs >= xc0 && cs < xc1;
+                    bstore(plane(p.out0, st_in ? cs : -1), off_own, v);
+                    if constexpr (T > 1) bstore(plane(p.out1, st_in ? cs : -1), off_own, q[s][CTR]);
                 }
             });
+            // Loads for tick i + PD.
+            fetch_far(i + PD, pf[SLOT]);
             i++;
             tick++;
         });
     }
+    if (nrl > 0) {
+        lds_barrier();
+        for (int k = tid; k < nrl; k += NTH) {
+            const int id = s_rec[k].y;
+            // Owned receiver planes lie inside every stage's x range, so each
+            // stage recorded every entry.
+#pragma unroll
+            for (int s = 0; s < T; s++)
+                p.rec_dcmp[(long long)(p.n0 + s + 1) * p.nrid + id] = s_recv[k][s];
+        }
+    }
 }
+
+// Prefetch depth (ticks of loads in flight): it must divide the window 2R+1,
+// and the deeper pipelines keep fewer ticks in flight so their register
+// windows still fit.
+template <int R, int T>
+constexpr int prefetch_depth()
+{
+    if constexpr (R == 4) return 3;
+    else if constexpr (R == 2) return T <= 2 ? 5 : 1;
+    else return 1;
+}
+static_assert((2 * 4 + 1) % 3 == 0 && (2 * 2 + 1) % 5 == 0, "depth must divide the window");
 
 template <int R, int T, int BYE>
 hipError_t launch_rtb(const AcParams &p, int nblocks, hipStream_t st)
 {
-    hipLaunchKernelGGL((acoustic_wavefront<R, T, BYE>), dim3(nblocks), dim3(kLanesZ * BYE), 0,
-                       st, p);
+    hipLaunchKernelGGL((acoustic_wavefront<R, T, BYE, prefetch_depth<R, T>()>), dim3(nblocks),
+                       dim3(kLanesZ * BYE), 0, st, p);
     return hipGetLastError();
 }
 
 // LDS bytes of one workgroup of acoustic_wavefront<R, T, BYE>.
-constexpr int wavefront_lds(int R, int T, int BYE) { return 16 * kLanesZ * 2 * T * (BYE + 2 * R); }
+constexpr int wavefront_lds(int R, int T, int BYE)
+{
+    return 16 * 2 * T * (BYE + 2 * R) * kLdsRow + kSrcCap * (8 + 4 * T) +
+           kRecCap * (8 + 4 * T) + 4 * kDxCap;
+}
 
-// Instantiated shapes: the halo must leave owned rows, LDS must fit, and a
-// 1024-thread workgroup (at most 128 VGPRs per lane) only for the shallow
-// pipelines whose register queues fit without spilling.
+// Instantiated shapes: the halo must leave owned rows, LDS must fit, and the
+// register windows of the deeper pipelines must fit in 256 VGPRs.
 template <int R, int T, int BYE>
 constexpr bool wavefront_fits()
 {
-    return BYE - 2 * R * (T - 1) > 0 && wavefront_lds(R, T, BYE) <= 160 * 1024 &&
-           (BYE <= 32 || (R <= 2 && T <= 2));
+    return BYE - 2 * R * (T - 1) > 0 && wavefront_lds(R, T, BYE) <= 160 * 1024 && BYE <= 32 &&
+           (R <= 2 || T <= 3);
 }
 
 template <int R, int T>
@@ -349,9 +482,6 @@ hipError_t launch_rt(const AcParams &p, int BYE, int nblocks, hipStream_t st)
         break;
     case 32:
         if constexpr (wavefront_fits<R, T, 32>()) return launch_rtb<R, T, 32>(p, nblocks, st);
-        break;
-    case 64:
-        if constexpr (wavefront_fits<R, T, 64>()) return launch_rtb<R, T, 64>(p, nblocks, st);
         break;
     }
     return hipErrorInvalidValue;

@@ -9,6 +9,7 @@ struct AcParams {
     const float *__restrict__ u;   // u^n      [nx][ny][nzp]
     const float *__restrict__ um;  // u^{n-1}
     const float *__restrict__ c;   // dt^2 vp^2
+    const float *zero;             // 16 zeroed bytes (target of masked-off loads)
     float *out0;                   // u^{n+T}
     float *out1;                   // u^{n+T-1} (T >= 2)
     const float *__restrict__ dx;  // damping per axis
@@ -20,11 +21,11 @@ struct AcParams {
     int nx, ny, nz, nzp;
     long long sx;  // plane stride ny * nzp
     int tiles_y, tiles_z, chunk, nblocks;
-    const int4 *__restrict__ src;
+    const int2 *__restrict__ src;
     const int *__restrict__ src_off;
     const float *__restrict__ dcmp;
     int npts, n0;
-    const int4 *__restrict__ rec;
+    const int2 *__restrict__ rec;
     const int *__restrict__ rec_off;
     float *rec_dcmp;
     int nrid;
@@ -34,5 +35,10 @@ struct AcParams {
 // unit per radius so the instantiations compile in parallel).
 hipError_t launch_acoustic_r2(const AcParams &p, int T, int BYE, int nblocks, hipStream_t st);
 hipError_t launch_acoustic_r4(const AcParams &p, int T, int BYE, int nblocks, hipStream_t st);
+
+// Optional per-launch event timing of the propagation kernels.
+bool timing_enabled();
+void timing_begin(hipStream_t st, hipEvent_t *a, hipEvent_t *b);
+void timing_end(hipStream_t st, hipEvent_t a, hipEvent_t b);
 
 }  // namespace tbw

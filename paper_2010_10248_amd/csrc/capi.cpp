@@ -18,6 +18,7 @@ tb_model::~tb_model()
 {
     if (d_c) (void)hipFree(d_c);
     if (d_damp) (void)hipFree(d_damp);
+    if (d_zero) (void)hipFree(d_zero);
 }
 
 tb_sparse::~tb_sparse()
@@ -93,8 +94,12 @@ tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice 
         set_error("time_tile %d not in 1..4", c.T);
         return TB_EUNSUPPORTED;
     }
-    if (c.BYE != 16 && c.BYE != 32 && c.BYE != 64) {
-        set_error("tile_y %d not in {16, 32, 64}", c.BYE);
+    if (c.BYE != 16 && c.BYE != 32) {
+        set_error("tile_y %d not in {16, 32}", c.BYE);
+        return TB_EUNSUPPORTED;
+    }
+    if (m->r == 4 && c.T > 3) {
+        set_error("time_tile %d exceeds 3 at space order 8", c.T);
         return TB_EUNSUPPORTED;
     }
     if (c.BYE - 2 * m->r * (c.T - 1) <= 0) {
@@ -152,6 +157,16 @@ tb_status time_loop(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int 
         TileGeom g = make_geom(m->r, T, sc.BYE, sc.chunk, m->n[0], m->n[1], m->n[2]);
         TileLists *tl = nullptr;
         if ((rc = get_lists(m, s, adjoint, g, &tl))) return rc;
+        // Tiles whose lists exceed the LDS capacities run with shorter chunks.
+        while (tl->max_src > kSrcCap || tl->max_rec > kRecCap) {
+            if (g.chunk <= 1) {
+                set_error("a single plane of one tile holds more sparse points than the "
+                          "kernel capacity (%d / %d)", kSrcCap, kRecCap);
+                return TB_EUNSUPPORTED;
+            }
+            g = make_geom(m->r, T, sc.BYE, (g.chunk + 1) / 2, m->n[0], m->n[1], m->n[2]);
+            if ((rc = get_lists(m, s, adjoint, g, &tl))) return rc;
+        }
         AcLaunch a{};
         a.u = F[cur];
         a.um = F[prev];
@@ -191,6 +206,16 @@ extern "C" {
 const char *tb_last_error(void) { return tbw::last_error(); }
 
 const char *tb_version(void) { return "tbwave 0.1 (gfx950)"; }
+
+tb_status tb_kernel_timing(int32_t enable) { return tbw::kernel_timing(enable); }
+
+tb_status tb_kernel_timing_read(int32_t *launches, double *total_ms)
+{
+    int n = 0;
+    tb_status st = tbw::kernel_timing_read(&n, total_ms);
+    if (launches) *launches = n;
+    return st;
+}
 
 tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
 {
@@ -280,6 +305,8 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
     damping_axis(nz, m->nbl, m->h[2], m->vmax, m->damp.data() + nx + ny);
     TB_HIP(hipMalloc(&m->d_c, m->field_elems() * sizeof(float)));
     TB_HIP(hipMemcpy(m->d_c, cpad.data(), cpad.size() * sizeof(float), hipMemcpyHostToDevice));
+    TB_HIP(hipMalloc(&m->d_zero, 256));
+    TB_HIP(hipMemset(m->d_zero, 0, 256));
     TB_HIP(hipMalloc(&m->d_damp, m->damp.size() * sizeof(float)));
     TB_HIP(hipMemcpy(m->d_damp, m->damp.data(), m->damp.size() * sizeof(float),
                      hipMemcpyHostToDevice));

@@ -120,6 +120,7 @@ TileGeom make_geom(int R, int T, int BYE, int chunk, int nx, int ny, int nz)
     g.OY = BYE - 2 * g.HY;
     g.OZ = kTileZ - 2 * g.HZ;
     g.chunk = (chunk <= 0 || chunk > nx) ? nx : chunk;
+    if (g.chunk > kMaxChunk) g.chunk = kMaxChunk;
     g.tiles_y = g.OY > 0 ? (ny + g.OY - 1) / g.OY : 0;
     g.tiles_z = g.OZ > 0 ? (nz + g.OZ - 1) / g.OZ : 0;
     g.nchunks = (nx + g.chunk - 1) / g.chunk;
@@ -142,7 +143,7 @@ static inline int tile_index(const TileGeom &g, int ch, int ty, int tz)
 }
 
 static void bin_points(const TileGeom &g, const int n[3], const std::vector<int64_t> &nodes,
-                       bool owned_only, std::vector<std::vector<int4>> *bins)
+                       bool owned_only, std::vector<std::vector<int2>> *bins)
 {
     const int halo_x = g.R * (g.T - 1);
     for (size_t id = 0; id < nodes.size(); id++) {
@@ -183,31 +184,31 @@ static void bin_points(const TileGeom &g, const int n[3], const std::vector<int6
                                    : (col < 0 || col >= kTileZ))
                         continue;
                     (*bins)[tile_index(g, ch, ty, tz)].push_back(
-                        make_int4(x, row, col, (int)id));
+                        make_int2(tile_key(row, col >> 2, x, col & 3), (int)id));
                 }
             }
         }
     }
     for (auto &b : *bins)
-        std::sort(b.begin(), b.end(), [](const int4 &a, const int4 &c) {
-            if (a.x != c.x) return a.x < c.x;
-            if (a.y != c.y) return a.y < c.y;
-            return a.z < c.z;
-        });
+        std::sort(b.begin(), b.end(), [](const int2 &a, const int2 &c) { return a.x < c.x; });
 }
 
-static tb_status upload_csr(const std::vector<std::vector<int4>> &bins, int4 **d_list,
-                            int **d_off, int *count)
+static tb_status upload_csr(const std::vector<std::vector<int2>> &bins, int2 **d_list,
+                            int **d_off, int *count, int *longest)
 {
     std::vector<int> off(bins.size() + 1, 0);
-    for (size_t t = 0; t < bins.size(); t++) off[t + 1] = off[t] + (int)bins[t].size();
-    std::vector<int4> flat;
+    *longest = 0;
+    for (size_t t = 0; t < bins.size(); t++) {
+        off[t + 1] = off[t] + (int)bins[t].size();
+        *longest = std::max(*longest, (int)bins[t].size());
+    }
+    std::vector<int2> flat;
     flat.reserve(off.back() + 1);
     for (auto &b : bins) flat.insert(flat.end(), b.begin(), b.end());
-    flat.push_back(make_int4(0x7fffffff, 0, 0, 0));  // sentinel
+    flat.push_back(make_int2(0x7fffffff, 0));  // sentinel
     *count = off.back();
-    TB_HIP(hipMalloc(d_list, flat.size() * sizeof(int4)));
-    TB_HIP(hipMemcpy(*d_list, flat.data(), flat.size() * sizeof(int4), hipMemcpyHostToDevice));
+    TB_HIP(hipMalloc(d_list, flat.size() * sizeof(int2)));
+    TB_HIP(hipMemcpy(*d_list, flat.data(), flat.size() * sizeof(int2), hipMemcpyHostToDevice));
     TB_HIP(hipMalloc(d_off, off.size() * sizeof(int)));
     TB_HIP(hipMemcpy(*d_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
     return TB_OK;
@@ -217,12 +218,12 @@ tb_status build_tile_lists(const tb_model *m, const std::vector<int64_t> &inj,
                            const std::vector<int64_t> &rec, const TileGeom &g, TileLists *out)
 {
     const int nb = g.nblocks();
-    std::vector<std::vector<int4>> sb(nb), rb(nb);
+    std::vector<std::vector<int2>> sb(nb), rb(nb);
     bin_points(g, m->n, inj, false, &sb);
     bin_points(g, m->n, rec, true, &rb);
-    tb_status st = upload_csr(sb, &out->d_src, &out->d_src_off, &out->nsrc_entries);
+    tb_status st = upload_csr(sb, &out->d_src, &out->d_src_off, &out->nsrc_entries, &out->max_src);
     if (st) return st;
-    return upload_csr(rb, &out->d_rec, &out->d_rec_off, &out->nrec_entries);
+    return upload_csr(rb, &out->d_rec, &out->d_rec_off, &out->nrec_entries, &out->max_rec);
 }
 
 }  // namespace tbw

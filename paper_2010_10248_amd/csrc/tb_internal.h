@@ -30,6 +30,20 @@ void set_error(const char *fmt, ...);
 // Workgroup z extent of the acoustic kernels: 16 lanes, 4 consecutive z each.
 constexpr int kTileZ = 64;
 constexpr int kLanesZ = 16;
+// Longest x chunk one workgroup streams (its damping values sit in LDS).
+constexpr int kMaxChunk = 2048;
+// Per-tile list capacities (the lists are staged in LDS); a schedule whose
+// tiles exceed them is run with shorter x chunks.
+constexpr int kSrcCap = 512;
+constexpr int kRecCap = 2048;
+
+// A list entry: key = ((row*16 + lane) << 18) | (x << 2) | k, with k the z
+// component inside the lane's float4; id = point ID. Sorted by key, so each
+// lane's entries are contiguous and ordered by x.
+__host__ __device__ inline int tile_key(int row, int lane, int x, int k)
+{
+    return ((row * 16 + lane) << 18) | (x << 2) | k;
+}
 
 // Geometry of one schedule (shared by the binning and the launch code).
 struct TileGeom {
@@ -41,13 +55,14 @@ struct TileGeom {
 };
 TileGeom make_geom(int R, int T, int BYE, int chunk, int nx, int ny, int nz);
 
-// Per-tile injection / recording lists in CSR form. Entry = {x, row, col, id}.
+// Per-tile injection / recording lists in CSR form, entries {key, id}.
 struct TileLists {
-    int4 *d_src = nullptr;
+    int2 *d_src = nullptr;
     int *d_src_off = nullptr;
-    int4 *d_rec = nullptr;
+    int2 *d_rec = nullptr;
     int *d_rec_off = nullptr;
     int nsrc_entries = 0, nrec_entries = 0;
+    int max_src = 0, max_rec = 0;  // longest list of one tile
     ~TileLists();
 };
 
@@ -65,6 +80,7 @@ struct tb_model {
     int device = 0;
     float *d_c = nullptr;     // dt^2 vp^2, [nx][ny][nzp]
     float *d_damp = nullptr;  // d_x[nx] | d_y[ny] | d_z[nzp]
+    float *d_zero = nullptr;  // 256 zeroed bytes
     std::vector<double> c64;  // host copy of dt^2 vp^2 (FP64 from the FP32 vp)
     std::vector<float> damp;  // host copy of the three tables
     size_t field_elems() const { return (size_t)n[0] * n[1] * nzp; }
@@ -132,6 +148,8 @@ struct AcLaunch {
 tb_status launch_acoustic(const tb_model *m, const TileGeom &g, const TileLists &tl,
                           const AcLaunch &a, hipStream_t st);
 tb_status launch_fill(float *p, size_t n, float v, hipStream_t st);
+tb_status kernel_timing(int enable);
+tb_status kernel_timing_read(int *n, double *ms);
 tb_status launch_trace_reduce(const float *rec_dcmp, int nrid, int nt, const int *ptr,
                               const int *id, const float *w, int nrec, float *out,
                               int reverse, hipStream_t st);

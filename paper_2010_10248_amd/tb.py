@@ -84,6 +84,8 @@ _SIGNATURES = {
     "tb_gradient": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(Schedule), _vp, ctypes.c_size_t,
                                      _vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                      _vp]),
+    "tb_kernel_timing": (ctypes.c_int32, [ctypes.c_int32]),
+    "tb_kernel_timing_read": (ctypes.c_int32, [_ip, ctypes.POINTER(ctypes.c_double)]),
     "tb_last_error": (ctypes.c_char_p, []),
     "tb_version": (ctypes.c_char_p, []),
 }
@@ -111,6 +113,18 @@ def last_error() -> str:
 
 def version() -> str:
     return lib().tb_version().decode()
+
+
+def kernel_timing(enable: bool):
+    _check(lib().tb_kernel_timing(1 if enable else 0), "tb_kernel_timing")
+
+
+def kernel_timing_read():
+    """(launches, total device ms) of the propagation kernels since enable."""
+    n = ctypes.c_int32()
+    ms = ctypes.c_double()
+    _check(lib().tb_kernel_timing_read(ctypes.byref(n), ctypes.byref(ms)), "tb_kernel_timing_read")
+    return n.value, ms.value
 
 
 def _check(st: int, what: str):

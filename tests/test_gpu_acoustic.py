@@ -53,7 +53,7 @@ def _check_case(torch_cuda, orc, shot, scheds=SCHEDS, tol=TOL):
     prop = tb.Acoustic(shot)
     base = None
     for mode, T, by, ch in scheds:
-        if shot.space_order == 8 and T >= 4 and by < 32:
+        if shot.space_order == 8 and T >= 4:
             continue
         sc = tb.schedule(mode, T, by, ch)
         _say(f"case {shot.name} sched {sc}")
