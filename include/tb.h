@@ -91,9 +91,14 @@ typedef struct {
  * last listing). mode TB_SCHED_SB runs one step per pass; TB_SCHED_TB runs
  * time_tile steps per pass with a wave-front along x and overlapped y-z
  * halos. time_tile is 1..4 at space order 4 and 1..3 at space order 8.
- * tile_y is the number of y rows one workgroup holds (16 or 32), chunk_x the
- * number of x planes one workgroup streams (0 = all of x; at most 2048).
- * Passing NULL where a schedule is accepted selects the tuned default.
+ *  tile_y   y rows one workgroup holds: 16 or 32 (16 lanes x 4 z per row),
+ *           or 0 for the shape whose tile owns 64 z (16 + halo/2 lanes).
+ *  chunk_x  x planes one work segment streams: 1..n, each (chunk, tile) pair
+ *           one workgroup, dispatched chunk-major; 0 splits the tile-x space
+ *           evenly over two workgroups per compute unit.
+ * Every schedule gives bit-identical results. Passing NULL where a schedule
+ * is accepted selects the default: TB, time_tile 2, tile_y 32, chunk_x 64
+ * when nx >= 256, else 0.
  */
 typedef struct {
     int32_t mode;

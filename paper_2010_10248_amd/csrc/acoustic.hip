@@ -57,9 +57,10 @@ __global__ void adj_inject_kernel(const float *__restrict__ res, int nt, int nre
 
 }  // namespace
 
-tb_status launch_acoustic(const tb_model *m, const TileGeom &g, const TileLists &tl,
-                          const AcLaunch &a, hipStream_t st)
+tb_status launch_acoustic(const tb_model *m, const TileLists &tl, const AcLaunch &a,
+                          hipStream_t st)
 {
+    const TileGeom &g = tl.g;
     AcParams p{};
     p.u = a.u;
     p.um = a.um;
@@ -90,28 +91,26 @@ tb_status launch_acoustic(const tb_model *m, const TileGeom &g, const TileLists 
     p.nz = m->n[2];
     p.nzp = m->nzp;
     p.sx = (long long)m->n[1] * m->nzp;
-    p.tiles_y = g.tiles_y;
     p.tiles_z = g.tiles_z;
-    p.chunk = g.chunk;
-    p.nblocks = g.nblocks();
+    p.nwg = g.nwg;
+    p.segs = tl.d_segs;
+    p.seg_off = tl.d_seg_off;
     p.src = tl.d_src;
-    p.src_off = tl.d_src_off;
     p.dcmp = a.dcmp;
     p.npts = a.npts;
     p.n0 = a.n0;
     p.rec = tl.d_rec;
-    p.rec_off = tl.d_rec_off;
     p.rec_dcmp = a.rec_dcmp;
     p.nrid = a.nrid;
     hipError_t e = hipErrorInvalidValue;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (timing_enabled()) timing_begin(st, &ev0, &ev1);
-    if (m->r == 2) e = launch_acoustic_r2(p, g.T, g.BYE, g.nblocks(), st);
-    else if (m->r == 4) e = launch_acoustic_r4(p, g.T, g.BYE, g.nblocks(), st);
+    if (m->r == 2) e = launch_acoustic_r2(p, g.T, g.LZ, g.BYE, st);
+    else if (m->r == 4) e = launch_acoustic_r4(p, g.T, g.LZ, g.BYE, st);
     if (ev0) timing_end(st, ev0, ev1);
     if (e != hipSuccess) {
-        set_error("acoustic kernel launch (R=%d T=%d BYE=%d) failed: %s", m->r, g.T, g.BYE,
-                  hipGetErrorString(e));
+        set_error("acoustic kernel launch (R=%d T=%d LZ=%d BYE=%d) failed: %s", m->r, g.T, g.LZ,
+                  g.BYE, hipGetErrorString(e));
         return TB_EHIP;
     }
     return TB_OK;

@@ -52,8 +52,8 @@ constexpr int kRsrcWord3 = 0x00020000;
 // Byte offset beyond any buffer: loads return 0, stores are discarded.
 constexpr unsigned kNoLane = 0x80000000u;
 
-// LDS row stride in float4 (16 lanes + 2 ring columns + padding).
-constexpr int kLdsRow = 18;
+// LDS row: the lanes, two z-ring columns (and padding) in float4.
+constexpr int kLdsPad = 2;
 // Damping values of the chunk's x range (chunk plus halo) staged in LDS.
 constexpr int kDxCap = kMaxChunk + 32;
 
@@ -142,23 +142,22 @@ struct RingIn {
     f4v yr;
 };
 
-template <int R, int T, int BYE, int PD>
-__global__ void __launch_bounds__(kLanesZ *BYE) acoustic_wavefront(const AcParams p)
+template <int R, int T, int LZ, int BYE, int PD>
+__global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
 {
     constexpr int U = 2 * R + 1;  // window slots: the 2R+1 live planes
     static_assert(U % PD == 0, "prefetch ring must divide the window");
     constexpr int HY = R * (T - 1);
     constexpr int HZ = ((R * (T - 1) + 3) / 4) * 4;
     constexpr int OY = BYE - 2 * HY;
-    constexpr int OZ = kTileZ - 2 * HZ;
-    constexpr int LR = BYE + 2 * R;       // LDS rows per stage (with the y ring)
-    // LDS row: 16 lane columns, then the left and right z ring, padded to
-    // kLdsRow float4 (the row stride decides the bank mapping).
-    constexpr int LC = kLdsRow;
-    static_assert(LC >= kLanesZ + 2, "row must hold the lanes and the z ring");
-    constexpr int NTH = kLanesZ * BYE;
+    constexpr int OZ = 4 * LZ - 2 * HZ;
+    constexpr int LR = BYE + 2 * R;  // LDS rows per stage (with the y ring)
+    // LDS row: LZ lane columns, then the left and right z ring, padded.
+    constexpr int LC = LZ + kLdsPad;
+    constexpr int NTH = LZ * BYE;
     static_assert(OY > 0 && OZ > 0, "tile too small for this depth");
     static_assert(R >= 1 && R <= 4, "radius must be 1..4");
+    static_assert(NTH <= kMaxThreads && LZ <= 32 && BYE <= 32, "workgroup shape");
 
     __shared__ f4v sh[2][T][LR][LC];
     __shared__ int2 s_src[kSrcCap];
@@ -168,44 +167,44 @@ __global__ void __launch_bounds__(kLanesZ *BYE) acoustic_wavefront(const AcParam
     __shared__ float s_dx[kDxCap];
 
     const int tid = threadIdx.x;
-    const int zl = tid & (kLanesZ - 1);
-    const int row = tid >> 4;
+    const int zl = tid % LZ;
+    const int row = tid / LZ;
+    const int rg_col = zl == 0 ? LZ : LZ + 1;
+    const int col_l = zl == 0 ? LZ : zl - 1;  // left z neighbour (or ring)
+    const int col_r = zl == LZ - 1 ? LZ + 1 : zl + 1;
+    const bool has_rg = zl == 0 || zl == LZ - 1;
+    const bool has_yr = tid < 2 * R * LZ;
+    const int yr_lds = row < R ? row : BYE + row;
+    const bool own_rc = row >= HY && row < HY + OY && zl >= HZ / 4 && zl < (HZ + OZ) / 4;
+    const unsigned plane_bytes = (unsigned)(p.sx * 4);
+    const int mykey = row * 32 + zl;
 
-    // XCD-aware tile order: hardware hands consecutive workgroups to the 8
-    // XCDs round-robin; give each XCD a contiguous run of neighbouring tiles
-    // so halo re-reads hit the same L2.
-    const int b = blockIdx.x, nb = p.nblocks;
+    // XCD-aware order: hardware hands consecutive workgroups to the 8 XCDs
+    // round-robin; give each XCD a contiguous run of work (neighbouring
+    // tiles or x ranges) so halo re-reads hit the same L2.
+    const int b = blockIdx.x, nb = p.nwg;
     const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
-    const int L = xcd * q8 + min(xcd, r8) + (b >> 3);
-    const int tz = L % p.tiles_z;
-    const int rest = L / p.tiles_z;
-    const int tyi = rest % p.tiles_y;
-    const int ch = rest / p.tiles_y;
+    const int wg = xcd * q8 + min(xcd, r8) + (b >> 3);
 
+    for (int sg = p.seg_off[wg]; sg < p.seg_off[wg + 1]; sg++) {
+    const SegDesc sd = p.segs[sg];
+    const int tz = sd.tile % p.tiles_z;
+    const int tyi = sd.tile / p.tiles_z;
     const int y0 = tyi * OY - HY, z0 = tz * OZ - HZ;
-    const int xc0 = ch * p.chunk;
-    const int xc1 = min(p.nx, xc0 + p.chunk);
+    const int xc0 = sd.xs, xc1 = sd.xe;
     const int y = y0 + row, z = z0 + 4 * zl;
     const bool yin = (unsigned)y < (unsigned)p.ny;
     const bool zin = z >= 0 && z < p.nzp;
-    const unsigned plane_bytes = (unsigned)(p.sx * 4);
     // In-plane byte offsets (kNoLane for lanes outside the grid).
     const unsigned off_c = (yin && zin) ? (unsigned)((y * p.nzp + z) * 4) : kNoLane;
-    const bool own = row >= HY && row < HY + OY && zl >= HZ / 4 && zl < (HZ + OZ) / 4;
-    const unsigned off_own = own ? off_c : kNoLane;
-    // z ring of stage 0: lane 0 of each row loads z0-4..z0-1, lane 15 loads
-    // z0+64..z0+67 (one float4 covers the radius).
+    const unsigned off_own = own_rc ? off_c : kNoLane;
+    // z ring of stage 0: lane 0 of each row loads z0-4..z0-1, lane LZ-1 loads
+    // the float4 after the tile (one float4 covers the radius).
     const int zr = zl == 0 ? z - 4 : z + 4;
-    const bool rgok = yin && (zl == 0 || zl == kLanesZ - 1) && zr >= 0 && zr < p.nzp;
+    const bool rgok = yin && has_rg && zr >= 0 && zr < p.nzp;
     const unsigned off_rg = rgok ? (unsigned)((y * p.nzp + zr) * 4) : kNoLane;
-    const int rg_col = zl == 0 ? kLanesZ : kLanesZ + 1;
-    const int col_l = zl == 0 ? kLanesZ : zl - 1;  // left z neighbour (or ring)
-    const int col_r = zl == kLanesZ - 1 ? kLanesZ + 1 : zl + 1;
-    const bool has_rg = zl == 0 || zl == kLanesZ - 1;
     // y ring of stage 0: rows y0-R..y0-1 and y0+BYE..y0+BYE+R-1.
-    const bool has_yr = tid < 2 * R * kLanesZ;
     const int yr = row < R ? y0 - R + row : y0 + BYE + row - R;
-    const int yr_lds = row < R ? row : BYE + row;
     const bool yrok = has_yr && (unsigned)yr < (unsigned)p.ny && zin;
     const unsigned off_yr = yrok ? (unsigned)((yr * p.nzp + z) * 4) : kNoLane;
 
@@ -220,6 +219,8 @@ __global__ void __launch_bounds__(kLanesZ *BYE) acoustic_wavefront(const AcParam
     }
     const bool wave_dyz = __builtin_amdgcn_ballot_w64(any_dyz) != 0;
 
+    // The previous segment's readers are done with LDS before it is reused.
+    lds_barrier();
     // Clear the LDS planes so the unused ring rows/columns stay zero.
     for (int k = tid; k < 2 * T * LR * LC; k += NTH)
         (&sh[0][0][0][0])[k] = f4v{0.f, 0.f, 0.f, 0.f};
@@ -235,11 +236,11 @@ __global__ void __launch_bounds__(kLanesZ *BYE) acoustic_wavefront(const AcParam
     const int nxd = hi[0] - lo[0];
     for (int k = tid; k < nxd; k += NTH) s_dx[k] = p.dx[xlo + k];
 
-    // Stage this tile's injection list (with the decomposed wavelet values of
-    // this pass's T steps) and its receiver list in LDS. The host keeps every
-    // tile within the capacities (shorter x chunks otherwise).
-    const int sbeg = p.src_off[L], nsl = p.src_off[L + 1] - sbeg;
-    const int rbeg = p.rec_off[L], nrl = p.rec_off[L + 1] - rbeg;
+    // Stage the segment's injection list (with the decomposed wavelet values
+    // of this pass's T steps) and its receiver list in LDS. The host keeps
+    // every segment within the capacities.
+    const int sbeg = sd.sbeg, nsl = sd.sn;
+    const int rbeg = sd.rbeg, nrl = sd.rn;
     for (int k = tid; k < nsl; k += NTH) {
         const int2 e = p.src[sbeg + k];
         s_src[k] = e;
@@ -251,9 +252,8 @@ __global__ void __launch_bounds__(kLanesZ *BYE) acoustic_wavefront(const AcParam
     // Each lane walks its own entries (sorted by x) with one cursor per stage,
     // so a tick costs one compare per stage unless this lane has a point on
     // the stage's plane.
-    const int mykey = row * 16 + zl;
     auto first_at = [&](const int2 *lst, int n, int x) {
-        const int want = tile_key(row, zl, x, 0);
+        const int want = tile_key(row, zl, x, 0);  // first entry of this lane at >= x
         int a = 0, b2 = n;
         while (a < b2) {
             const int mid = (a + b2) >> 1;
@@ -435,6 +435,7 @@ __global__ void __launch_bounds__(kLanesZ *BYE) acoustic_wavefront(const AcParam
                 p.rec_dcmp[(long long)(p.n0 + s + 1) * p.nrid + id] = s_recv[k][s];
         }
     }
+    }  // segments
 }
 
 // Prefetch depth (ticks of loads in flight): it must divide the window 2R+1,
@@ -449,52 +450,55 @@ constexpr int prefetch_depth()
 }
 static_assert((2 * 4 + 1) % 3 == 0 && (2 * 2 + 1) % 5 == 0, "depth must divide the window");
 
-template <int R, int T, int BYE>
-hipError_t launch_rtb(const AcParams &p, int nblocks, hipStream_t st)
+template <int R, int T, int LZ, int BYE>
+hipError_t launch_shape(const AcParams &p, hipStream_t st)
 {
-    hipLaunchKernelGGL((acoustic_wavefront<R, T, BYE, prefetch_depth<R, T>()>), dim3(nblocks),
-                       dim3(kLanesZ * BYE), 0, st, p);
+    hipLaunchKernelGGL((acoustic_wavefront<R, T, LZ, BYE, prefetch_depth<R, T>()>), dim3(p.nwg),
+                       dim3(LZ * BYE), 0, st, p);
     return hipGetLastError();
 }
 
-// LDS bytes of one workgroup of acoustic_wavefront<R, T, BYE>.
-constexpr int wavefront_lds(int R, int T, int BYE)
+// LDS bytes of one workgroup of acoustic_wavefront<R, T, LZ, BYE>.
+constexpr int wavefront_lds(int R, int T, int LZ, int BYE)
 {
-    return 16 * 2 * T * (BYE + 2 * R) * kLdsRow + kSrcCap * (8 + 4 * T) +
+    return 16 * 2 * T * (BYE + 2 * R) * (LZ + kLdsPad) + kSrcCap * (8 + 4 * T) +
            kRecCap * (8 + 4 * T) + 4 * kDxCap;
 }
 
-// Instantiated shapes: the halo must leave owned rows, LDS must fit, and the
-// register windows of the deeper pipelines must fit in 256 VGPRs.
-template <int R, int T, int BYE>
+// Instantiated shapes: 16-lane tiles of 16 or 32 rows (the shape a schedule
+// may request), and the default shape for (R, T), whose tile owns 64 z.
+template <int R, int T, int LZ, int BYE>
 constexpr bool wavefront_fits()
 {
-    return BYE - 2 * R * (T - 1) > 0 && wavefront_lds(R, T, BYE) <= 160 * 1024 && BYE <= 32 &&
-           (R <= 2 || T <= 3);
+    return BYE - 2 * R * (T - 1) > 0 && wavefront_lds(R, T, LZ, BYE) <= 160 * 1024 &&
+           LZ * BYE <= kMaxThreads;
 }
 
 template <int R, int T>
-hipError_t launch_rt(const AcParams &p, int BYE, int nblocks, hipStream_t st)
+hipError_t launch_rt(const AcParams &p, int LZ, int BYE, hipStream_t st)
 {
-    switch (BYE) {
-    case 16:
-        if constexpr (wavefront_fits<R, T, 16>()) return launch_rtb<R, T, 16>(p, nblocks, st);
-        break;
-    case 32:
-        if constexpr (wavefront_fits<R, T, 32>()) return launch_rtb<R, T, 32>(p, nblocks, st);
-        break;
+    constexpr int HZ = ((R * (T - 1) + 3) / 4) * 4;
+    constexpr int DLZ = 16 + HZ / 2;                  // default lanes per row
+    constexpr int DBYE = (kMaxThreads / DLZ) & ~3;    // default rows
+    if (LZ == 16 && BYE == 16) {
+        if constexpr (wavefront_fits<R, T, 16, 16>()) return launch_shape<R, T, 16, 16>(p, st);
+    } else if (LZ == 16 && BYE == 32) {
+        if constexpr (wavefront_fits<R, T, 16, 32>()) return launch_shape<R, T, 16, 32>(p, st);
+    } else if (LZ == DLZ && BYE == DBYE) {
+        if constexpr (DLZ != 16 && wavefront_fits<R, T, DLZ, DBYE>())
+            return launch_shape<R, T, DLZ, DBYE>(p, st);
     }
     return hipErrorInvalidValue;
 }
 
 template <int R>
-hipError_t launch_r(const AcParams &p, int T, int BYE, int nblocks, hipStream_t st)
+hipError_t launch_r(const AcParams &p, int T, int LZ, int BYE, hipStream_t st)
 {
     switch (T) {
-    case 1: return launch_rt<R, 1>(p, BYE, nblocks, st);
-    case 2: return launch_rt<R, 2>(p, BYE, nblocks, st);
-    case 3: return launch_rt<R, 3>(p, BYE, nblocks, st);
-    case 4: return launch_rt<R, 4>(p, BYE, nblocks, st);
+    case 1: return launch_rt<R, 1>(p, LZ, BYE, st);
+    case 2: return launch_rt<R, 2>(p, LZ, BYE, st);
+    case 3: return launch_rt<R, 3>(p, LZ, BYE, st);
+    case 4: return launch_rt<R, 4>(p, LZ, BYE, st);
     }
     return hipErrorInvalidValue;
 }

@@ -20,21 +20,21 @@ struct AcParams {
     float wx[4], wy[4], wz[4];
     int nx, ny, nz, nzp;
     long long sx;  // plane stride ny * nzp
-    int tiles_y, tiles_z, chunk, nblocks;
+    int tiles_z, nwg;
+    const SegDesc *__restrict__ segs;
+    const int *__restrict__ seg_off;
     const int2 *__restrict__ src;
-    const int *__restrict__ src_off;
     const float *__restrict__ dcmp;
     int npts, n0;
     const int2 *__restrict__ rec;
-    const int *__restrict__ rec_off;
     float *rec_dcmp;
     int nrid;
 };
 
 // Launchers of the wave-front kernel for one stencil radius (one translation
 // unit per radius so the instantiations compile in parallel).
-hipError_t launch_acoustic_r2(const AcParams &p, int T, int BYE, int nblocks, hipStream_t st);
-hipError_t launch_acoustic_r4(const AcParams &p, int T, int BYE, int nblocks, hipStream_t st);
+hipError_t launch_acoustic_r2(const AcParams &p, int T, int LZ, int BYE, hipStream_t st);
+hipError_t launch_acoustic_r4(const AcParams &p, int T, int LZ, int BYE, hipStream_t st);
 
 // Optional per-launch event timing of the propagation kernels.
 bool timing_enabled();

@@ -3,9 +3,9 @@
 
 namespace tbw {
 
-hipError_t launch_acoustic_r2(const AcParams &p, int T, int BYE, int nblocks, hipStream_t st)
+hipError_t launch_acoustic_r2(const AcParams &p, int T, int LZ, int BYE, hipStream_t st)
 {
-    return wf::launch_r<2>(p, T, BYE, nblocks, st);
+    return wf::launch_r<2>(p, T, LZ, BYE, st);
 }
 
 }  // namespace tbw

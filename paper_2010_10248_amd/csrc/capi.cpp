@@ -69,12 +69,16 @@ tb_status upload(T **dst, const std::vector<T> &src)
 }
 
 struct SchedChoice {
-    int T, BYE, chunk;
+    int T, tile_y, chunk, wgs_per_cu;
 };
 
 tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice *out)
 {
-    SchedChoice c{2, 32, 0};
+    // Default: two steps per pass on 32-row tiles; on long x axes, 64-plane
+    // chunks dispatched chunk-major, so that workgroups resident together
+    // cover neighbouring tiles of the same x range and share halo reads in
+    // L2. Short axes use the even partition of the tile-x space.
+    SchedChoice c{2, 32, m->n[0] >= 256 ? 64 : 0, 2};
     if (s) {
         if (s->mode == TB_SCHED_SB) c.T = 1;
         else if (s->mode == TB_SCHED_TB) c.T = s->time_tile;
@@ -82,28 +86,23 @@ tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice 
             set_error("schedule mode %d unknown", s->mode);
             return TB_EINVAL;
         }
-        if (s->tile_y) c.BYE = s->tile_y;
+        c.tile_y = s->tile_y;
         c.chunk = s->chunk_x;
-    } else {
-        // Tuned default for large grids: two steps per pass.
-        c.T = 2;
-        c.BYE = 32;
-        c.chunk = m->n[0] >= 256 ? 128 : 0;
     }
     if (c.T < 1 || c.T > 4) {
         set_error("time_tile %d not in 1..4", c.T);
-        return TB_EUNSUPPORTED;
-    }
-    if (c.BYE != 16 && c.BYE != 32) {
-        set_error("tile_y %d not in {16, 32}", c.BYE);
         return TB_EUNSUPPORTED;
     }
     if (m->r == 4 && c.T > 3) {
         set_error("time_tile %d exceeds 3 at space order 8", c.T);
         return TB_EUNSUPPORTED;
     }
-    if (c.BYE - 2 * m->r * (c.T - 1) <= 0) {
-        set_error("tile_y %d too small for time_tile %d at radius %d", c.BYE, c.T, m->r);
+    if (c.tile_y != 0 && c.tile_y != 16 && c.tile_y != 32) {
+        set_error("tile_y %d not in {0 (default), 16, 32}", c.tile_y);
+        return TB_EUNSUPPORTED;
+    }
+    if (c.tile_y != 0 && c.tile_y - 2 * m->r * (c.T - 1) <= 0) {
+        set_error("tile_y %d too small for time_tile %d at radius %d", c.tile_y, c.T, m->r);
         return TB_EUNSUPPORTED;
     }
     if (c.chunk < 0) {
@@ -114,24 +113,52 @@ tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice 
     return TB_OK;
 }
 
-// Cached per-tile lists for (direction, T, BYE, chunk).
-tb_status get_lists(const tb_model *m, tb_sparse *s, int adjoint, const TileGeom &g,
-                    TileLists **out)
+// Cached per-segment lists for (direction, T, tile_y, chunk, workgroups).
+tb_status get_lists(const tb_model *m, tb_sparse *s, int adjoint, int T, int tile_y, int chunk,
+                    int wgs, TileLists **out)
 {
     std::lock_guard<std::mutex> lk(s->mu);
-    auto key = std::make_tuple(adjoint, g.T, g.BYE, g.chunk);
+    auto key = std::make_tuple(adjoint, T, tile_y, chunk, wgs);
     auto it = s->tiles.find(key);
     if (it != s->tiles.end()) {
         *out = it->second.get();
         return TB_OK;
     }
     auto tl = std::make_unique<TileLists>();
-    tb_status st = adjoint ? build_tile_lists(m, s->rid_nodes, s->src_nodes, g, tl.get())
-                           : build_tile_lists(m, s->src_nodes, s->rid_nodes, g, tl.get());
+    tl->g = make_geom(m->r, T, tile_y, chunk, wgs, m->n[0], m->n[1], m->n[2]);
+    if (tl->g.nwg == 0) {
+        set_error("empty tile geometry");
+        return TB_EINVAL;
+    }
+    tb_status st = adjoint ? build_tile_lists(m, s->rid_nodes, s->src_nodes, tl.get())
+                           : build_tile_lists(m, s->src_nodes, s->rid_nodes, tl.get());
     if (st) return st;
     *out = tl.get();
     s->tiles[key] = std::move(tl);
     return TB_OK;
+}
+
+// Lists of the schedule with every segment within the kernel's LDS list
+// capacities: denser sparse sets get shorter segments.
+tb_status lists_for(const tb_model *m, tb_sparse *s, int adjoint, const SchedChoice &sc, int T,
+                    TileLists **out)
+{
+    int chunk = sc.chunk, wgs = m->ncu * sc.wgs_per_cu;
+    for (;;) {
+        tb_status st = get_lists(m, s, adjoint, T, sc.tile_y, chunk, wgs, out);
+        if (st) return st;
+        if ((*out)->max_src <= kSrcCap && (*out)->max_rec <= kRecCap) return TB_OK;
+        if (chunk > 0) {
+            if (chunk == 1) break;
+            chunk = (chunk + 1) / 2;
+        } else {
+            if (wgs >= m->n[0] * 64) break;
+            wgs *= 2;
+        }
+    }
+    set_error("a single plane of one tile holds more sparse points than the kernel capacity "
+              "(%d / %d)", kSrcCap, kRecCap);
+    return TB_EUNSUPPORTED;
 }
 
 size_t field_bytes(const tb_model *m) { return align256(m->field_elems() * sizeof(float)); }
@@ -154,19 +181,8 @@ tb_status time_loop(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int 
     int n = 0;
     while (n < nt) {
         const int T = std::min(sc.T, nt - n);
-        TileGeom g = make_geom(m->r, T, sc.BYE, sc.chunk, m->n[0], m->n[1], m->n[2]);
         TileLists *tl = nullptr;
-        if ((rc = get_lists(m, s, adjoint, g, &tl))) return rc;
-        // Tiles whose lists exceed the LDS capacities run with shorter chunks.
-        while (tl->max_src > kSrcCap || tl->max_rec > kRecCap) {
-            if (g.chunk <= 1) {
-                set_error("a single plane of one tile holds more sparse points than the "
-                          "kernel capacity (%d / %d)", kSrcCap, kRecCap);
-                return TB_EUNSUPPORTED;
-            }
-            g = make_geom(m->r, T, sc.BYE, (g.chunk + 1) / 2, m->n[0], m->n[1], m->n[2]);
-            if ((rc = get_lists(m, s, adjoint, g, &tl))) return rc;
-        }
+        if ((rc = lists_for(m, s, adjoint, sc, T, &tl))) return rc;
         AcLaunch a{};
         a.u = F[cur];
         a.um = F[prev];
@@ -185,7 +201,7 @@ tb_status time_loop(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int 
             a.out0 = F[f0];
             a.out1 = F[f1];
         }
-        if ((rc = launch_acoustic(m, g, *tl, a, st))) return rc;
+        if ((rc = launch_acoustic(m, *tl, a, st))) return rc;
         if (T == 1) {
             std::swap(cur, prev);
         } else {
@@ -263,6 +279,8 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
     m->dt = d->dt;
     m->nt = d->nt;
     TB_HIP(hipGetDevice(&m->device));
+    TB_HIP(hipDeviceGetAttribute(&m->ncu, hipDeviceAttributeMultiprocessorCount, m->device));
+    if (m->ncu < 1) m->ncu = 1;
 
     const size_t N = (size_t)nx * ny * nz;
     std::vector<float> vp(N);

@@ -109,83 +109,107 @@ static void node_xyz(int64_t r, const int n[3], int *x, int *y, int *z)
     *x = (int)(q / n[1]);
 }
 
-TileGeom make_geom(int R, int T, int BYE, int chunk, int nx, int ny, int nz)
+// Default tile width for (R, T): enough lanes that a tile owns 64 z after
+// removing its halo of HZ columns on each side (so 64-multiples of nz are
+// covered without a ragged last tile); rows fill one 512-thread workgroup.
+TileGeom make_geom(int R, int T, int tile_y, int chunk, int wgs, int nx, int ny, int nz)
 {
     TileGeom g;
     g.R = R;
     g.T = T;
-    g.BYE = BYE;
     g.HY = R * (T - 1);
     g.HZ = ((R * (T - 1) + 3) / 4) * 4;
-    g.OY = BYE - 2 * g.HY;
-    g.OZ = kTileZ - 2 * g.HZ;
-    g.chunk = (chunk <= 0 || chunk > nx) ? nx : chunk;
-    if (g.chunk > kMaxChunk) g.chunk = kMaxChunk;
+    if (tile_y > 0) {
+        g.LZ = 16;
+        g.BYE = tile_y;
+    } else {
+        g.LZ = 16 + g.HZ / 2;
+        g.BYE = (kMaxThreads / g.LZ) & ~3;
+    }
+    g.OY = g.BYE - 2 * g.HY;
+    g.OZ = 4 * g.LZ - 2 * g.HZ;
     g.tiles_y = g.OY > 0 ? (ny + g.OY - 1) / g.OY : 0;
     g.tiles_z = g.OZ > 0 ? (nz + g.OZ - 1) / g.OZ : 0;
-    g.nchunks = (nx + g.chunk - 1) / g.chunk;
+    const int nt = g.ntiles();
+    g.segs.clear();
+    g.seg_off.assign(1, 0);
+    if (nt == 0) return g;
+    if (chunk > 0) {
+        // One workgroup per (chunk of x, tile), chunk-major so that the
+        // workgroups running together stream the same x range of
+        // neighbouring tiles.
+        g.chunk = std::min(std::min(chunk, nx), kMaxChunk);
+        for (int x0 = 0; x0 < nx; x0 += g.chunk)
+            for (int t = 0; t < nt; t++) {
+                g.segs.push_back(SegDesc{t, x0, std::min(nx, x0 + g.chunk), 0, 0, 0, 0, 0});
+                g.seg_off.push_back((int)g.segs.size());
+            }
+    } else {
+        // Even partition of the (tile, x) space over `wgs` workgroups: each
+        // workgroup streams one contiguous range, split where it crosses a
+        // tile boundary (or exceeds the longest chunk).
+        g.chunk = 0;
+        const long long W = (long long)nt * nx;
+        const int nwg = (int)std::max<long long>(1, std::min<long long>(wgs, W));
+        for (int b = 0; b < nwg; b++) {
+            long long a = W * b / nwg, e = W * (b + 1) / nwg;
+            while (a < e) {
+                const int t = (int)(a / nx), x0 = (int)(a % nx);
+                const int x1 = (int)std::min<long long>({(long long)nx, x0 + (e - a),
+                                                          (long long)x0 + kMaxChunk});
+                g.segs.push_back(SegDesc{t, x0, x1, 0, 0, 0, 0, 0});
+                a += x1 - x0;
+            }
+            g.seg_off.push_back((int)g.segs.size());
+        }
+    }
+    g.nwg = (int)g.seg_off.size() - 1;
     return g;
 }
 
 TileLists::~TileLists()
 {
     if (d_src) (void)hipFree(d_src);
-    if (d_src_off) (void)hipFree(d_src_off);
     if (d_rec) (void)hipFree(d_rec);
-    if (d_rec_off) (void)hipFree(d_rec_off);
+    if (d_segs) (void)hipFree(d_segs);
+    if (d_seg_off) (void)hipFree(d_seg_off);
 }
 
-// Tile index of (chunk, tile_y, tile_z), z fastest: the kernels decode it the
-// same way.
-static inline int tile_index(const TileGeom &g, int ch, int ty, int tz)
-{
-    return (ch * g.tiles_y + ty) * g.tiles_z + tz;
-}
+// Tile index of (tile_y, tile_z), z fastest; the kernels decode it the same way.
+static inline int tile_index(const TileGeom &g, int ty, int tz) { return ty * g.tiles_z + tz; }
 
+// Bin points by tile: inj points into every tile whose extended region
+// (rows [0, BYE), columns [0, 4 LZ)) holds them, rec points into the tile
+// that owns them. Entries carry x in the key; segments select by x later.
 static void bin_points(const TileGeom &g, const int n[3], const std::vector<int64_t> &nodes,
                        bool owned_only, std::vector<std::vector<int2>> *bins)
 {
-    const int halo_x = g.R * (g.T - 1);
+    const int EZ = 4 * g.LZ;
     for (size_t id = 0; id < nodes.size(); id++) {
         int x, y, z;
         node_xyz(nodes[id], n, &x, &y, &z);
-        // Candidate tiles along each axis.
-        int ty_lo, ty_hi, tz_lo, tz_hi, ch_lo, ch_hi;
+        int ty_lo, ty_hi, tz_lo, tz_hi;
         if (owned_only) {
             ty_lo = ty_hi = y / g.OY;
             tz_lo = tz_hi = z / g.OZ;
-            ch_lo = ch_hi = x / g.chunk;
         } else {
             // tile t covers rows [t*OY - HY, t*OY - HY + BYE); the exact test
             // is applied below, this only bounds the candidates.
             ty_hi = std::min(g.tiles_y - 1, (y + g.HY) / g.OY);
             ty_lo = std::max(0, ty_hi - (g.BYE / g.OY + 2));
             tz_hi = std::min(g.tiles_z - 1, (z + g.HZ) / g.OZ);
-            tz_lo = std::max(0, tz_hi - (kTileZ / g.OZ + 2));
-            ch_lo = 0;
-            ch_hi = g.nchunks - 1;
+            tz_lo = std::max(0, tz_hi - (EZ / g.OZ + 2));
         }
-        for (int ch = ch_lo; ch <= ch_hi; ch++) {
-            int xc0 = ch * g.chunk, xc1 = std::min(n[0], xc0 + g.chunk);
-            if (owned_only) {
-                if (x < xc0 || x >= xc1) continue;
-            } else if (x < xc0 - halo_x || x >= xc1 + halo_x) {
+        for (int ty = ty_lo; ty <= ty_hi; ty++) {
+            const int row = y - (ty * g.OY - g.HY);
+            if (owned_only ? (row < g.HY || row >= g.HY + g.OY) : (row < 0 || row >= g.BYE))
                 continue;
-            }
-            for (int ty = ty_lo; ty <= ty_hi; ty++) {
-                int y0 = ty * g.OY - g.HY;
-                int row = y - y0;
-                if (owned_only ? (row < g.HY || row >= g.HY + g.OY) : (row < 0 || row >= g.BYE))
+            for (int tz = tz_lo; tz <= tz_hi; tz++) {
+                const int col = z - (tz * g.OZ - g.HZ);
+                if (owned_only ? (col < g.HZ || col >= g.HZ + g.OZ) : (col < 0 || col >= EZ))
                     continue;
-                for (int tz = tz_lo; tz <= tz_hi; tz++) {
-                    int z0 = tz * g.OZ - g.HZ;
-                    int col = z - z0;
-                    if (owned_only ? (col < g.HZ || col >= g.HZ + g.OZ)
-                                   : (col < 0 || col >= kTileZ))
-                        continue;
-                    (*bins)[tile_index(g, ch, ty, tz)].push_back(
-                        make_int2(tile_key(row, col >> 2, x, col & 3), (int)id));
-                }
+                (*bins)[tile_index(g, ty, tz)].push_back(
+                    make_int2(tile_key(row, col >> 2, x, col & 3), (int)id));
             }
         }
     }
@@ -193,37 +217,51 @@ static void bin_points(const TileGeom &g, const int n[3], const std::vector<int6
         std::sort(b.begin(), b.end(), [](const int2 &a, const int2 &c) { return a.x < c.x; });
 }
 
-static tb_status upload_csr(const std::vector<std::vector<int2>> &bins, int2 **d_list,
-                            int **d_off, int *count, int *longest)
+template <class T>
+static tb_status upload_vec(T **d, const std::vector<T> &v)
 {
-    std::vector<int> off(bins.size() + 1, 0);
-    *longest = 0;
-    for (size_t t = 0; t < bins.size(); t++) {
-        off[t + 1] = off[t] + (int)bins[t].size();
-        *longest = std::max(*longest, (int)bins[t].size());
-    }
-    std::vector<int2> flat;
-    flat.reserve(off.back() + 1);
-    for (auto &b : bins) flat.insert(flat.end(), b.begin(), b.end());
-    flat.push_back(make_int2(0x7fffffff, 0));  // sentinel
-    *count = off.back();
-    TB_HIP(hipMalloc(d_list, flat.size() * sizeof(int2)));
-    TB_HIP(hipMemcpy(*d_list, flat.data(), flat.size() * sizeof(int2), hipMemcpyHostToDevice));
-    TB_HIP(hipMalloc(d_off, off.size() * sizeof(int)));
-    TB_HIP(hipMemcpy(*d_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
+    const size_t n = std::max<size_t>(v.size(), 1);
+    TB_HIP(hipMalloc(d, n * sizeof(T)));
+    if (!v.empty()) TB_HIP(hipMemcpy(*d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
     return TB_OK;
 }
 
+// Per-segment lists: the tile's entries whose x lies in the segment's range
+// (extended by the x halo for injection points), kept in key order.
 tb_status build_tile_lists(const tb_model *m, const std::vector<int64_t> &inj,
-                           const std::vector<int64_t> &rec, const TileGeom &g, TileLists *out)
+                           const std::vector<int64_t> &rec, TileLists *out)
 {
-    const int nb = g.nblocks();
-    std::vector<std::vector<int2>> sb(nb), rb(nb);
+    TileGeom &g = out->g;
+    const int nt = g.ntiles();
+    std::vector<std::vector<int2>> sb(nt), rb(nt);
     bin_points(g, m->n, inj, false, &sb);
     bin_points(g, m->n, rec, true, &rb);
-    tb_status st = upload_csr(sb, &out->d_src, &out->d_src_off, &out->nsrc_entries, &out->max_src);
-    if (st) return st;
-    return upload_csr(rb, &out->d_rec, &out->d_rec_off, &out->nrec_entries, &out->max_rec);
+    const int halo_x = g.R * (g.T - 1);
+    std::vector<int2> sflat, rflat;
+    out->max_src = out->max_rec = 0;
+    for (SegDesc &sd : g.segs) {
+        sd.sbeg = (int)sflat.size();
+        for (const int2 &e : sb[sd.tile]) {
+            const int x = (e.x >> 2) & 0xffff;
+            if (x >= sd.xs - halo_x && x < sd.xe + halo_x) sflat.push_back(e);
+        }
+        sd.sn = (int)sflat.size() - sd.sbeg;
+        sd.rbeg = (int)rflat.size();
+        for (const int2 &e : rb[sd.tile]) {
+            const int x = (e.x >> 2) & 0xffff;
+            if (x >= sd.xs && x < sd.xe) rflat.push_back(e);
+        }
+        sd.rn = (int)rflat.size() - sd.rbeg;
+        out->max_src = std::max(out->max_src, sd.sn);
+        out->max_rec = std::max(out->max_rec, sd.rn);
+    }
+    out->nsrc_entries = (int)sflat.size();
+    out->nrec_entries = (int)rflat.size();
+    tb_status st;
+    if ((st = upload_vec(&out->d_src, sflat)) || (st = upload_vec(&out->d_rec, rflat)) ||
+        (st = upload_vec(&out->d_segs, g.segs)) || (st = upload_vec(&out->d_seg_off, g.seg_off)))
+        return st;
+    return TB_OK;
 }
 
 }  // namespace tbw

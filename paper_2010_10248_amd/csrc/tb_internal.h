@@ -27,9 +27,9 @@ void set_error(const char *fmt, ...);
         }                                                                              \
     } while (0)
 
-// Workgroup z extent of the acoustic kernels: 16 lanes, 4 consecutive z each.
-constexpr int kTileZ = 64;
-constexpr int kLanesZ = 16;
+// Each lane of the acoustic kernels holds 4 consecutive z as one float4; a
+// tile row has LZ lanes (16, 18 or 20).
+constexpr int kMaxThreads = 512;
 // Longest x chunk one workgroup streams (its damping values sit in LDS).
 constexpr int kMaxChunk = 2048;
 // Per-tile list capacities (the lists are staged in LDS); a schedule whose
@@ -37,32 +37,50 @@ constexpr int kMaxChunk = 2048;
 constexpr int kSrcCap = 512;
 constexpr int kRecCap = 2048;
 
-// A list entry: key = ((row*16 + lane) << 18) | (x << 2) | k, with k the z
+// A list entry: key = ((row*32 + lane) << 18) | (x << 2) | k, with k the z
 // component inside the lane's float4; id = point ID. Sorted by key, so each
 // lane's entries are contiguous and ordered by x.
 __host__ __device__ inline int tile_key(int row, int lane, int x, int k)
 {
-    return ((row * 16 + lane) << 18) | (x << 2) | k;
+    return ((row * 32 + lane) << 18) | (x << 2) | k;
 }
+
+// One unit of work of a workgroup: tile `tile` over planes [xs, xe), with the
+// offsets of its injection and receiver lists.
+struct SegDesc {
+    int tile, xs, xe, pad;
+    int sbeg, sn, rbeg, rn;
+};
 
 // Geometry of one schedule (shared by the binning and the launch code).
 struct TileGeom {
-    int R = 0, T = 1, BYE = 32;  // radius, steps per pass, y rows per workgroup
-    int HY = 0, HZ = 0;          // halo rows / halo columns (columns multiple of 4)
-    int OY = 0, OZ = 0;          // owned rows / owned columns per tile
-    int tiles_y = 0, tiles_z = 0, nchunks = 0, chunk = 0;
-    int nblocks() const { return tiles_y * tiles_z * nchunks; }
+    int R = 0, T = 1;
+    int LZ = 16, BYE = 32;  // lanes per tile row, rows per tile
+    int HY = 0, HZ = 0;     // halo rows / halo columns (columns multiple of 4)
+    int OY = 0, OZ = 0;     // owned rows / owned columns per tile
+    int tiles_y = 0, tiles_z = 0;
+    int chunk = 0;          // > 0: one workgroup per (tile, chunk of x)
+    int nwg = 0;            // workgroups of the launch
+    std::vector<SegDesc> segs;  // work segments (list fields filled by binning)
+    std::vector<int> seg_off;   // per workgroup: [seg_off[b], seg_off[b+1])
+    int ntiles() const { return tiles_y * tiles_z; }
 };
-TileGeom make_geom(int R, int T, int BYE, int chunk, int nx, int ny, int nz);
+// Tile shape: tile_y == 0 picks the default for (R, T) (a tile owns 64 z);
+// otherwise 16 lanes and tile_y rows. chunk > 0 gives one workgroup per
+// (tile, chunk of x); chunk == 0 partitions the tile-x space evenly over
+// `wgs` workgroups.
+TileGeom make_geom(int R, int T, int tile_y, int chunk, int wgs, int nx, int ny, int nz);
 
-// Per-tile injection / recording lists in CSR form, entries {key, id}.
+// Per-segment injection / recording lists, entries {key, id}, and the
+// segment table of one schedule geometry.
 struct TileLists {
+    TileGeom g;
     int2 *d_src = nullptr;
-    int *d_src_off = nullptr;
     int2 *d_rec = nullptr;
-    int *d_rec_off = nullptr;
+    SegDesc *d_segs = nullptr;
+    int *d_seg_off = nullptr;
     int nsrc_entries = 0, nrec_entries = 0;
-    int max_src = 0, max_rec = 0;  // longest list of one tile
+    int max_src = 0, max_rec = 0;  // longest list of one segment
     ~TileLists();
 };
 
@@ -78,6 +96,7 @@ struct tb_model {
     int nt = 0;
     double vmax = 0;  // velocity of the damping profile
     int device = 0;
+    int ncu = 1;              // compute units of the device
     float *d_c = nullptr;     // dt^2 vp^2, [nx][ny][nzp]
     float *d_damp = nullptr;  // d_x[nx] | d_y[ny] | d_z[nzp]
     float *d_zero = nullptr;  // 256 zeroed bytes
@@ -114,7 +133,7 @@ struct tb_sparse {
     float *d_rr_w = nullptr;
     float *d_rid_scale = nullptr;  // (c/alpha)(rid node)
     std::mutex mu;
-    std::map<std::tuple<int, int, int, int>, std::unique_ptr<tbw::TileLists>> tiles;
+    std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<tbw::TileLists>> tiles;
     ~tb_sparse();
 };
 
@@ -133,7 +152,7 @@ tb_status build_support(const int n[3], const double h[3], const double o[3], in
 // inj: points injected at every computed copy (extended region); rec: points
 // recorded from the owned copy only.
 tb_status build_tile_lists(const tb_model *m, const std::vector<int64_t> &inj,
-                           const std::vector<int64_t> &rec, const TileGeom &g, TileLists *out);
+                           const std::vector<int64_t> &rec, TileLists *out);
 
 // Kernel launchers (acoustic.hip).
 struct AcLaunch {
@@ -145,8 +164,8 @@ struct AcLaunch {
     float *rec_dcmp;
     int nrid;
 };
-tb_status launch_acoustic(const tb_model *m, const TileGeom &g, const TileLists &tl,
-                          const AcLaunch &a, hipStream_t st);
+tb_status launch_acoustic(const tb_model *m, const TileLists &tl, const AcLaunch &a,
+                          hipStream_t st);
 tb_status launch_fill(float *p, size_t n, float v, hipStream_t st);
 tb_status kernel_timing(int enable);
 tb_status kernel_timing_read(int *n, double *ms);
