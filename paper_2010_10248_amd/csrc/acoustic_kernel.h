@@ -125,14 +125,35 @@ __device__ __forceinline__ float point_update(const AcParams &p, float ctr, cons
     }
 }
 
-// Side inputs of one tick. The HBM-bound ones are loaded PD ticks ahead into
-// a register ring; the ones the caches mostly serve (halo rings, c planes of
-// the later stages, read R*s ticks earlier by stage 0) one tick ahead.
-template <int T>
+// LDS bytes of the stage planes, sparse lists and damping table of one
+// workgroup of acoustic_wavefront<R, T, LZ, BYE>.
+constexpr int wavefront_lds_base(int R, int T, int LZ, int BYE)
+{
+    return 16 * 2 * T * (BYE + 2 * R) * (LZ + kLdsPad) + kSrcCap * (8 + 4 * T) +
+           kRecCap * (8 + 4 * T) + 4 * kDxCap;
+}
+// Slots of the c ring: stage s reads the c plane stage 0 loaded R*s ticks
+// earlier; two spare slots keep each overwrite a barrier behind the last read.
+constexpr int cring_slots(int R, int T, int LZ, int BYE)
+{
+    const int ns = R * (T - 1) + 2;
+    return (T > 1 && wavefront_lds_base(R, T, LZ, BYE) + 16 * ns * BYE * LZ <= 160 * 1024) ? ns
+                                                                                            : 0;
+}
+constexpr int wavefront_lds(int R, int T, int LZ, int BYE)
+{
+    return wavefront_lds_base(R, T, LZ, BYE) + 16 * cring_slots(R, T, LZ, BYE) * BYE * LZ;
+}
+
+// Side inputs of one tick, loaded PD ticks ahead into a register ring: the
+// newest u^n plane, u^{n-1} at the stage-0 centre, and c at the centre plane
+// of stage 0 (NC == 1, later stages take it from the LDS c ring) or of every
+// stage (NC == T, when the ring does not fit).
+template <int NC>
 struct FarIn {
-    f4v u;     // u^n at the newest plane i (enters the stage-0 window)
-    f4v um;    // u^{n-1} at the stage-0 centre plane
-    f4v c[T];  // c at every stage's centre plane
+    f4v u;
+    f4v um;
+    f4v c[NC];
 };
 // Halo rings of stage 0 (z ring: lanes 0 and 15; y ring: threads < 2R*16),
 // mostly served by the caches: loaded right after a tick's barrier for the
@@ -158,6 +179,8 @@ __global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
     static_assert(OY > 0 && OZ > 0, "tile too small for this depth");
     static_assert(R >= 1 && R <= 4, "radius must be 1..4");
     static_assert(NTH <= kMaxThreads && LZ <= 32 && BYE <= 32, "workgroup shape");
+    constexpr int NS = cring_slots(R, T, LZ, BYE);
+    constexpr int NC = NS ? 1 : T;
 
     __shared__ f4v sh[2][T][LR][LC];
     __shared__ int2 s_src[kSrcCap];
@@ -165,6 +188,7 @@ __global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
     __shared__ int2 s_rec[kRecCap];
     __shared__ float s_recv[kRecCap][T];
     __shared__ float s_dx[kDxCap];
+    __shared__ f4v s_c[NS ? NS : 1][NS ? BYE : 1][NS ? LZ : 1];
 
     const int tid = threadIdx.x;
     const int zl = tid % LZ;
@@ -292,12 +316,12 @@ __global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
     // Inputs of tick i: the newest plane i of u^n, u^{n-1} at the stage-0
     // centre plane, c at every stage's centre plane (stages >= 1 re-read c
     // planes stage 0 read R*s ticks earlier, which the caches still hold).
-    auto fetch_far = [&](int i, FarIn<T> &f) {
+    auto fetch_far = [&](int i, FarIn<NC> &f) {
         const int c0 = i - R;
         f.u = bload(plane(p.u, i), off_c);
         f.um = bload(plane(p.um, c0), off_c);
 #pragma unroll
-        for (int s = 0; s < T; s++) {
+        for (int s = 0; s < NC; s++) {
             const int cs = c0 - R * s;
             f.c[s] = bload(plane(p.c, (cs >= lo[s] && cs < hi[s]) ? cs : -1), off_c);
         }
@@ -307,7 +331,7 @@ __global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
         f.rg = bload(ru, off_rg);
         f.yr = bload(ru, off_yr);
     };
-    FarIn<T> pf[PD];
+    FarIn<NC> pf[PD];
     RingIn rgn;
     static_for<0, PD>([&](auto KC) {
         constexpr int k = decltype(KC)::value;
@@ -318,6 +342,7 @@ __global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
 
     int i = i0;
     int tick = 0;
+    int cslot = 0;
     while (i <= ilast) {
         static_for<0, U>([&](auto PC) {
             constexpr int P = PC.value;
@@ -326,13 +351,14 @@ __global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
             constexpr int OLD = P % U;
             constexpr int NEW = (P + 2 * R) % U;
             if (i > ilast) return;
-            const FarIn<T> &in = pf[SLOT];
+            const FarIn<NC> &in = pf[SLOT];
             q[0][NEW] = in.u;
             const int buf = tick & 1;
 #pragma unroll
             for (int s = 0; s < T; s++) sh[buf][s][row + R][zl] = q[s][CTR];
             if (has_rg) sh[buf][0][row + R][rg_col] = rgn.rg;
             if (has_yr) sh[buf][0][yr_lds][zl] = rgn.yr;
+            if constexpr (NS > 0) s_c[cslot][row][zl] = in.c[0];
             lds_barrier();
             fetch_ring(i + 1, rgn);
 
@@ -343,7 +369,13 @@ __global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
                 if (cs >= lo[s] && cs < hi[s]) {
                     const f4v ctr = q[s][CTR];
                     const f4v prev = (s == 0) ? in.um : q[s > 0 ? s - 1 : 0][OLD];
-                    const f4v cf = in.c[s];
+                    f4v cf;
+                    if constexpr (NS > 0 && s > 0) {
+                        const int sl = cslot - R * s;
+                        cf = s_c[sl < 0 ? sl + NS : sl][row][zl];
+                    } else {
+                        cf = in.c[NS > 0 ? 0 : s];
+                    }
                     const f4v zl4 = sh[buf][s][row + R][col_l];
                     const f4v zr4 = sh[buf][s][row + R][col_r];
                     float zw[12];
@@ -422,6 +454,7 @@ __global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
             fetch_far(i + PD, pf[SLOT]);
             i++;
             tick++;
+            if constexpr (NS > 0) cslot = cslot + 1 == NS ? 0 : cslot + 1;
         });
     }
     if (nrl > 0) {
@@ -456,13 +489,6 @@ hipError_t launch_shape(const AcParams &p, hipStream_t st)
     hipLaunchKernelGGL((acoustic_wavefront<R, T, LZ, BYE, prefetch_depth<R, T>()>), dim3(p.nwg),
                        dim3(LZ * BYE), 0, st, p);
     return hipGetLastError();
-}
-
-// LDS bytes of one workgroup of acoustic_wavefront<R, T, LZ, BYE>.
-constexpr int wavefront_lds(int R, int T, int LZ, int BYE)
-{
-    return 16 * 2 * T * (BYE + 2 * R) * (LZ + kLdsPad) + kSrcCap * (8 + 4 * T) +
-           kRecCap * (8 + 4 * T) + 4 * kDxCap;
 }
 
 // Instantiated shapes: 16-lane tiles of 16 or 32 rows (the shape a schedule
