@@ -184,17 +184,33 @@ tb_status tb_adjoint(const tb_model *m, const tb_sparse *s, const tb_schedule *s
                      size_t ws_bytes, const float *rec_in, float *src_out, void *stream);
 
 /*
- * Gradient of J = 1/2 sum_n |P_r u^n - d_obs^n|^2 with respect to the squared
- * slowness m = 1/vp^2 (damping profile held fixed), by a forward run with
- * checkpoints every checkpoint_every steps (0 = ceil(sqrt(nt))), recompute of
- * each segment and the adjoint run with the imaging condition fused.
- * d_obs[nt][nrec] device; grad_m [nx][ny][nz] device (overwritten);
- * loss_out host (may be NULL; written after the call synchronises the
- * stream). Acoustic only: TB_EUNSUPPORTED otherwise.
+ * Gradient of J = 1/2 sum_{n<nt} |P_r u^n - d_obs^n|^2 with respect to the
+ * squared slowness m = 1/vp^2, the damping profile held fixed (the exact
+ * discrete adjoint of the update of equation (acou); the paper names
+ * full-waveform inversion as the use of the adjoint, Section I, and leaves
+ * its form open). With nu the adjoint wavefield,
+ *   dJ/dm = -(1/dt^2) sum_{k=1}^{nt-1} nu^k (c L u^{k-1} + alpha s^{k-1}),
+ * s^{k-1} the injected increment of step k-1 (which carries the dt^2/m
+ * source scaling). The call runs the forward pass keeping (u^{jK}, u^{jK-1})
+ * every K = checkpoint_every steps (0 = ceil(sqrt(nt)); rounded up to a
+ * multiple of the schedule's time_tile), then for each segment in reverse
+ * recomputes its levels from the checkpoint and runs the adjoint through it,
+ * imaging every level (FP64 accumulation). The recomputed levels are
+ * bit-identical to the forward ones, so K does not change the result.
+ * d_obs[nt][nrec] device; grad_m [nx][ny][nz] device FP32 (overwritten);
+ * loss_out host (may be NULL; when given, the call synchronises the stream to
+ * write it). ws must hold tb_gradient_workspace_size(checkpoint_every) bytes
+ * (tb_workspace_size(TB_OP_GRADIENT) is the size for checkpoint_every = 0).
+ * Errors: TB_EINVAL, TB_EWORKSPACE, TB_EUNSUPPORTED, TB_EHIP.
  */
 tb_status tb_gradient(const tb_model *m, const tb_sparse *s, const tb_schedule *sched, void *ws,
                       size_t ws_bytes, const float *d_obs, float *grad_m, double *loss_out,
                       int32_t checkpoint_every, void *stream);
+
+/* Bytes of workspace tb_gradient needs for a given checkpoint interval. */
+tb_status tb_gradient_workspace_size(const tb_model *m, const tb_sparse *s,
+                                     const tb_schedule *sched, int32_t checkpoint_every,
+                                     size_t *bytes);
 
 /*
  * Kernel timing for measurement. While enabled, every propagation kernel

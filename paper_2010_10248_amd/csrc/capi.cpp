@@ -26,7 +26,8 @@ tb_sparse::~tb_sparse()
     tiles.clear();
     for (void *p : {(void *)d_dcmp, (void *)d_rc_ptr, (void *)d_rc_id, (void *)d_rc_w,
                     (void *)d_sc_ptr, (void *)d_sc_id, (void *)d_sc_w, (void *)d_rr_ptr,
-                    (void *)d_rr_rec, (void *)d_rr_w, (void *)d_rid_scale})
+                    (void *)d_rr_rec, (void *)d_rr_w, (void *)d_rid_scale, (void *)d_src_off,
+                    (void *)d_src_alpha})
         if (p) (void)hipFree(p);
 }
 
@@ -163,6 +164,28 @@ tb_status lists_for(const tb_model *m, tb_sparse *s, int adjoint, const SchedCho
 
 size_t field_bytes(const tb_model *m) { return align256(m->field_elems() * sizeof(float)); }
 
+// One launch of T updates from (u = level n0, um = level n0-1): writes level
+// n0+T to out0 and, for T > 1, level n0+T-1 to out1.
+tb_status step_launch(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int adjoint, int T,
+                      const float *u, const float *um, float *out0, float *out1, int n0,
+                      const float *dcmp, int ninj, float *rec_dcmp, int nrecp, hipStream_t st)
+{
+    TileLists *tl = nullptr;
+    tb_status rc = lists_for(m, s, adjoint, sc, T, &tl);
+    if (rc) return rc;
+    AcLaunch a{};
+    a.u = u;
+    a.um = um;
+    a.out0 = out0;
+    a.out1 = out1;
+    a.n0 = n0;
+    a.dcmp = dcmp;
+    a.npts = ninj;
+    a.rec_dcmp = rec_dcmp;
+    a.nrid = nrecp;
+    return launch_acoustic(m, *tl, a, st);
+}
+
 // Run the propagation time loop: nt updates from zero state in F[0..3],
 // injecting dcmp rows 0..nt-1 at inj points and recording at the nrecp rec
 // points into rec_dcmp rows 1..nt (row 0, the zero initial level, is
@@ -181,27 +204,14 @@ tb_status time_loop(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int 
     int n = 0;
     while (n < nt) {
         const int T = std::min(sc.T, nt - n);
-        TileLists *tl = nullptr;
-        if ((rc = lists_for(m, s, adjoint, sc, T, &tl))) return rc;
-        AcLaunch a{};
-        a.u = F[cur];
-        a.um = F[prev];
-        a.n0 = n;
-        a.dcmp = dcmp;
-        a.npts = ninj;
-        a.rec_dcmp = rec_dcmp;
-        a.nrid = nrecp;
         int f0 = -1, f1 = -1;
-        if (T == 1) {
-            a.out0 = F[prev];  // u^{n+1} overwrites u^{n-1} point by point
-            a.out1 = nullptr;
-        } else {
+        if (T > 1)
             for (int k = 0; k < 4; k++)
                 if (k != cur && k != prev) (f0 < 0 ? f0 : f1) = k;
-            a.out0 = F[f0];
-            a.out1 = F[f1];
-        }
-        if ((rc = launch_acoustic(m, *tl, a, st))) return rc;
+        // T == 1: u^{n+1} overwrites u^{n-1} point by point.
+        if ((rc = step_launch(m, s, sc, adjoint, T, F[cur], F[prev], T == 1 ? F[prev] : F[f0],
+                              T == 1 ? nullptr : F[f1], n, dcmp, ninj, rec_dcmp, nrecp, st)))
+            return rc;
         if (T == 1) {
             std::swap(cur, prev);
         } else {
@@ -213,6 +223,63 @@ tb_status time_loop(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int 
     *cur_out = cur;
     *prev_out = prev;
     return TB_OK;
+}
+
+// Workspace of the gradient (offsets in bytes from the base).
+struct GradLayout {
+    int K = 0;       // checkpoint interval (a multiple of the forward depth)
+    int ncp = 0;     // stored checkpoints (levels jK, jK-1 for j >= 1)
+    int nslot = 0;   // segment slots (levels jK-1 .. jK+K-1)
+    size_t F = 0, A = 0, slots = 0, cps = 0, g = 0, rec = 0, traces = 0, res = 0, adj_dcmp = 0,
+           adj_rec = 0, loss = 0, total = 0;
+};
+
+int ceil_sqrt(int n)
+{
+    int k = (int)std::ceil(std::sqrt((double)n));
+    while (k > 1 && (k - 1) * (k - 1) >= n) k--;
+    return std::max(k, 1);
+}
+
+GradLayout grad_layout(const tb_model *m, const tb_sparse *s, const SchedChoice &sc, int every)
+{
+    GradLayout L;
+    const int nt = m->nt;
+    int K = every > 0 ? every : ceil_sqrt(std::max(nt, 1));
+    K = (K + sc.T - 1) / sc.T * sc.T;
+    L.K = K;
+    // Checkpoints at levels jK for j >= 1 with jK <= nt - 2 (level 0 is zero).
+    L.ncp = nt >= 2 ? (nt - 2) / K : 0;
+    L.nslot = K + 1;
+    const size_t fb = field_bytes(m);
+    const size_t nt1 = (size_t)nt + 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    L.F = take(4 * fb);
+    L.A = take(4 * fb);
+    L.slots = take(L.nslot * fb);
+    L.cps = take(2 * (size_t)L.ncp * fb);
+    L.g = take(m->field_elems() * sizeof(double));
+    L.rec = take(nt1 * std::max(s->nrid, 1) * sizeof(float));
+    L.traces = take((size_t)nt * std::max(s->nrec, 1) * sizeof(float));
+    L.res = take((size_t)nt * std::max(s->nrec, 1) * sizeof(float));
+    L.adj_dcmp = take((size_t)nt * std::max(s->nrid, 1) * sizeof(float));
+    L.adj_rec = take(nt1 * std::max(s->npts, 1) * sizeof(float));
+    L.loss = take(sizeof(double));
+    L.total = o;
+    return L;
+}
+
+// Centred second-derivative weights per axis scaled by h^-2 (FP64).
+void image_weights(const tb_model *m, double w[3][5])
+{
+    const double *d2 = d2_weights(m->so);
+    for (int a = 0; a < 3; a++)
+        for (int j = 0; j < 5; j++) w[a][j] = j <= m->r ? d2[j] / (m->h[a] * m->h[a]) : 0.0;
 }
 
 }  // namespace
@@ -392,6 +459,16 @@ tb_status tb_inspect_sparse(const tb_model *m, int32_t nsrc, const double *src_x
     if ((st = upload(&s->d_rr_ptr, cnt)) || (st = upload(&s->d_rr_rec, rr_rec)) ||
         (st = upload(&s->d_rr_w, rr_w)) || (st = upload(&s->d_rid_scale, scale)))
         return st;
+    // Imaging at the injection points: padded offsets and alpha per SID.
+    std::vector<long long> soff(s->npts);
+    std::vector<double> salpha(s->npts);
+    for (int i = 0; i < s->npts; i++) {
+        const int64_t r = s->src_nodes[i];
+        const int64_t xy = r / nz;
+        soff[i] = (long long)(xy * m->nzp + r % nz);
+        salpha[i] = alpha_at(r);
+    }
+    if ((st = upload(&s->d_src_off, soff)) || (st = upload(&s->d_src_alpha, salpha))) return st;
     *out = s.release();
     return TB_OK;
 }
@@ -428,6 +505,9 @@ tb_status tb_workspace_size(const tb_model *m, const tb_sparse *s, const tb_sche
     case TB_OP_ADJOINT:
         *bytes = 4 * fb + align256(nt1 * std::max(s->npts, 1) * sizeof(float)) +
                  align256((size_t)m->nt * std::max(s->nrid, 1) * sizeof(float));
+        return TB_OK;
+    case TB_OP_GRADIENT:
+        *bytes = grad_layout(m, s, sc, 0).total;
         return TB_OK;
     default:
         set_error("operation %d has no workspace query", op);
@@ -515,14 +595,173 @@ tb_status tb_adjoint(const tb_model *m, const tb_sparse *s_, const tb_schedule *
     return TB_OK;
 }
 
-tb_status tb_gradient(const tb_model *m, const tb_sparse *s, const tb_schedule *sched, void *ws,
+tb_status tb_gradient_workspace_size(const tb_model *m, const tb_sparse *s,
+                                     const tb_schedule *sched, int32_t checkpoint_every,
+                                     size_t *bytes)
+{
+    if (!m || !s || !bytes || checkpoint_every < 0) {
+        set_error("tb_gradient_workspace_size: invalid argument");
+        return TB_EINVAL;
+    }
+    SchedChoice sc;
+    tb_status st = resolve_schedule(m, sched, &sc);
+    if (st) return st;
+    *bytes = grad_layout(m, s, sc, checkpoint_every).total;
+    return TB_OK;
+}
+
+tb_status tb_gradient(const tb_model *m, const tb_sparse *s_, const tb_schedule *sched, void *ws,
                       size_t ws_bytes, const float *d_obs, float *grad_m, double *loss_out,
                       int32_t checkpoint_every, void *stream)
 {
-    (void)m; (void)s; (void)sched; (void)ws; (void)ws_bytes; (void)d_obs; (void)grad_m;
-    (void)loss_out; (void)checkpoint_every; (void)stream;
-    set_error("tb_gradient is not built yet");
-    return TB_EUNSUPPORTED;
+    tb_sparse *s = const_cast<tb_sparse *>(s_);
+    if (!m || !s || s->m != m || !ws || !grad_m || checkpoint_every < 0 ||
+        (s->nrec > 0 && m->nt > 0 && !d_obs)) {
+        set_error("tb_gradient: invalid argument");
+        return TB_EINVAL;
+    }
+    SchedChoice sc;
+    tb_status st = resolve_schedule(m, sched, &sc);
+    if (st) return st;
+    const GradLayout L = grad_layout(m, s, sc, checkpoint_every);
+    if (ws_bytes < L.total) {
+        set_error("workspace %zu bytes < %zu needed", ws_bytes, L.total);
+        return TB_EWORKSPACE;
+    }
+    hipStream_t strm = (hipStream_t)stream;
+    const int nt = m->nt, K = L.K;
+    const size_t fb = field_bytes(m), fe = m->field_elems();
+    char *base = (char *)ws;
+    auto fld = [&](size_t off, int i) { return (float *)(base + off + (size_t)i * fb); };
+    float *F[4] = {fld(L.F, 0), fld(L.F, 1), fld(L.F, 2), fld(L.F, 3)};
+    float *A[4] = {fld(L.A, 0), fld(L.A, 1), fld(L.A, 2), fld(L.A, 3)};
+    double *g = (double *)(base + L.g);
+    float *rec = (float *)(base + L.rec), *traces = (float *)(base + L.traces);
+    float *res = (float *)(base + L.res), *adj_dcmp = (float *)(base + L.adj_dcmp);
+    float *adj_rec = (float *)(base + L.adj_rec);
+    double *loss = (double *)(base + L.loss);
+
+    // 1. Forward run from zero state, keeping (u^{jK}, u^{jK-1}) for j >= 1.
+    for (int k = 0; k < 2; k++)
+        if ((st = launch_fill(F[k], fe, 0.0f, strm))) return st;
+    if (s->nrid > 0 && (st = launch_fill(rec, (size_t)s->nrid, 0.0f, strm))) return st;
+    int cur = 0, prev = 1, n = 0, j = 1;
+    while (n < nt) {
+        const int T = std::min(sc.T, nt - n);
+        int f0 = -1, f1 = -1;
+        if (T > 1)
+            for (int k = 0; k < 4; k++)
+                if (k != cur && k != prev) (f0 < 0 ? f0 : f1) = k;
+        if ((st = step_launch(m, s, sc, 0, T, F[cur], F[prev], T == 1 ? F[prev] : F[f0],
+                              T == 1 ? nullptr : F[f1], n, s->d_dcmp, s->npts, rec, s->nrid,
+                              strm)))
+            return st;
+        if (T == 1) std::swap(cur, prev);
+        else {
+            cur = f0;
+            prev = f1;
+        }
+        n += T;
+        if (j <= L.ncp && n == j * K) {
+            TB_HIP(hipMemcpyAsync(fld(L.cps, 2 * (j - 1)), F[cur], fb, hipMemcpyDeviceToDevice,
+                                  strm));
+            TB_HIP(hipMemcpyAsync(fld(L.cps, 2 * (j - 1) + 1), F[prev], fb,
+                                  hipMemcpyDeviceToDevice, strm));
+            j++;
+        }
+    }
+    // 2. Traces, residual and misfit; the adjoint source.
+    if (s->nrec > 0 && nt > 0)
+        if ((st = launch_trace_reduce(rec, s->nrid, nt, s->d_rc_ptr, s->d_rc_id, s->d_rc_w,
+                                      s->nrec, traces, 0, strm)))
+            return st;
+    if ((st = launch_residual_loss(traces, d_obs, (long long)nt * s->nrec, res, loss, strm)))
+        return st;
+    if (s->nrid > 0 && nt > 0)
+        if ((st = launch_adj_inject(res, nt, s->nrec, s->nrid, s->d_rr_ptr, s->d_rr_rec,
+                                    s->d_rr_w, s->d_rid_scale, adj_dcmp, strm)))
+            return st;
+    // 3. Segments in reverse: recompute levels jK-1 .. e into the slots, then
+    //    run the adjoint through levels e+1 .. jK+1 and image each one.
+    if ((st = launch_zero64(g, fe, strm))) return st;
+    for (int k = 0; k < 2; k++)
+        if ((st = launch_fill(A[k], fe, 0.0f, strm))) return st;
+    if (s->npts > 0 && (st = launch_fill(adj_rec, (size_t)s->npts, 0.0f, strm))) return st;
+    ImageArgs ia{};
+    ia.c = m->d_c;
+    ia.g = g;
+    ia.nx = m->n[0];
+    ia.ny = m->n[1];
+    ia.nz = m->n[2];
+    ia.nzp = m->nzp;
+    ia.r = m->r;
+    image_weights(m, ia.w);
+    const int Td = std::min(sc.T, 2);  // every level of these passes is stored
+    int acur = 0, aprev = 1;
+    for (int seg = L.ncp; seg >= 0 && nt >= 2; seg--) {
+        const int k0 = seg * K;
+        const int e = std::min(k0 + K - 1, nt - 2);
+        float *slot0 = fld(L.slots, 0), *slot1 = fld(L.slots, 1);
+        if (seg == 0) {
+            if ((st = launch_fill(slot0, fe, 0.0f, strm)) || (st = launch_fill(slot1, fe, 0.0f, strm)))
+                return st;
+        } else {
+            TB_HIP(hipMemcpyAsync(slot0, fld(L.cps, 2 * (seg - 1) + 1), fb,
+                                  hipMemcpyDeviceToDevice, strm));
+            TB_HIP(hipMemcpyAsync(slot1, fld(L.cps, 2 * (seg - 1)), fb, hipMemcpyDeviceToDevice,
+                                  strm));
+        }
+        // slot i holds level k0 - 1 + i.
+        for (int nn = k0; nn < e;) {
+            const int T = std::min(Td, e - nn);
+            const int b = nn - k0;
+            if ((st = step_launch(m, s, sc, 0, T, fld(L.slots, b + 1), fld(L.slots, b),
+                                  fld(L.slots, b + 1 + T), T == 1 ? nullptr : fld(L.slots, b + 2),
+                                  nn, s->d_dcmp, s->npts, rec, s->nrid, strm)))
+                return st;
+            nn += T;
+        }
+        // Adjoint step na produces nu^{nt-1-na}.
+        int na = nt - 2 - e;
+        for (int left = e - k0 + 1; left > 0;) {
+            const int T = std::min(Td, left);
+            int f0 = -1, f1 = -1;
+            if (T > 1)
+                for (int k = 0; k < 4; k++)
+                    if (k != acur && k != aprev) (f0 < 0 ? f0 : f1) = k;
+            float *o0 = T == 1 ? A[aprev] : A[f0];
+            float *o1 = T == 1 ? nullptr : A[f1];
+            if ((st = step_launch(m, s, sc, 1, T, A[acur], A[aprev], o0, o1, na, adj_dcmp,
+                                  s->nrid, adj_rec, s->npts, strm)))
+                return st;
+            // Levels of this pass, newest-in-k first.
+            for (int t = 0; t < T; t++) {
+                const int k = nt - 1 - na - t;
+                const float *nu = (t == T - 1) ? o0 : o1;
+                ia.nu = nu;
+                ia.u = fld(L.slots, k - k0);
+                if ((st = launch_image(ia, strm))) return st;
+                if ((st = launch_image_sparse(nu, s->d_dcmp + (size_t)(k - 1) * s->npts, s->npts,
+                                              s->d_src_off, s->d_src_alpha, g, strm)))
+                    return st;
+            }
+            if (T == 1) std::swap(acur, aprev);
+            else {
+                acur = f0;
+                aprev = f1;
+            }
+            na += T;
+            left -= T;
+        }
+    }
+    if ((st = launch_finish_grad(g, grad_m, m->n[0], m->n[1], m->n[2], m->nzp,
+                                 -1.0 / (m->dt * m->dt), strm)))
+        return st;
+    if (loss_out) {
+        TB_HIP(hipMemcpyAsync(loss_out, loss, sizeof(double), hipMemcpyDeviceToHost, strm));
+        TB_HIP(hipStreamSynchronize(strm));
+    }
+    return TB_OK;
 }
 
 }  // extern "C"

@@ -132,6 +132,9 @@ struct tb_sparse {
     int *d_rr_ptr = nullptr, *d_rr_rec = nullptr;
     float *d_rr_w = nullptr;
     float *d_rid_scale = nullptr;  // (c/alpha)(rid node)
+    // Imaging at the injection points: padded offset and alpha of each SID.
+    long long *d_src_off = nullptr;
+    double *d_src_alpha = nullptr;
     std::mutex mu;
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<tbw::TileLists>> tiles;
     ~tb_sparse();
@@ -177,5 +180,21 @@ tb_status launch_unpad(const float *src, float *dst, int nx, int ny, int nz, int
 tb_status launch_adj_inject(const float *res, int nt, int nrec, int nrid, const int *rr_ptr,
                             const int *rr_rec, const float *rr_w, const float *rid_scale,
                             float *dcmp_out, hipStream_t st);
+
+// Gradient kernels (imaging.hip).
+struct ImageArgs {
+    const float *nu, *u, *c;
+    double *g;
+    int nx, ny, nz, nzp, r;
+    double w[3][5];  // centred second-derivative weights per axis, scaled by h^-2
+};
+tb_status launch_residual_loss(const float *d, const float *dobs, long long n, float *res,
+                               double *loss, hipStream_t st);
+tb_status launch_image(const ImageArgs &a, hipStream_t st);
+tb_status launch_image_sparse(const float *nu, const float *s, int npts, const long long *off,
+                              const double *alpha, double *g, hipStream_t st);
+tb_status launch_finish_grad(const double *g, float *out, int nx, int ny, int nz, int nzp,
+                             double scale, hipStream_t st);
+tb_status launch_zero64(double *p, size_t n, hipStream_t st);
 
 }  // namespace tbw

@@ -84,6 +84,9 @@ _SIGNATURES = {
     "tb_gradient": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(Schedule), _vp, ctypes.c_size_t,
                                      _vp, _vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
                                      _vp]),
+    "tb_gradient_workspace_size": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(Schedule),
+                                                    ctypes.c_int32,
+                                                    ctypes.POINTER(ctypes.c_size_t)]),
     "tb_kernel_timing": (ctypes.c_int32, [ctypes.c_int32]),
     "tb_kernel_timing_read": (ctypes.c_int32, [_ip, ctypes.POINTER(ctypes.c_double)]),
     "tb_last_error": (ctypes.c_char_p, []),
@@ -233,7 +236,17 @@ def adjoint(model, sparse, sched, ws, rec_in, src_out, stream=None):
                             _tptr(src_out), _stream(stream)), "tb_adjoint")
 
 
+def gradient_workspace_size(model, sparse, sched: Optional[Schedule], checkpoint_every=0) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().tb_gradient_workspace_size(model, sparse,
+                                            None if sched is None else ctypes.byref(sched),
+                                            int(checkpoint_every), ctypes.byref(b)),
+           "tb_gradient_workspace_size")
+    return b.value
+
+
 def gradient(model, sparse, sched, ws, d_obs, grad_m, checkpoint_every=0, stream=None):
+    """dJ/dm into grad_m; returns J (synchronises the stream)."""
     loss = ctypes.c_double()
     _check(lib().tb_gradient(model, sparse, None if sched is None else ctypes.byref(sched),
                              _tptr(ws), ws.numel() * ws.element_size(), _tptr(d_obs),
@@ -251,7 +264,11 @@ class Acoustic:
         self.shot = shot
         self.device = torch.device(device)
         vp = shot.vp if vp is None else vp
-        self.vp = torch.as_tensor(np.ascontiguousarray(vp, dtype=np.float32), device=self.device)
+        if isinstance(vp, torch.Tensor):
+            self.vp = vp.to(device=self.device, dtype=torch.float32).contiguous()
+        else:
+            self.vp = torch.as_tensor(np.ascontiguousarray(vp, dtype=np.float32),
+                                      device=self.device)
         self.model = create_model(shot.shape, shot.spacing, shot.origin, shot.space_order,
                                   shot.nbl, shot.dt, shot.nt, self.vp, damp_vmax=damp_vmax)
         wav = shot.src_wav if src_wav is None else src_wav
@@ -300,3 +317,19 @@ class Acoustic:
         out = torch.empty((self.shot.nt, self.nsrc), dtype=torch.float32, device=self.device)
         adjoint(self.model, self.sparse, sched, ws, rec_in.contiguous(), out, stream)
         return out
+
+    def gradient(self, d_obs, sched=None, checkpoint_every=0, stream=None):
+        """(J, dJ/dm) for observed traces d_obs [nt][nrec] (CUDA float32)."""
+        import torch
+
+        nb = gradient_workspace_size(self.model, self.sparse, sched, checkpoint_every)
+        key = ("grad", nb)
+        ws = self._ws.get(key)
+        if ws is None:
+            self._ws = {k: v for k, v in self._ws.items() if not (isinstance(k, tuple))}
+            ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        g = torch.empty(self.shot.shape, dtype=torch.float32, device=self.device)
+        J = gradient(self.model, self.sparse, sched, ws, d_obs.contiguous(), g, checkpoint_every,
+                     stream)
+        return J, g
