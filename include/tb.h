@@ -213,6 +213,71 @@ tb_status tb_gradient_workspace_size(const tb_model *m, const tb_sparse *s,
                                      size_t *bytes);
 
 /*
+ * Autotuner (the paper sweeps tile and block sizes per kernel and platform,
+ * Section IV-C / Table 1, and leaves the time-tile depth open). Times every
+ * valid (time_tile, tile_y, chunk_x) on the device for `steps` updates of
+ * this model and sparse set (zero initial state; no output is written),
+ * caches the fastest per (physics, space order, grid shape) for the process,
+ * and returns it. Afterwards a NULL schedule on any model of that key
+ * resolves to the tuned choice. Allocates a temporary four-field workspace.
+ * Errors: TB_EINVAL, TB_ENOMEM, TB_EHIP.
+ */
+tb_status tb_autotune(const tb_model *m, const tb_sparse *s, int32_t steps, void *stream,
+                      tb_schedule *best, double *ms_per_step);
+/* Forget every tuned schedule. */
+tb_status tb_autotune_clear(void);
+
+/*
+ * Serving runtime (continuous batching of shots on one device).
+ *
+ * A request is a forward run (traces) or a checkpointed gradient (the
+ * forward, residual, adjoint and imaging of tb_gradient) on a caller-created
+ * model and sparse set, which must stay alive until the request completes.
+ * Requests queue in submission order; the head is admitted when fewer than
+ * max_active requests run and its workspace fits in the server's device
+ * arena of arena_bytes (allocated once by tb_server_create). Each
+ * tb_server_step runs the pending side actions of every admitted request and
+ * then an epoch of up to 8 rounds in which every admitted request advances by
+ * one propagation pass, the passes of one round that share a kernel shape
+ * forming one batched launch (TB_SERVE_GRAPHS: each epoch structure is
+ * captured once as a hipGraph and replayed). A request's results are
+ * bit-identical to running it alone with tb_forward / tb_gradient and the
+ * same schedule. All work runs on the server's own stream; the call blocks
+ * at most until the epoch before last has started executing. Completed
+ * requests are reported by tb_server_poll (ids and, for gradients, J).
+ * A server is not thread-safe; use one per host thread.
+ */
+typedef struct tb_server tb_server;
+typedef struct {
+    int32_t op;                /* TB_OP_FORWARD or TB_OP_GRADIENT                   */
+    const tb_model *model;
+    const tb_sparse *sparse;
+    const tb_schedule *sched;  /* read at submission; NULL: tuned, else default    */
+    const float *d_obs;        /* gradient: device [nt][nrec]                       */
+    float *rec_out;            /* forward: device [nt][nrec] traces, or NULL        */
+    float *grad_out;           /* gradient: device [nx][ny][nz] dJ/dm               */
+    int32_t checkpoint_every;  /* gradient: as in tb_gradient                       */
+} tb_request;
+
+#define TB_SERVE_GRAPHS 1
+
+tb_status tb_server_create(size_t arena_bytes, int32_t max_active, int32_t flags,
+                           tb_server **out);
+/* Queue a request; *id identifies it in tb_server_poll. TB_EWORKSPACE if its
+ * workspace exceeds the arena. */
+tb_status tb_server_submit(tb_server *sv, const tb_request *rq, int64_t *id);
+/* Admit, run side actions, enqueue one epoch; report running / queued. */
+tb_status tb_server_step(tb_server *sv, int32_t *n_active, int32_t *n_queued);
+/* Up to cap completed requests (device work finished): ids and losses. */
+tb_status tb_server_poll(tb_server *sv, int32_t cap, int64_t *ids, double *losses,
+                         int32_t *n_done);
+/* Counters: epochs, rounds, batched launches, passes batched, graph captures,
+ * graph replays, side actions, completed requests (first n of these 8). */
+tb_status tb_server_stats(const tb_server *sv, int64_t *stats, int32_t n);
+/* Waits for the server's stream, then frees everything it owns. */
+void tb_server_destroy(tb_server *sv);
+
+/*
  * Kernel timing for measurement. While enabled, every propagation kernel
  * launch made by this library (from any thread) is bracketed by HIP events on
  * the stream it is launched on. tb_kernel_timing_read synchronises those

@@ -57,8 +57,7 @@ __global__ void adj_inject_kernel(const float *__restrict__ res, int nt, int nre
 
 }  // namespace
 
-tb_status launch_acoustic(const tb_model *m, const TileLists &tl, const AcLaunch &a,
-                          hipStream_t st)
+AcParams make_params(const tb_model *m, const TileLists &tl, const AcLaunch &a)
 {
     const TileGeom &g = tl.g;
     AcParams p{};
@@ -102,6 +101,14 @@ tb_status launch_acoustic(const tb_model *m, const TileLists &tl, const AcLaunch
     p.rec = tl.d_rec;
     p.rec_dcmp = a.rec_dcmp;
     p.nrid = a.nrid;
+    return p;
+}
+
+tb_status launch_acoustic(const tb_model *m, const TileLists &tl, const AcLaunch &a,
+                          hipStream_t st)
+{
+    const TileGeom &g = tl.g;
+    const AcParams p = make_params(m, tl, a);
     hipError_t e = hipErrorInvalidValue;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (timing_enabled()) timing_begin(st, &ev0, &ev1);
@@ -111,6 +118,25 @@ tb_status launch_acoustic(const tb_model *m, const TileLists &tl, const AcLaunch
     if (e != hipSuccess) {
         set_error("acoustic kernel launch (R=%d T=%d LZ=%d BYE=%d) failed: %s", m->r, g.T, g.LZ,
                   g.BYE, hipGetErrorString(e));
+        return TB_EHIP;
+    }
+    return TB_OK;
+}
+
+tb_status launch_acoustic_batch(int r, const AcParams *d_jobs, const int *d_wgoff, int njobs,
+                                int total_wg, int T, int LZ, int BYE, hipStream_t st,
+                                bool allow_timing)
+{
+    if (njobs == 0 || total_wg == 0) return TB_OK;
+    hipError_t e = hipErrorInvalidValue;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (allow_timing && timing_enabled()) timing_begin(st, &ev0, &ev1);
+    if (r == 2) e = launch_acoustic_batch_r2(d_jobs, d_wgoff, njobs, total_wg, T, LZ, BYE, st);
+    else if (r == 4) e = launch_acoustic_batch_r4(d_jobs, d_wgoff, njobs, total_wg, T, LZ, BYE, st);
+    if (ev0) timing_end(st, ev0, ev1);
+    if (e != hipSuccess) {
+        set_error("batched acoustic kernel launch (R=%d T=%d LZ=%d BYE=%d, %d jobs) failed: %s", r,
+                  T, LZ, BYE, njobs, hipGetErrorString(e));
         return TB_EHIP;
     }
     return TB_OK;

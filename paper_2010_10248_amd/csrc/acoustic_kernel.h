@@ -163,8 +163,10 @@ struct RingIn {
     f4v yr;
 };
 
+// The kernel body for one job: b is the workgroup's index within the job's
+// grid of p.nwg workgroups.
 template <int R, int T, int LZ, int BYE, int PD>
-__global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
+__device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
 {
     constexpr int U = 2 * R + 1;  // window slots: the 2R+1 live planes
     static_assert(U % PD == 0, "prefetch ring must divide the window");
@@ -206,7 +208,7 @@ __global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
     // XCD-aware order: hardware hands consecutive workgroups to the 8 XCDs
     // round-robin; give each XCD a contiguous run of work (neighbouring
     // tiles or x ranges) so halo re-reads hit the same L2.
-    const int b = blockIdx.x, nb = p.nwg;
+    const int nb = p.nwg;
     const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
     const int wg = xcd * q8 + min(xcd, r8) + (b >> 3);
 
@@ -471,6 +473,31 @@ __global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
     }  // segments
 }
 
+template <int R, int T, int LZ, int BYE, int PD>
+__global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
+{
+    wavefront_body<R, T, LZ, BYE, PD>(p, blockIdx.x);
+}
+
+// Several jobs (different grids, sparse sets and time levels) in one launch:
+// job j owns workgroups [wg_off[j], wg_off[j] + jobs[j].nwg); every wg_off[j]
+// is a multiple of 8, so a job's local index keeps the hardware's XCD
+// round-robin, and workgroups of the padding exit at once. Each job
+// evaluates exactly the arithmetic of a launch of its own.
+template <int R, int T, int LZ, int BYE, int PD>
+__global__ void __launch_bounds__(LZ *BYE)
+    acoustic_wavefront_batch(const AcParams *__restrict__ jobs, const int *__restrict__ wg_off,
+                             int njobs)
+{
+    const int bx = blockIdx.x;
+    int j = 0;
+    while (j + 1 < njobs && wg_off[j + 1] <= bx) j++;
+    const AcParams &p = jobs[j];
+    const int b = bx - wg_off[j];
+    if (b >= p.nwg) return;
+    wavefront_body<R, T, LZ, BYE, PD>(p, b);
+}
+
 // Prefetch depth (ticks of loads in flight): it must divide the window 2R+1,
 // and the deeper pipelines keep fewer ticks in flight so their register
 // windows still fit.
@@ -483,14 +510,6 @@ constexpr int prefetch_depth()
 }
 static_assert((2 * 4 + 1) % 3 == 0 && (2 * 2 + 1) % 5 == 0, "depth must divide the window");
 
-template <int R, int T, int LZ, int BYE>
-hipError_t launch_shape(const AcParams &p, hipStream_t st)
-{
-    hipLaunchKernelGGL((acoustic_wavefront<R, T, LZ, BYE, prefetch_depth<R, T>()>), dim3(p.nwg),
-                       dim3(LZ * BYE), 0, st, p);
-    return hipGetLastError();
-}
-
 // Instantiated shapes: 16-lane tiles of 16 or 32 rows (the shape a schedule
 // may request), and the default shape for (R, T), whose tile owns 64 z.
 template <int R, int T, int LZ, int BYE>
@@ -500,19 +519,29 @@ constexpr bool wavefront_fits()
            LZ * BYE <= kMaxThreads;
 }
 
-template <int R, int T>
-hipError_t launch_rt(const AcParams &p, int LZ, int BYE, hipStream_t st)
+// Calls f.template operator()<T, LZ, BYE>() for an instantiated shape.
+template <int R, class F>
+hipError_t dispatch_shape(int T, int LZ, int BYE, F &&f)
 {
-    constexpr int HZ = ((R * (T - 1) + 3) / 4) * 4;
-    constexpr int DLZ = 16 + HZ / 2;                  // default lanes per row
-    constexpr int DBYE = (kMaxThreads / DLZ) & ~3;    // default rows
-    if (LZ == 16 && BYE == 16) {
-        if constexpr (wavefront_fits<R, T, 16, 16>()) return launch_shape<R, T, 16, 16>(p, st);
-    } else if (LZ == 16 && BYE == 32) {
-        if constexpr (wavefront_fits<R, T, 16, 32>()) return launch_shape<R, T, 16, 32>(p, st);
-    } else if (LZ == DLZ && BYE == DBYE) {
-        if constexpr (DLZ != 16 && wavefront_fits<R, T, DLZ, DBYE>())
-            return launch_shape<R, T, DLZ, DBYE>(p, st);
+    auto rt = [&]<int TT>() -> hipError_t {
+        constexpr int HZ = ((R * (TT - 1) + 3) / 4) * 4;
+        constexpr int DLZ = 16 + HZ / 2;                // default lanes per row
+        constexpr int DBYE = (kMaxThreads / DLZ) & ~3;  // default rows
+        if (LZ == 16 && BYE == 16) {
+            if constexpr (wavefront_fits<R, TT, 16, 16>()) return f.template operator()<TT, 16, 16>();
+        } else if (LZ == 16 && BYE == 32) {
+            if constexpr (wavefront_fits<R, TT, 16, 32>()) return f.template operator()<TT, 16, 32>();
+        } else if (LZ == DLZ && BYE == DBYE) {
+            if constexpr (DLZ != 16 && wavefront_fits<R, TT, DLZ, DBYE>())
+                return f.template operator()<TT, DLZ, DBYE>();
+        }
+        return hipErrorInvalidValue;
+    };
+    switch (T) {
+    case 1: return rt.template operator()<1>();
+    case 2: return rt.template operator()<2>();
+    case 3: return rt.template operator()<3>();
+    case 4: return rt.template operator()<4>();
     }
     return hipErrorInvalidValue;
 }
@@ -520,13 +549,22 @@ hipError_t launch_rt(const AcParams &p, int LZ, int BYE, hipStream_t st)
 template <int R>
 hipError_t launch_r(const AcParams &p, int T, int LZ, int BYE, hipStream_t st)
 {
-    switch (T) {
-    case 1: return launch_rt<R, 1>(p, LZ, BYE, st);
-    case 2: return launch_rt<R, 2>(p, LZ, BYE, st);
-    case 3: return launch_rt<R, 3>(p, LZ, BYE, st);
-    case 4: return launch_rt<R, 4>(p, LZ, BYE, st);
-    }
-    return hipErrorInvalidValue;
+    return dispatch_shape<R>(T, LZ, BYE, [&]<int TT, int L, int B>() {
+        hipLaunchKernelGGL((acoustic_wavefront<R, TT, L, B, prefetch_depth<R, TT>()>),
+                           dim3(p.nwg), dim3(L * B), 0, st, p);
+        return hipGetLastError();
+    });
+}
+
+template <int R>
+hipError_t launch_batch_r(const AcParams *jobs, const int *wg_off, int njobs, int total_wg, int T,
+                          int LZ, int BYE, hipStream_t st)
+{
+    return dispatch_shape<R>(T, LZ, BYE, [&]<int TT, int L, int B>() {
+        hipLaunchKernelGGL((acoustic_wavefront_batch<R, TT, L, B, prefetch_depth<R, TT>()>),
+                           dim3(total_wg), dim3(L * B), 0, st, jobs, wg_off, njobs);
+        return hipGetLastError();
+    });
 }
 
 }  // namespace wf

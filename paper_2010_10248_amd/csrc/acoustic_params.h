@@ -35,6 +35,20 @@ struct AcParams {
 // unit per radius so the instantiations compile in parallel).
 hipError_t launch_acoustic_r2(const AcParams &p, int T, int LZ, int BYE, hipStream_t st);
 hipError_t launch_acoustic_r4(const AcParams &p, int T, int LZ, int BYE, hipStream_t st);
+// Batched launch: jobs[njobs] in device memory, wg_off[njobs] (device) the
+// first workgroup of each job (multiples of 8), total_wg the grid size.
+hipError_t launch_acoustic_batch_r2(const AcParams *jobs, const int *wg_off, int njobs,
+                                    int total_wg, int T, int LZ, int BYE, hipStream_t st);
+hipError_t launch_acoustic_batch_r4(const AcParams *jobs, const int *wg_off, int njobs,
+                                    int total_wg, int T, int LZ, int BYE, hipStream_t st);
+
+// Kernel parameters of one pass of one job.
+AcParams make_params(const tb_model *m, const TileLists &tl, const AcLaunch &a);
+// One batched launch over several jobs of the same radius and kernel shape
+// (device tables; see launch_acoustic_batch_r*).
+tb_status launch_acoustic_batch(int r, const AcParams *d_jobs, const int *d_wgoff, int njobs,
+                                int total_wg, int T, int LZ, int BYE, hipStream_t st,
+                                bool allow_timing);
 
 // Optional per-launch event timing of the propagation kernels.
 bool timing_enabled();

@@ -8,4 +8,10 @@ hipError_t launch_acoustic_r2(const AcParams &p, int T, int LZ, int BYE, hipStre
     return wf::launch_r<2>(p, T, LZ, BYE, st);
 }
 
+hipError_t launch_acoustic_batch_r2(const AcParams *jobs, const int *wg_off, int njobs,
+                                    int total_wg, int T, int LZ, int BYE, hipStream_t st)
+{
+    return wf::launch_batch_r<2>(jobs, wg_off, njobs, total_wg, T, LZ, BYE, st);
+}
+
 }  // namespace tbw

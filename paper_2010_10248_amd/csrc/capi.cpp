@@ -4,7 +4,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "tb_internal.h"
+#include "plan.h"
 
 namespace tbw {
 const char *last_error();
@@ -69,16 +69,19 @@ tb_status upload(T **dst, const std::vector<T> &src)
     return TB_OK;
 }
 
-struct SchedChoice {
-    int T, tile_y, chunk, wgs_per_cu;
-};
+}  // namespace
+
+namespace tbw {
+
+size_t field_bytes(const tb_model *m) { return align256(m->field_elems() * sizeof(float)); }
 
 tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice *out)
 {
     // Default: two steps per pass on 32-row tiles; on long x axes, 64-plane
     // chunks dispatched chunk-major, so that workgroups resident together
     // cover neighbouring tiles of the same x range and share halo reads in
-    // L2. Short axes use the even partition of the tile-x space.
+    // L2. Short axes use the even partition of the tile-x space. A schedule
+    // tuned for the model's shape (tb_autotune) replaces the default.
     SchedChoice c{2, 32, m->n[0] >= 256 ? 64 : 0, 2};
     if (s) {
         if (s->mode == TB_SCHED_SB) c.T = 1;
@@ -89,6 +92,9 @@ tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice 
         }
         c.tile_y = s->tile_y;
         c.chunk = s->chunk_x;
+    } else {
+        SchedChoice t;
+        if (tuned_schedule(m, &t)) c = t;
     }
     if (c.T < 1 || c.T > 4) {
         set_error("time_tile %d not in 1..4", c.T);
@@ -113,6 +119,8 @@ tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice 
     *out = c;
     return TB_OK;
 }
+
+namespace {
 
 // Cached per-segment lists for (direction, T, tile_y, chunk, workgroups).
 tb_status get_lists(const tb_model *m, tb_sparse *s, int adjoint, int T, int tile_y, int chunk,
@@ -139,6 +147,8 @@ tb_status get_lists(const tb_model *m, tb_sparse *s, int adjoint, int T, int til
     return TB_OK;
 }
 
+}  // namespace
+
 // Lists of the schedule with every segment within the kernel's LDS list
 // capacities: denser sparse sets get shorter segments.
 tb_status lists_for(const tb_model *m, tb_sparse *s, int adjoint, const SchedChoice &sc, int T,
@@ -162,67 +172,87 @@ tb_status lists_for(const tb_model *m, tb_sparse *s, int adjoint, const SchedCho
     return TB_EUNSUPPORTED;
 }
 
-size_t field_bytes(const tb_model *m) { return align256(m->field_elems() * sizeof(float)); }
+namespace {
 
-// One launch of T updates from (u = level n0, um = level n0-1): writes level
-// n0+T to out0 and, for T > 1, level n0+T-1 to out1.
-tb_status step_launch(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int adjoint, int T,
-                      const float *u, const float *um, float *out0, float *out1, int n0,
-                      const float *dcmp, int ninj, float *rec_dcmp, int nrecp, hipStream_t st)
+AcLaunch to_launch(const Pass &p)
 {
-    TileLists *tl = nullptr;
-    tb_status rc = lists_for(m, s, adjoint, sc, T, &tl);
-    if (rc) return rc;
     AcLaunch a{};
-    a.u = u;
-    a.um = um;
-    a.out0 = out0;
-    a.out1 = out1;
-    a.n0 = n0;
-    a.dcmp = dcmp;
-    a.npts = ninj;
-    a.rec_dcmp = rec_dcmp;
-    a.nrid = nrecp;
-    return launch_acoustic(m, *tl, a, st);
+    a.u = p.u;
+    a.um = p.um;
+    a.out0 = p.out0;
+    a.out1 = p.out1;
+    a.n0 = p.n0;
+    a.dcmp = p.dcmp;
+    a.npts = p.ninj;
+    a.rec_dcmp = p.rec;
+    a.nrid = p.nrecp;
+    return a;
 }
 
-// Run the propagation time loop: nt updates from zero state in F[0..3],
-// injecting dcmp rows 0..nt-1 at inj points and recording at the nrecp rec
-// points into rec_dcmp rows 1..nt (row 0, the zero initial level, is
-// cleared here). Returns the buffer indices of the last two levels.
-tb_status time_loop(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int adjoint,
-                    float *F[4], const float *dcmp, int ninj, float *rec_dcmp, int nrecp,
-                    int *cur_out, int *prev_out, hipStream_t st)
+Item pass_item(const Pass &p)
 {
-    const int nt = m->nt;
-    const size_t fe = m->field_elems();
-    tb_status rc;
-    for (int k = 0; k < 2; k++)
-        if ((rc = launch_fill(F[k], fe, 0.0f, st))) return rc;
-    if (nrecp > 0 && (rc = launch_fill(rec_dcmp, (size_t)nrecp, 0.0f, st))) return rc;
-    int cur = 0, prev = 1;
-    int n = 0;
-    while (n < nt) {
-        const int T = std::min(sc.T, nt - n);
+    Item it;
+    it.is_pass = true;
+    it.pass = p;
+    return it;
+}
+
+Item act_item(std::function<tb_status(hipStream_t)> f)
+{
+    Item it;
+    it.act = std::move(f);
+    return it;
+}
+
+// Append the passes of a time loop of `steps` updates starting at level n0
+// from buffers (F[cur] = level n0, F[prev] = level n0-1), four buffers
+// rotating (T == 1 updates in place over level n-1). after(n, cur, prev) is
+// called after each pass ending at level n.
+void plan_time_loop(Plan *plan, int adjoint, int Tmax, float *F[4], int n0, int steps,
+                    const float *dcmp, int ninj, float *rec, int nrecp, int *cur, int *prev,
+                    const std::function<void(int, int, int)> &after)
+{
+    int n = n0;
+    while (n < n0 + steps) {
+        const int T = std::min(Tmax, n0 + steps - n);
         int f0 = -1, f1 = -1;
         if (T > 1)
             for (int k = 0; k < 4; k++)
-                if (k != cur && k != prev) (f0 < 0 ? f0 : f1) = k;
-        // T == 1: u^{n+1} overwrites u^{n-1} point by point.
-        if ((rc = step_launch(m, s, sc, adjoint, T, F[cur], F[prev], T == 1 ? F[prev] : F[f0],
-                              T == 1 ? nullptr : F[f1], n, dcmp, ninj, rec_dcmp, nrecp, st)))
-            return rc;
-        if (T == 1) {
-            std::swap(cur, prev);
-        } else {
-            cur = f0;
-            prev = f1;
+                if (k != *cur && k != *prev) (f0 < 0 ? f0 : f1) = k;
+        Pass p;
+        p.adjoint = adjoint;
+        p.T = T;
+        p.u = F[*cur];
+        p.um = F[*prev];
+        p.out0 = T == 1 ? F[*prev] : F[f0];
+        p.out1 = T == 1 ? nullptr : F[f1];
+        p.n0 = n;
+        p.dcmp = dcmp;
+        p.ninj = ninj;
+        p.rec = rec;
+        p.nrecp = nrecp;
+        plan->push_back(pass_item(p));
+        if (T == 1) std::swap(*cur, *prev);
+        else {
+            *cur = f0;
+            *prev = f1;
         }
         n += T;
+        if (after) after(n, *cur, *prev);
     }
-    *cur_out = cur;
-    *prev_out = prev;
-    return TB_OK;
+}
+
+Item fill_item(float *p, size_t n)
+{
+    return act_item([=](hipStream_t st) { return launch_fill(p, n, 0.0f, st); });
+}
+
+Item copy_item(void *dst, const void *src, size_t bytes)
+{
+    return act_item([=](hipStream_t st) -> tb_status {
+        TB_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st));
+        return TB_OK;
+    });
 }
 
 // Workspace of the gradient (offsets in bytes from the base).
@@ -281,6 +311,253 @@ void image_weights(const tb_model *m, double w[3][5])
     for (int a = 0; a < 3; a++)
         for (int j = 0; j < 5; j++) w[a][j] = j <= m->r ? d2[j] / (m->h[a] * m->h[a]) : 0.0;
 }
+
+}  // namespace
+
+tb_status pass_params(const tb_model *m, tb_sparse *s, const SchedChoice &sc, const Pass &p,
+                      AcParams *out, const TileGeom **geom)
+{
+    TileLists *tl = nullptr;
+    tb_status rc = lists_for(m, s, p.adjoint, sc, p.T, &tl);
+    if (rc) return rc;
+    *out = make_params(m, *tl, to_launch(p));
+    if (geom) *geom = &tl->g;
+    return TB_OK;
+}
+
+tb_status run_plan(const tb_model *m, tb_sparse *s, const SchedChoice &sc, const Plan &plan,
+                   hipStream_t st)
+{
+    for (const Item &it : plan) {
+        tb_status rc;
+        if (it.is_pass) {
+            TileLists *tl = nullptr;
+            if ((rc = lists_for(m, s, it.pass.adjoint, sc, it.pass.T, &tl))) return rc;
+            rc = launch_acoustic(m, *tl, to_launch(it.pass), st);
+        } else {
+            rc = it.act(st);
+        }
+        if (rc) return rc;
+    }
+    return TB_OK;
+}
+
+size_t forward_ws_bytes(const tb_model *m, const tb_sparse *s)
+{
+    return 4 * field_bytes(m) + align256(((size_t)m->nt + 1) * std::max(s->nrid, 1) * sizeof(float));
+}
+
+size_t gradient_ws_bytes(const tb_model *m, const tb_sparse *s, const SchedChoice &sc, int every)
+{
+    return grad_layout(m, s, sc, every).total;
+}
+
+tb_status plan_forward(const tb_model *m, tb_sparse *s, const SchedChoice &sc, void *ws,
+                       float *rec_out, float *field_out, float *field_prev_out, Plan *plan)
+{
+    const size_t fb = field_bytes(m), fe = m->field_elems();
+    char *base = (char *)ws;
+    float *F[4] = {(float *)base, (float *)(base + fb), (float *)(base + 2 * fb),
+                   (float *)(base + 3 * fb)};
+    float *rec = (float *)(base + 4 * fb);
+    plan->push_back(fill_item(F[0], fe));
+    plan->push_back(fill_item(F[1], fe));
+    if (s->nrid > 0) plan->push_back(fill_item(rec, (size_t)s->nrid));
+    int cur = 0, prev = 1;
+    plan_time_loop(plan, 0, sc.T, F, 0, m->nt, s->d_dcmp, s->npts, rec, s->nrid, &cur, &prev,
+                   nullptr);
+    if (rec_out && s->nrec > 0 && m->nt > 0) {
+        const int nrid = s->nrid, nt = m->nt, nrec = s->nrec;
+        const int *pp = s->d_rc_ptr, *id = s->d_rc_id;
+        const float *w = s->d_rc_w;
+        plan->push_back(act_item([=](hipStream_t st) {
+            return launch_trace_reduce(rec, nrid, nt, pp, id, w, nrec, rec_out, 0, st);
+        }));
+    }
+    const int nx = m->n[0], ny = m->n[1], nz = m->n[2], nzp = m->nzp;
+    float *fc = F[cur], *fp = F[prev];
+    if (field_out)
+        plan->push_back(act_item([=](hipStream_t st) {
+            return launch_unpad(fc, field_out, nx, ny, nz, nzp, st);
+        }));
+    if (field_prev_out)
+        plan->push_back(act_item([=](hipStream_t st) {
+            return launch_unpad(fp, field_prev_out, nx, ny, nz, nzp, st);
+        }));
+    return TB_OK;
+}
+
+tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int every,
+                        void *ws, const float *d_obs, float *grad_m, double *loss_dst, Plan *plan)
+{
+    const GradLayout L = grad_layout(m, s, sc, every);
+    const int nt = m->nt, K = L.K;
+    const size_t fb = field_bytes(m), fe = m->field_elems();
+    char *base = (char *)ws;
+    auto fld = [=](size_t off, int i) { return (float *)(base + off + (size_t)i * fb); };
+    float *F[4] = {fld(L.F, 0), fld(L.F, 1), fld(L.F, 2), fld(L.F, 3)};
+    float *A[4] = {fld(L.A, 0), fld(L.A, 1), fld(L.A, 2), fld(L.A, 3)};
+    double *g = (double *)(base + L.g);
+    float *rec = (float *)(base + L.rec), *traces = (float *)(base + L.traces);
+    float *res = (float *)(base + L.res), *adj_dcmp = (float *)(base + L.adj_dcmp);
+    float *adj_rec = (float *)(base + L.adj_rec);
+    double *loss = (double *)(base + L.loss);
+    const int nrec = s->nrec, nrid = s->nrid, npts = s->npts;
+
+    // 1. Forward run from zero state, keeping (u^{jK}, u^{jK-1}) for j >= 1.
+    plan->push_back(fill_item(F[0], fe));
+    plan->push_back(fill_item(F[1], fe));
+    if (nrid > 0) plan->push_back(fill_item(rec, (size_t)nrid));
+    int cur = 0, prev = 1, j = 1;
+    plan_time_loop(plan, 0, sc.T, F, 0, nt, s->d_dcmp, npts, rec, nrid, &cur, &prev,
+                   [&](int n, int c, int pv) {
+                       if (j <= L.ncp && n == j * K) {
+                           plan->push_back(copy_item(fld(L.cps, 2 * (j - 1)), F[c], fb));
+                           plan->push_back(copy_item(fld(L.cps, 2 * (j - 1) + 1), F[pv], fb));
+                           j++;
+                       }
+                   });
+    // 2. Traces, residual and misfit; the adjoint source.
+    {
+        const int *pp = s->d_rc_ptr, *id = s->d_rc_id, *rp = s->d_rr_ptr, *rr = s->d_rr_rec;
+        const float *w = s->d_rc_w, *rw = s->d_rr_w, *rs = s->d_rid_scale;
+        plan->push_back(act_item([=](hipStream_t st) -> tb_status {
+            tb_status rc;
+            if (nrec > 0 && nt > 0 &&
+                (rc = launch_trace_reduce(rec, nrid, nt, pp, id, w, nrec, traces, 0, st)))
+                return rc;
+            if ((rc = launch_residual_loss(traces, d_obs, (long long)nt * nrec, res, loss, st)))
+                return rc;
+            if (nrid > 0 && nt > 0 &&
+                (rc = launch_adj_inject(res, nt, nrec, nrid, rp, rr, rw, rs, adj_dcmp, st)))
+                return rc;
+            return TB_OK;
+        }));
+    }
+    // 3. Segments in reverse: recompute levels k0-1 .. e into the slots, then
+    //    run the adjoint through levels e+1 .. k0+1 and image each one.
+    plan->push_back(act_item([=](hipStream_t st) { return launch_zero64(g, fe, st); }));
+    plan->push_back(fill_item(A[0], fe));
+    plan->push_back(fill_item(A[1], fe));
+    if (npts > 0) plan->push_back(fill_item(adj_rec, (size_t)npts));
+    ImageArgs ia{};
+    ia.c = m->d_c;
+    ia.g = g;
+    ia.nx = m->n[0];
+    ia.ny = m->n[1];
+    ia.nz = m->n[2];
+    ia.nzp = m->nzp;
+    ia.r = m->r;
+    image_weights(m, ia.w);
+    const float *dcmp = s->d_dcmp;
+    const long long *soff = s->d_src_off;
+    const double *salpha = s->d_src_alpha;
+    const int Td = std::min(sc.T, 2);  // every level of these passes is stored
+    int acur = 0, aprev = 1;
+    for (int seg = L.ncp; seg >= 0 && nt >= 2; seg--) {
+        const int k0 = seg * K;
+        const int e = std::min(k0 + K - 1, nt - 2);
+        float *slot0 = fld(L.slots, 0), *slot1 = fld(L.slots, 1);
+        if (seg == 0) {
+            plan->push_back(fill_item(slot0, fe));
+            plan->push_back(fill_item(slot1, fe));
+        } else {
+            plan->push_back(copy_item(slot0, fld(L.cps, 2 * (seg - 1) + 1), fb));
+            plan->push_back(copy_item(slot1, fld(L.cps, 2 * (seg - 1)), fb));
+        }
+        // slot i holds level k0 - 1 + i.
+        for (int nn = k0; nn < e;) {
+            const int T = std::min(Td, e - nn);
+            const int b = nn - k0;
+            Pass p;
+            p.T = T;
+            p.u = fld(L.slots, b + 1);
+            p.um = fld(L.slots, b);
+            p.out0 = fld(L.slots, b + 1 + T);
+            p.out1 = T == 1 ? nullptr : fld(L.slots, b + 2);
+            p.n0 = nn;
+            p.dcmp = dcmp;
+            p.ninj = npts;
+            p.rec = rec;
+            p.nrecp = nrid;
+            plan->push_back(pass_item(p));
+            nn += T;
+        }
+        // Adjoint step na produces nu^{nt-1-na}.
+        int na = nt - 2 - e;
+        for (int left = e - k0 + 1; left > 0;) {
+            const int T = std::min(Td, left);
+            int f0 = -1, f1 = -1;
+            if (T > 1)
+                for (int k = 0; k < 4; k++)
+                    if (k != acur && k != aprev) (f0 < 0 ? f0 : f1) = k;
+            Pass p;
+            p.adjoint = 1;
+            p.T = T;
+            p.u = A[acur];
+            p.um = A[aprev];
+            p.out0 = T == 1 ? A[aprev] : A[f0];
+            p.out1 = T == 1 ? nullptr : A[f1];
+            p.n0 = na;
+            p.dcmp = adj_dcmp;
+            p.ninj = nrid;
+            p.rec = adj_rec;
+            p.nrecp = npts;
+            plan->push_back(pass_item(p));
+            // Image the levels of this pass, newest-in-k first.
+            for (int t = 0; t < T; t++) {
+                const int k = nt - 1 - na - t;
+                ImageArgs a2 = ia;
+                a2.nu = (t == T - 1) ? p.out0 : p.out1;
+                a2.u = fld(L.slots, k - k0);
+                const float *srow = dcmp + (size_t)(k - 1) * npts;
+                plan->push_back(act_item([=](hipStream_t st) -> tb_status {
+                    tb_status rc = launch_image(a2, st);
+                    if (rc) return rc;
+                    return launch_image_sparse(a2.nu, srow, npts, soff, salpha, g, st);
+                }));
+            }
+            if (T == 1) std::swap(acur, aprev);
+            else {
+                acur = f0;
+                aprev = f1;
+            }
+            na += T;
+            left -= T;
+        }
+    }
+    const int nx = m->n[0], ny = m->n[1], nz = m->n[2], nzp = m->nzp;
+    const double scale = -1.0 / (m->dt * m->dt);
+    plan->push_back(act_item([=](hipStream_t st) {
+        return launch_finish_grad(g, grad_m, nx, ny, nz, nzp, scale, st);
+    }));
+    if (loss_dst)
+        plan->push_back(act_item([=](hipStream_t st) -> tb_status {
+            TB_HIP(hipMemcpyAsync(loss_dst, loss, sizeof(double), hipMemcpyDeviceToHost, st));
+            return TB_OK;
+        }));
+    return TB_OK;
+}
+
+// Adjoint time loop (tb_adjoint): nt updates from zero state.
+tb_status time_loop(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int adjoint,
+                    float *F[4], const float *dcmp, int ninj, float *rec_dcmp, int nrecp,
+                    hipStream_t st)
+{
+    Plan plan;
+    const size_t fe = m->field_elems();
+    plan.push_back(fill_item(F[0], fe));
+    plan.push_back(fill_item(F[1], fe));
+    if (nrecp > 0) plan.push_back(fill_item(rec_dcmp, (size_t)nrecp));
+    int cur = 0, prev = 1;
+    plan_time_loop(&plan, adjoint, sc.T, F, 0, m->nt, dcmp, ninj, rec_dcmp, nrecp, &cur, &prev,
+                   nullptr);
+    return run_plan(m, s, sc, plan, st);
+}
+
+}  // namespace tbw
+
+namespace {
 
 }  // namespace
 
@@ -500,14 +777,14 @@ tb_status tb_workspace_size(const tb_model *m, const tb_sparse *s, const tb_sche
     const size_t nt1 = (size_t)m->nt + 1;
     switch (op) {
     case TB_OP_FORWARD:
-        *bytes = 4 * fb + align256(nt1 * std::max(s->nrid, 1) * sizeof(float));
+        *bytes = forward_ws_bytes(m, s);
         return TB_OK;
     case TB_OP_ADJOINT:
         *bytes = 4 * fb + align256(nt1 * std::max(s->npts, 1) * sizeof(float)) +
                  align256((size_t)m->nt * std::max(s->nrid, 1) * sizeof(float));
         return TB_OK;
     case TB_OP_GRADIENT:
-        *bytes = grad_layout(m, s, sc, 0).total;
+        *bytes = gradient_ws_bytes(m, s, sc, 0);
         return TB_OK;
     default:
         set_error("operation %d has no workspace query", op);
@@ -533,26 +810,9 @@ tb_status tb_forward(const tb_model *m, const tb_sparse *s_, const tb_schedule *
         set_error("workspace %zu bytes < %zu needed", ws_bytes, need);
         return TB_EWORKSPACE;
     }
-    hipStream_t strm = (hipStream_t)stream;
-    const size_t fb = field_bytes(m);
-    char *base = (char *)ws;
-    float *F[4] = {(float *)base, (float *)(base + fb), (float *)(base + 2 * fb),
-                   (float *)(base + 3 * fb)};
-    float *rec_dcmp = (float *)(base + 4 * fb);
-    const int nrecp = s->nrid;
-    int cur = 0, prev = 1;
-    st = time_loop(m, s, sc, 0, F, s->d_dcmp, s->npts, rec_dcmp, nrecp, &cur, &prev, strm);
-    if (st) return st;
-    if (rec_out && s->nrec > 0 && m->nt > 0)
-        if ((st = launch_trace_reduce(rec_dcmp, s->nrid, m->nt, s->d_rc_ptr, s->d_rc_id,
-                                      s->d_rc_w, s->nrec, rec_out, 0, strm)))
-            return st;
-    if (field_out && (st = launch_unpad(F[cur], field_out, m->n[0], m->n[1], m->n[2], m->nzp, strm)))
-        return st;
-    if (field_prev_out &&
-        (st = launch_unpad(F[prev], field_prev_out, m->n[0], m->n[1], m->n[2], m->nzp, strm)))
-        return st;
-    return TB_OK;
+    Plan plan;
+    if ((st = plan_forward(m, s, sc, ws, rec_out, field_out, field_prev_out, &plan))) return st;
+    return run_plan(m, s, sc, plan, (hipStream_t)stream);
 }
 
 tb_status tb_adjoint(const tb_model *m, const tb_sparse *s_, const tb_schedule *sched, void *ws,
@@ -584,8 +844,7 @@ tb_status tb_adjoint(const tb_model *m, const tb_sparse *s_, const tb_schedule *
         if ((st = launch_adj_inject(rec_in, m->nt, s->nrec, s->nrid, s->d_rr_ptr, s->d_rr_rec,
                                     s->d_rr_w, s->d_rid_scale, adj_dcmp, strm)))
             return st;
-    int cur = 0, prev = 1;
-    st = time_loop(m, s, sc, 1, F, adj_dcmp, s->nrid, rec_dcmp, s->npts, &cur, &prev, strm);
+    st = time_loop(m, s, sc, 1, F, adj_dcmp, s->nrid, rec_dcmp, s->npts, strm);
     if (st) return st;
     // qhat^n = P_s (alpha nu^{n+1}); nu^{n+1} is adjoint level nt-1-n.
     if (src_out && s->nsrc > 0 && m->nt > 0)
@@ -606,7 +865,7 @@ tb_status tb_gradient_workspace_size(const tb_model *m, const tb_sparse *s,
     SchedChoice sc;
     tb_status st = resolve_schedule(m, sched, &sc);
     if (st) return st;
-    *bytes = grad_layout(m, s, sc, checkpoint_every).total;
+    *bytes = gradient_ws_bytes(m, s, sc, checkpoint_every);
     return TB_OK;
 }
 
@@ -623,144 +882,17 @@ tb_status tb_gradient(const tb_model *m, const tb_sparse *s_, const tb_schedule 
     SchedChoice sc;
     tb_status st = resolve_schedule(m, sched, &sc);
     if (st) return st;
-    const GradLayout L = grad_layout(m, s, sc, checkpoint_every);
-    if (ws_bytes < L.total) {
-        set_error("workspace %zu bytes < %zu needed", ws_bytes, L.total);
+    const size_t need = gradient_ws_bytes(m, s, sc, checkpoint_every);
+    if (ws_bytes < need) {
+        set_error("workspace %zu bytes < %zu needed", ws_bytes, need);
         return TB_EWORKSPACE;
     }
     hipStream_t strm = (hipStream_t)stream;
-    const int nt = m->nt, K = L.K;
-    const size_t fb = field_bytes(m), fe = m->field_elems();
-    char *base = (char *)ws;
-    auto fld = [&](size_t off, int i) { return (float *)(base + off + (size_t)i * fb); };
-    float *F[4] = {fld(L.F, 0), fld(L.F, 1), fld(L.F, 2), fld(L.F, 3)};
-    float *A[4] = {fld(L.A, 0), fld(L.A, 1), fld(L.A, 2), fld(L.A, 3)};
-    double *g = (double *)(base + L.g);
-    float *rec = (float *)(base + L.rec), *traces = (float *)(base + L.traces);
-    float *res = (float *)(base + L.res), *adj_dcmp = (float *)(base + L.adj_dcmp);
-    float *adj_rec = (float *)(base + L.adj_rec);
-    double *loss = (double *)(base + L.loss);
-
-    // 1. Forward run from zero state, keeping (u^{jK}, u^{jK-1}) for j >= 1.
-    for (int k = 0; k < 2; k++)
-        if ((st = launch_fill(F[k], fe, 0.0f, strm))) return st;
-    if (s->nrid > 0 && (st = launch_fill(rec, (size_t)s->nrid, 0.0f, strm))) return st;
-    int cur = 0, prev = 1, n = 0, j = 1;
-    while (n < nt) {
-        const int T = std::min(sc.T, nt - n);
-        int f0 = -1, f1 = -1;
-        if (T > 1)
-            for (int k = 0; k < 4; k++)
-                if (k != cur && k != prev) (f0 < 0 ? f0 : f1) = k;
-        if ((st = step_launch(m, s, sc, 0, T, F[cur], F[prev], T == 1 ? F[prev] : F[f0],
-                              T == 1 ? nullptr : F[f1], n, s->d_dcmp, s->npts, rec, s->nrid,
-                              strm)))
-            return st;
-        if (T == 1) std::swap(cur, prev);
-        else {
-            cur = f0;
-            prev = f1;
-        }
-        n += T;
-        if (j <= L.ncp && n == j * K) {
-            TB_HIP(hipMemcpyAsync(fld(L.cps, 2 * (j - 1)), F[cur], fb, hipMemcpyDeviceToDevice,
-                                  strm));
-            TB_HIP(hipMemcpyAsync(fld(L.cps, 2 * (j - 1) + 1), F[prev], fb,
-                                  hipMemcpyDeviceToDevice, strm));
-            j++;
-        }
-    }
-    // 2. Traces, residual and misfit; the adjoint source.
-    if (s->nrec > 0 && nt > 0)
-        if ((st = launch_trace_reduce(rec, s->nrid, nt, s->d_rc_ptr, s->d_rc_id, s->d_rc_w,
-                                      s->nrec, traces, 0, strm)))
-            return st;
-    if ((st = launch_residual_loss(traces, d_obs, (long long)nt * s->nrec, res, loss, strm)))
+    Plan plan;
+    if ((st = plan_gradient(m, s, sc, checkpoint_every, ws, d_obs, grad_m, loss_out, &plan)))
         return st;
-    if (s->nrid > 0 && nt > 0)
-        if ((st = launch_adj_inject(res, nt, s->nrec, s->nrid, s->d_rr_ptr, s->d_rr_rec,
-                                    s->d_rr_w, s->d_rid_scale, adj_dcmp, strm)))
-            return st;
-    // 3. Segments in reverse: recompute levels jK-1 .. e into the slots, then
-    //    run the adjoint through levels e+1 .. jK+1 and image each one.
-    if ((st = launch_zero64(g, fe, strm))) return st;
-    for (int k = 0; k < 2; k++)
-        if ((st = launch_fill(A[k], fe, 0.0f, strm))) return st;
-    if (s->npts > 0 && (st = launch_fill(adj_rec, (size_t)s->npts, 0.0f, strm))) return st;
-    ImageArgs ia{};
-    ia.c = m->d_c;
-    ia.g = g;
-    ia.nx = m->n[0];
-    ia.ny = m->n[1];
-    ia.nz = m->n[2];
-    ia.nzp = m->nzp;
-    ia.r = m->r;
-    image_weights(m, ia.w);
-    const int Td = std::min(sc.T, 2);  // every level of these passes is stored
-    int acur = 0, aprev = 1;
-    for (int seg = L.ncp; seg >= 0 && nt >= 2; seg--) {
-        const int k0 = seg * K;
-        const int e = std::min(k0 + K - 1, nt - 2);
-        float *slot0 = fld(L.slots, 0), *slot1 = fld(L.slots, 1);
-        if (seg == 0) {
-            if ((st = launch_fill(slot0, fe, 0.0f, strm)) || (st = launch_fill(slot1, fe, 0.0f, strm)))
-                return st;
-        } else {
-            TB_HIP(hipMemcpyAsync(slot0, fld(L.cps, 2 * (seg - 1) + 1), fb,
-                                  hipMemcpyDeviceToDevice, strm));
-            TB_HIP(hipMemcpyAsync(slot1, fld(L.cps, 2 * (seg - 1)), fb, hipMemcpyDeviceToDevice,
-                                  strm));
-        }
-        // slot i holds level k0 - 1 + i.
-        for (int nn = k0; nn < e;) {
-            const int T = std::min(Td, e - nn);
-            const int b = nn - k0;
-            if ((st = step_launch(m, s, sc, 0, T, fld(L.slots, b + 1), fld(L.slots, b),
-                                  fld(L.slots, b + 1 + T), T == 1 ? nullptr : fld(L.slots, b + 2),
-                                  nn, s->d_dcmp, s->npts, rec, s->nrid, strm)))
-                return st;
-            nn += T;
-        }
-        // Adjoint step na produces nu^{nt-1-na}.
-        int na = nt - 2 - e;
-        for (int left = e - k0 + 1; left > 0;) {
-            const int T = std::min(Td, left);
-            int f0 = -1, f1 = -1;
-            if (T > 1)
-                for (int k = 0; k < 4; k++)
-                    if (k != acur && k != aprev) (f0 < 0 ? f0 : f1) = k;
-            float *o0 = T == 1 ? A[aprev] : A[f0];
-            float *o1 = T == 1 ? nullptr : A[f1];
-            if ((st = step_launch(m, s, sc, 1, T, A[acur], A[aprev], o0, o1, na, adj_dcmp,
-                                  s->nrid, adj_rec, s->npts, strm)))
-                return st;
-            // Levels of this pass, newest-in-k first.
-            for (int t = 0; t < T; t++) {
-                const int k = nt - 1 - na - t;
-                const float *nu = (t == T - 1) ? o0 : o1;
-                ia.nu = nu;
-                ia.u = fld(L.slots, k - k0);
-                if ((st = launch_image(ia, strm))) return st;
-                if ((st = launch_image_sparse(nu, s->d_dcmp + (size_t)(k - 1) * s->npts, s->npts,
-                                              s->d_src_off, s->d_src_alpha, g, strm)))
-                    return st;
-            }
-            if (T == 1) std::swap(acur, aprev);
-            else {
-                acur = f0;
-                aprev = f1;
-            }
-            na += T;
-            left -= T;
-        }
-    }
-    if ((st = launch_finish_grad(g, grad_m, m->n[0], m->n[1], m->n[2], m->nzp,
-                                 -1.0 / (m->dt * m->dt), strm)))
-        return st;
-    if (loss_out) {
-        TB_HIP(hipMemcpyAsync(loss_out, loss, sizeof(double), hipMemcpyDeviceToHost, strm));
-        TB_HIP(hipStreamSynchronize(strm));
-    }
+    if ((st = run_plan(m, s, sc, plan, strm))) return st;
+    if (loss_out) TB_HIP(hipStreamSynchronize(strm));
     return TB_OK;
 }
 

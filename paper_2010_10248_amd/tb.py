@@ -59,6 +59,15 @@ def schedule(mode: str = "tb", T: int = 2, tile_y: int = 32, chunk_x: int = 0) -
     return Schedule(SCHED_TB, T, tile_y, chunk_x)
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("model", ctypes.c_void_p), ("sparse", ctypes.c_void_p),
+                ("sched", ctypes.POINTER(Schedule)), ("d_obs", ctypes.c_void_p),
+                ("rec_out", ctypes.c_void_p), ("grad_out", ctypes.c_void_p),
+                ("checkpoint_every", ctypes.c_int32)]
+
+
+SERVE_GRAPHS = 1
+
 _lib = None
 _dp = ctypes.POINTER(ctypes.c_double)
 _fp = ctypes.POINTER(ctypes.c_float)
@@ -87,6 +96,18 @@ _SIGNATURES = {
     "tb_gradient_workspace_size": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(Schedule),
                                                     ctypes.c_int32,
                                                     ctypes.POINTER(ctypes.c_size_t)]),
+    "tb_autotune": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, ctypes.POINTER(Schedule),
+                                     ctypes.POINTER(ctypes.c_double)]),
+    "tb_autotune_clear": (ctypes.c_int32, []),
+    "tb_server_create": (ctypes.c_int32, [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(_vp)]),
+    "tb_server_submit": (ctypes.c_int32, [_vp, ctypes.POINTER(Request),
+                                          ctypes.POINTER(ctypes.c_int64)]),
+    "tb_server_step": (ctypes.c_int32, [_vp, _ip, _ip]),
+    "tb_server_poll": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_double), _ip]),
+    "tb_server_stats": (ctypes.c_int32, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
+    "tb_server_destroy": (None, [_vp]),
     "tb_kernel_timing": (ctypes.c_int32, [ctypes.c_int32]),
     "tb_kernel_timing_read": (ctypes.c_int32, [_ip, ctypes.POINTER(ctypes.c_double)]),
     "tb_last_error": (ctypes.c_char_p, []),
@@ -253,6 +274,87 @@ def gradient(model, sparse, sched, ws, d_obs, grad_m, checkpoint_every=0, stream
                              _tptr(grad_m), ctypes.byref(loss), int(checkpoint_every),
                              _stream(stream)), "tb_gradient")
     return loss.value
+
+
+def autotune(model, sparse, steps=8, stream=None):
+    """Time every valid schedule on the device; cache and return the best
+    (Schedule, ms per step)."""
+    best = Schedule()
+    ms = ctypes.c_double()
+    _check(lib().tb_autotune(model, sparse, int(steps), _stream(stream), ctypes.byref(best),
+                             ctypes.byref(ms)), "tb_autotune")
+    return best, ms.value
+
+
+def autotune_clear():
+    _check(lib().tb_autotune_clear(), "tb_autotune_clear")
+
+
+class Server:
+    """Continuous-batching server (tb_server_*). Requests reference models and
+    sparse sets (and output tensors) that must stay alive until completion."""
+
+    STAT_NAMES = ("epochs", "rounds", "launches", "passes_batched", "graph_captures",
+                  "graph_replays", "actions", "completed")
+
+    def __init__(self, arena_bytes: int, max_active: int, graphs: bool = True):
+        h = _vp()
+        _check(lib().tb_server_create(int(arena_bytes), int(max_active),
+                                      SERVE_GRAPHS if graphs else 0, ctypes.byref(h)),
+               "tb_server_create")
+        self.h = h
+        self._keep = {}
+
+    def _submit(self, rq, keep):
+        rid = ctypes.c_int64()
+        _check(lib().tb_server_submit(self.h, ctypes.byref(rq), ctypes.byref(rid)),
+               "tb_server_submit")
+        self._keep[rid.value] = keep
+        return rid.value
+
+    def submit_forward(self, prop, rec_out, sched=None):
+        rq = Request(OP_FORWARD, prop.model, prop.sparse,
+                     None if sched is None else ctypes.pointer(sched), None,
+                     rec_out.data_ptr(), None, 0)
+        return self._submit(rq, (prop, rec_out))
+
+    def submit_gradient(self, prop, d_obs, grad_out, sched=None, checkpoint_every=0):
+        rq = Request(OP_GRADIENT, prop.model, prop.sparse,
+                     None if sched is None else ctypes.pointer(sched), d_obs.data_ptr(), None,
+                     grad_out.data_ptr(), int(checkpoint_every))
+        return self._submit(rq, (prop, d_obs, grad_out))
+
+    def step(self):
+        a, q = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().tb_server_step(self.h, ctypes.byref(a), ctypes.byref(q)), "tb_server_step")
+        return a.value, q.value
+
+    def poll(self, cap=256):
+        ids = (ctypes.c_int64 * cap)()
+        losses = (ctypes.c_double * cap)()
+        n = ctypes.c_int32()
+        _check(lib().tb_server_poll(self.h, cap, ids, losses, ctypes.byref(n)), "tb_server_poll")
+        out = [(ids[i], losses[i]) for i in range(n.value)]
+        for rid, _ in out:
+            self._keep.pop(rid, None)
+        return out
+
+    def stats(self):
+        v = (ctypes.c_int64 * 8)()
+        _check(lib().tb_server_stats(self.h, v, 8), "tb_server_stats")
+        return dict(zip(self.STAT_NAMES, list(v)))
+
+    def close(self):
+        if self.h:
+            lib().tb_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Acoustic:
