@@ -71,6 +71,85 @@ def copy_calibration(torch):
     return 0
 
 
+def serve_bench(tb, W, torch, nreq, load, max_active, arena_gb):
+    """C5 serving: gradient requests (forward, residual vs observed traces,
+    adjoint, checkpointed squared-slowness gradient) on mixed 128-384^3 SO8
+    grids with 500-1500 steps. Phase 1 submits every request at once
+    (saturated shots/s); phase 2 replays the same requests with Poisson
+    arrivals at `load` x that rate and reports completion - arrival latency.
+    Models, sparse sets and observed data (forward runs of the true model
+    with a +5% velocity anomaly) are made before the clock starts."""
+    import numpy as np
+
+    rng = np.random.Generator(np.random.PCG64(10253))
+    reqs = []
+    t0 = time.perf_counter()
+    for _ in range(nreq):
+        shot, vp_true = W.serving_request(rng)
+        vmax = float(shot.vp.max())
+        true = tb.Acoustic(shot, vp=vp_true, damp_vmax=vmax)
+        d_obs = true.forward(None, want_fields=False)["traces"]
+        true.close()
+        prop = tb.Acoustic(shot, damp_vmax=vmax)
+        reqs.append((shot, prop, d_obs))
+    torch.cuda.synchronize()
+    log(f"serving: {nreq} requests prepared in {time.perf_counter() - t0:.1f} s "
+        f"(sizes {sorted(r[0].shape[0] for r in reqs)}, nt {sorted(r[0].nt for r in reqs)})")
+    work = sum(int(np.prod(r[0].shape)) * r[0].nt for r in reqs)
+
+    def run(arrivals):
+        sv = tb.Server(arena_bytes=int(arena_gb * 2**30), max_active=max_active, graphs=True)
+        grads = [torch.empty(r[0].shape, dtype=torch.float32, device="cuda") for r in reqs]
+        rid_of = {}
+        lat = [None] * nreq
+        losses = [None] * nreq
+        nxt = 0
+        start = time.perf_counter()
+        while any(v is None for v in lat):
+            now = time.perf_counter() - start
+            while nxt < nreq and arrivals[nxt] <= now:
+                shot, prop, d_obs = reqs[nxt]
+                rid_of[sv.submit_gradient(prop, d_obs, grads[nxt])] = nxt
+                nxt += 1
+            act, queued = sv.step()
+            for rid, J in sv.poll():
+                i = rid_of[rid]
+                lat[i] = time.perf_counter() - start - arrivals[i]
+                losses[i] = J
+            if act == 0 and queued == 0 and nxt < nreq:
+                time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - start)))
+        span = time.perf_counter() - start
+        st = sv.stats()
+        sv.close()
+        return span, lat, losses, st
+
+    span, lat_sat, losses, st = run([0.0] * nreq)
+    rate = nreq / span
+    log(f"serving saturated: {nreq} requests in {span:.2f} s = {rate:.3f} shots/s; stats {st}")
+    arr = np.cumsum(np.random.Generator(np.random.PCG64(7)).exponential(1.0 / (load * rate), nreq))
+    arr = arr - arr[0]
+    span2, lat, losses2, st2 = run(list(arr))
+    assert losses2 == losses, "a request's misfit changed between runs"
+    lat_ms = np.array(lat) * 1e3
+    out = dict(shots_per_s=round(rate, 4), requests=nreq,
+               point_updates_per_request_mean=round(work / nreq / 1e9, 3),
+               gradient_gpts_per_s_equiv=round(work / span / 1e9, 2),
+               poisson_load=load, poisson_shots_per_s=round(nreq / span2, 4),
+               p50_ms=round(float(np.percentile(lat_ms, 50)), 1),
+               p99_ms=round(float(np.percentile(lat_ms, 99)), 1),
+               saturated_p50_ms=round(float(np.percentile(np.array(lat_sat) * 1e3, 50)), 1),
+               max_active=max_active, arena_gib=arena_gb,
+               batched_passes_per_launch=round(st2["passes_batched"] / max(st2["launches"], 1), 2),
+               graph_replays=st2["graph_replays"], graph_captures=st2["graph_captures"],
+               request="gradient (forward + residual + adjoint + imaging, checkpoints every "
+                       "ceil(sqrt(nt)))",
+               mix="SO8 two-layer, N in {128,192,256,384}, nt 500-1500, Poisson arrivals")
+    log(f"serving Poisson at {load}x: p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms")
+    for _, prop, _ in reqs:
+        prop.close()
+    return out
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -120,6 +199,11 @@ def main(argv=None):
     ap.add_argument("--no-sb", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-active", type=int, default=4)
+    ap.add_argument("--serve-arena-gb", type=float, default=128.0)
     ap.add_argument("--cpu-steps", type=int, default=64,
                     help="steps of the full grid the FP64 oracle runs as the CPU sample")
     args = ap.parse_args(argv)
@@ -226,6 +310,11 @@ def main(argv=None):
                                           for k, v in errs.items()})
         log(f"parity vs FP64 oracle at {sample.nt} steps: {parity}")
 
+    serving = None
+    if not args.no_serve:
+        serving = serve_bench(tb, W, torch, args.serve_requests, args.serve_load,
+                              args.serve_active, args.serve_arena_gb)
+
     line = {
         "metric": METRIC,
         "value": round(gpts_tb, 2),
@@ -249,6 +338,7 @@ def main(argv=None):
             "tb_over_sb": round(gpts_tb / sb["value"], 3) if sb else None,
             "parity_rel_l2": parity,
             "inspector_s": round(setup_s, 3),
+            "serving": serving,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -239,7 +239,6 @@ tb_status issue(tb_server *sv, const std::vector<LaunchRec> &L, bool timing)
         tb_status rc = launch_acoustic_batch(l.r, sv->d_par + l.poff, sv->d_wg + l.woff, l.njobs,
                                              l.total_wg, l.T, l.LZ, l.BYE, sv->st, timing);
         if (rc) return rc;
-        sv->stats[kLaunches]++;
     }
     return TB_OK;
 }
@@ -338,6 +337,7 @@ tb_status epoch(tb_server *sv)
         if ((rc = issue(sv, L, true))) return rc;
     }
     for (auto &jp : sv->active) jp->pos += P;
+    sv->stats[kLaunches] += (int64_t)L.size();
     sv->stats[kEpochs]++;
     sv->stats[kRounds] += P;
     return TB_OK;
