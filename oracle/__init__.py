@@ -66,6 +66,8 @@ def lib():
             L.or_tti_forward.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int,
                                          _dp, _dp, _dp, _dp, _dp, c_double,
                                          c_int, _dp, _dp, c_int, _dp, vp, vp, vp, vp, vp]
+        if hasattr(L, "or_tti_operators"):
+            L.or_tti_operators.argtypes = [_ip, _dp, c_int, _dp, _dp, _dp, vp, vp]
         if hasattr(L, "or_elastic_forward"):
             L.or_elastic_forward.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int,
                                              _dp, _dp, _dp, c_double,
@@ -222,6 +224,42 @@ def acoustic_gradient(shot, dobs: np.ndarray, vp=None, vmax_damp: float = 0.0):
     adj = acoustic_adjoint(shot, res, vp=vp, vmax_damp=vmax_damp,
                            u_hist=fw["history"][:shot.nt], want_grad=True, want_qhat=False)
     return float(J), adj["grad"], fw
+
+
+def tti_forward(shot, vp=None, vmax_damp: float = 0.0, src_wav=None, epsilon=None, delta=None,
+                theta=None, phi=None):
+    """FP64 pseudo-acoustic TTI forward of a ``workloads.Shot`` (zero initial
+    state). Returns dict(traces[nt][nrec] of p, p_last, p_prev, r_last, r_prev)."""
+    n = np.asarray(shot.shape, dtype=np.int32)
+    f = lambda a, b: _f64(b if a is None else a)
+    vp = f(vp, shot.vp)
+    eps, dl, th, ph = (f(epsilon, shot.epsilon), f(delta, shot.delta), f(theta, shot.theta),
+                       f(phi, shot.phi))
+    wav = f(src_wav, shot.src_wav)
+    sx = _f64(shot.src_xyz)
+    rx = _f64(shot.rec_xyz)
+    out = dict(traces=np.zeros((shot.nt, rx.shape[0])))
+    for k in ("p_last", "p_prev", "r_last", "r_prev"):
+        out[k] = np.zeros(shot.shape)
+    st = lib().or_tti_forward(n, _f64(shot.spacing), _f64(shot.origin), shot.space_order,
+                              shot.nbl, float(shot.dt), shot.nt, vp, eps, dl, th, ph,
+                              float(vmax_damp), sx.shape[0], sx, wav, rx.shape[0], rx,
+                              _ptr(out["traces"]), _ptr(out["p_last"]), _ptr(out["p_prev"]),
+                              _ptr(out["r_last"]), _ptr(out["r_prev"]))
+    _check(st, "tti_forward")
+    return out
+
+
+def tti_operators(u, spacing, so: int, theta, phi):
+    """(L u, Hz u) of the TTI oracle for a field u with per-node angles."""
+    u = _f64(u)
+    n = np.asarray(u.shape, dtype=np.int32)
+    lap_out = np.zeros(u.shape)
+    hz = np.zeros(u.shape)
+    _check(lib().or_tti_operators(n, _f64(spacing), so, _f64(np.broadcast_to(theta, u.shape)),
+                                  _f64(np.broadcast_to(phi, u.shape)), u, _ptr(lap_out),
+                                  _ptr(hz)), "tti_operators")
+    return lap_out, hz
 
 
 def misfit(d, dobs) -> float:

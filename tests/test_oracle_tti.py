@@ -1,0 +1,126 @@
+"""Pins of the FP64 TTI oracle (Section III-B) against what the mathematics
+fixes: the isotropic limit, exactness of the rotated operator on quadratics,
+its symmetry and sign, the zero-source invariant, and the kinematics of an
+elliptically anisotropic medium."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2010_10248_amd import workloads as W
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) /
+                 max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def _tti_shot(seed, shape, so, nt, nbl, eps, dlt, th, ph, vp=None, nsrc=2, nrec=6):
+    s = W.acoustic_scaled(seed, shape, so, nt, nbl, nsrc=nsrc, nrec=nrec, layered=True)
+    if vp is not None:
+        s.vp = np.broadcast_to(vp, shape).astype(np.float64).copy()
+    s.physics = W.TTI
+    s.epsilon = np.broadcast_to(eps, shape).astype(np.float64).copy()
+    s.delta = np.broadcast_to(dlt, shape).astype(np.float64).copy()
+    s.theta = np.broadcast_to(th, shape).astype(np.float64).copy()
+    s.phi = np.broadcast_to(ph, shape).astype(np.float64).copy()
+    return s
+
+
+@pytest.mark.parametrize("so", [4, 8])
+def test_isotropic_limit_equals_acoustic(orc, so):
+    """eps = delta = 0: p and r obey the same update with the same source, so
+    p == r exactly, and H0 + Hz = L makes p the acoustic field for any tilt."""
+    shape = (22, 24, 26)
+    rng = np.random.Generator(np.random.PCG64(2))
+    th = W.smooth_field(rng, shape, -math.pi / 3, math.pi / 3, 3.0)
+    ph = W.smooth_field(rng, shape, -math.pi, math.pi, 3.0)
+    s = _tti_shot(11, shape, so, 40, 4, 0.0, 0.0, th, ph)
+    t = orc.tti_forward(s)
+    a = orc.acoustic_forward(s)
+    assert np.array_equal(t["p_last"], t["r_last"]) and np.array_equal(t["p_prev"], t["r_prev"])
+    assert np.abs(a["u_last"]).max() > 0
+    for k_t, k_a in (("traces", "traces"), ("p_last", "u_last"), ("p_prev", "u_prev")):
+        assert _rel(t[k_t], a[k_a]) <= 1e-12, k_t
+
+
+@pytest.mark.parametrize("so", [4, 8])
+@pytest.mark.parametrize("th,ph", [(0.0, 0.0), (math.pi / 2, 0.0), (0.4, -1.1), (-0.7, 2.3)])
+def test_rotated_operator_exact_on_quadratics(orc, so, th, ph):
+    """For u = x^T A x + b.x and a constant axis a, Hz u = a^T (A + A^T) a and
+    L u = trace(A + A^T) wherever the composed stencils stay inside the grid."""
+    n = (30, 31, 32)
+    h = (10.0, 12.0, 9.0)
+    rng = np.random.Generator(np.random.PCG64(int(10 * th + 100 * ph) % 1000 + so))
+    A = rng.standard_normal((3, 3))
+    b = rng.standard_normal(3)
+    xs = [(np.arange(m) - m / 2) * hh for m, hh in zip(n, h)]
+    X = np.meshgrid(*xs, indexing="ij")
+    u = sum(A[i, j] * X[i] * X[j] for i in range(3) for j in range(3)) + sum(
+        b[i] * X[i] for i in range(3))
+    lap, hz = orc.tti_operators(u, h, so, th, ph)
+    H = A + A.T
+    a = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+    r = so // 2
+    inner = tuple(slice(2 * r, m - 2 * r) for m in n)
+    scale = np.abs(H).max()
+    assert np.abs(hz[inner] - a @ H @ a).max() <= 1e-9 * scale
+    inner1 = tuple(slice(r, m - r) for m in n)
+    assert np.abs(lap[inner1] - np.trace(H)).max() <= 1e-9 * scale
+    # The near-boundary rows differ (zero outside the grid): the check above
+    # is not vacuous.
+    assert np.abs(hz - a @ H @ a).max() > 1e-3 * scale
+
+
+def test_rotated_operator_symmetric_negative_semidefinite(orc):
+    """Hz = -D^T D with the intermediate zero outside the grid."""
+    n = (20, 22, 24)
+    rng = np.random.Generator(np.random.PCG64(9))
+    th = W.smooth_field(rng, n, -1.0, 1.0, 3.0)
+    ph = W.smooth_field(rng, n, -3.0, 3.0, 3.0)
+    u = rng.standard_normal(n)
+    v = rng.standard_normal(n)
+    _, hu = orc.tti_operators(u, (10.0, 10.0, 10.0), 8, th, ph)
+    _, hv = orc.tti_operators(v, (10.0, 10.0, 10.0), 8, th, ph)
+    lhs, rhs = float(np.sum(v * hu)), float(np.sum(hv * u))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    assert float(np.sum(u * hu)) < 0 and float(np.sum(v * hv)) < 0
+
+
+def test_tti_zero_source_is_exactly_zero(orc):
+    n = (18, 20, 22)
+    s = _tti_shot(4, n, 8, 20, 3, 0.2, 0.1, 0.5, 0.3)
+    t = orc.tti_forward(s, src_wav=np.zeros_like(s.src_wav))
+    for k in ("traces", "p_last", "p_prev", "r_last", "r_prev"):
+        assert np.all(t[k] == 0.0), k
+
+
+def test_elliptic_kinematics(orc):
+    """eps = delta (elliptic anisotropy), vertical axis: the wavefront is an
+    ellipse with speed vp along the axis and vp sqrt(1+2 eps) across it, so
+    the Ricker peak reaches distance R at angle psi from the axis at
+    t0 + R sqrt(sin^2 psi / vx^2 + cos^2 psi / vz^2)."""
+    n = (60, 44, 60)
+    h = 10.0
+    eps = 0.2
+    vp = 1500.0
+    vx = vp * math.sqrt(1 + 2 * eps)
+    dt = W.cfl_dt(vx, h)
+    f0 = 12.0
+    nt = int(0.27 / dt)
+    s = _tti_shot(1, n, 8, nt, 8, eps, eps, 0.0, 0.0, vp=vp, nsrc=1, nrec=3)
+    s.dt = dt
+    src = np.array([20.3, 22.0, 16.2]) * h
+    R = 18.0 * h
+    psis = [0.0, math.pi / 2, math.pi / 4]
+    s.src_xyz = src[None, :]
+    s.src_wav = W.ricker(f0, nt, dt)[:, None]
+    s.rec_xyz = np.array([src + R * np.array([math.sin(p), 0.0, math.cos(p)]) for p in psis])
+    tr = orc.tti_forward(s)["traces"]
+    t0 = 1.0 / f0
+    for k, psi in enumerate(psis):
+        i = int(np.argmax(tr[:, k]))
+        y0, y1, y2 = tr[i - 1, k], tr[i, k], tr[i + 1, k]
+        t_pk = (i + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)) * dt
+        want = t0 + R * math.sqrt(math.sin(psi) ** 2 / vx ** 2 + math.cos(psi) ** 2 / vp ** 2)
+        assert abs(t_pk - want) <= 0.01 * (want - t0), (psi, t_pk, want)
