@@ -67,6 +67,10 @@ tb_status tb_autotune(const tb_model *m, const tb_sparse *s_, int32_t steps, voi
         set_error("tb_autotune: invalid argument");
         return TB_EINVAL;
     }
+    if (m->physics != TB_ACOUSTIC) {
+        set_error("tb_autotune: only the acoustic propagator has schedules to tune");
+        return TB_EUNSUPPORTED;
+    }
     hipStream_t st = (hipStream_t)stream;
     steps = std::min<int32_t>(steps, std::max(m->nt, 1));
     const size_t fb = (m->field_elems() * sizeof(float) + 255) & ~(size_t)255;

@@ -5,6 +5,7 @@
 #include <cstring>
 
 #include "plan.h"
+#include "tti_params.h"
 
 namespace tbw {
 const char *last_error();
@@ -19,6 +20,7 @@ tb_model::~tb_model()
     if (d_c) (void)hipFree(d_c);
     if (d_damp) (void)hipFree(d_damp);
     if (d_zero) (void)hipFree(d_zero);
+    if (d_tti) (void)hipFree(d_tti);
 }
 
 tb_sparse::~tb_sparse()
@@ -27,7 +29,7 @@ tb_sparse::~tb_sparse()
     for (void *p : {(void *)d_dcmp, (void *)d_rc_ptr, (void *)d_rc_id, (void *)d_rc_w,
                     (void *)d_sc_ptr, (void *)d_sc_id, (void *)d_sc_w, (void *)d_rr_ptr,
                     (void *)d_rr_rec, (void *)d_rr_w, (void *)d_rid_scale, (void *)d_src_off,
-                    (void *)d_src_alpha})
+                    (void *)d_src_alpha, (void *)d_rid_off})
         if (p) (void)hipFree(p);
 }
 
@@ -95,6 +97,11 @@ tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice 
     } else {
         SchedChoice t;
         if (tuned_schedule(m, &t)) c = t;
+        if (m->physics != TB_ACOUSTIC) c.T = 1;
+    }
+    if (m->physics != TB_ACOUSTIC && c.T != 1) {
+        set_error("temporal blocking is built for the acoustic propagator only");
+        return TB_EUNSUPPORTED;
     }
     if (c.T < 1 || c.T > 4) {
         set_error("time_tile %d not in 1..4", c.T);
@@ -344,8 +351,92 @@ tb_status run_plan(const tb_model *m, tb_sparse *s, const SchedChoice &sc, const
 
 size_t forward_ws_bytes(const tb_model *m, const tb_sparse *s)
 {
-    return 4 * field_bytes(m) + align256(((size_t)m->nt + 1) * std::max(s->nrid, 1) * sizeof(float));
+    const size_t nf = m->physics == TB_TTI ? 6 : 4;
+    return nf * field_bytes(m) +
+           align256(((size_t)m->nt + 1) * std::max(s->nrid, 1) * sizeof(float));
 }
+
+namespace {
+
+// TTI forward (SB): p, p_prev, r, r_prev, q_p, q_r, then rec_dcmp.
+tb_status plan_forward_tti(const tb_model *m, tb_sparse *s, void *ws, float *rec_out,
+                           float *field_out, float *field_prev_out, Plan *plan)
+{
+    const size_t fb = field_bytes(m), fe = m->field_elems();
+    char *base = (char *)ws;
+    float *F[6];
+    for (int k = 0; k < 6; k++) F[k] = (float *)(base + k * fb);
+    float *rec = (float *)(base + 6 * fb);
+    for (int k = 0; k < 6; k++) plan->push_back(fill_item(F[k], fe));
+    const int nrid = s->nrid, npts = s->npts, nt = m->nt;
+    if (nrid > 0) plan->push_back(fill_item(rec, (size_t)nrid));
+    TtiParams P{};
+    P.ax = m->d_tti;
+    P.ay = m->d_tti + fe;
+    P.az = m->d_tti + 2 * fe;
+    P.e1 = m->d_tti + 3 * fe;
+    P.sd = m->d_tti + 4 * fe;
+    P.c = m->d_c;
+    P.dx = m->d_damp;
+    P.dy = m->d_damp + m->n[0];
+    P.dz = m->d_damp + m->n[0] + m->n[1];
+    P.hdt = (float)(m->dt / 2.0);
+    // Centred weights on unit spacing (Fornberg rationals).
+    static const double d1_4[2] = {2.0 / 3.0, -1.0 / 12.0};
+    static const double d1_8[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+    const double *d1 = m->so == 4 ? d1_4 : d1_8;
+    const double *d2 = d2_weights(m->so);
+    for (int j = 0; j < 4; j++) P.w1[j] = j < m->r ? (float)d1[j] : 0.0f;
+    for (int j = 0; j < 5; j++) P.w2[j] = j <= m->r ? (float)d2[j] : 0.0f;
+    for (int a = 0; a < 3; a++) {
+        P.ih[a] = (float)(1.0 / m->h[a]);
+        P.ih2[a] = (float)(1.0 / (m->h[a] * m->h[a]));
+    }
+    P.nx = m->n[0];
+    P.ny = m->n[1];
+    P.nz = m->n[2];
+    P.nzp = m->nzp;
+    P.qp = F[4];
+    P.qr = F[5];
+    const int r = m->r;
+    const float *dcmp = s->d_dcmp;
+    const long long *soff = s->d_src_off, *roff = s->d_rid_off;
+    int pc = 0, pp = 1;  // p^n in F[pc], p^{n-1} in F[pp]; r in F[pc + 2], F[pp + 2]
+    for (int n = 0; n < nt; n++) {
+        TtiParams Q = P;
+        Q.p = F[pc];
+        Q.pm = F[pp];
+        Q.r = F[pc + 2];
+        Q.rm = F[pp + 2];
+        const float *inc = dcmp + (size_t)n * npts;
+        float *row = rec + (size_t)(n + 1) * nrid;
+        plan->push_back(act_item([=](hipStream_t st) {
+            return launch_tti_step(Q, r, inc, soff, npts, row, roff, nrid, st);
+        }));
+        std::swap(pc, pp);
+    }
+    if (rec_out && s->nrec > 0 && nt > 0) {
+        const int nrec = s->nrec;
+        const int *ptr = s->d_rc_ptr, *id = s->d_rc_id;
+        const float *w = s->d_rc_w;
+        plan->push_back(act_item([=](hipStream_t st) {
+            return launch_trace_reduce(rec, nrid, nt, ptr, id, w, nrec, rec_out, 0, st);
+        }));
+    }
+    const int nx = m->n[0], ny = m->n[1], nz = m->n[2], nzp = m->nzp;
+    float *fc = F[pc], *fp = F[pp];
+    if (field_out)
+        plan->push_back(act_item([=](hipStream_t st) {
+            return launch_unpad(fc, field_out, nx, ny, nz, nzp, st);
+        }));
+    if (field_prev_out)
+        plan->push_back(act_item([=](hipStream_t st) {
+            return launch_unpad(fp, field_prev_out, nx, ny, nz, nzp, st);
+        }));
+    return TB_OK;
+}
+
+}  // namespace
 
 size_t gradient_ws_bytes(const tb_model *m, const tb_sparse *s, const SchedChoice &sc, int every)
 {
@@ -355,6 +446,8 @@ size_t gradient_ws_bytes(const tb_model *m, const tb_sparse *s, const SchedChoic
 tb_status plan_forward(const tb_model *m, tb_sparse *s, const SchedChoice &sc, void *ws,
                        float *rec_out, float *field_out, float *field_prev_out, Plan *plan)
 {
+    if (m->physics == TB_TTI)
+        return plan_forward_tti(m, s, ws, rec_out, field_out, field_prev_out, plan);
     const size_t fb = field_bytes(m), fe = m->field_elems();
     char *base = (char *)ws;
     float *F[4] = {(float *)base, (float *)(base + fb), (float *)(base + 2 * fb),
@@ -390,6 +483,10 @@ tb_status plan_forward(const tb_model *m, tb_sparse *s, const SchedChoice &sc, v
 tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int every,
                         void *ws, const float *d_obs, float *grad_m, double *loss_dst, Plan *plan)
 {
+    if (m->physics != TB_ACOUSTIC) {
+        set_error("the gradient is built for the acoustic propagator only");
+        return TB_EUNSUPPORTED;
+    }
     const GradLayout L = grad_layout(m, s, sc, every);
     const int nt = m->nt, K = L.K;
     const size_t fb = field_bytes(m), fe = m->field_elems();
@@ -588,9 +685,13 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
         set_error("tb_create_model: desc is NULL");
         return TB_EINVAL;
     }
-    if (d->physics != TB_ACOUSTIC) {
+    if (d->physics != TB_ACOUSTIC && d->physics != TB_TTI) {
         set_error("physics %d is not built", d->physics);
         return TB_EUNSUPPORTED;
+    }
+    if (d->physics == TB_TTI && (!d->epsilon || !d->delta || !d->theta || !d->phi)) {
+        set_error("TTI needs epsilon, delta, theta and phi");
+        return TB_EINVAL;
     }
     if (d->space_order != 4 && d->space_order != 8) {
         set_error("space order %d not supported (4 or 8)", d->space_order);
@@ -638,6 +739,36 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
         vpmax = std::max(vpmax, (double)vp[i]);
     }
     m->vmax = d->damp_vmax > 0.0 ? d->damp_vmax : vpmax;
+    // TTI parameters: the fastest phase velocity is vp sqrt(1 + 2 eps).
+    std::vector<float> tti_host;
+    double vstab = vpmax;
+    if (d->physics == TB_TTI) {
+        std::vector<float> ep(N), de(N), th(N), ph(N);
+        TB_HIP(hipMemcpy(ep.data(), d->epsilon, N * sizeof(float), hipMemcpyDeviceToHost));
+        TB_HIP(hipMemcpy(de.data(), d->delta, N * sizeof(float), hipMemcpyDeviceToHost));
+        TB_HIP(hipMemcpy(th.data(), d->theta, N * sizeof(float), hipMemcpyDeviceToHost));
+        TB_HIP(hipMemcpy(ph.data(), d->phi, N * sizeof(float), hipMemcpyDeviceToHost));
+        const size_t fe = m->field_elems();
+        tti_host.assign(5 * fe, 0.0f);
+        for (size_t x = 0; x < (size_t)nx; x++)
+            for (size_t y = 0; y < (size_t)ny; y++)
+                for (size_t z = 0; z < (size_t)nz; z++) {
+                    const size_t i = (x * ny + y) * nz + z, q = (x * ny + y) * m->nzp + z;
+                    const double e = ep[i], dl = std::min((double)de[i], e);
+                    if (!(e >= 0.0) || !(dl > -0.5) || !std::isfinite(th[i]) ||
+                        !std::isfinite(ph[i])) {
+                        set_error("TTI parameters at node %zu invalid", i);
+                        return TB_EINVAL;
+                    }
+                    const double t = th[i], f = ph[i];
+                    tti_host[q] = (float)(std::sin(t) * std::cos(f));
+                    tti_host[fe + q] = (float)(std::sin(t) * std::sin(f));
+                    tti_host[2 * fe + q] = (float)std::cos(t);
+                    tti_host[3 * fe + q] = (float)(1.0 + 2.0 * e);
+                    tti_host[4 * fe + q] = (float)std::sqrt(1.0 + 2.0 * dl);
+                    vstab = std::max(vstab, (double)vp[i] * std::sqrt(1.0 + 2.0 * e));
+                }
+    }
     // Leapfrog stability: dt^2 vp_max^2 * sum_a |symbol max| / h_a^2 <= 4.
     const double *w = d2_weights(m->so);
     double sym = w[0];
@@ -645,9 +776,9 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
     sym = std::fabs(sym);
     double rho = 0.0;
     for (int a = 0; a < 3; a++) rho += sym / (m->h[a] * m->h[a]);
-    if (m->dt * m->dt * vpmax * vpmax * rho > 4.0) {
-        set_error("dt = %g exceeds the stability bound %g for vp_max = %g", m->dt,
-                  2.0 / (vpmax * std::sqrt(rho)), vpmax);
+    if (m->dt * m->dt * vstab * vstab * rho > 4.0) {
+        set_error("dt = %g exceeds the stability bound %g for the fastest velocity %g", m->dt,
+                  2.0 / (vstab * std::sqrt(rho)), vstab);
         return TB_EUNSTABLE;
     }
     m->c64.resize(N);
@@ -669,6 +800,11 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
     TB_HIP(hipMemcpy(m->d_c, cpad.data(), cpad.size() * sizeof(float), hipMemcpyHostToDevice));
     TB_HIP(hipMalloc(&m->d_zero, 256));
     TB_HIP(hipMemset(m->d_zero, 0, 256));
+    if (!tti_host.empty()) {
+        TB_HIP(hipMalloc(&m->d_tti, tti_host.size() * sizeof(float)));
+        TB_HIP(hipMemcpy(m->d_tti, tti_host.data(), tti_host.size() * sizeof(float),
+                         hipMemcpyHostToDevice));
+    }
     TB_HIP(hipMalloc(&m->d_damp, m->damp.size() * sizeof(float)));
     TB_HIP(hipMemcpy(m->d_damp, m->damp.data(), m->damp.size() * sizeof(float),
                      hipMemcpyHostToDevice));
@@ -746,6 +882,12 @@ tb_status tb_inspect_sparse(const tb_model *m, int32_t nsrc, const double *src_x
         salpha[i] = alpha_at(r);
     }
     if ((st = upload(&s->d_src_off, soff)) || (st = upload(&s->d_src_alpha, salpha))) return st;
+    std::vector<long long> roff(s->nrid);
+    for (int i = 0; i < s->nrid; i++) {
+        const int64_t r = s->rid_nodes[i];
+        roff[i] = (long long)((r / nz) * m->nzp + r % nz);
+    }
+    if ((st = upload(&s->d_rid_off, roff))) return st;
     *out = s.release();
     return TB_OK;
 }
@@ -822,6 +964,10 @@ tb_status tb_adjoint(const tb_model *m, const tb_sparse *s_, const tb_schedule *
     if (!m || !s || s->m != m || !ws || (s->nrec > 0 && m->nt > 0 && !rec_in)) {
         set_error("tb_adjoint: invalid argument");
         return TB_EINVAL;
+    }
+    if (m->physics != TB_ACOUSTIC) {
+        set_error("the adjoint is built for the acoustic propagator only");
+        return TB_EUNSUPPORTED;
     }
     SchedChoice sc;
     tb_status st = resolve_schedule(m, sched, &sc);

@@ -100,6 +100,9 @@ struct tb_model {
     float *d_c = nullptr;     // dt^2 vp^2, [nx][ny][nzp]
     float *d_damp = nullptr;  // d_x[nx] | d_y[ny] | d_z[nzp]
     float *d_zero = nullptr;  // 256 zeroed bytes
+    // TTI: five padded fields ax, ay, az (symmetry axis), 1 + 2 eps and
+    // sqrt(1 + 2 min(delta, eps)), each field_elems() long.
+    float *d_tti = nullptr;
     std::vector<double> c64;  // host copy of dt^2 vp^2 (FP64 from the FP32 vp)
     std::vector<float> damp;  // host copy of the three tables
     size_t field_elems() const { return (size_t)n[0] * n[1] * nzp; }
@@ -135,6 +138,9 @@ struct tb_sparse {
     // Imaging at the injection points: padded offset and alpha of each SID.
     long long *d_src_off = nullptr;
     double *d_src_alpha = nullptr;
+    // Padded offsets of the receiver points (gathers outside the wave-front
+    // kernel).
+    long long *d_rid_off = nullptr;
     std::mutex mu;
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<tbw::TileLists>> tiles;
     ~tb_sparse();

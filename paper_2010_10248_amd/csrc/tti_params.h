@@ -1,0 +1,30 @@
+// Kernel arguments of the TTI step kernels (tti.hip).
+#pragma once
+
+#include "tb_internal.h"
+
+namespace tbw {
+
+struct TtiParams {
+    const float *p, *r;  // current levels p^n, r^n        [nx][ny][nzp]
+    float *pm, *rm;      // p^{n-1}, r^{n-1}; receive p^{n+1}, r^{n+1}
+    float *qp, *qr;      // rotated gradients (scratch)
+    const float *ax, *ay, *az;  // symmetry axis per node
+    const float *e1, *sd;       // 1 + 2 eps, sqrt(1 + 2 min(delta, eps))
+    const float *c;             // dt^2 vp^2
+    const float *dx, *dy, *dz;  // damping per axis
+    float hdt;                  // dt / 2
+    float w1[4];                // centred first derivative, unit spacing
+    float w2[5];                // centred second derivative, unit spacing
+    float ih[3], ih2[3];        // 1/h and 1/h^2 per axis
+    int nx, ny, nz, nzp;
+};
+
+// One step: rotated gradients, coupled update (in place over the previous
+// levels), injection of inc[npts] at soff into both fields, gather of p into
+// rec_row[nrid] at roff.
+tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const long long *soff,
+                          int npts, float *rec_row, const long long *roff, int nrid,
+                          hipStream_t st);
+
+}  // namespace tbw

@@ -172,8 +172,10 @@ def _stream(stream) -> Optional[int]:
 
 
 def create_model(shape, spacing, origin, space_order, nbl, dt, nt, vp, damp_vmax=0.0,
-                 physics=ACOUSTIC):
-    """vp: float32 CUDA tensor [nx][ny][nz]. Returns an opaque handle."""
+                 physics=ACOUSTIC, epsilon=None, delta=None, theta=None, phi=None, vs=None,
+                 rho=None):
+    """vp (and the physics' other parameters): float32 CUDA tensors
+    [nx][ny][nz]. Returns an opaque handle."""
     d = ModelDesc()
     d.physics = physics
     d.shape[:] = [int(v) for v in shape]
@@ -185,6 +187,9 @@ def create_model(shape, spacing, origin, space_order, nbl, dt, nt, vp, damp_vmax
     d.nt = int(nt)
     d.damp_vmax = float(damp_vmax)
     d.vp = None if vp is None else vp.data_ptr()
+    for name, t in (("epsilon", epsilon), ("delta", delta), ("theta", theta), ("phi", phi),
+                    ("vs", vs), ("rho", rho)):
+        setattr(d, name, None if t is None else t.data_ptr())
     h = _vp()
     _check(lib().tb_create_model(ctypes.byref(d), ctypes.byref(h)), "tb_create_model")
     return h
@@ -357,8 +362,9 @@ class Server:
             pass
 
 
-class Acoustic:
-    """A model plus its sparse operators on the current CUDA device."""
+class Propagator:
+    """A model (acoustic or TTI, from the shot's physics) plus its sparse
+    operators on the current CUDA device."""
 
     def __init__(self, shot, vp=None, src_wav=None, device="cuda", damp_vmax: float = 0.0):
         import torch
@@ -371,8 +377,17 @@ class Acoustic:
         else:
             self.vp = torch.as_tensor(np.ascontiguousarray(vp, dtype=np.float32),
                                       device=self.device)
+        physics = getattr(shot, "physics", ACOUSTIC)
+        extra = {}
+        if physics == TTI:
+            for name in ("epsilon", "delta", "theta", "phi"):
+                extra[name] = torch.as_tensor(
+                    np.ascontiguousarray(getattr(shot, name), dtype=np.float32),
+                    device=self.device)
+        self._params = extra
         self.model = create_model(shot.shape, shot.spacing, shot.origin, shot.space_order,
-                                  shot.nbl, shot.dt, shot.nt, self.vp, damp_vmax=damp_vmax)
+                                  shot.nbl, shot.dt, shot.nt, self.vp, damp_vmax=damp_vmax,
+                                  physics=physics, **extra)
         wav = shot.src_wav if src_wav is None else src_wav
         self.sparse = inspect_sparse(self.model, shot.src_xyz, wav, shot.rec_xyz)
         self.nsrc = shot.src_xyz.shape[0]
@@ -435,3 +450,6 @@ class Acoustic:
         J = gradient(self.model, self.sparse, sched, ws, d_obs.contiguous(), g, checkpoint_every,
                      stream)
         return J, g
+
+
+Acoustic = Propagator
