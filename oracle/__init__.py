@@ -262,6 +262,36 @@ def tti_operators(u, spacing, so: int, theta, phi):
     return lap_out, hz
 
 
+ELASTIC_FIELDS = ("vx", "vy", "vz", "txx", "tyy", "tzz", "txy", "txz", "tyz")
+
+
+def elastic_forward(shot, vmax_damp: float = 0.0, src_wav=None, vp=None, vs=None, rho=None,
+                    want_energy: bool = False):
+    """FP64 elastic velocity-stress forward of a ``workloads.Shot`` (zero
+    initial state). Returns dict(vz[nt][nrec], p[nt][nrec] traces, the nine
+    final fields by name, energy[nt] if asked)."""
+    n = np.asarray(shot.shape, dtype=np.int32)
+    f = lambda a, b: _f64(b if a is None else a)
+    vp, vs, rho = f(vp, shot.vp), f(vs, shot.vs), f(rho, shot.rho)
+    wav = f(src_wav, shot.src_wav)
+    sx = _f64(shot.src_xyz)
+    rx = _f64(shot.rec_xyz)
+    nrec = rx.shape[0]
+    traces = np.zeros((2, shot.nt, nrec))
+    state = np.zeros((9,) + tuple(shot.shape))
+    energy = np.zeros(shot.nt) if want_energy else None
+    st = lib().or_elastic_forward(n, _f64(shot.spacing), _f64(shot.origin), shot.space_order,
+                                  shot.nbl, float(shot.dt), shot.nt, vp, vs, rho,
+                                  float(vmax_damp), sx.shape[0], sx, wav, nrec, rx,
+                                  _ptr(traces), _ptr(state), _ptr(energy))
+    _check(st, "elastic_forward")
+    out = dict(vz=traces[0], p=traces[1])
+    out.update({k: state[i] for i, k in enumerate(ELASTIC_FIELDS)})
+    if want_energy:
+        out["energy"] = energy
+    return out
+
+
 def misfit(d, dobs) -> float:
     d = _f64(d)
     dobs = _f64(dobs)

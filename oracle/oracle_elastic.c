@@ -1,0 +1,247 @@
+/*
+ * FP64 CPU oracle of the isotropic elastic velocity-stress propagator
+ * (Section III-C of "Temporal blocking of finite-difference stencil operators
+ * with sparse off-the-grid sources", Bisbas et al., arXiv 2010.10248).
+ *
+ * TEST INFRASTRUCTURE ONLY, like oracle.c.
+ *
+ * The paper gives the first-order system (its elastic equations) and leaves
+ * the discretisation open. Reading used here (listed in the design notes):
+ *  - Staggered grid: txx, tyy, tzz at nodes (i, j, k); vx at (i+1/2, j, k),
+ *    vy at (i, j+1/2, k), vz at (i, j, k+1/2); txy at (i+1/2, j+1/2, k),
+ *    txz at (i+1/2, j, k+1/2), tyz at (i, j+1/2, k+1/2); all arrays n^3, the
+ *    element [i][j][k] at the node index plus the component's half offsets.
+ *  - Staggered first derivatives of the space order (weights of +-(m+1/2)),
+ *    every field zero outside the grid.
+ *  - b = 1/rho, mu = rho vs^2, lambda = rho (vp^2 - 2 vs^2) at nodes; b at a
+ *    velocity point is the mean of its 2 neighbouring nodes, mu at a shear
+ *    point the mean of its 4 neighbouring nodes (a neighbour outside the grid
+ *    takes the value of the nearest node inside).
+ *  - Step n from (v^{n-1/2}, t^n), damping d at the element's node index:
+ *      v^{n+1/2} = (beta v^{n-1/2} + dt b (div t^n)) / alpha
+ *      t^{n+1}   = (beta t^n + dt (lambda tr(grad v) I + mu (grad v + grad v^T))) / alpha
+ *      t_ii^{n+1} += dt W q(t_n)       (explosive source, i = x, y, z)
+ *  - Receivers read the current levels: vz^{n-1/2} (trilinear on the vz grid,
+ *    whose origin is shifted by h/2 in z) and P^n = (txx + tyy + tzz)^n / 3.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef int64_t i64;
+
+#define OR_OK 0
+#define OR_EINVAL -1
+#define OR_ENOMEM -3
+
+int or_weights_d1_staggered(int so, double *w);
+int or_trilinear(const double *p, const double *o, const double *h, const int *n, int *nodes,
+                 double *w);
+void or_damping(const int *n, const double *h, int nbl, double vmax, double *d);
+
+enum { VX, VY, VZ, TXX, TYY, TZZ, TXY, TXZ, TYZ, NF };
+
+typedef struct {
+    int n[3], r;
+    double h[3];
+    double w[8];
+} egrid;
+
+static inline i64 idx(const egrid *G, i64 i, i64 j, i64 k)
+{
+    return (i * G->n[1] + j) * G->n[2] + k;
+}
+
+static inline double at(const egrid *G, const double *u, i64 i, i64 j, i64 k)
+{
+    if (i < 0 || j < 0 || k < 0 || i >= G->n[0] || j >= G->n[1] || k >= G->n[2]) return 0.0;
+    return u[idx(G, i, j, k)];
+}
+
+/* Staggered derivative along axis ax at element (i, j, k). fwd = 1: the field
+ * sits at integer positions along ax and the target half a cell above
+ * (samples [i+m+1] - [i-m]); fwd = 0: the field sits half a cell above its
+ * index and the target at the integer position (samples [i+m] - [i-m-1]). */
+static double dst(const egrid *G, const double *u, i64 i, i64 j, i64 k, int ax, int fwd)
+{
+    double s = 0.0;
+    for (int m = 0; m < G->r; m++) {
+        i64 a = fwd ? m + 1 : m, b = fwd ? -m : -m - 1;
+        double up = at(G, u, i + (ax == 0 ? a : 0), j + (ax == 1 ? a : 0), k + (ax == 2 ? a : 0));
+        double dn = at(G, u, i + (ax == 0 ? b : 0), j + (ax == 1 ? b : 0), k + (ax == 2 ? b : 0));
+        s += G->w[m] * (up - dn);
+    }
+    return s / G->h[ax];
+}
+
+static inline double clampv(const egrid *G, const double *p, i64 i, i64 j, i64 k)
+{
+    i = i < 0 ? 0 : (i >= G->n[0] ? G->n[0] - 1 : i);
+    j = j < 0 ? 0 : (j >= G->n[1] ? G->n[1] - 1 : j);
+    k = k < 0 ? 0 : (k >= G->n[2] ? G->n[2] - 1 : k);
+    return p[idx(G, i, j, k)];
+}
+
+static int interp(const egrid *G, const double *o, const double *u, const double *xyz,
+                  double *out)
+{
+    int nodes[24];
+    double w[8];
+    int cnt = or_trilinear(xyz, o, G->h, G->n, nodes, w);
+    if (cnt < 0) return cnt;
+    double s = 0.0;
+    for (int c = 0; c < cnt; c++) s += w[c] * u[idx(G, nodes[3 * c], nodes[3 * c + 1], nodes[3 * c + 2])];
+    *out = s;
+    return OR_OK;
+}
+
+/*
+ * Forward run from zero state. traces[2][nt][nrec]: vz then P (either block
+ * zero-sized if traces is NULL). state[9][N] (optional): v^{nt-1/2} and
+ * t^{nt} in the order vx vy vz txx tyy tzz txy txz tyz. energy[nt]
+ * (optional): E^{n+1/2} = 1/2 sum_v |v^{n+1/2}|^2 / b + 1/2 <t^{n+1}, C^-1 t^n>
+ * after step n (needs mu > 0 everywhere; exactly conserved by the scheme
+ * without damping and source).
+ */
+int or_elastic_forward(const int *n, const double *h, const double *o, int so, int nbl,
+                       double dt, int nt, const double *vp, const double *vs, const double *rho,
+                       double vmax_damp, int nsrc, const double *src_xyz, const double *src_wav,
+                       int nrec, const double *rec_xyz, double *traces, double *state,
+                       double *energy)
+{
+    egrid G;
+    memcpy(G.n, n, sizeof(int) * 3);
+    memcpy(G.h, h, sizeof(double) * 3);
+    G.r = so / 2;
+    if (so < 2 || so > 16 || so % 2 || or_weights_d1_staggered(so, G.w)) return OR_EINVAL;
+    const i64 N = (i64)n[0] * n[1] * n[2];
+    double *F = calloc((size_t)NF * N, sizeof(double));
+    double *Fold = calloc(6 * (size_t)N, sizeof(double));
+    double *P = calloc((size_t)10 * N, sizeof(double));
+    if (!F || !Fold || !P) {
+        free(F); free(Fold); free(P);
+        return OR_ENOMEM;
+    }
+    double *b = P, *lam = P + N, *mu = P + 2 * N, *bx = P + 3 * N, *by = P + 4 * N,
+           *bz = P + 5 * N, *mxy = P + 6 * N, *mxz = P + 7 * N, *myz = P + 8 * N, *dmp = P + 9 * N;
+    double vmax = vmax_damp;
+    if (!(vmax > 0.0)) {
+        vmax = 0.0;
+        for (i64 q = 0; q < N; q++)
+            if (vp[q] > vmax) vmax = vp[q];
+    }
+    or_damping(n, h, nbl, vmax, dmp);
+    for (i64 q = 0; q < N; q++) {
+        b[q] = 1.0 / rho[q];
+        mu[q] = rho[q] * vs[q] * vs[q];
+        lam[q] = rho[q] * (vp[q] * vp[q] - 2.0 * vs[q] * vs[q]);
+    }
+    for (i64 i = 0; i < n[0]; i++)
+        for (i64 j = 0; j < n[1]; j++)
+            for (i64 k = 0; k < n[2]; k++) {
+                i64 q = idx(&G, i, j, k);
+                bx[q] = 0.5 * (clampv(&G, b, i, j, k) + clampv(&G, b, i + 1, j, k));
+                by[q] = 0.5 * (clampv(&G, b, i, j, k) + clampv(&G, b, i, j + 1, k));
+                bz[q] = 0.5 * (clampv(&G, b, i, j, k) + clampv(&G, b, i, j, k + 1));
+                mxy[q] = 0.25 * (clampv(&G, mu, i, j, k) + clampv(&G, mu, i + 1, j, k) +
+                                 clampv(&G, mu, i, j + 1, k) + clampv(&G, mu, i + 1, j + 1, k));
+                mxz[q] = 0.25 * (clampv(&G, mu, i, j, k) + clampv(&G, mu, i + 1, j, k) +
+                                 clampv(&G, mu, i, j, k + 1) + clampv(&G, mu, i + 1, j, k + 1));
+                myz[q] = 0.25 * (clampv(&G, mu, i, j, k) + clampv(&G, mu, i, j + 1, k) +
+                                 clampv(&G, mu, i, j, k + 1) + clampv(&G, mu, i, j + 1, k + 1));
+            }
+    double *vx = F + VX * N, *vy = F + VY * N, *vz = F + VZ * N;
+    double *txx = F + TXX * N, *tyy = F + TYY * N, *tzz = F + TZZ * N;
+    double *txy = F + TXY * N, *txz = F + TXZ * N, *tyz = F + TYZ * N;
+    double ovz[3] = {o[0], o[1], o[2] + 0.5 * h[2]};
+    int st = OR_OK;
+    for (int t = 0; t < nt; t++) {
+        /* Receivers read the current levels v^{t-1/2}, t^t. */
+        if (traces) {
+            for (int r = 0; r < nrec; r++) {
+                double a, sxx, syy, szz;
+                if ((st = interp(&G, ovz, vz, rec_xyz + 3 * r, &a))) goto done;
+                if ((st = interp(&G, o, txx, rec_xyz + 3 * r, &sxx))) goto done;
+                if ((st = interp(&G, o, tyy, rec_xyz + 3 * r, &syy))) goto done;
+                if ((st = interp(&G, o, tzz, rec_xyz + 3 * r, &szz))) goto done;
+                traces[(i64)t * nrec + r] = a;
+                traces[((i64)nt + t) * nrec + r] = (sxx + syy + szz) / 3.0;
+            }
+        }
+        if (energy) memcpy(Fold, F + TXX * N, sizeof(double) * 6 * N);
+        /* Velocity pass. */
+#pragma omp parallel for schedule(static)
+        for (i64 i = 0; i < n[0]; i++)
+            for (i64 j = 0; j < n[1]; j++)
+                for (i64 k = 0; k < n[2]; k++) {
+                    i64 q = idx(&G, i, j, k);
+                    double al = 1.0 + dmp[q] * dt / 2.0, be = 1.0 - dmp[q] * dt / 2.0;
+                    double fx = dst(&G, txx, i, j, k, 0, 1) + dst(&G, txy, i, j, k, 1, 0) +
+                                dst(&G, txz, i, j, k, 2, 0);
+                    double fy = dst(&G, txy, i, j, k, 0, 0) + dst(&G, tyy, i, j, k, 1, 1) +
+                                dst(&G, tyz, i, j, k, 2, 0);
+                    double fz = dst(&G, txz, i, j, k, 0, 0) + dst(&G, tyz, i, j, k, 1, 0) +
+                                dst(&G, tzz, i, j, k, 2, 1);
+                    vx[q] = (be * vx[q] + dt * bx[q] * fx) / al;
+                    vy[q] = (be * vy[q] + dt * by[q] * fy) / al;
+                    vz[q] = (be * vz[q] + dt * bz[q] * fz) / al;
+                }
+        /* Stress pass. */
+#pragma omp parallel for schedule(static)
+        for (i64 i = 0; i < n[0]; i++)
+            for (i64 j = 0; j < n[1]; j++)
+                for (i64 k = 0; k < n[2]; k++) {
+                    i64 q = idx(&G, i, j, k);
+                    double al = 1.0 + dmp[q] * dt / 2.0, be = 1.0 - dmp[q] * dt / 2.0;
+                    double exx = dst(&G, vx, i, j, k, 0, 0), eyy = dst(&G, vy, i, j, k, 1, 0),
+                           ezz = dst(&G, vz, i, j, k, 2, 0);
+                    double tr = exx + eyy + ezz;
+                    txx[q] = (be * txx[q] + dt * (lam[q] * tr + 2.0 * mu[q] * exx)) / al;
+                    tyy[q] = (be * tyy[q] + dt * (lam[q] * tr + 2.0 * mu[q] * eyy)) / al;
+                    tzz[q] = (be * tzz[q] + dt * (lam[q] * tr + 2.0 * mu[q] * ezz)) / al;
+                    double gxy = dst(&G, vx, i, j, k, 1, 1) + dst(&G, vy, i, j, k, 0, 1);
+                    double gxz = dst(&G, vx, i, j, k, 2, 1) + dst(&G, vz, i, j, k, 0, 1);
+                    double gyz = dst(&G, vy, i, j, k, 2, 1) + dst(&G, vz, i, j, k, 1, 1);
+                    txy[q] = (be * txy[q] + dt * mxy[q] * gxy) / al;
+                    txz[q] = (be * txz[q] + dt * mxz[q] * gxz) / al;
+                    tyz[q] = (be * tyz[q] + dt * myz[q] * gyz) / al;
+                }
+        /* Explosive source into the normal stresses. */
+        for (int s = 0; s < nsrc; s++) {
+            int nodes[24];
+            double w[8];
+            int cnt = or_trilinear(src_xyz + 3 * s, o, h, n, nodes, w);
+            if (cnt < 0) { st = cnt; goto done; }
+            double qv = src_wav[(i64)t * nsrc + s];
+            for (int c = 0; c < cnt; c++) {
+                i64 q = idx(&G, nodes[3 * c], nodes[3 * c + 1], nodes[3 * c + 2]);
+                txx[q] += dt * w[c] * qv;
+                tyy[q] += dt * w[c] * qv;
+                tzz[q] += dt * w[c] * qv;
+            }
+        }
+        if (energy) {
+            double e = 0.0;
+            for (i64 q = 0; q < N; q++) {
+                e += 0.5 * (vx[q] * vx[q] / bx[q] + vy[q] * vy[q] / by[q] + vz[q] * vz[q] / bz[q]);
+                /* Normal part: C^-1 = (I - lam/(3 lam + 2 mu) 1 1^T) / (2 mu). */
+                const double *o6 = Fold;
+                double a1 = txx[q], a2 = tyy[q], a3 = tzz[q];
+                double c1 = o6[q], c2 = o6[N + q], c3 = o6[2 * N + q];
+                double k = lam[q] / (3.0 * lam[q] + 2.0 * mu[q]);
+                double sa = a1 + a2 + a3, sc = c1 + c2 + c3;
+                e += 0.5 * ((a1 * c1 + a2 * c2 + a3 * c3) - k * sa * sc) / (2.0 * mu[q]);
+                e += 0.5 * (txy[q] * o6[3 * N + q] / mxy[q] + txz[q] * o6[4 * N + q] / mxz[q] +
+                            tyz[q] * o6[5 * N + q] / myz[q]);
+            }
+            energy[t] = e;
+        }
+    }
+    if (state) memcpy(state, F, sizeof(double) * NF * N);
+done:
+    free(F);
+    free(Fold);
+    free(P);
+    return st;
+}
