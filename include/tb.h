@@ -55,7 +55,8 @@ typedef struct tb_model tb_model;
 typedef struct tb_sparse tb_sparse;
 
 /*
- * Model description (equation (acou) of Section III-A and Section IV-B).
+ * Model description (equation (acou) of Section III-A, the TTI system of
+ * Section III-B, the elastic system of Section III-C; Section IV-B).
  *  shape       grid nodes per axis; the absorbing layers lie inside it.
  *  spacing     h per axis in metres; origin in metres.
  *  space_order 4 or 8 (centred Taylor weights, radius space_order/2).
@@ -64,8 +65,12 @@ typedef struct tb_sparse tb_sparse;
  *  damp_vmax   velocity used by the damping profile (<= 0: max(vp)).
  *  vp          device float32 [nx][ny][nz] P velocity (m/s); read during the
  *              call only (the library derives its own coefficient arrays).
- *  epsilon, delta, theta, phi   TTI only (device float32 [nx][ny][nz]).
- *  vs, rho     elastic only (device float32 [nx][ny][nz]).
+ *  epsilon, delta, theta, phi   TTI only (device float32 [nx][ny][nz]):
+ *              Thomsen parameters (delta is clipped to epsilon) and the tilt
+ *              from vertical / azimuth (radians) of the symmetry axis.
+ *  vs, rho     elastic only (device float32 [nx][ny][nz]): S velocity (m/s)
+ *              and density (kg/m^3).
+ * All parameter arrays are read during the call only.
  */
 typedef struct {
     int32_t physics;
@@ -162,12 +167,19 @@ tb_status tb_workspace_size(const tb_model *m, const tb_sparse *s, const tb_sche
                             int32_t op, size_t *bytes);
 
 /*
- * Forward propagation from zero initial conditions over nt steps (equation
- * (acou); naive-order semantics of the first listing, computed in the order
- * of the chosen schedule). Outputs (device, caller-owned, any may be NULL):
- * rec_out[nt][nrec] with d^n = P_r u^n (so d^0 = 0), field_out = u^{nt} and
- * field_prev_out = u^{nt-1} as [nx][ny][nz]. ws must hold
- * tb_workspace_size(TB_OP_FORWARD) bytes of device memory.
+ * Forward propagation from zero initial conditions over nt steps
+ * (naive-order semantics of the first listing, computed in the order of the
+ * chosen schedule). Outputs (device, caller-owned, any may be NULL):
+ *  acoustic  rec_out[nt][nrec] with d^n = P_r u^n (so d^0 = 0),
+ *            field_out = u^{nt}, field_prev_out = u^{nt-1};
+ *  TTI       the same for the field p (the source enters p and r);
+ *  elastic   rec_out[2][nt][nrec]: vz^{n-1/2} (interpolated on the vz grid)
+ *            then P^n = (txx + tyy + tzz)^n / 3; field_out = vz^{nt-1/2},
+ *            field_prev_out = tzz^{nt}.
+ * Fields are [nx][ny][nz]. ws must hold tb_workspace_size(TB_OP_FORWARD)
+ * bytes of device memory. TTI and elastic run the spatially blocked schedule
+ * only (a temporally blocked schedule returns TB_EUNSUPPORTED; NULL selects
+ * the spatially blocked one).
  * Errors: TB_EINVAL, TB_EWORKSPACE, TB_EUNSUPPORTED, TB_EHIP.
  */
 tb_status tb_forward(const tb_model *m, const tb_sparse *s, const tb_schedule *sched, void *ws,

@@ -269,7 +269,7 @@ def elastic_forward(shot, vmax_damp: float = 0.0, src_wav=None, vp=None, vs=None
                     want_energy: bool = False):
     """FP64 elastic velocity-stress forward of a ``workloads.Shot`` (zero
     initial state). Returns dict(vz[nt][nrec], p[nt][nrec] traces, the nine
-    final fields by name, energy[nt] if asked)."""
+    final fields by name (vz as "vz_field"), energy[nt] if asked)."""
     n = np.asarray(shot.shape, dtype=np.int32)
     f = lambda a, b: _f64(b if a is None else a)
     vp, vs, rho = f(vp, shot.vp), f(vs, shot.vs), f(rho, shot.rho)
@@ -285,8 +285,8 @@ def elastic_forward(shot, vmax_damp: float = 0.0, src_wav=None, vp=None, vs=None
                                   float(vmax_damp), sx.shape[0], sx, wav, nrec, rx,
                                   _ptr(traces), _ptr(state), _ptr(energy))
     _check(st, "elastic_forward")
-    out = dict(vz=traces[0], p=traces[1])
-    out.update({k: state[i] for i, k in enumerate(ELASTIC_FIELDS)})
+    out = {k if k != "vz" else "vz_field": state[i] for i, k in enumerate(ELASTIC_FIELDS)}
+    out.update(vz=traces[0], p=traces[1])
     if want_energy:
         out["energy"] = energy
     return out

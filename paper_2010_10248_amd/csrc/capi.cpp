@@ -5,6 +5,7 @@
 #include <cstring>
 
 #include "plan.h"
+#include "elastic_params.h"
 #include "tti_params.h"
 
 namespace tbw {
@@ -21,6 +22,7 @@ tb_model::~tb_model()
     if (d_damp) (void)hipFree(d_damp);
     if (d_zero) (void)hipFree(d_zero);
     if (d_tti) (void)hipFree(d_tti);
+    if (d_el) (void)hipFree(d_el);
 }
 
 tb_sparse::~tb_sparse()
@@ -29,7 +31,8 @@ tb_sparse::~tb_sparse()
     for (void *p : {(void *)d_dcmp, (void *)d_rc_ptr, (void *)d_rc_id, (void *)d_rc_w,
                     (void *)d_sc_ptr, (void *)d_sc_id, (void *)d_sc_w, (void *)d_rr_ptr,
                     (void *)d_rr_rec, (void *)d_rr_w, (void *)d_rid_scale, (void *)d_src_off,
-                    (void *)d_src_alpha, (void *)d_rid_off})
+                    (void *)d_src_alpha, (void *)d_rid_off, (void *)d_rc2_ptr, (void *)d_rc2_id,
+                    (void *)d_rc2_w, (void *)d_rid2_off})
         if (p) (void)hipFree(p);
 }
 
@@ -351,9 +354,9 @@ tb_status run_plan(const tb_model *m, tb_sparse *s, const SchedChoice &sc, const
 
 size_t forward_ws_bytes(const tb_model *m, const tb_sparse *s)
 {
-    const size_t nf = m->physics == TB_TTI ? 6 : 4;
+    const size_t nf = m->physics == TB_TTI ? 6 : (m->physics == TB_ELASTIC ? 9 : 4);
     return nf * field_bytes(m) +
-           align256(((size_t)m->nt + 1) * std::max(s->nrid, 1) * sizeof(float));
+           align256(((size_t)m->nt + 1) * std::max(s->nrid + s->nrid2, 1) * sizeof(float));
 }
 
 namespace {
@@ -436,6 +439,78 @@ tb_status plan_forward_tti(const tb_model *m, tb_sparse *s, void *ws, float *rec
     return TB_OK;
 }
 
+// Elastic forward (SB): vx vy vz txx tyy tzz txy txz tyz, then rows of P and
+// vz samples; traces [2][nt][nrec] (vz, then P).
+tb_status plan_forward_elastic(const tb_model *m, tb_sparse *s, void *ws, float *rec_out,
+                               float *field_out, float *field_prev_out, Plan *plan)
+{
+    const size_t fb = field_bytes(m), fe = m->field_elems();
+    char *base = (char *)ws;
+    float *F[9];
+    for (int k = 0; k < 9; k++) F[k] = (float *)(base + k * fb);
+    const int nrid = s->nrid, nrid2 = s->nrid2, npts = s->npts, nt = m->nt;
+    const int stride = nrid + nrid2;
+    float *rec = (float *)(base + 9 * fb);  // row k: P at nrid points, vz at nrid2
+    for (int k = 0; k < 9; k++) plan->push_back(fill_item(F[k], fe));
+    if (stride > 0) plan->push_back(fill_item(rec, (size_t)stride));
+    ElParams P{};
+    for (int k = 0; k < 3; k++) P.v[k] = F[k];
+    for (int k = 0; k < 6; k++) P.t[k] = F[3 + k];
+    for (int k = 0; k < 3; k++) P.bq[k] = m->d_el + k * fe;
+    P.lam = m->d_el + 3 * fe;
+    P.mu = m->d_el + 4 * fe;
+    for (int k = 0; k < 3; k++) P.ms[k] = m->d_el + (5 + k) * fe;
+    P.dx = m->d_damp;
+    P.dy = m->d_damp + m->n[0];
+    P.dz = m->d_damp + m->n[0] + m->n[1];
+    P.hdt = (float)(m->dt / 2.0);
+    static const double s4[2] = {9.0 / 8.0, -1.0 / 24.0};
+    static const double s8[4] = {1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0, -5.0 / 7168.0};
+    const double *sw = m->so == 4 ? s4 : s8;
+    for (int j = 0; j < 4; j++) P.w[j] = j < m->r ? (float)sw[j] : 0.0f;
+    for (int a = 0; a < 3; a++) P.ih[a] = (float)(1.0 / m->h[a]);
+    P.nx = m->n[0];
+    P.ny = m->n[1];
+    P.nz = m->n[2];
+    P.nzp = m->nzp;
+    const int r = m->r;
+    const float *dcmp = s->d_dcmp;
+    const long long *soff = s->d_src_off, *roff = s->d_rid_off, *roff2 = s->d_rid2_off;
+    for (int n = 0; n < nt; n++) {
+        const float *inc = dcmp + (size_t)n * npts;
+        float *row = rec + (size_t)(n + 1) * stride;
+        plan->push_back(act_item([=](hipStream_t st) {
+            return launch_elastic_step(P, r, inc, soff, npts, row, roff, nrid, row + nrid, roff2,
+                                       nrid2, st);
+        }));
+    }
+    if (rec_out && s->nrec > 0 && nt > 0) {
+        // Rows are [P (nrid) | vz (nrid2)]: reduce each part with its mirror.
+        const int nrec = s->nrec;
+        const int *p1 = s->d_rc_ptr, *i1 = s->d_rc_id, *p2 = s->d_rc2_ptr, *i2 = s->d_rc2_id;
+        const float *w1 = s->d_rc_w, *w2 = s->d_rc2_w;
+        plan->push_back(act_item([=](hipStream_t st) -> tb_status {
+            tb_status rc =
+                launch_trace_reduce(rec + nrid, stride, nt, p2, i2, w2, nrec, rec_out, 0, st);
+            if (rc) return rc;
+            return launch_trace_reduce(rec, stride, nt, p1, i1, w1, nrec,
+                                       rec_out + (size_t)nt * nrec, 0, st);
+        }));
+    }
+    // Field outputs: vz^{nt-1/2} (field_out) and tzz^{nt} (field_prev_out).
+    const int nx = m->n[0], ny = m->n[1], nz = m->n[2], nzp = m->nzp;
+    float *fv = F[2], *ft = F[5];
+    if (field_out)
+        plan->push_back(act_item([=](hipStream_t st) {
+            return launch_unpad(fv, field_out, nx, ny, nz, nzp, st);
+        }));
+    if (field_prev_out)
+        plan->push_back(act_item([=](hipStream_t st) {
+            return launch_unpad(ft, field_prev_out, nx, ny, nz, nzp, st);
+        }));
+    return TB_OK;
+}
+
 }  // namespace
 
 size_t gradient_ws_bytes(const tb_model *m, const tb_sparse *s, const SchedChoice &sc, int every)
@@ -448,6 +523,8 @@ tb_status plan_forward(const tb_model *m, tb_sparse *s, const SchedChoice &sc, v
 {
     if (m->physics == TB_TTI)
         return plan_forward_tti(m, s, ws, rec_out, field_out, field_prev_out, plan);
+    if (m->physics == TB_ELASTIC)
+        return plan_forward_elastic(m, s, ws, rec_out, field_out, field_prev_out, plan);
     const size_t fb = field_bytes(m), fe = m->field_elems();
     char *base = (char *)ws;
     float *F[4] = {(float *)base, (float *)(base + fb), (float *)(base + 2 * fb),
@@ -685,9 +762,13 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
         set_error("tb_create_model: desc is NULL");
         return TB_EINVAL;
     }
-    if (d->physics != TB_ACOUSTIC && d->physics != TB_TTI) {
+    if (d->physics != TB_ACOUSTIC && d->physics != TB_TTI && d->physics != TB_ELASTIC) {
         set_error("physics %d is not built", d->physics);
         return TB_EUNSUPPORTED;
+    }
+    if (d->physics == TB_ELASTIC && (!d->vs || !d->rho)) {
+        set_error("the elastic model needs vs and rho");
+        return TB_EINVAL;
     }
     if (d->physics == TB_TTI && (!d->epsilon || !d->delta || !d->theta || !d->phi)) {
         set_error("TTI needs epsilon, delta, theta and phi");
@@ -769,11 +850,72 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
                     vstab = std::max(vstab, (double)vp[i] * std::sqrt(1.0 + 2.0 * e));
                 }
     }
-    // Leapfrog stability: dt^2 vp_max^2 * sum_a |symbol max| / h_a^2 <= 4.
+    // Elastic parameters at their staggered positions, times dt (FP64, one
+    // rounding): b averaged over the 2 nodes of a velocity point, mu over the
+    // 4 nodes of a shear point (a node outside the grid takes the nearest
+    // inside value).
+    std::vector<float> el_host;
+    if (d->physics == TB_ELASTIC) {
+        std::vector<float> vsh(N), rh(N);
+        TB_HIP(hipMemcpy(vsh.data(), d->vs, N * sizeof(float), hipMemcpyDeviceToHost));
+        TB_HIP(hipMemcpy(rh.data(), d->rho, N * sizeof(float), hipMemcpyDeviceToHost));
+        std::vector<double> b(N), mu(N), lam(N);
+        for (size_t i = 0; i < N; i++) {
+            const double r = rh[i], sv = vsh[i], p = vp[i];
+            if (!(r > 0.0) || !(sv >= 0.0) || !(p * p - 2.0 * sv * sv >= -1e-12 * p * p)) {
+                set_error("elastic parameters at node %zu invalid", i);
+                return TB_EINVAL;
+            }
+            b[i] = 1.0 / r;
+            mu[i] = r * sv * sv;
+            lam[i] = r * (p * p - 2.0 * sv * sv);
+        }
+        auto cl = [&](const std::vector<double> &f, long x, long y, long z) {
+            x = std::min<long>(std::max<long>(x, 0), nx - 1);
+            y = std::min<long>(std::max<long>(y, 0), ny - 1);
+            z = std::min<long>(std::max<long>(z, 0), nz - 1);
+            return f[((size_t)x * ny + y) * nz + z];
+        };
+        const size_t fe = m->field_elems();
+        el_host.assign(8 * fe, 0.0f);
+        const double dt = m->dt;
+        for (long x = 0; x < nx; x++)
+            for (long y = 0; y < ny; y++)
+                for (long z = 0; z < nz; z++) {
+                    const size_t q = ((size_t)x * ny + y) * m->nzp + z;
+                    const size_t i = ((size_t)x * ny + y) * nz + z;
+                    el_host[q] = (float)(dt * 0.5 * (cl(b, x, y, z) + cl(b, x + 1, y, z)));
+                    el_host[fe + q] = (float)(dt * 0.5 * (cl(b, x, y, z) + cl(b, x, y + 1, z)));
+                    el_host[2 * fe + q] = (float)(dt * 0.5 * (cl(b, x, y, z) + cl(b, x, y, z + 1)));
+                    el_host[3 * fe + q] = (float)(dt * lam[i]);
+                    el_host[4 * fe + q] = (float)(dt * mu[i]);
+                    el_host[5 * fe + q] =
+                        (float)(dt * 0.25 * (cl(mu, x, y, z) + cl(mu, x + 1, y, z) +
+                                             cl(mu, x, y + 1, z) + cl(mu, x + 1, y + 1, z)));
+                    el_host[6 * fe + q] =
+                        (float)(dt * 0.25 * (cl(mu, x, y, z) + cl(mu, x + 1, y, z) +
+                                             cl(mu, x, y, z + 1) + cl(mu, x + 1, y, z + 1)));
+                    el_host[7 * fe + q] =
+                        (float)(dt * 0.25 * (cl(mu, x, y, z) + cl(mu, x, y + 1, z) +
+                                             cl(mu, x, y, z + 1) + cl(mu, x, y + 1, z + 1)));
+                }
+    }
+    // Leapfrog stability: dt^2 v_max^2 * sum_a |symbol max| / h_a^2 <= 4, with
+    // the symbol of the centred second derivative, or for the staggered
+    // system the square of that of the staggered first derivative.
     const double *w = d2_weights(m->so);
     double sym = w[0];
     for (int j = 1; j <= m->r; j++) sym += 2.0 * w[j] * ((j & 1) ? -1.0 : 1.0);
     sym = std::fabs(sym);
+    if (d->physics == TB_ELASTIC) {
+        static const double s4[2] = {9.0 / 8.0, -1.0 / 24.0};
+        static const double s8[4] = {1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0,
+                                     -5.0 / 7168.0};
+        const double *sw = m->so == 4 ? s4 : s8;
+        double a = 0.0;
+        for (int j = 0; j < m->r; j++) a += 2.0 * std::fabs(sw[j]);
+        sym = a * a;
+    }
     double rho = 0.0;
     for (int a = 0; a < 3; a++) rho += sym / (m->h[a] * m->h[a]);
     if (m->dt * m->dt * vstab * vstab * rho > 4.0) {
@@ -789,7 +931,9 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
                 const size_t i = (x * ny + y) * nz + z;
                 const double v = (double)vp[i];
                 const double c = m->dt * m->dt * v * v;
-                m->c64[i] = c;
+                // The inspector scales injected values by c64: dt^2/m for the
+                // second-order systems, dt for the stress injection.
+                m->c64[i] = d->physics == TB_ELASTIC ? m->dt : c;
                 cpad[(x * ny + y) * m->nzp + z] = (float)c;
             }
     m->damp.assign((size_t)nx + ny + m->nzp, 0.0f);
@@ -800,6 +944,11 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
     TB_HIP(hipMemcpy(m->d_c, cpad.data(), cpad.size() * sizeof(float), hipMemcpyHostToDevice));
     TB_HIP(hipMalloc(&m->d_zero, 256));
     TB_HIP(hipMemset(m->d_zero, 0, 256));
+    if (!el_host.empty()) {
+        TB_HIP(hipMalloc(&m->d_el, el_host.size() * sizeof(float)));
+        TB_HIP(hipMemcpy(m->d_el, el_host.data(), el_host.size() * sizeof(float),
+                         hipMemcpyHostToDevice));
+    }
     if (!tti_host.empty()) {
         TB_HIP(hipMalloc(&m->d_tti, tti_host.size() * sizeof(float)));
         TB_HIP(hipMemcpy(m->d_tti, tti_host.data(), tti_host.size() * sizeof(float),
@@ -888,6 +1037,17 @@ tb_status tb_inspect_sparse(const tb_model *m, int32_t nsrc, const double *src_x
         roff[i] = (long long)((r / nz) * m->nzp + r % nz);
     }
     if ((st = upload(&s->d_rid_off, roff))) return st;
+    if (m->physics == TB_ELASTIC) {
+        std::vector<float> w2(s->rc2_w.begin(), s->rc2_w.end());
+        std::vector<long long> roff2(s->nrid2);
+        for (int i = 0; i < s->nrid2; i++) {
+            const int64_t r = s->rid2_nodes[i];
+            roff2[i] = (long long)((r / nz) * m->nzp + r % nz);
+        }
+        if ((st = upload(&s->d_rc2_ptr, s->rc2_ptr)) || (st = upload(&s->d_rc2_id, s->rc2_id)) ||
+            (st = upload(&s->d_rc2_w, w2)) || (st = upload(&s->d_rid2_off, roff2)))
+            return st;
+    }
     *out = s.release();
     return TB_OK;
 }

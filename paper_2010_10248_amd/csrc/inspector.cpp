@@ -334,6 +334,17 @@ tb_status inspect_into(tb_sparse *s, int nsrc, const double *src_xyz, const doub
     s->rc_ptr = rs.ptr;
     s->rc_id = rs.id;
     s->rc_w = rs.w;
+    if (m->physics == TB_ELASTIC) {
+        // vz lives half a cell above the nodes in z: its own receiver mirror.
+        const double o2[3] = {m->o[0], m->o[1], m->o[2] + 0.5 * m->h[2]};
+        Support r2;
+        if ((st = build_support(m->n, m->h, o2, nrec, rec_xyz, &r2))) return st;
+        s->nrid2 = (int)r2.nodes.size();
+        s->rid2_nodes = r2.nodes;
+        s->rc2_ptr = r2.ptr;
+        s->rc2_id = r2.id;
+        s->rc2_w = r2.w;
+    }
     return TB_OK;
 }
 }  // namespace tbw

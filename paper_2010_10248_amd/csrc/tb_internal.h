@@ -103,6 +103,9 @@ struct tb_model {
     // TTI: five padded fields ax, ay, az (symmetry axis), 1 + 2 eps and
     // sqrt(1 + 2 min(delta, eps)), each field_elems() long.
     float *d_tti = nullptr;
+    // Elastic: eight padded fields, each multiplied by dt: b at the vx, vy,
+    // vz points, lambda and mu at the nodes, mu at the txy, txz, tyz points.
+    float *d_el = nullptr;
     std::vector<double> c64;  // host copy of dt^2 vp^2 (FP64 from the FP32 vp)
     std::vector<float> damp;  // host copy of the three tables
     size_t field_elems() const { return (size_t)n[0] * n[1] * nzp; }
@@ -141,6 +144,14 @@ struct tb_sparse {
     // Padded offsets of the receiver points (gathers outside the wave-front
     // kernel).
     long long *d_rid_off = nullptr;
+    // Elastic: the receiver mirror on the vz grid (origin + h/2 in z).
+    int nrid2 = 0;
+    std::vector<int64_t> rid2_nodes;
+    std::vector<int> rc2_ptr, rc2_id;
+    std::vector<double> rc2_w;
+    int *d_rc2_ptr = nullptr, *d_rc2_id = nullptr;
+    float *d_rc2_w = nullptr;
+    long long *d_rid2_off = nullptr;
     std::mutex mu;
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<tbw::TileLists>> tiles;
     ~tb_sparse();

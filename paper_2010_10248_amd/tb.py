@@ -379,8 +379,9 @@ class Propagator:
                                       device=self.device)
         physics = getattr(shot, "physics", ACOUSTIC)
         extra = {}
-        if physics == TTI:
-            for name in ("epsilon", "delta", "theta", "phi"):
+        names = {TTI: ("epsilon", "delta", "theta", "phi"), ELASTIC: ("vs", "rho")}
+        if physics in names:
+            for name in names[physics]:
                 extra[name] = torch.as_tensor(
                     np.ascontiguousarray(getattr(shot, name), dtype=np.float32),
                     device=self.device)
@@ -417,11 +418,15 @@ class Propagator:
         return ws
 
     def forward(self, sched=None, want_fields=True, stream=None):
+        """Traces and the last two levels. Elastic: traces [2][nt][nrec]
+        (vz, then pressure), u_last = vz^{nt-1/2}, u_prev = tzz^{nt}."""
         import torch
 
         ws = self.workspace(sched, OP_FORWARD)
         nt = self.shot.nt
-        rec = torch.empty((nt, self.nrec), dtype=torch.float32, device=self.device)
+        shape = ((2, nt, self.nrec) if getattr(self.shot, "physics", ACOUSTIC) == ELASTIC
+                 else (nt, self.nrec))
+        rec = torch.empty(shape, dtype=torch.float32, device=self.device)
         u = torch.empty(self.shot.shape, dtype=torch.float32, device=self.device) if want_fields else None
         up = torch.empty(self.shot.shape, dtype=torch.float32, device=self.device) if want_fields else None
         forward(self.model, self.sparse, sched, ws, rec, u, up, stream)

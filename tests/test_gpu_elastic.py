@@ -1,0 +1,63 @@
+"""GPU elastic velocity-stress propagator (Section III-C) against the FP64
+elastic oracle (relative L2 <= 1e-5 on the vz and pressure traces and on the
+final vz and tzz fields), the zero-source invariant, and the operations that
+are built for the acoustic propagator only."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2010_10248_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.mark.parametrize("so,n,nt", [(8, (40, 44, 48), 70), (4, (35, 30, 33), 60)])
+def test_elastic_parity_with_oracle(torch_cuda, orc, so, n, nt):
+    from paper_2010_10248_amd import tb
+
+    s = W.elastic_smooth(seed=80 + so, n=n, so=so, nt=nt, nbl=6, nrec=20, sigma=4.0)
+    ref = orc.elastic_forward(s)
+    prop = tb.Propagator(s)
+    out = prop.forward(tb.schedule("sb"))
+    tr = out["traces"].cpu().numpy()
+    e = dict(vz=_rel(tr[0], ref["vz"]), p=_rel(tr[1], ref["p"]),
+             vz_field=_rel(out["u_last"].cpu().numpy(), ref["vz_field"]),
+             tzz_field=_rel(out["u_prev"].cpu().numpy(), ref["tzz"]))
+    print(f"elastic SO{so} {n} nt={nt}: {e}", flush=True)
+    sys.stdout.flush()
+    assert np.abs(ref["p"]).max() > 0 and np.abs(ref["vz"]).max() > 0
+    assert all(v <= TOL for v in e.values()), e
+    prop.close()
+
+
+def test_elastic_zero_source_and_unsupported_paths(torch_cuda):
+    import torch
+
+    from paper_2010_10248_amd import tb
+
+    s = W.elastic_smooth(seed=7, n=(24, 26, 28), so=8, nt=20, nbl=4, nrec=4, sigma=3.0)
+    prop = tb.Propagator(s, src_wav=np.zeros_like(s.src_wav))
+    out = prop.forward(None)
+    for k in ("traces", "u_last", "u_prev"):
+        assert torch.count_nonzero(out[k]) == 0, k
+    with pytest.raises(tb.TbError) as e:
+        prop.forward(tb.schedule("tb", 2, 32))
+    assert e.value.status == tb.EUNSUPPORTED
+    prop.close()

@@ -21,7 +21,7 @@ def _shot(seed, n, so, nt, nbl, vp, vs, rho, h=10.0, nrec=6):
 def test_zero_source_is_exactly_zero(orc):
     s = _shot(1, (20, 22, 24), 8, 20, 3, None, None, None)
     o = orc.elastic_forward(s, src_wav=np.zeros_like(s.src_wav))
-    for k in ("vz", "p") + orc.ELASTIC_FIELDS:
+    for k in o:
         assert np.all(o[k] == 0.0), k
 
 
