@@ -62,23 +62,24 @@ AcParams make_params(const tb_model *m, const TileLists &tl, const AcLaunch &a)
     const TileGeom &g = tl.g;
     AcParams p{};
     p.u = a.u;
-    p.um = a.um;
+    p.v = a.v;
     p.c = m->d_c;
     p.zero = m->d_zero;
-    p.out0 = a.out0;
-    p.out1 = a.out1;
+    p.out_u = a.out_u;
+    p.out_v = a.out_v;
+    p.out_mid = a.out_mid;
     p.dx = m->d_damp;
     p.dy = m->d_damp + m->n[0];
     p.dz = m->d_damp + m->n[0] + m->n[1];
     p.hdt = (float)(m->dt / 2.0);
     // Centred second-derivative weights of order so (Fornberg), tabulated
-    // as exact rationals and scaled by h^-2 per axis.
+    // as exact rationals and scaled by h^-2 per axis; the kernel applies them
+    // to differences from the centre, so the centre weight is not needed.
     static const double w4[3] = {-5.0 / 2.0, 4.0 / 3.0, -1.0 / 12.0};
     static const double w8[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
     const double *w = m->so == 4 ? w4 : w8;
     const double ihx = 1.0 / (m->h[0] * m->h[0]), ihy = 1.0 / (m->h[1] * m->h[1]),
                  ihz = 1.0 / (m->h[2] * m->h[2]);
-    p.w0 = (float)(w[0] * (ihx + ihy + ihz));
     for (int j = 0; j < 4; j++) {
         const double wj = j < m->r ? w[j + 1] : 0.0;
         p.wx[j] = (float)(wj * ihx);
@@ -121,6 +122,12 @@ tb_status launch_acoustic(const tb_model *m, const TileLists &tl, const AcLaunch
         return TB_EHIP;
     }
     return TB_OK;
+}
+
+bool acoustic_shape_ok(int R, int T, int LZ, int BYE)
+{
+    return R == 2 ? acoustic_shape_ok_r2(T, LZ, BYE)
+                  : (R == 4 ? acoustic_shape_ok_r4(T, LZ, BYE) : false);
 }
 
 tb_status launch_acoustic_batch(int r, const AcParams *d_jobs, const int *d_wgoff, int njobs,

@@ -94,66 +94,66 @@ __device__ __forceinline__ void static_for(F &&f)
     }
 }
 
-// The per-point update shared by every schedule (fixed operation order):
-//   lap = w0 u + sum_j wx_j (x-j + x+j) + sum_j wz_j (z-j + z+j) + sum_j wy_j (y-j + y+j)
-//   r   = c lap + (2u - beta u^{n-1});  r /= alpha where the damping is non-zero.
-// Without damping (d == 0, beta == alpha == 1) the same expression is
-// evaluated by the fast path below with identical rounding.
+// The per-point update shared by every schedule (fixed operation order), in
+// the velocity form of the leapfrog recursion, v^n = u^n - u^{n-1}:
+//   lap = sum_j wx_j ((x-j + x+j) - 2u) + (same in z) + (same in y)
+//   v'  = (c lap + beta v) / alpha       (the division only where d != 0)
+// and then u' = u + v' (after the injection into v'). With differences from
+// the centre the Laplacian of a constant is exactly zero whatever the FP32
+// rounding of the weights, and carrying v instead of u^{n-1} keeps the
+// rounding of u' from entering as a velocity error; in FP32 over a thousand
+// steps each of the two changes removes most of the drift from the FP64
+// definition. Without damping (d == 0, beta == 1) the fast path evaluates
+// the same expression with identical rounding.
 template <int R, bool DAMP>
 __device__ __forceinline__ float point_update(const AcParams &p, float ctr, const float *xm,
                                               const float *xp, const float *ym, const float *yp,
-                                              const float *zm, const float *zp, float prev,
+                                              const float *zm, const float *zp, float vold,
                                               float cc, float d)
 {
     // x terms (register window) first, so LDS reads of the y/z neighbours
     // overlap with arithmetic.
-    float lap = p.w0 * ctr;
+    const float t2 = 2.0f * ctr;
+    float lap = 0.0f;
 #pragma unroll
-    for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wx[j], xm[j] + xp[j], lap);
+    for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wx[j], (xm[j] + xp[j]) - t2, lap);
 #pragma unroll
-    for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wz[j], zm[j] + zp[j], lap);
+    for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wz[j], (zm[j] + zp[j]) - t2, lap);
 #pragma unroll
-    for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wy[j], ym[j] + yp[j], lap);
+    for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wy[j], (ym[j] + yp[j]) - t2, lap);
     if constexpr (DAMP) {
         const float dd = d * p.hdt;
         const float beta = 1.0f - dd;
-        float r = __builtin_fmaf(cc, lap, __builtin_fmaf(-beta, prev, 2.0f * ctr));
+        float r = __builtin_fmaf(cc, lap, beta * vold);
         if (d != 0.0f) r = r / (1.0f + dd);
         return r;
     } else {
-        return __builtin_fmaf(cc, lap, __builtin_fmaf(-1.0f, prev, 2.0f * ctr));
+        return __builtin_fmaf(cc, lap, vold);
     }
 }
 
-// LDS bytes of the stage planes, sparse lists and damping table of one
-// workgroup of acoustic_wavefront<R, T, LZ, BYE>.
-constexpr int wavefront_lds_base(int R, int T, int LZ, int BYE)
-{
-    return 16 * 2 * T * (BYE + 2 * R) * (LZ + kLdsPad) + kSrcCap * (8 + 4 * T) +
-           kRecCap * (8 + 4 * T) + 4 * kDxCap;
-}
-// Slots of the c ring: stage s reads the c plane stage 0 loaded R*s ticks
-// earlier; two spare slots keep each overwrite a barrier behind the last read.
-constexpr int cring_slots(int R, int T, int LZ, int BYE)
-{
-    const int ns = R * (T - 1) + 2;
-    return (T > 1 && wavefront_lds_base(R, T, LZ, BYE) + 16 * ns * BYE * LZ <= 160 * 1024) ? ns
-                                                                                            : 0;
-}
+// Thread-private LDS rings (each lane reads back only its own points, so
+// they need no barrier): stage 0 keeps its c planes for the later stages
+// (stage s reads the one of R*s ticks earlier; written after the tick's
+// reads, R*(T-1) slots), and stage s hands v to stage s+1, which reads it R
+// ticks later (R+1 slots: the writer runs first within a tick).
+constexpr int cring_slots(int R, int T) { return T > 1 ? R * (T - 1) : 0; }
+constexpr int vring_slots(int R, int T) { return T > 1 ? R + 1 : 0; }
+
+// LDS bytes of one workgroup of acoustic_wavefront<R, T, LZ, BYE>.
 constexpr int wavefront_lds(int R, int T, int LZ, int BYE)
 {
-    return wavefront_lds_base(R, T, LZ, BYE) + 16 * cring_slots(R, T, LZ, BYE) * BYE * LZ;
+    return 16 * 2 * T * (BYE + 2 * R) * (LZ + kLdsPad) + kSrcCap * (8 + 4 * T) +
+           kRecCap * (8 + 4 * T) + 4 * kDxCap +
+           16 * LZ * BYE * (cring_slots(R, T) + (T - 1) * vring_slots(R, T));
 }
 
 // Side inputs of one tick, loaded PD ticks ahead into a register ring: the
-// newest u^n plane, u^{n-1} at the stage-0 centre, and c at the centre plane
-// of stage 0 (NC == 1, later stages take it from the LDS c ring) or of every
-// stage (NC == T, when the ring does not fit).
-template <int NC>
+// newest u^n plane, and v^n and c at the stage-0 centre plane.
 struct FarIn {
     f4v u;
-    f4v um;
-    f4v c[NC];
+    f4v v;
+    f4v c;
 };
 // Halo rings of stage 0 (z ring: lanes 0 and 15; y ring: threads < 2R*16),
 // mostly served by the caches: loaded right after a tick's barrier for the
@@ -181,8 +181,8 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
     static_assert(OY > 0 && OZ > 0, "tile too small for this depth");
     static_assert(R >= 1 && R <= 4, "radius must be 1..4");
     static_assert(NTH <= kMaxThreads && LZ <= 32 && BYE <= 32, "workgroup shape");
-    constexpr int NS = cring_slots(R, T, LZ, BYE);
-    constexpr int NC = NS ? 1 : T;
+    constexpr int NSC = cring_slots(R, T);
+    constexpr int NSV = vring_slots(R, T);
 
     __shared__ f4v sh[2][T][LR][LC];
     __shared__ int2 s_src[kSrcCap];
@@ -190,7 +190,8 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
     __shared__ int2 s_rec[kRecCap];
     __shared__ float s_recv[kRecCap][T];
     __shared__ float s_dx[kDxCap];
-    __shared__ f4v s_c[NS ? NS : 1][NS ? BYE : 1][NS ? LZ : 1];
+    __shared__ f4v s_c[NSC ? NSC : 1][NSC ? NTH : 1];
+    __shared__ f4v s_v[T > 1 ? T - 1 : 1][NSV ? NSV : 1][NSV ? NTH : 1];
 
     const int tid = threadIdx.x;
     const int zl = tid % LZ;
@@ -315,25 +316,20 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
         const bool in = x >= 0 && x < p.nx;
         return make_rsrc(f + (in ? (long long)x * p.sx : 0), in ? plane_bytes : 0u);
     };
-    // Inputs of tick i: the newest plane i of u^n, u^{n-1} at the stage-0
-    // centre plane, c at every stage's centre plane (stages >= 1 re-read c
-    // planes stage 0 read R*s ticks earlier, which the caches still hold).
-    auto fetch_far = [&](int i, FarIn<NC> &f) {
+    // Inputs of tick i: the newest plane i of u^n, and v^n and c at the
+    // stage-0 centre plane (later stages take c and v from the LDS rings).
+    auto fetch_far = [&](int i, FarIn &f) {
         const int c0 = i - R;
         f.u = bload(plane(p.u, i), off_c);
-        f.um = bload(plane(p.um, c0), off_c);
-#pragma unroll
-        for (int s = 0; s < NC; s++) {
-            const int cs = c0 - R * s;
-            f.c[s] = bload(plane(p.c, (cs >= lo[s] && cs < hi[s]) ? cs : -1), off_c);
-        }
+        f.v = bload(plane(p.v, c0), off_c);
+        f.c = bload(plane(p.c, (c0 >= lo[0] && c0 < hi[0]) ? c0 : -1), off_c);
     };
     auto fetch_ring = [&](int i, RingIn &f) {
         const rsrc_t ru = plane(p.u, i - R);
         f.rg = bload(ru, off_rg);
         f.yr = bload(ru, off_yr);
     };
-    FarIn<NC> pf[PD];
+    FarIn pf[PD];
     RingIn rgn;
     static_for<0, PD>([&](auto KC) {
         constexpr int k = decltype(KC)::value;
@@ -344,39 +340,41 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
 
     int i = i0;
     int tick = 0;
-    int cslot = 0;
+    int cslot = 0;  // tick mod NSC
+    int vslot = 0;  // tick mod NSV
     while (i <= ilast) {
         static_for<0, U>([&](auto PC) {
             constexpr int P = PC.value;
             constexpr int SLOT = P % PD;
             constexpr int CTR = (P + R) % U;
-            constexpr int OLD = P % U;
             constexpr int NEW = (P + 2 * R) % U;
             if (i > ilast) return;
-            const FarIn<NC> &in = pf[SLOT];
+            const FarIn &in = pf[SLOT];
             q[0][NEW] = in.u;
             const int buf = tick & 1;
 #pragma unroll
             for (int s = 0; s < T; s++) sh[buf][s][row + R][zl] = q[s][CTR];
             if (has_rg) sh[buf][0][row + R][rg_col] = rgn.rg;
             if (has_yr) sh[buf][0][yr_lds][zl] = rgn.yr;
-            if constexpr (NS > 0) s_c[cslot][row][zl] = in.c[0];
             lds_barrier();
             fetch_ring(i + 1, rgn);
 
             static_for<0, T>([&](auto SC) {
                 constexpr int s = SC.value;
                 const int cs = i - R * (s + 1);
-                f4v v = f4v{0.f, 0.f, 0.f, 0.f};
+                f4v v = f4v{0.f, 0.f, 0.f, 0.f};   // v^{n+s+1}
+                f4v un = f4v{0.f, 0.f, 0.f, 0.f};  // u^{n+s+1}
                 if (cs >= lo[s] && cs < hi[s]) {
                     const f4v ctr = q[s][CTR];
-                    const f4v prev = (s == 0) ? in.um : q[s > 0 ? s - 1 : 0][OLD];
-                    f4v cf;
-                    if constexpr (NS > 0 && s > 0) {
-                        const int sl = cslot - R * s;
-                        cf = s_c[sl < 0 ? sl + NS : sl][row][zl];
+                    f4v vold, cf;
+                    if constexpr (s == 0) {
+                        vold = in.v;
+                        cf = in.c;
                     } else {
-                        cf = in.c[NS > 0 ? 0 : s];
+                        const int vs = vslot + 1 == NSV ? 0 : vslot + 1;  // tick - R
+                        vold = s_v[s - 1][vs][tid];
+                        const int sl = cslot - R * s;                      // tick - R s
+                        cf = s_c[sl < 0 ? sl + NSC : sl][tid];
                     }
                     const f4v zl4 = sh[buf][s][row + R][col_l];
                     const f4v zr4 = sh[buf][s][row + R][col_r];
@@ -409,7 +407,7 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
                                 zp[j - 1] = zw[4 + k + j];
                             }
                             v[k] = point_update<R, DAMP>(p, ctr[k], xm, xp, a, bb, zm, zp,
-                                                         prev[k], cf[k], dxs + dyz[k]);
+                                                         vold[k], cf[k], dxs + dyz[k]);
                         }
                     };
                     if (dxs != 0.0f || wave_dyz) compute(std::true_type{});
@@ -430,6 +428,8 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
                         scur[s] = kk;
                         snx[s] = next_x(s_src, nsl, kk);
                     }
+#pragma unroll
+                    for (int k = 0; k < 4; k++) un[k] = ctr[k] + v[k];
                     // Receiver points (owned copy only), buffered in LDS and
                     // written out once at the end.
                     if (rnx[s] == cs) {
@@ -438,25 +438,33 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
                                ((s_rec[kk].x >> 2) & 0xffff) == cs;
                              kk++) {
                             const int k = s_rec[kk].x & 3;
-                            s_recv[kk][s] = k == 0 ? v[0] : k == 1 ? v[1] : k == 2 ? v[2] : v[3];
+                            s_recv[kk][s] = k == 0 ? un[0] : k == 1 ? un[1] : k == 2 ? un[2] : un[3];
                         }
                         rcur[s] = kk;
                         rnx[s] = next_x(s_rec, nrl, kk);
                     }
                 }
                 if constexpr (s + 1 < T) {
-                    q[s + 1 < T ? s + 1 : 0][NEW] = v;
+                    q[s + 1 < T ? s + 1 : 0][NEW] = un;
+                    s_v[s + 1 < T ? s : 0][vslot][tid] = v;
                 } else {
                     const bool st_in = cs >= xc0 && cs < xc1;
-                    bstore(plane(p.out0, st_in ? cs : -1), off_own, v);
-                    if constexpr (T > 1) bstore(plane(p.out1, st_in ? cs : -1), off_own, q[s][CTR]);
+                    bstore(plane(p.out_u, st_in ? cs : -1), off_own, un);
+                    bstore(plane(p.out_v, st_in ? cs : -1), off_own, v);
+                    if constexpr (T > 1)
+                        if (p.out_mid) bstore(plane(p.out_mid, st_in ? cs : -1), off_own, q[s][CTR]);
                 }
             });
+            // Stage 0's c plane for the later stages, after this tick's reads.
+            if constexpr (NSC > 0) {
+                s_c[cslot][tid] = in.c;
+                cslot = cslot + 1 == NSC ? 0 : cslot + 1;
+            }
+            if constexpr (NSV > 0) vslot = vslot + 1 == NSV ? 0 : vslot + 1;
             // Loads for tick i + PD.
             fetch_far(i + PD, pf[SLOT]);
             i++;
             tick++;
-            if constexpr (NS > 0) cslot = cslot + 1 == NS ? 0 : cslot + 1;
         });
     }
     if (nrl > 0) {

@@ -7,17 +7,17 @@ namespace tbw {
 
 struct AcParams {
     const float *__restrict__ u;   // u^n      [nx][ny][nzp]
-    const float *__restrict__ um;  // u^{n-1}
+    const float *__restrict__ v;   // v^n = u^n - u^{n-1}
     const float *__restrict__ c;   // dt^2 vp^2
     const float *zero;             // 16 zeroed bytes (target of masked-off loads)
-    float *out0;                   // u^{n+T}
-    float *out1;                   // u^{n+T-1} (T >= 2)
+    float *out_u;                  // u^{n+T}
+    float *out_v;                  // v^{n+T}
+    float *out_mid;                // u^{n+T-1} (T >= 2), or NULL
     const float *__restrict__ dx;  // damping per axis
     const float *__restrict__ dy;
     const float *__restrict__ dz;
     float hdt;  // dt / 2
-    float w0;   // centre weight, summed over the three axes
-    float wx[4], wy[4], wz[4];
+    float wx[4], wy[4], wz[4];  // off-centre weights per axis (h^-2 scaled)
     int nx, ny, nz, nzp;
     long long sx;  // plane stride ny * nzp
     int tiles_z, nwg;
@@ -41,6 +41,9 @@ hipError_t launch_acoustic_batch_r2(const AcParams *jobs, const int *wg_off, int
                                     int total_wg, int T, int LZ, int BYE, hipStream_t st);
 hipError_t launch_acoustic_batch_r4(const AcParams *jobs, const int *wg_off, int njobs,
                                     int total_wg, int T, int LZ, int BYE, hipStream_t st);
+
+bool acoustic_shape_ok_r2(int T, int LZ, int BYE);
+bool acoustic_shape_ok_r4(int T, int LZ, int BYE);
 
 // Kernel parameters of one pass of one job.
 AcParams make_params(const tb_model *m, const TileLists &tl, const AcLaunch &a);

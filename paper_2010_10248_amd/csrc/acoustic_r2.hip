@@ -14,4 +14,10 @@ hipError_t launch_acoustic_batch_r2(const AcParams *jobs, const int *wg_off, int
     return wf::launch_batch_r<2>(jobs, wg_off, njobs, total_wg, T, LZ, BYE, st);
 }
 
+bool acoustic_shape_ok_r2(int T, int LZ, int BYE)
+{
+    return wf::dispatch_shape<2>(T, LZ, BYE, []<int TT, int L, int B>() { return hipSuccess; }) ==
+           hipSuccess;
+}
+
 }  // namespace tbw

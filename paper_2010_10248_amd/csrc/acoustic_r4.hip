@@ -14,4 +14,10 @@ hipError_t launch_acoustic_batch_r4(const AcParams *jobs, const int *wg_off, int
     return wf::launch_batch_r<4>(jobs, wg_off, njobs, total_wg, T, LZ, BYE, st);
 }
 
+bool acoustic_shape_ok_r4(int T, int LZ, int BYE)
+{
+    return wf::dispatch_shape<4>(T, LZ, BYE, []<int TT, int L, int B>() { return hipSuccess; }) ==
+           hipSuccess;
+}
+
 }  // namespace tbw

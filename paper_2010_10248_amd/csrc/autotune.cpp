@@ -101,37 +101,31 @@ tb_status tb_autotune(const tb_model *m, const tb_sparse *s_, int32_t steps, voi
                 bool ok = true;
                 for (int rep = 0; rep < 2 && ok; rep++) {
                     Plan plan;
-                    int cur = 0, prev = 1;
+                    int ua = 0, va = 0;
                     const size_t fe = m->field_elems();
                     tb_status rc = launch_fill(F[0], fe, 0.0f, st);
-                    if (!rc) rc = launch_fill(F[1], fe, 0.0f, st);
+                    if (!rc) rc = launch_fill(F[2], fe, 0.0f, st);
                     if (rc) return rc;
-                    // Passes of `steps` updates from zero state.
+                    // Passes of `steps` updates from zero state (u in F[0..1],
+                    // v in F[2..3]).
                     int n = 0;
                     while (n < steps) {
                         const int Tp = std::min(sc.T, steps - n);
-                        int f0 = -1, f1 = -1;
-                        if (Tp > 1)
-                            for (int k = 0; k < 4; k++)
-                                if (k != cur && k != prev) (f0 < 0 ? f0 : f1) = k;
                         Item it;
                         it.is_pass = true;
                         it.pass.T = Tp;
-                        it.pass.u = F[cur];
-                        it.pass.um = F[prev];
-                        it.pass.out0 = Tp == 1 ? F[prev] : F[f0];
-                        it.pass.out1 = Tp == 1 ? nullptr : F[f1];
+                        it.pass.u = F[ua];
+                        it.pass.v = F[2 + va];
+                        it.pass.out_u = F[1 - ua];
+                        it.pass.out_v = F[3 - va];
                         it.pass.n0 = n;
                         it.pass.dcmp = s->d_dcmp;
                         it.pass.ninj = s->npts;
                         it.pass.rec = rec;
                         it.pass.nrecp = s->nrid;
                         plan.push_back(it);
-                        if (Tp == 1) std::swap(cur, prev);
-                        else {
-                            cur = f0;
-                            prev = f1;
-                        }
+                        ua = 1 - ua;
+                        va = 1 - va;
                         n += Tp;
                     }
                     TB_HIP(hipEventRecord(e0.e, st));

@@ -126,6 +126,19 @@ tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice 
         set_error("chunk_x %d negative", c.chunk);
         return TB_EINVAL;
     }
+    if (m->physics == TB_ACOUSTIC) {
+        // Every depth up to T is launched (the remainder of nt), so each one
+        // needs a kernel of the selected shape.
+        for (int t = 1; t <= c.T; t++) {
+            int lz = 0, bye = 0;
+            tile_shape(m->r, t, c.tile_y, &lz, &bye);
+            if (!acoustic_shape_ok(m->r, t, lz, bye)) {
+                set_error("no wave-front kernel for radius %d, time_tile %d, tile %dx%d (LDS)",
+                          m->r, t, bye, 4 * lz);
+                return TB_EUNSUPPORTED;
+            }
+        }
+    }
     *out = c;
     return TB_OK;
 }
@@ -188,9 +201,10 @@ AcLaunch to_launch(const Pass &p)
 {
     AcLaunch a{};
     a.u = p.u;
-    a.um = p.um;
-    a.out0 = p.out0;
-    a.out1 = p.out1;
+    a.v = p.v;
+    a.out_u = p.out_u;
+    a.out_v = p.out_v;
+    a.out_mid = p.out_mid;
     a.n0 = p.n0;
     a.dcmp = p.dcmp;
     a.npts = p.ninj;
@@ -214,41 +228,36 @@ Item act_item(std::function<tb_status(hipStream_t)> f)
     return it;
 }
 
-// Append the passes of a time loop of `steps` updates starting at level n0
-// from buffers (F[cur] = level n0, F[prev] = level n0-1), four buffers
-// rotating (T == 1 updates in place over level n-1). after(n, cur, prev) is
-// called after each pass ending at level n.
-void plan_time_loop(Plan *plan, int adjoint, int Tmax, float *F[4], int n0, int steps,
-                    const float *dcmp, int ninj, float *rec, int nrecp, int *cur, int *prev,
-                    const std::function<void(int, int, int)> &after)
+// Append the passes of a time loop of `steps` updates from level n0 with the
+// state in U[*ua] = u^{n0} and V[*va] = v^{n0}: each pass reads one u and one
+// v buffer and writes the other two. mid (may be NULL) receives u^{n0+steps-1}
+// from the last pass when that pass advances two or more steps. after(n, ua,
+// va) is called after each pass ending at level n.
+void plan_time_loop(Plan *plan, int adjoint, int Tmax, float *U[2], float *V[2], float *mid,
+                    int n0, int steps, const float *dcmp, int ninj, float *rec, int nrecp,
+                    int *ua, int *va, const std::function<void(int, int, int)> &after)
 {
     int n = n0;
     while (n < n0 + steps) {
         const int T = std::min(Tmax, n0 + steps - n);
-        int f0 = -1, f1 = -1;
-        if (T > 1)
-            for (int k = 0; k < 4; k++)
-                if (k != *cur && k != *prev) (f0 < 0 ? f0 : f1) = k;
         Pass p;
         p.adjoint = adjoint;
         p.T = T;
-        p.u = F[*cur];
-        p.um = F[*prev];
-        p.out0 = T == 1 ? F[*prev] : F[f0];
-        p.out1 = T == 1 ? nullptr : F[f1];
+        p.u = U[*ua];
+        p.v = V[*va];
+        p.out_u = U[1 - *ua];
+        p.out_v = V[1 - *va];
+        p.out_mid = (T > 1 && n + T == n0 + steps) ? mid : nullptr;
         p.n0 = n;
         p.dcmp = dcmp;
         p.ninj = ninj;
         p.rec = rec;
         p.nrecp = nrecp;
         plan->push_back(pass_item(p));
-        if (T == 1) std::swap(*cur, *prev);
-        else {
-            *cur = f0;
-            *prev = f1;
-        }
+        *ua = 1 - *ua;
+        *va = 1 - *va;
         n += T;
-        if (after) after(n, *cur, *prev);
+        if (after) after(n, *ua, *va);
     }
 }
 
@@ -268,10 +277,10 @@ Item copy_item(void *dst, const void *src, size_t bytes)
 // Workspace of the gradient (offsets in bytes from the base).
 struct GradLayout {
     int K = 0;       // checkpoint interval (a multiple of the forward depth)
-    int ncp = 0;     // stored checkpoints (levels jK, jK-1 for j >= 1)
-    int nslot = 0;   // segment slots (levels jK-1 .. jK+K-1)
-    size_t F = 0, A = 0, slots = 0, cps = 0, g = 0, rec = 0, traces = 0, res = 0, adj_dcmp = 0,
-           adj_rec = 0, loss = 0, total = 0;
+    int ncp = 0;     // stored checkpoints (u^{jK}, v^{jK} for j >= 1)
+    int nslot = 0;   // segment slots (u levels jK .. jK+K-1)
+    size_t F = 0, A = 0, RV = 0, slots = 0, cps = 0, g = 0, rec = 0, traces = 0, res = 0,
+           adj_dcmp = 0, adj_rec = 0, loss = 0, total = 0;
 };
 
 int ceil_sqrt(int n)
@@ -290,7 +299,7 @@ GradLayout grad_layout(const tb_model *m, const tb_sparse *s, const SchedChoice 
     L.K = K;
     // Checkpoints at levels jK for j >= 1 with jK <= nt - 2 (level 0 is zero).
     L.ncp = nt >= 2 ? (nt - 2) / K : 0;
-    L.nslot = K + 1;
+    L.nslot = K;
     const size_t fb = field_bytes(m);
     const size_t nt1 = (size_t)nt + 1;
     size_t o = 0;
@@ -299,8 +308,9 @@ GradLayout grad_layout(const tb_model *m, const tb_sparse *s, const SchedChoice 
         o += align256(bytes);
         return at;
     };
-    L.F = take(4 * fb);
-    L.A = take(4 * fb);
+    L.F = take(4 * fb);   // forward u, u', v, v'
+    L.A = take(5 * fb);   // adjoint u, u', v, v', intermediate level
+    L.RV = take(2 * fb);  // v of the recomputed segment
     L.slots = take(L.nslot * fb);
     L.cps = take(2 * (size_t)L.ncp * fb);
     L.g = take(m->field_elems() * sizeof(double));
@@ -354,7 +364,7 @@ tb_status run_plan(const tb_model *m, tb_sparse *s, const SchedChoice &sc, const
 
 size_t forward_ws_bytes(const tb_model *m, const tb_sparse *s)
 {
-    const size_t nf = m->physics == TB_TTI ? 6 : (m->physics == TB_ELASTIC ? 9 : 4);
+    const size_t nf = m->physics == TB_TTI ? 6 : (m->physics == TB_ELASTIC ? 9 : 5);
     return nf * field_bytes(m) +
            align256(((size_t)m->nt + 1) * std::max(s->nrid + s->nrid2, 1) * sizeof(float));
 }
@@ -527,15 +537,22 @@ tb_status plan_forward(const tb_model *m, tb_sparse *s, const SchedChoice &sc, v
         return plan_forward_elastic(m, s, ws, rec_out, field_out, field_prev_out, plan);
     const size_t fb = field_bytes(m), fe = m->field_elems();
     char *base = (char *)ws;
-    float *F[4] = {(float *)base, (float *)(base + fb), (float *)(base + 2 * fb),
-                   (float *)(base + 3 * fb)};
-    float *rec = (float *)(base + 4 * fb);
-    plan->push_back(fill_item(F[0], fe));
-    plan->push_back(fill_item(F[1], fe));
+    float *U[2] = {(float *)base, (float *)(base + fb)};
+    float *V[2] = {(float *)(base + 2 * fb), (float *)(base + 3 * fb)};
+    float *mid = (float *)(base + 4 * fb);
+    float *rec = (float *)(base + 5 * fb);
+    // u^0 = u^{-1} = 0: both u buffers (the second is u^{-1} when nt = 0)
+    // and v^0.
+    plan->push_back(fill_item(U[0], fe));
+    plan->push_back(fill_item(U[1], fe));
+    plan->push_back(fill_item(V[0], fe));
     if (s->nrid > 0) plan->push_back(fill_item(rec, (size_t)s->nrid));
-    int cur = 0, prev = 1;
-    plan_time_loop(plan, 0, sc.T, F, 0, m->nt, s->d_dcmp, s->npts, rec, s->nrid, &cur, &prev,
-                   nullptr);
+    int ua = 0, va = 0;
+    plan_time_loop(plan, 0, sc.T, U, V, mid, 0, m->nt, s->d_dcmp, s->npts, rec, s->nrid, &ua,
+                   &va, nullptr);
+    // u^{nt-1}: the intermediate level of a last pass of two or more steps,
+    // else the input of the last (single-step) pass.
+    const int tl = m->nt == 0 ? 1 : (m->nt % sc.T == 0 ? sc.T : m->nt % sc.T);
     if (rec_out && s->nrec > 0 && m->nt > 0) {
         const int nrid = s->nrid, nt = m->nt, nrec = s->nrec;
         const int *pp = s->d_rc_ptr, *id = s->d_rc_id;
@@ -545,7 +562,7 @@ tb_status plan_forward(const tb_model *m, tb_sparse *s, const SchedChoice &sc, v
         }));
     }
     const int nx = m->n[0], ny = m->n[1], nz = m->n[2], nzp = m->nzp;
-    float *fc = F[cur], *fp = F[prev];
+    float *fc = U[ua], *fp = tl > 1 ? mid : U[1 - ua];
     if (field_out)
         plan->push_back(act_item([=](hipStream_t st) {
             return launch_unpad(fc, field_out, nx, ny, nz, nzp, st);
@@ -569,8 +586,10 @@ tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, 
     const size_t fb = field_bytes(m), fe = m->field_elems();
     char *base = (char *)ws;
     auto fld = [=](size_t off, int i) { return (float *)(base + off + (size_t)i * fb); };
-    float *F[4] = {fld(L.F, 0), fld(L.F, 1), fld(L.F, 2), fld(L.F, 3)};
-    float *A[4] = {fld(L.A, 0), fld(L.A, 1), fld(L.A, 2), fld(L.A, 3)};
+    float *FU[2] = {fld(L.F, 0), fld(L.F, 1)}, *FV[2] = {fld(L.F, 2), fld(L.F, 3)};
+    float *AU[2] = {fld(L.A, 0), fld(L.A, 1)}, *AV[2] = {fld(L.A, 2), fld(L.A, 3)};
+    float *AM = fld(L.A, 4);
+    float *RV[2] = {fld(L.RV, 0), fld(L.RV, 1)};
     double *g = (double *)(base + L.g);
     float *rec = (float *)(base + L.rec), *traces = (float *)(base + L.traces);
     float *res = (float *)(base + L.res), *adj_dcmp = (float *)(base + L.adj_dcmp);
@@ -578,16 +597,16 @@ tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, 
     double *loss = (double *)(base + L.loss);
     const int nrec = s->nrec, nrid = s->nrid, npts = s->npts;
 
-    // 1. Forward run from zero state, keeping (u^{jK}, u^{jK-1}) for j >= 1.
-    plan->push_back(fill_item(F[0], fe));
-    plan->push_back(fill_item(F[1], fe));
+    // 1. Forward run from zero state, keeping (u^{jK}, v^{jK}) for j >= 1.
+    plan->push_back(fill_item(FU[0], fe));
+    plan->push_back(fill_item(FV[0], fe));
     if (nrid > 0) plan->push_back(fill_item(rec, (size_t)nrid));
-    int cur = 0, prev = 1, j = 1;
-    plan_time_loop(plan, 0, sc.T, F, 0, nt, s->d_dcmp, npts, rec, nrid, &cur, &prev,
-                   [&](int n, int c, int pv) {
+    int ua = 0, va = 0, j = 1;
+    plan_time_loop(plan, 0, sc.T, FU, FV, nullptr, 0, nt, s->d_dcmp, npts, rec, nrid, &ua, &va,
+                   [&](int n, int cu, int cv) {
                        if (j <= L.ncp && n == j * K) {
-                           plan->push_back(copy_item(fld(L.cps, 2 * (j - 1)), F[c], fb));
-                           plan->push_back(copy_item(fld(L.cps, 2 * (j - 1) + 1), F[pv], fb));
+                           plan->push_back(copy_item(fld(L.cps, 2 * (j - 1)), FU[cu], fb));
+                           plan->push_back(copy_item(fld(L.cps, 2 * (j - 1) + 1), FV[cv], fb));
                            j++;
                        }
                    });
@@ -608,11 +627,11 @@ tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, 
             return TB_OK;
         }));
     }
-    // 3. Segments in reverse: recompute levels k0-1 .. e into the slots, then
+    // 3. Segments in reverse: recompute levels k0 .. e into the slots, then
     //    run the adjoint through levels e+1 .. k0+1 and image each one.
     plan->push_back(act_item([=](hipStream_t st) { return launch_zero64(g, fe, st); }));
-    plan->push_back(fill_item(A[0], fe));
-    plan->push_back(fill_item(A[1], fe));
+    plan->push_back(fill_item(AU[0], fe));
+    plan->push_back(fill_item(AV[0], fe));
     if (npts > 0) plan->push_back(fill_item(adj_rec, (size_t)npts));
     ImageArgs ia{};
     ia.c = m->d_c;
@@ -627,63 +646,63 @@ tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, 
     const long long *soff = s->d_src_off;
     const double *salpha = s->d_src_alpha;
     const int Td = std::min(sc.T, 2);  // every level of these passes is stored
-    int acur = 0, aprev = 1;
+    int au = 0, av = 0;
     for (int seg = L.ncp; seg >= 0 && nt >= 2; seg--) {
         const int k0 = seg * K;
         const int e = std::min(k0 + K - 1, nt - 2);
-        float *slot0 = fld(L.slots, 0), *slot1 = fld(L.slots, 1);
+        // slot i holds u^{k0 + i}; RV holds v of the recomputed levels.
         if (seg == 0) {
-            plan->push_back(fill_item(slot0, fe));
-            plan->push_back(fill_item(slot1, fe));
+            plan->push_back(fill_item(fld(L.slots, 0), fe));
+            plan->push_back(fill_item(RV[0], fe));
         } else {
-            plan->push_back(copy_item(slot0, fld(L.cps, 2 * (seg - 1) + 1), fb));
-            plan->push_back(copy_item(slot1, fld(L.cps, 2 * (seg - 1)), fb));
+            plan->push_back(copy_item(fld(L.slots, 0), fld(L.cps, 2 * (seg - 1)), fb));
+            plan->push_back(copy_item(RV[0], fld(L.cps, 2 * (seg - 1) + 1), fb));
         }
-        // slot i holds level k0 - 1 + i.
+        int rv = 0;
         for (int nn = k0; nn < e;) {
             const int T = std::min(Td, e - nn);
             const int b = nn - k0;
             Pass p;
             p.T = T;
-            p.u = fld(L.slots, b + 1);
-            p.um = fld(L.slots, b);
-            p.out0 = fld(L.slots, b + 1 + T);
-            p.out1 = T == 1 ? nullptr : fld(L.slots, b + 2);
+            p.u = fld(L.slots, b);
+            p.v = RV[rv];
+            p.out_u = fld(L.slots, b + T);
+            p.out_v = RV[1 - rv];
+            p.out_mid = T > 1 ? fld(L.slots, b + 1) : nullptr;
             p.n0 = nn;
             p.dcmp = dcmp;
             p.ninj = npts;
             p.rec = rec;
             p.nrecp = nrid;
             plan->push_back(pass_item(p));
+            rv = 1 - rv;
             nn += T;
         }
         // Adjoint step na produces nu^{nt-1-na}.
         int na = nt - 2 - e;
         for (int left = e - k0 + 1; left > 0;) {
             const int T = std::min(Td, left);
-            int f0 = -1, f1 = -1;
-            if (T > 1)
-                for (int k = 0; k < 4; k++)
-                    if (k != acur && k != aprev) (f0 < 0 ? f0 : f1) = k;
             Pass p;
             p.adjoint = 1;
             p.T = T;
-            p.u = A[acur];
-            p.um = A[aprev];
-            p.out0 = T == 1 ? A[aprev] : A[f0];
-            p.out1 = T == 1 ? nullptr : A[f1];
+            p.u = AU[au];
+            p.v = AV[av];
+            p.out_u = AU[1 - au];
+            p.out_v = AV[1 - av];
+            p.out_mid = T > 1 ? AM : nullptr;
             p.n0 = na;
             p.dcmp = adj_dcmp;
             p.ninj = nrid;
             p.rec = adj_rec;
             p.nrecp = npts;
             plan->push_back(pass_item(p));
-            // Image the levels of this pass, newest-in-k first.
+            // Image the levels of this pass, newest-in-k first (the
+            // intermediate level is overwritten by the next pass).
             for (int t = 0; t < T; t++) {
                 const int k = nt - 1 - na - t;
                 ImageArgs a2 = ia;
-                a2.nu = (t == T - 1) ? p.out0 : p.out1;
-                a2.u = fld(L.slots, k - k0);
+                a2.nu = (t == T - 1) ? p.out_u : p.out_mid;
+                a2.u = fld(L.slots, k - 1 - k0);
                 const float *srow = dcmp + (size_t)(k - 1) * npts;
                 plan->push_back(act_item([=](hipStream_t st) -> tb_status {
                     tb_status rc = launch_image(a2, st);
@@ -691,11 +710,8 @@ tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, 
                     return launch_image_sparse(a2.nu, srow, npts, soff, salpha, g, st);
                 }));
             }
-            if (T == 1) std::swap(acur, aprev);
-            else {
-                acur = f0;
-                aprev = f1;
-            }
+            au = 1 - au;
+            av = 1 - av;
             na += T;
             left -= T;
         }
@@ -713,19 +729,20 @@ tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, 
     return TB_OK;
 }
 
-// Adjoint time loop (tb_adjoint): nt updates from zero state.
+// Adjoint time loop (tb_adjoint): nt updates from zero state in F[0..3].
 tb_status time_loop(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int adjoint,
                     float *F[4], const float *dcmp, int ninj, float *rec_dcmp, int nrecp,
                     hipStream_t st)
 {
     Plan plan;
     const size_t fe = m->field_elems();
-    plan.push_back(fill_item(F[0], fe));
-    plan.push_back(fill_item(F[1], fe));
+    float *U[2] = {F[0], F[1]}, *V[2] = {F[2], F[3]};
+    plan.push_back(fill_item(U[0], fe));
+    plan.push_back(fill_item(V[0], fe));
     if (nrecp > 0) plan.push_back(fill_item(rec_dcmp, (size_t)nrecp));
-    int cur = 0, prev = 1;
-    plan_time_loop(&plan, adjoint, sc.T, F, 0, m->nt, dcmp, ninj, rec_dcmp, nrecp, &cur, &prev,
-                   nullptr);
+    int ua = 0, va = 0;
+    plan_time_loop(&plan, adjoint, sc.T, U, V, nullptr, 0, m->nt, dcmp, ninj, rec_dcmp, nrecp,
+                   &ua, &va, nullptr);
     return run_plan(m, s, sc, plan, st);
 }
 

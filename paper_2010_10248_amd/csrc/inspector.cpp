@@ -112,6 +112,18 @@ static void node_xyz(int64_t r, const int n[3], int *x, int *y, int *z)
 // Default tile width for (R, T): enough lanes that a tile owns 64 z after
 // removing its halo of HZ columns on each side (so 64-multiples of nz are
 // covered without a ragged last tile); rows fill one 512-thread workgroup.
+void tile_shape(int R, int T, int tile_y, int *LZ, int *BYE)
+{
+    const int HZ = ((R * (T - 1) + 3) / 4) * 4;
+    if (tile_y > 0) {
+        *LZ = 16;
+        *BYE = tile_y;
+    } else {
+        *LZ = 16 + HZ / 2;
+        *BYE = (kMaxThreads / *LZ) & ~3;
+    }
+}
+
 TileGeom make_geom(int R, int T, int tile_y, int chunk, int wgs, int nx, int ny, int nz)
 {
     TileGeom g;
@@ -119,13 +131,7 @@ TileGeom make_geom(int R, int T, int tile_y, int chunk, int wgs, int nx, int ny,
     g.T = T;
     g.HY = R * (T - 1);
     g.HZ = ((R * (T - 1) + 3) / 4) * 4;
-    if (tile_y > 0) {
-        g.LZ = 16;
-        g.BYE = tile_y;
-    } else {
-        g.LZ = 16 + g.HZ / 2;
-        g.BYE = (kMaxThreads / g.LZ) & ~3;
-    }
+    tile_shape(R, T, tile_y, &g.LZ, &g.BYE);
     g.OY = g.BYE - 2 * g.HY;
     g.OZ = 4 * g.LZ - 2 * g.HZ;
     g.tiles_y = g.OY > 0 ? (ny + g.OY - 1) / g.OY : 0;

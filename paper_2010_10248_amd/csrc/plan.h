@@ -27,12 +27,13 @@ tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice 
 tb_status lists_for(const tb_model *m, tb_sparse *s, int adjoint, const SchedChoice &sc, int T,
                     TileLists **out);
 
-// One wave-front launch of T updates of one job: from (u = level n0,
-// um = level n0-1) to out0 = level n0+T and, for T > 1, out1 = level n0+T-1.
+// One wave-front launch of T updates of one job: from (u = u^{n0},
+// v = u^{n0} - u^{n0-1}) to out_u = u^{n0+T}, out_v = v^{n0+T} and, if
+// out_mid is set and T > 1, out_mid = u^{n0+T-1}.
 struct Pass {
     int adjoint = 0, T = 1;
-    const float *u = nullptr, *um = nullptr;
-    float *out0 = nullptr, *out1 = nullptr;
+    const float *u = nullptr, *v = nullptr;
+    float *out_u = nullptr, *out_v = nullptr, *out_mid = nullptr;
     int n0 = 0;
     const float *dcmp = nullptr;
     int ninj = 0;

@@ -35,7 +35,7 @@ constexpr int kMaxChunk = 2048;
 // Per-tile list capacities (the lists are staged in LDS); a schedule whose
 // tiles exceed them is run with shorter x chunks.
 constexpr int kSrcCap = 512;
-constexpr int kRecCap = 2048;
+constexpr int kRecCap = 1024;
 
 // A list entry: key = ((row*32 + lane) << 18) | (x << 2) | k, with k the z
 // component inside the lane's float4; id = point ID. Sorted by key, so each
@@ -70,6 +70,11 @@ struct TileGeom {
 // (tile, chunk of x); chunk == 0 partitions the tile-x space evenly over
 // `wgs` workgroups.
 TileGeom make_geom(int R, int T, int tile_y, int chunk, int wgs, int nx, int ny, int nz);
+// Lanes per row and rows of the tile a schedule selects.
+void tile_shape(int R, int T, int tile_y, int *LZ, int *BYE);
+// Whether the wave-front kernel is built for this radius, depth and shape
+// (it must fit the LDS of one workgroup).
+bool acoustic_shape_ok(int R, int T, int LZ, int BYE);
 
 // Per-segment injection / recording lists, entries {key, id}, and the
 // segment table of one schedule geometry.
@@ -176,8 +181,8 @@ tb_status build_tile_lists(const tb_model *m, const std::vector<int64_t> &inj,
 
 // Kernel launchers (acoustic.hip).
 struct AcLaunch {
-    const float *u, *um;
-    float *out0, *out1;
+    const float *u, *v;  // u^n, v^n = u^n - u^{n-1}
+    float *out_u, *out_v, *out_mid;  // u^{n+T}, v^{n+T}, u^{n+T-1} (or NULL)
     int n0;  // time index of the first update of this pass
     const float *dcmp;
     int npts;

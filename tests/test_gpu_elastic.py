@@ -61,3 +61,17 @@ def test_elastic_zero_source_and_unsupported_paths(torch_cuda):
         prop.forward(tb.schedule("tb", 2, 32))
     assert e.value.status == tb.EUNSUPPORTED
     prop.close()
+
+
+def test_elastic_full_size_first_steps(torch_cuda, orc):
+    """The 256^3 SO8 elastic workload: the first 4 steps against the oracle
+    on the full grid (vz and tzz fields)."""
+    from paper_2010_10248_amd import tb
+
+    s = W.elastic_smooth(nt=4)
+    ref = orc.elastic_forward(s)
+    out = tb.Propagator(s).forward(None)
+    e = (_rel(out["u_last"].cpu().numpy(), ref["vz_field"]),
+         _rel(out["u_prev"].cpu().numpy(), ref["tzz"]))
+    print(f"elastic 256^3 first 4 steps: {e}", flush=True)
+    assert max(e) <= TOL

@@ -91,3 +91,17 @@ def test_tti_zero_source_and_unsupported_paths(torch_cuda):
         prop.adjoint(torch.zeros((s.nt, s.rec_xyz.shape[0]), device="cuda"))
     assert e.value.status == tb.EUNSUPPORTED
     prop.close()
+
+
+def test_tti_full_size_first_steps(torch_cuda, orc):
+    """The 256^3 SO8 TTI workload (smooth random parameters, 4 sources): the
+    first 4 steps against the oracle on the full grid."""
+    from paper_2010_10248_amd import tb
+
+    s = W.tti_smooth(nt=4)
+    ref = orc.tti_forward(s)
+    out = tb.Propagator(s).forward(None)
+    e = (_rel(out["u_last"].cpu().numpy(), ref["p_last"]),
+         _rel(out["u_prev"].cpu().numpy(), ref["p_prev"]))
+    _say(f"TTI 256^3 first 4 steps: {e}")
+    assert max(e) <= TOL
