@@ -364,23 +364,24 @@ tb_status run_plan(const tb_model *m, tb_sparse *s, const SchedChoice &sc, const
 
 size_t forward_ws_bytes(const tb_model *m, const tb_sparse *s)
 {
-    const size_t nf = m->physics == TB_TTI ? 6 : (m->physics == TB_ELASTIC ? 9 : 5);
+    const size_t nf = m->physics == TB_TTI ? 8 : (m->physics == TB_ELASTIC ? 9 : 5);
     return nf * field_bytes(m) +
            align256(((size_t)m->nt + 1) * std::max(s->nrid + s->nrid2, 1) * sizeof(float));
 }
 
 namespace {
 
-// TTI forward (SB): p, p_prev, r, r_prev, q_p, q_r, then rec_dcmp.
+// TTI forward (SB): p (two levels), r (two levels), w_p, w_r, q_p, q_r, then
+// rec_dcmp.
 tb_status plan_forward_tti(const tb_model *m, tb_sparse *s, void *ws, float *rec_out,
                            float *field_out, float *field_prev_out, Plan *plan)
 {
     const size_t fb = field_bytes(m), fe = m->field_elems();
     char *base = (char *)ws;
-    float *F[6];
-    for (int k = 0; k < 6; k++) F[k] = (float *)(base + k * fb);
-    float *rec = (float *)(base + 6 * fb);
-    for (int k = 0; k < 6; k++) plan->push_back(fill_item(F[k], fe));
+    float *F[8];
+    for (int k = 0; k < 8; k++) F[k] = (float *)(base + k * fb);
+    float *rec = (float *)(base + 8 * fb);
+    for (int k = 0; k < 8; k++) plan->push_back(fill_item(F[k], fe));
     const int nrid = s->nrid, npts = s->npts, nt = m->nt;
     if (nrid > 0) plan->push_back(fill_item(rec, (size_t)nrid));
     TtiParams P{};
@@ -409,8 +410,10 @@ tb_status plan_forward_tti(const tb_model *m, tb_sparse *s, void *ws, float *rec
     P.ny = m->n[1];
     P.nz = m->n[2];
     P.nzp = m->nzp;
-    P.qp = F[4];
-    P.qr = F[5];
+    P.vp = F[4];
+    P.vr = F[5];
+    P.qp = F[6];
+    P.qr = F[7];
     const int r = m->r;
     const float *dcmp = s->d_dcmp;
     const long long *soff = s->d_src_off, *roff = s->d_rid_off;
@@ -418,9 +421,9 @@ tb_status plan_forward_tti(const tb_model *m, tb_sparse *s, void *ws, float *rec
     for (int n = 0; n < nt; n++) {
         TtiParams Q = P;
         Q.p = F[pc];
-        Q.pm = F[pp];
+        Q.pn = F[pp];
         Q.r = F[pc + 2];
-        Q.rm = F[pp + 2];
+        Q.rn = F[pp + 2];
         const float *inc = dcmp + (size_t)n * npts;
         float *row = rec + (size_t)(n + 1) * nrid;
         plan->push_back(act_item([=](hipStream_t st) {

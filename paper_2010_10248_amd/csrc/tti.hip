@@ -2,11 +2,15 @@
 // kernels over the padded grid [nx][ny][nzp], z fastest:
 //   tti_rot      q_p = a . grad p,  q_r = a . grad r   (a = symmetry axis,
 //                centred first derivatives of the space order, zero outside);
-//   tti_update   Hz u = sum_b d_b (a_b q_u), H0 p = L p - Hz p,
-//                p' = (c [(1+2e) H0 p + s Hz r] + 2p - beta p_prev) / alpha,
-//                r' = (c [s H0 p + Hz r]       + 2r - beta r_prev) / alpha,
-//                with s = sqrt(1 + 2 min(delta, eps)); p', r' overwrite the
-//                previous levels in place (read only at the same point);
+//   tti_update   Hz u = sum_b d_b (a_b q_u), H0 p = L p - Hz p, and in the
+//                velocity form of the leapfrog (w = u^n - u^{n-1}):
+//                w_p' = (c [(1+2e) H0 p + s Hz r] + beta w_p) / alpha,
+//                w_r' = (c [s H0 p + Hz r]        + beta w_r) / alpha,
+//                p' = p + w_p', r' = r + w_r', s = sqrt(1 + 2 min(delta, eps));
+//                L is applied to differences from the centre, so a constant
+//                has an exactly zero Laplacian in FP32 (as in the acoustic
+//                kernel, this keeps FP32 runs of many steps on the FP64
+//                definition); w updates in place, p' and r' go to new buffers;
 //   tti_sparse   injection of the inspector's per-point increments into p'
 //                and r', and the receiver gather of p'.
 // Every field is zero outside the grid (bounds-checked neighbour reads), so
@@ -67,18 +71,19 @@ __global__ void __launch_bounds__(256) tti_update(const TtiParams P)
     const int y = (int)(xy % P.ny), x = (int)(xy / P.ny);
     const long long sx = (long long)P.ny * P.nzp, sy = P.nzp;
     const float pc = P.p[gid], rc = P.r[gid];
-    // L p: centred second derivatives.
-    float lx = P.w2[0] * pc, ly = P.w2[0] * pc, lz = P.w2[0] * pc;
+    // L p: centred second derivatives on differences from the centre.
+    const float p2 = 2.0f * pc;
+    float lx = 0.0f, ly = 0.0f, lz = 0.0f;
     // Hz u = sum_b d_b (a_b q_u).
     float hp[3] = {0.f, 0.f, 0.f}, hr[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int m = 1; m <= R; m++) {
-        lx = __builtin_fmaf(P.w2[m], nb(P.p, P, x + m, y, z, gid + m * sx) +
-                                         nb(P.p, P, x - m, y, z, gid - m * sx), lx);
-        ly = __builtin_fmaf(P.w2[m], nb(P.p, P, x, y + m, z, gid + m * sy) +
-                                         nb(P.p, P, x, y - m, z, gid - m * sy), ly);
-        lz = __builtin_fmaf(P.w2[m], nb(P.p, P, x, y, z + m, gid + m) +
-                                         nb(P.p, P, x, y, z - m, gid - m), lz);
+        lx = __builtin_fmaf(P.w2[m], (nb(P.p, P, x + m, y, z, gid + m * sx) +
+                                      nb(P.p, P, x - m, y, z, gid - m * sx)) - p2, lx);
+        ly = __builtin_fmaf(P.w2[m], (nb(P.p, P, x, y + m, z, gid + m * sy) +
+                                      nb(P.p, P, x, y - m, z, gid - m * sy)) - p2, ly);
+        lz = __builtin_fmaf(P.w2[m], (nb(P.p, P, x, y, z + m, gid + m) +
+                                      nb(P.p, P, x, y, z - m, gid - m)) - p2, lz);
         const float w = P.w1[m - 1];
         const long long o[3] = {m * sx, m * sy, (long long)m};
         const int dx[3] = {m, 0, 0}, dy[3] = {0, m, 0}, dz[3] = {0, 0, m};
@@ -105,25 +110,30 @@ __global__ void __launch_bounds__(256) tti_update(const TtiParams P)
     const float d = P.dx[x] + P.dy[y] + P.dz[z];
     const float dd = d * P.hdt;
     const float beta = 1.0f - dd;
-    float pn = __builtin_fmaf(cc, rhs_p, __builtin_fmaf(-beta, P.pm[gid], 2.0f * pc));
-    float rn = __builtin_fmaf(cc, rhs_r, __builtin_fmaf(-beta, P.rm[gid], 2.0f * rc));
+    float wp = __builtin_fmaf(cc, rhs_p, beta * P.vp[gid]);
+    float wr = __builtin_fmaf(cc, rhs_r, beta * P.vr[gid]);
     if (d != 0.0f) {
-        pn = pn / (1.0f + dd);
-        rn = rn / (1.0f + dd);
+        wp = wp / (1.0f + dd);
+        wr = wr / (1.0f + dd);
     }
-    P.pm[gid] = pn;
-    P.rm[gid] = rn;
+    P.vp[gid] = wp;
+    P.vr[gid] = wr;
+    P.pn[gid] = pc + wp;
+    P.rn[gid] = rc + wr;
 }
 
-__global__ void tti_sparse(float *__restrict__ p, float *__restrict__ r,
-                           const float *__restrict__ inc, const long long *__restrict__ soff,
-                           int npts)
+// The injected increment enters the new level and its velocity alike.
+__global__ void tti_sparse(float *__restrict__ p, float *__restrict__ r, float *__restrict__ vp,
+                           float *__restrict__ vr, const float *__restrict__ inc,
+                           const long long *__restrict__ soff, int npts)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < npts) {
         const long long o = soff[i];
         p[o] += inc[i];
         r[o] += inc[i];
+        vp[o] += inc[i];
+        vr[o] += inc[i];
     }
 }
 
@@ -155,14 +165,13 @@ tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const lon
         return TB_EUNSUPPORTED;
     }
     TB_HIP(hipGetLastError());
-    // The new levels are in pm / rm.
     if (npts > 0) {
-        hipLaunchKernelGGL(tti_sparse, dim3(nblocks(npts)), dim3(256), 0, st, P.pm, P.rm, inc,
-                           soff, npts);
+        hipLaunchKernelGGL(tti_sparse, dim3(nblocks(npts)), dim3(256), 0, st, P.pn, P.rn, P.vp,
+                           P.vr, inc, soff, npts);
         TB_HIP(hipGetLastError());
     }
     if (nrid > 0) {
-        hipLaunchKernelGGL(tti_record, dim3(nblocks(nrid)), dim3(256), 0, st, P.pm, rec_row, roff,
+        hipLaunchKernelGGL(tti_record, dim3(nblocks(nrid)), dim3(256), 0, st, P.pn, rec_row, roff,
                            nrid);
         TB_HIP(hipGetLastError());
     }

@@ -7,7 +7,8 @@ namespace tbw {
 
 struct TtiParams {
     const float *p, *r;  // current levels p^n, r^n        [nx][ny][nzp]
-    float *pm, *rm;      // p^{n-1}, r^{n-1}; receive p^{n+1}, r^{n+1}
+    float *vp, *vr;      // p^n - p^{n-1}, r^n - r^{n-1}; updated in place
+    float *pn, *rn;      // receive p^{n+1}, r^{n+1}
     float *qp, *qr;      // rotated gradients (scratch)
     const float *ax, *ay, *az;  // symmetry axis per node
     const float *e1, *sd;       // 1 + 2 eps, sqrt(1 + 2 min(delta, eps))
@@ -20,9 +21,9 @@ struct TtiParams {
     int nx, ny, nz, nzp;
 };
 
-// One step: rotated gradients, coupled update (in place over the previous
-// levels), injection of inc[npts] at soff into both fields, gather of p into
-// rec_row[nrid] at roff.
+// One step: rotated gradients, coupled update (velocity form), injection of
+// inc[npts] at soff into both fields, gather of p^{n+1} into rec_row[nrid] at
+// roff.
 tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const long long *soff,
                           int npts, float *rec_row, const long long *roff, int nrid,
                           hipStream_t st);

@@ -75,3 +75,26 @@ def test_elastic_full_size_first_steps(torch_cuda, orc):
          _rel(out["u_prev"].cpu().numpy(), ref["tzz"]))
     print(f"elastic 256^3 first 4 steps: {e}", flush=True)
     assert max(e) <= TOL
+
+
+def test_elastic_long_run(torch_cuda, orc):
+    """600 steps on a reduced grid against the oracle: traces over the whole
+    record by relative L2. On this small absorbing grid the wavefield has
+    decayed 150-600x by the last step, so the final fields are compared with
+    the field scale of the energetic phase (step 100): the FP32 rounding error
+    is a fixed fraction of that scale, not of the decayed remainder."""
+    from paper_2010_10248_amd import tb
+
+    s = W.elastic_smooth(seed=10, n=(36, 40, 44), so=8, nt=600, nbl=6, nrec=16, sigma=4.0)
+    ref = orc.elastic_forward(s)
+    early = orc.elastic_forward(W.elastic_smooth(seed=10, n=(36, 40, 44), so=8, nt=100, nbl=6,
+                                                 nrec=16, sigma=4.0))
+    out = tb.Propagator(s).forward(None)
+    tr = out["traces"].cpu().numpy()
+    dv = np.linalg.norm(out["u_last"].cpu().numpy() - ref["vz_field"])
+    dt = np.linalg.norm(out["u_prev"].cpu().numpy() - ref["tzz"])
+    e = dict(vz=_rel(tr[0], ref["vz"]), p=_rel(tr[1], ref["p"]),
+             vz_field=float(dv / np.linalg.norm(early["vz_field"])),
+             tzz_field=float(dt / np.linalg.norm(early["tzz"])))
+    print(f"elastic 600 steps: {e}", flush=True)
+    assert all(v <= TOL for v in e.values()), e

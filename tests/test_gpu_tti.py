@@ -105,3 +105,17 @@ def test_tti_full_size_first_steps(torch_cuda, orc):
          _rel(out["u_prev"].cpu().numpy(), ref["p_prev"]))
     _say(f"TTI 256^3 first 4 steps: {e}")
     assert max(e) <= TOL
+
+
+def test_tti_long_run(torch_cuda, orc):
+    """600 steps on a reduced grid: the FP32 run stays on the FP64 definition."""
+    from paper_2010_10248_amd import tb
+
+    s = W.tti_smooth(seed=9, n=(36, 40, 44), so=8, nt=600, nbl=6, nsrc=2, nrec=16, sigma=4.0)
+    ref = orc.tti_forward(s)
+    out = tb.Propagator(s).forward(None)
+    e = dict(traces=_rel(out["traces"].cpu().numpy(), ref["traces"]),
+             p_last=_rel(out["u_last"].cpu().numpy(), ref["p_last"]),
+             p_prev=_rel(out["u_prev"].cpu().numpy(), ref["p_prev"]))
+    _say(f"TTI 600 steps: {e}")
+    assert all(v <= TOL for v in e.values()), e
