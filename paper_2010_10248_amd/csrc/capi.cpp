@@ -279,7 +279,7 @@ struct GradLayout {
     int K = 0;       // checkpoint interval (a multiple of the forward depth)
     int ncp = 0;     // stored checkpoints (u^{jK}, v^{jK} for j >= 1)
     int nslot = 0;   // segment slots (u levels jK .. jK+K-1)
-    size_t F = 0, A = 0, RV = 0, slots = 0, cps = 0, g = 0, rec = 0, traces = 0, res = 0,
+    size_t F = 0, A = 0, RV = 0, slots = 0, cps = 0, g = 0, gs = 0, rec = 0, traces = 0, res = 0,
            adj_dcmp = 0, adj_rec = 0, loss = 0, total = 0;
 };
 
@@ -314,6 +314,7 @@ GradLayout grad_layout(const tb_model *m, const tb_sparse *s, const SchedChoice 
     L.slots = take(L.nslot * fb);
     L.cps = take(2 * (size_t)L.ncp * fb);
     L.g = take(m->field_elems() * sizeof(double));
+    L.gs = take((size_t)std::max(s->npts, 1) * sizeof(double));
     L.rec = take(nt1 * std::max(s->nrid, 1) * sizeof(float));
     L.traces = take((size_t)nt * std::max(s->nrec, 1) * sizeof(float));
     L.res = take((size_t)nt * std::max(s->nrec, 1) * sizeof(float));
@@ -594,6 +595,7 @@ tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, 
     float *AM = fld(L.A, 4);
     float *RV[2] = {fld(L.RV, 0), fld(L.RV, 1)};
     double *g = (double *)(base + L.g);
+    double *gs = (double *)(base + L.gs);
     float *rec = (float *)(base + L.rec), *traces = (float *)(base + L.traces);
     float *res = (float *)(base + L.res), *adj_dcmp = (float *)(base + L.adj_dcmp);
     float *adj_rec = (float *)(base + L.adj_rec);
@@ -632,7 +634,11 @@ tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, 
     }
     // 3. Segments in reverse: recompute levels k0 .. e into the slots, then
     //    run the adjoint through levels e+1 .. k0+1 and image each one.
-    plan->push_back(act_item([=](hipStream_t st) { return launch_zero64(g, fe, st); }));
+    plan->push_back(act_item([=](hipStream_t st) -> tb_status {
+        tb_status rc = launch_zero64(g, fe, st);
+        if (rc) return rc;
+        return launch_zero64(gs, (size_t)npts, st);
+    }));
     plan->push_back(fill_item(AU[0], fe));
     plan->push_back(fill_item(AV[0], fe));
     if (npts > 0) plan->push_back(fill_item(adj_rec, (size_t)npts));
@@ -699,20 +705,25 @@ tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, 
             p.rec = adj_rec;
             p.nrecp = npts;
             plan->push_back(pass_item(p));
-            // Image the levels of this pass, newest-in-k first (the
-            // intermediate level is overwritten by the next pass).
+            // Image the levels of this pass in one sweep, newest-in-k first
+            // (the intermediate level is overwritten by the next pass); the
+            // source-point terms go to their own accumulator in the same
+            // level order, so the sums do not depend on the pass depth.
+            ImageArgs a2 = ia;
+            a2.nlev = T;
+            const float *srow[2] = {nullptr, nullptr};
             for (int t = 0; t < T; t++) {
                 const int k = nt - 1 - na - t;
-                ImageArgs a2 = ia;
-                a2.nu = (t == T - 1) ? p.out_u : p.out_mid;
-                a2.u = fld(L.slots, k - 1 - k0);
-                const float *srow = dcmp + (size_t)(k - 1) * npts;
-                plan->push_back(act_item([=](hipStream_t st) -> tb_status {
-                    tb_status rc = launch_image(a2, st);
-                    if (rc) return rc;
-                    return launch_image_sparse(a2.nu, srow, npts, soff, salpha, g, st);
-                }));
+                a2.nu[t] = (t == T - 1) ? p.out_u : p.out_mid;
+                a2.u[t] = fld(L.slots, k - 1 - k0);
+                srow[t] = dcmp + (size_t)(k - 1) * npts;
             }
+            plan->push_back(act_item([=](hipStream_t st) -> tb_status {
+                tb_status rc = launch_image(a2, st);
+                for (int t = 0; t < a2.nlev && !rc; t++)
+                    rc = launch_image_sparse(a2.nu[t], srow[t], npts, soff, salpha, gs, st);
+                return rc;
+            }));
             au = 1 - au;
             av = 1 - av;
             na += T;
@@ -721,7 +732,9 @@ tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, 
     }
     const int nx = m->n[0], ny = m->n[1], nz = m->n[2], nzp = m->nzp;
     const double scale = -1.0 / (m->dt * m->dt);
-    plan->push_back(act_item([=](hipStream_t st) {
+    plan->push_back(act_item([=](hipStream_t st) -> tb_status {
+        tb_status rc = launch_image_merge(gs, npts, soff, g, st);
+        if (rc) return rc;
         return launch_finish_grad(g, grad_m, nx, ny, nz, nzp, scale, st);
     }));
     if (loss_dst)

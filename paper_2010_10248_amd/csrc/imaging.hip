@@ -52,47 +52,95 @@ __global__ void __launch_bounds__(kLossThreads)
     if (threadIdx.x == 0) out[0] = part[0];
 }
 
-// g += nu * c * L(u) at every grid point (padded layout, z padding skipped).
-__global__ void image_kernel(const ImageArgs a)
+// g += nu * c * L(u) for one or two levels; each thread takes 4 consecutive z
+// (float4 loads of the fields; the z neighbours come from the float4 on each
+// side), z padding skipped.
+__global__ void __launch_bounds__(256) image_kernel(const ImageArgs a)
 {
-    const long long total = (long long)a.nx * a.ny * a.nz;
+    const int nz4 = a.nzp / 4;
+    const long long total = (long long)a.nx * a.ny * nz4;
     const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (gid >= total) return;
-    const int z = (int)(gid % a.nz);
-    const long long xy = gid / a.nz;
+    const int z4 = (int)(gid % nz4) * 4;
+    const long long xy = gid / nz4;
     const int y = (int)(xy % a.ny);
     const int x = (int)(xy / a.ny);
     const long long sx = (long long)a.ny * a.nzp;
-    const long long off = xy * a.nzp + z;
-    const float nu = a.nu[off];
-    if (nu == 0.0f) return;  // adds +0 to a finite g
-    const float *u = a.u;
-    const double uc = u[off];
-    double lx = a.w[0][0] * uc, ly = a.w[1][0] * uc, lz = a.w[2][0] * uc;
-    for (int j = 1; j <= a.r; j++) {
-        const double xm = x - j >= 0 ? (double)u[off - j * sx] : 0.0;
-        const double xp = x + j < a.nx ? (double)u[off + j * sx] : 0.0;
-        const double ym = y - j >= 0 ? (double)u[off - (long long)j * a.nzp] : 0.0;
-        const double yp = y + j < a.ny ? (double)u[off + (long long)j * a.nzp] : 0.0;
-        const double zm = z - j >= 0 ? (double)u[off - j] : 0.0;
-        const double zp = z + j < a.nz ? (double)u[off + j] : 0.0;
-        lx += a.w[0][j] * (xm + xp);
-        ly += a.w[1][j] * (ym + yp);
-        lz += a.w[2][j] * (zm + zp);
+    const long long off = xy * a.nzp + z4;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    auto ld4 = [&](const float *f, long long o, bool in) {
+        return in ? *(const f4 *)(f + o) : f4{0.f, 0.f, 0.f, 0.f};
+    };
+    const f4 cc = ld4(a.c, off, true);
+    double acc[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) acc[k] = 0.0;
+    bool touched = false;
+    for (int l = 0; l < a.nlev; l++) {
+        const f4 nu = ld4(a.nu[l], off, true);
+        // A zero adjoint level adds +0 to a finite g: skip its stencil.
+        if (nu[0] == 0.0f && nu[1] == 0.0f && nu[2] == 0.0f && nu[3] == 0.0f) continue;
+        const float *u = a.u[l];
+        const f4 uc = ld4(u, off, true);
+        const f4 zl = ld4(u, off - 4, z4 >= 4);
+        const f4 zr = ld4(u, off + 4, z4 + 4 < a.nzp);
+        const float zw[12] = {zl[0], zl[1], zl[2], zl[3], uc[0], uc[1], uc[2], uc[3],
+                              zr[0], zr[1], zr[2], zr[3]};
+        double lx[4], ly[4], lz[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            lx[k] = a.w[0][0] * (double)uc[k];
+            ly[k] = a.w[1][0] * (double)uc[k];
+            lz[k] = a.w[2][0] * (double)uc[k];
+        }
+        for (int j = 1; j <= a.r; j++) {
+            const f4 xm = ld4(u, off - j * sx, x - j >= 0);
+            const f4 xp = ld4(u, off + j * sx, x + j < a.nx);
+            const f4 ym = ld4(u, off - (long long)j * a.nzp, y - j >= 0);
+            const f4 yp = ld4(u, off + (long long)j * a.nzp, y + j < a.ny);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                lx[k] += a.w[0][j] * ((double)xm[k] + (double)xp[k]);
+                ly[k] += a.w[1][j] * ((double)ym[k] + (double)yp[k]);
+                lz[k] += a.w[2][j] * ((double)zw[4 + k - j] + (double)zw[4 + k + j]);
+            }
+        }
+        double *g = a.g + off;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (z4 + k >= a.nz || nu[k] == 0.0f) continue;
+            if (!touched) {
+#pragma unroll
+                for (int kk = 0; kk < 4; kk++) acc[kk] = z4 + kk < a.nz ? g[kk] : 0.0;
+                touched = true;
+            }
+            acc[k] += (double)nu[k] * ((double)cc[k] * (lx[k] + ly[k] + lz[k]));
+        }
     }
-    a.g[off] += (double)nu * ((double)a.c[off] * (lx + ly + lz));
+    if (touched) {
+        double *g = a.g + off;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            if (z4 + k < a.nz) g[k] = acc[k];
+    }
 }
 
-// g += nu * alpha * s at the injection points (s = the decomposed increment
+// gs += nu * alpha * s at the injection points (s = the decomposed increment
 // of one step, one value per point).
 __global__ void image_sparse_kernel(const float *__restrict__ nu, const float *__restrict__ s,
                                     int npts, const long long *__restrict__ off,
-                                    const double *__restrict__ alpha, double *__restrict__ g)
+                                    const double *__restrict__ alpha, double *__restrict__ gs)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npts) return;
-    const long long o = off[i];
-    g[o] += (double)nu[o] * (alpha[i] * (double)s[i]);
+    gs[i] += (double)nu[off[i]] * (alpha[i] * (double)s[i]);
+}
+
+__global__ void image_merge_kernel(const double *__restrict__ gs, int npts,
+                                   const long long *__restrict__ off, double *__restrict__ g)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < npts) g[off[i]] += gs[i];
 }
 
 // grad_m = scale * g, unpadded.
@@ -132,19 +180,29 @@ tb_status launch_residual_loss(const float *d, const float *dobs, long long n, f
 
 tb_status launch_image(const ImageArgs &a, hipStream_t st)
 {
-    const long long total = (long long)a.nx * a.ny * a.nz;
-    if (total == 0) return TB_OK;
+    const long long total = (long long)a.nx * a.ny * (a.nzp / 4);
+    if (total == 0 || a.nlev == 0) return TB_OK;
     hipLaunchKernelGGL(image_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, st, a);
     TB_HIP(hipGetLastError());
     return TB_OK;
 }
 
 tb_status launch_image_sparse(const float *nu, const float *s, int npts, const long long *off,
-                              const double *alpha, double *g, hipStream_t st)
+                              const double *alpha, double *gs, hipStream_t st)
 {
     if (npts == 0) return TB_OK;
     hipLaunchKernelGGL(image_sparse_kernel, dim3(blocks_for(npts, 256)), dim3(256), 0, st, nu, s,
-                       npts, off, alpha, g);
+                       npts, off, alpha, gs);
+    TB_HIP(hipGetLastError());
+    return TB_OK;
+}
+
+tb_status launch_image_merge(const double *gs, int npts, const long long *off, double *g,
+                             hipStream_t st)
+{
+    if (npts == 0) return TB_OK;
+    hipLaunchKernelGGL(image_merge_kernel, dim3(blocks_for(npts, 256)), dim3(256), 0, st, gs,
+                       npts, off, g);
     TB_HIP(hipGetLastError());
     return TB_OK;
 }

@@ -204,8 +204,12 @@ tb_status launch_adj_inject(const float *res, int nt, int nrec, int nrid, const 
                             float *dcmp_out, hipStream_t st);
 
 // Gradient kernels (imaging.hip).
+// Imaging of one or two consecutive levels in one pass over memory:
+// g += nu[l] * c * L(u[l]) for l = 0 .. nlev-1, in that order.
 struct ImageArgs {
-    const float *nu, *u, *c;
+    const float *nu[2], *u[2];
+    int nlev;
+    const float *c;
     double *g;
     int nx, ny, nz, nzp, r;
     double w[3][5];  // centred second-derivative weights per axis, scaled by h^-2
@@ -213,8 +217,12 @@ struct ImageArgs {
 tb_status launch_residual_loss(const float *d, const float *dobs, long long n, float *res,
                                double *loss, hipStream_t st);
 tb_status launch_image(const ImageArgs &a, hipStream_t st);
+// gs[i] += nu[off[i]] * alpha[i] * s[i] at the injection points (a separate
+// accumulator, merged into g once by launch_image_merge).
 tb_status launch_image_sparse(const float *nu, const float *s, int npts, const long long *off,
-                              const double *alpha, double *g, hipStream_t st);
+                              const double *alpha, double *gs, hipStream_t st);
+tb_status launch_image_merge(const double *gs, int npts, const long long *off, double *g,
+                             hipStream_t st);
 tb_status launch_finish_grad(const double *g, float *out, int nx, int ny, int nz, int nzp,
                              double scale, hipStream_t st);
 tb_status launch_zero64(double *p, size_t n, hipStream_t st);
