@@ -14,103 +14,144 @@
 namespace tbw {
 namespace {
 
-// Staggered first derivative along axis AX at element (x, y, z). FWD: the
-// field sits at integer positions along AX and the target half a cell above
-// (samples [i+m+1] - [i-m]); otherwise the field sits half a cell above its
-// index and the target at the integer position ([i+m] - [i-m-1]).
-template <int R, int AX, bool FWD>
-__device__ __forceinline__ float dstg(const float *__restrict__ f, const ElParams &P, int x, int y,
-                                      int z, long long gid)
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Each thread takes 4 consecutive z (float4 accesses); neighbours along x and
+// y are float4 loads, along z they come from the 12-value window [z4-4,
+// z4+8). Reads outside the grid give 0; the z padding holds 0 in every field.
+struct Site {
+    int x, y, z4;
+    long long off, sx, sy;
+};
+
+__device__ __forceinline__ bool locate4(const ElParams &P, Site &q)
 {
-    const int c = AX == 0 ? x : (AX == 1 ? y : z);
-    const int n = AX == 0 ? P.nx : (AX == 1 ? P.ny : P.nz);
-    const long long st = AX == 0 ? (long long)P.ny * P.nzp : (AX == 1 ? (long long)P.nzp : 1);
-    float s = 0.0f;
-#pragma unroll
-    for (int m = 0; m < R; m++) {
-        const int a = FWD ? m + 1 : m, b = FWD ? -m : -m - 1;
-        const float up = (c + a < n) ? f[gid + a * st] : 0.0f;
-        const float dn = (c + b >= 0) ? f[gid + b * st] : 0.0f;
-        s = __builtin_fmaf(P.w[m], up - dn, s);
-    }
-    return s * P.ih[AX];
+    const int nz4 = P.nzp / 4;
+    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (gid >= (long long)P.nx * P.ny * nz4) return false;
+    q.z4 = (int)(gid % nz4) * 4;
+    const long long xy = gid / nz4;
+    q.y = (int)(xy % P.ny);
+    q.x = (int)(xy / P.ny);
+    q.sx = (long long)P.ny * P.nzp;
+    q.sy = P.nzp;
+    q.off = xy * P.nzp + q.z4;
+    return true;
 }
 
-__device__ __forceinline__ void locate(const ElParams &P, long long gid, int &x, int &y, int &z)
+__device__ __forceinline__ f4 ld4(const float *f, long long o, bool in)
 {
-    z = (int)(gid % P.nzp);
-    const long long xy = gid / P.nzp;
-    y = (int)(xy % P.ny);
-    x = (int)(xy / P.ny);
+    return in ? *(const f4 *)(f + o) : f4{0.f, 0.f, 0.f, 0.f};
+}
+
+// Staggered first derivative (scaled by 1/h) along AX at the 4 sites. FWD:
+// the field sits at integer positions along AX and the target half a cell
+// above (samples [i+m+1] - [i-m]); otherwise [i+m] - [i-m-1].
+template <int R, int AX, bool FWD>
+__device__ __forceinline__ f4 dstg(const float *__restrict__ f, const ElParams &P, const Site &q)
+{
+    f4 s = f4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (AX == 2) {
+        const f4 a = ld4(f, q.off - 4, q.z4 >= 4), b = ld4(f, q.off, true),
+                 c = ld4(f, q.off + 4, q.z4 + 4 < P.nzp);
+        const float w[12] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3],
+                             c[0], c[1], c[2], c[3]};
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+#pragma unroll
+            for (int m = 0; m < R; m++) {
+                const int up = FWD ? m + 1 : m, dn = FWD ? -m : -m - 1;
+                s[k] = __builtin_fmaf(P.w[m], w[4 + k + up] - w[4 + k + dn], s[k]);
+            }
+    } else {
+        const int c = AX == 0 ? q.x : q.y, n = AX == 0 ? P.nx : P.ny;
+        const long long st = AX == 0 ? q.sx : q.sy;
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const int up = FWD ? m + 1 : m, dn = FWD ? -m : -m - 1;
+            const f4 fu = ld4(f, q.off + up * st, c + up < n);
+            const f4 fd = ld4(f, q.off + dn * st, c + dn >= 0);
+#pragma unroll
+            for (int k = 0; k < 4; k++) s[k] = __builtin_fmaf(P.w[m], fu[k] - fd[k], s[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) s[k] *= P.ih[AX];
+    return s;
 }
 
 template <int R>
 __global__ void __launch_bounds__(256) el_vel(const ElParams P)
 {
-    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (gid >= (long long)P.nx * P.ny * P.nzp) return;
-    int x, y, z;
-    locate(P, gid, x, y, z);
-    if (z >= P.nz) return;
-    const float fx = dstg<R, 0, true>(P.t[0], P, x, y, z, gid) +
-                     dstg<R, 1, false>(P.t[3], P, x, y, z, gid) +
-                     dstg<R, 2, false>(P.t[4], P, x, y, z, gid);
-    const float fy = dstg<R, 0, false>(P.t[3], P, x, y, z, gid) +
-                     dstg<R, 1, true>(P.t[1], P, x, y, z, gid) +
-                     dstg<R, 2, false>(P.t[5], P, x, y, z, gid);
-    const float fz = dstg<R, 0, false>(P.t[4], P, x, y, z, gid) +
-                     dstg<R, 1, false>(P.t[5], P, x, y, z, gid) +
-                     dstg<R, 2, true>(P.t[2], P, x, y, z, gid);
-    const float d = P.dx[x] + P.dy[y] + P.dz[z];
-    const float dd = d * P.hdt;
-    const float beta = 1.0f - dd;
-    float vx = __builtin_fmaf(beta, P.v[0][gid], P.bq[0][gid] * fx);
-    float vy = __builtin_fmaf(beta, P.v[1][gid], P.bq[1][gid] * fy);
-    float vz = __builtin_fmaf(beta, P.v[2][gid], P.bq[2][gid] * fz);
-    if (d != 0.0f) {
-        const float al = 1.0f + dd;
-        vx /= al;
-        vy /= al;
-        vz /= al;
+    Site q;
+    if (!locate4(P, q)) return;
+    const f4 fx = dstg<R, 0, true>(P.t[0], P, q) + dstg<R, 1, false>(P.t[3], P, q) +
+                  dstg<R, 2, false>(P.t[4], P, q);
+    const f4 fy = dstg<R, 0, false>(P.t[3], P, q) + dstg<R, 1, true>(P.t[1], P, q) +
+                  dstg<R, 2, false>(P.t[5], P, q);
+    const f4 fz = dstg<R, 0, false>(P.t[4], P, q) + dstg<R, 1, false>(P.t[5], P, q) +
+                  dstg<R, 2, true>(P.t[2], P, q);
+    const f4 f3[3] = {fx, fy, fz};
+    const float dxy = P.dx[q.x] + P.dy[q.y];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        f4 v = ld4(P.v[c], q.off, true);
+        const f4 b = ld4(P.bq[c], q.off, true);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int z = q.z4 + k;
+            const float d = dxy + (z < P.nz ? P.dz[z] : 0.0f);
+            const float dd = d * P.hdt;
+            float r = __builtin_fmaf(1.0f - dd, v[k], b[k] * f3[c][k]);
+            if (d != 0.0f) r /= 1.0f + dd;
+            v[k] = r;
+        }
+        *(f4 *)(P.v[c] + q.off) = v;
     }
-    P.v[0][gid] = vx;
-    P.v[1][gid] = vy;
-    P.v[2][gid] = vz;
 }
 
 template <int R>
 __global__ void __launch_bounds__(256) el_str(const ElParams P)
 {
-    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (gid >= (long long)P.nx * P.ny * P.nzp) return;
-    int x, y, z;
-    locate(P, gid, x, y, z);
-    if (z >= P.nz) return;
-    const float exx = dstg<R, 0, false>(P.v[0], P, x, y, z, gid);
-    const float eyy = dstg<R, 1, false>(P.v[1], P, x, y, z, gid);
-    const float ezz = dstg<R, 2, false>(P.v[2], P, x, y, z, gid);
-    const float gxy = dstg<R, 1, true>(P.v[0], P, x, y, z, gid) + dstg<R, 0, true>(P.v[1], P, x, y, z, gid);
-    const float gxz = dstg<R, 2, true>(P.v[0], P, x, y, z, gid) + dstg<R, 0, true>(P.v[2], P, x, y, z, gid);
-    const float gyz = dstg<R, 2, true>(P.v[1], P, x, y, z, gid) + dstg<R, 1, true>(P.v[2], P, x, y, z, gid);
-    const float tr = exx + eyy + ezz;
-    const float lam = P.lam[gid], mu2 = 2.0f * P.mu[gid];
-    const float d = P.dx[x] + P.dy[y] + P.dz[z];
-    const float dd = d * P.hdt;
-    const float beta = 1.0f - dd;
-    float t[6];
-    t[0] = __builtin_fmaf(beta, P.t[0][gid], __builtin_fmaf(lam, tr, mu2 * exx));
-    t[1] = __builtin_fmaf(beta, P.t[1][gid], __builtin_fmaf(lam, tr, mu2 * eyy));
-    t[2] = __builtin_fmaf(beta, P.t[2][gid], __builtin_fmaf(lam, tr, mu2 * ezz));
-    t[3] = __builtin_fmaf(beta, P.t[3][gid], P.ms[0][gid] * gxy);
-    t[4] = __builtin_fmaf(beta, P.t[4][gid], P.ms[1][gid] * gxz);
-    t[5] = __builtin_fmaf(beta, P.t[5][gid], P.ms[2][gid] * gyz);
-    if (d != 0.0f) {
-        const float al = 1.0f + dd;
+    Site q;
+    if (!locate4(P, q)) return;
+    const f4 exx = dstg<R, 0, false>(P.v[0], P, q);
+    const f4 eyy = dstg<R, 1, false>(P.v[1], P, q);
+    const f4 ezz = dstg<R, 2, false>(P.v[2], P, q);
+    const f4 gxy = dstg<R, 1, true>(P.v[0], P, q) + dstg<R, 0, true>(P.v[1], P, q);
+    const f4 gxz = dstg<R, 2, true>(P.v[0], P, q) + dstg<R, 0, true>(P.v[2], P, q);
+    const f4 gyz = dstg<R, 2, true>(P.v[1], P, q) + dstg<R, 1, true>(P.v[2], P, q);
+    const f4 lam = ld4(P.lam, q.off, true), mu = ld4(P.mu, q.off, true);
+    const f4 m0 = ld4(P.ms[0], q.off, true), m1 = ld4(P.ms[1], q.off, true),
+             m2 = ld4(P.ms[2], q.off, true);
+    f4 t[6];
 #pragma unroll
-        for (int k = 0; k < 6; k++) t[k] /= al;
+    for (int c = 0; c < 6; c++) t[c] = ld4(P.t[c], q.off, true);
+    const float dxy = P.dx[q.x] + P.dy[q.y];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int z = q.z4 + k;
+        const float d = dxy + (z < P.nz ? P.dz[z] : 0.0f);
+        const float dd = d * P.hdt;
+        const float beta = 1.0f - dd;
+        const float tr = exx[k] + eyy[k] + ezz[k];
+        const float mu2 = 2.0f * mu[k];
+        float n[6];
+        n[0] = __builtin_fmaf(beta, t[0][k], __builtin_fmaf(lam[k], tr, mu2 * exx[k]));
+        n[1] = __builtin_fmaf(beta, t[1][k], __builtin_fmaf(lam[k], tr, mu2 * eyy[k]));
+        n[2] = __builtin_fmaf(beta, t[2][k], __builtin_fmaf(lam[k], tr, mu2 * ezz[k]));
+        n[3] = __builtin_fmaf(beta, t[3][k], m0[k] * gxy[k]);
+        n[4] = __builtin_fmaf(beta, t[4][k], m1[k] * gxz[k]);
+        n[5] = __builtin_fmaf(beta, t[5][k], m2[k] * gyz[k]);
+        if (d != 0.0f) {
+#pragma unroll
+            for (int c = 0; c < 6; c++) n[c] /= 1.0f + dd;
+        }
+#pragma unroll
+        for (int c = 0; c < 6; c++) t[c][k] = n[c];
     }
 #pragma unroll
-    for (int k = 0; k < 6; k++) P.t[k][gid] = t[k];
+    for (int c = 0; c < 6; c++) *(f4 *)(P.t[c] + q.off) = t[c];
 }
 
 __global__ void el_src(float *__restrict__ txx, float *__restrict__ tyy, float *__restrict__ tzz,
@@ -147,7 +188,7 @@ tb_status launch_elastic_step(const ElParams &P, int r, const float *inc, const 
                               int npts, float *row_p, const long long *roff, int nrid,
                               float *row_v, const long long *roff2, int nrid2, hipStream_t st)
 {
-    const long long total = (long long)P.nx * P.ny * P.nzp;
+    const long long total = (long long)P.nx * P.ny * (P.nzp / 4);
     if (total == 0) return TB_OK;
     if (r == 2) {
         hipLaunchKernelGGL(el_vel<2>, dim3(nblocks(total)), dim3(256), 0, st, P);

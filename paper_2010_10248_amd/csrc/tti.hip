@@ -20,109 +20,173 @@
 namespace tbw {
 namespace {
 
-__device__ __forceinline__ float nb(const float *__restrict__ f, const TtiParams &P, int x, int y,
-                                    int z, long long off)
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Each thread takes 4 consecutive z (float4 accesses); neighbours along x and
+// y are float4 loads, neighbours along z come from the 12-value window
+// [z4-4, z4+8) of three float4 loads. Reads outside the grid give 0; the z
+// padding holds 0 in every field.
+struct Site {
+    int x, y, z4;
+    long long off, sx, sy;
+};
+
+__device__ __forceinline__ bool locate4(const TtiParams &P, Site &q)
 {
-    return (x >= 0 && x < P.nx && y >= 0 && y < P.ny && z >= 0 && z < P.nz) ? f[off] : 0.0f;
+    const int nz4 = P.nzp / 4;
+    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (gid >= (long long)P.nx * P.ny * nz4) return false;
+    q.z4 = (int)(gid % nz4) * 4;
+    const long long xy = gid / nz4;
+    q.y = (int)(xy % P.ny);
+    q.x = (int)(xy / P.ny);
+    q.sx = (long long)P.ny * P.nzp;
+    q.sy = P.nzp;
+    q.off = xy * P.nzp + q.z4;
+    return true;
+}
+
+__device__ __forceinline__ f4 ld4(const float *f, long long o, bool in)
+{
+    return in ? *(const f4 *)(f + o) : f4{0.f, 0.f, 0.f, 0.f};
+}
+
+__device__ __forceinline__ void zwin(const float *f, const Site &q, int nzp, float w[12])
+{
+    const f4 a = ld4(f, q.off - 4, q.z4 >= 4), b = ld4(f, q.off, true),
+             c = ld4(f, q.off + 4, q.z4 + 4 < nzp);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        w[k] = a[k];
+        w[4 + k] = b[k];
+        w[8 + k] = c[k];
+    }
+}
+
+// Centred first derivative (unit spacing) of f along x / y at the 4 sites.
+template <int R>
+__device__ __forceinline__ f4 d1xy(const float *f, const TtiParams &P, const Site &q, int ax)
+{
+    f4 s = f4{0.f, 0.f, 0.f, 0.f};
+    const long long st = ax == 0 ? q.sx : q.sy;
+    const int c = ax == 0 ? q.x : q.y, n = ax == 0 ? P.nx : P.ny;
+#pragma unroll
+    for (int m = 1; m <= R; m++) {
+        const f4 up = ld4(f, q.off + m * st, c + m < n), dn = ld4(f, q.off - m * st, c - m >= 0);
+#pragma unroll
+        for (int k = 0; k < 4; k++) s[k] = __builtin_fmaf(P.w1[m - 1], up[k] - dn[k], s[k]);
+    }
+    return s;
 }
 
 template <int R>
 __global__ void __launch_bounds__(256) tti_rot(const TtiParams P)
 {
-    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const long long total = (long long)P.nx * P.ny * P.nzp;
-    if (gid >= total) return;
-    const int z = (int)(gid % P.nzp);
-    if (z >= P.nz) return;
-    const long long xy = gid / P.nzp;
-    const int y = (int)(xy % P.ny), x = (int)(xy / P.ny);
-    const long long sx = (long long)P.ny * P.nzp, sy = P.nzp;
-    float gp[3] = {0.f, 0.f, 0.f}, gr[3] = {0.f, 0.f, 0.f};
+    Site q;
+    if (!locate4(P, q)) return;
+    float zp[12], zr[12];
+    zwin(P.p, q, P.nzp, zp);
+    zwin(P.r, q, P.nzp, zr);
+    const f4 gpx = d1xy<R>(P.p, P, q, 0), gpy = d1xy<R>(P.p, P, q, 1);
+    const f4 grx = d1xy<R>(P.r, P, q, 0), gry = d1xy<R>(P.r, P, q, 1);
+    const f4 ax = ld4(P.ax, q.off, true), ay = ld4(P.ay, q.off, true), az = ld4(P.az, q.off, true);
+    f4 qp, qr;
 #pragma unroll
-    for (int m = 1; m <= R; m++) {
-        const float w = P.w1[m - 1];
-        gp[0] = __builtin_fmaf(w, nb(P.p, P, x + m, y, z, gid + m * sx) -
-                                      nb(P.p, P, x - m, y, z, gid - m * sx), gp[0]);
-        gp[1] = __builtin_fmaf(w, nb(P.p, P, x, y + m, z, gid + m * sy) -
-                                      nb(P.p, P, x, y - m, z, gid - m * sy), gp[1]);
-        gp[2] = __builtin_fmaf(w, nb(P.p, P, x, y, z + m, gid + m) -
-                                      nb(P.p, P, x, y, z - m, gid - m), gp[2]);
-        gr[0] = __builtin_fmaf(w, nb(P.r, P, x + m, y, z, gid + m * sx) -
-                                      nb(P.r, P, x - m, y, z, gid - m * sx), gr[0]);
-        gr[1] = __builtin_fmaf(w, nb(P.r, P, x, y + m, z, gid + m * sy) -
-                                      nb(P.r, P, x, y - m, z, gid - m * sy), gr[1]);
-        gr[2] = __builtin_fmaf(w, nb(P.r, P, x, y, z + m, gid + m) -
-                                      nb(P.r, P, x, y, z - m, gid - m), gr[2]);
+    for (int k = 0; k < 4; k++) {
+        float gpz = 0.0f, grz = 0.0f;
+#pragma unroll
+        for (int m = 1; m <= R; m++) {
+            gpz = __builtin_fmaf(P.w1[m - 1], zp[4 + k + m] - zp[4 + k - m], gpz);
+            grz = __builtin_fmaf(P.w1[m - 1], zr[4 + k + m] - zr[4 + k - m], grz);
+        }
+        qp[k] = ax[k] * (gpx[k] * P.ih[0]) + ay[k] * (gpy[k] * P.ih[1]) + az[k] * (gpz * P.ih[2]);
+        qr[k] = ax[k] * (grx[k] * P.ih[0]) + ay[k] * (gry[k] * P.ih[1]) + az[k] * (grz * P.ih[2]);
     }
-    const float ax = P.ax[gid], ay = P.ay[gid], az = P.az[gid];
-    P.qp[gid] = ax * (gp[0] * P.ih[0]) + ay * (gp[1] * P.ih[1]) + az * (gp[2] * P.ih[2]);
-    P.qr[gid] = ax * (gr[0] * P.ih[0]) + ay * (gr[1] * P.ih[1]) + az * (gr[2] * P.ih[2]);
+    *(f4 *)(P.qp + q.off) = qp;
+    *(f4 *)(P.qr + q.off) = qr;
 }
 
 template <int R>
 __global__ void __launch_bounds__(256) tti_update(const TtiParams P)
 {
-    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    const long long total = (long long)P.nx * P.ny * P.nzp;
-    if (gid >= total) return;
-    const int z = (int)(gid % P.nzp);
-    if (z >= P.nz) return;
-    const long long xy = gid / P.nzp;
-    const int y = (int)(xy % P.ny), x = (int)(xy / P.ny);
-    const long long sx = (long long)P.ny * P.nzp, sy = P.nzp;
-    const float pc = P.p[gid], rc = P.r[gid];
-    // L p: centred second derivatives on differences from the centre.
-    const float p2 = 2.0f * pc;
-    float lx = 0.0f, ly = 0.0f, lz = 0.0f;
-    // Hz u = sum_b d_b (a_b q_u).
-    float hp[3] = {0.f, 0.f, 0.f}, hr[3] = {0.f, 0.f, 0.f};
+    Site q;
+    if (!locate4(P, q)) return;
+    float zp[12];
+    zwin(P.p, q, P.nzp, zp);
+    // Products a_z q along z for the z part of Hz.
+    float zaz[12], zqp[12], zqr[12];
+    zwin(P.az, q, P.nzp, zaz);
+    zwin(P.qp, q, P.nzp, zqp);
+    zwin(P.qr, q, P.nzp, zqr);
+    f4 lx = f4{0.f, 0.f, 0.f, 0.f}, ly = lx, hpx = lx, hpy = lx, hrx = lx, hry = lx;
+    const f4 pc = ld4(P.p, q.off, true);
 #pragma unroll
     for (int m = 1; m <= R; m++) {
-        lx = __builtin_fmaf(P.w2[m], (nb(P.p, P, x + m, y, z, gid + m * sx) +
-                                      nb(P.p, P, x - m, y, z, gid - m * sx)) - p2, lx);
-        ly = __builtin_fmaf(P.w2[m], (nb(P.p, P, x, y + m, z, gid + m * sy) +
-                                      nb(P.p, P, x, y - m, z, gid - m * sy)) - p2, ly);
-        lz = __builtin_fmaf(P.w2[m], (nb(P.p, P, x, y, z + m, gid + m) +
-                                      nb(P.p, P, x, y, z - m, gid - m)) - p2, lz);
-        const float w = P.w1[m - 1];
-        const long long o[3] = {m * sx, m * sy, (long long)m};
-        const int dx[3] = {m, 0, 0}, dy[3] = {0, m, 0}, dz[3] = {0, 0, m};
-        const float *a3[3] = {P.ax, P.ay, P.az};
+        const bool xp = q.x + m < P.nx, xm = q.x - m >= 0, yp = q.y + m < P.ny, ym = q.y - m >= 0;
+        const long long ox = m * q.sx, oy = m * q.sy;
+        const f4 pxp = ld4(P.p, q.off + ox, xp), pxm = ld4(P.p, q.off - ox, xm);
+        const f4 pyp = ld4(P.p, q.off + oy, yp), pym = ld4(P.p, q.off - oy, ym);
+        const f4 axp = ld4(P.ax, q.off + ox, xp), axm = ld4(P.ax, q.off - ox, xm);
+        const f4 ayp = ld4(P.ay, q.off + oy, yp), aym = ld4(P.ay, q.off - oy, ym);
+        const f4 qpxp = ld4(P.qp, q.off + ox, xp), qpxm = ld4(P.qp, q.off - ox, xm);
+        const f4 qpyp = ld4(P.qp, q.off + oy, yp), qpym = ld4(P.qp, q.off - oy, ym);
+        const f4 qrxp = ld4(P.qr, q.off + ox, xp), qrxm = ld4(P.qr, q.off - ox, xm);
+        const f4 qryp = ld4(P.qr, q.off + oy, yp), qrym = ld4(P.qr, q.off - oy, ym);
+        const float w1 = P.w1[m - 1], w2 = P.w2[m];
 #pragma unroll
-        for (int b = 0; b < 3; b++) {
-            const bool inp = x + dx[b] < P.nx && y + dy[b] < P.ny && z + dz[b] < P.nz;
-            const bool inm = x - dx[b] >= 0 && y - dy[b] >= 0 && z - dz[b] >= 0;
-            const float ap = inp ? a3[b][gid + o[b]] : 0.0f;
-            const float am = inm ? a3[b][gid - o[b]] : 0.0f;
-            const float qpp = inp ? P.qp[gid + o[b]] : 0.0f, qpm = inm ? P.qp[gid - o[b]] : 0.0f;
-            const float qrp = inp ? P.qr[gid + o[b]] : 0.0f, qrm = inm ? P.qr[gid - o[b]] : 0.0f;
-            hp[b] = __builtin_fmaf(w, ap * qpp - am * qpm, hp[b]);
-            hr[b] = __builtin_fmaf(w, ap * qrp - am * qrm, hr[b]);
+        for (int k = 0; k < 4; k++) {
+            const float p2 = 2.0f * pc[k];
+            lx[k] = __builtin_fmaf(w2, (pxp[k] + pxm[k]) - p2, lx[k]);
+            ly[k] = __builtin_fmaf(w2, (pyp[k] + pym[k]) - p2, ly[k]);
+            hpx[k] = __builtin_fmaf(w1, axp[k] * qpxp[k] - axm[k] * qpxm[k], hpx[k]);
+            hpy[k] = __builtin_fmaf(w1, ayp[k] * qpyp[k] - aym[k] * qpym[k], hpy[k]);
+            hrx[k] = __builtin_fmaf(w1, axp[k] * qrxp[k] - axm[k] * qrxm[k], hrx[k]);
+            hry[k] = __builtin_fmaf(w1, ayp[k] * qryp[k] - aym[k] * qrym[k], hry[k]);
         }
     }
-    const float lap = lx * P.ih2[0] + ly * P.ih2[1] + lz * P.ih2[2];
-    const float hzp = hp[0] * P.ih[0] + hp[1] * P.ih[1] + hp[2] * P.ih[2];
-    const float hzr = hr[0] * P.ih[0] + hr[1] * P.ih[1] + hr[2] * P.ih[2];
-    const float h0p = lap - hzp;
-    const float e1 = P.e1[gid], sd = P.sd[gid], cc = P.c[gid];
-    const float rhs_p = __builtin_fmaf(e1, h0p, sd * hzr);
-    const float rhs_r = __builtin_fmaf(sd, h0p, hzr);
-    const float d = P.dx[x] + P.dy[y] + P.dz[z];
-    const float dd = d * P.hdt;
-    const float beta = 1.0f - dd;
-    float wp = __builtin_fmaf(cc, rhs_p, beta * P.vp[gid]);
-    float wr = __builtin_fmaf(cc, rhs_r, beta * P.vr[gid]);
-    if (d != 0.0f) {
-        wp = wp / (1.0f + dd);
-        wr = wr / (1.0f + dd);
+    const f4 rc = ld4(P.r, q.off, true);
+    const f4 e1 = ld4(P.e1, q.off, true), sd = ld4(P.sd, q.off, true), cc = ld4(P.c, q.off, true);
+    f4 vp = ld4(P.vp, q.off, true), vr = ld4(P.vr, q.off, true), pn, rn;
+    const float dxy = P.dx[q.x] + P.dy[q.y];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const float p2 = 2.0f * pc[k];
+        float lz = 0.0f, hpz = 0.0f, hrz = 0.0f;
+#pragma unroll
+        for (int m = 1; m <= R; m++) {
+            lz = __builtin_fmaf(P.w2[m], (zp[4 + k + m] + zp[4 + k - m]) - p2, lz);
+            hpz = __builtin_fmaf(P.w1[m - 1], zaz[4 + k + m] * zqp[4 + k + m] -
+                                                  zaz[4 + k - m] * zqp[4 + k - m], hpz);
+            hrz = __builtin_fmaf(P.w1[m - 1], zaz[4 + k + m] * zqr[4 + k + m] -
+                                                  zaz[4 + k - m] * zqr[4 + k - m], hrz);
+        }
+        const float lap = lx[k] * P.ih2[0] + ly[k] * P.ih2[1] + lz * P.ih2[2];
+        const float hzp = hpx[k] * P.ih[0] + hpy[k] * P.ih[1] + hpz * P.ih[2];
+        const float hzr = hrx[k] * P.ih[0] + hry[k] * P.ih[1] + hrz * P.ih[2];
+        const float h0p = lap - hzp;
+        const float rhs_p = __builtin_fmaf(e1[k], h0p, sd[k] * hzr);
+        const float rhs_r = __builtin_fmaf(sd[k], h0p, hzr);
+        const int z = q.z4 + k;
+        const float d = dxy + (z < P.nz ? P.dz[z] : 0.0f);
+        const float dd = d * P.hdt;
+        const float beta = 1.0f - dd;
+        float wp = __builtin_fmaf(cc[k], rhs_p, beta * vp[k]);
+        float wr = __builtin_fmaf(cc[k], rhs_r, beta * vr[k]);
+        if (d != 0.0f) {
+            wp = wp / (1.0f + dd);
+            wr = wr / (1.0f + dd);
+        }
+        vp[k] = wp;
+        vr[k] = wr;
+        pn[k] = pc[k] + wp;
+        rn[k] = rc[k] + wr;
     }
-    P.vp[gid] = wp;
-    P.vr[gid] = wr;
-    P.pn[gid] = pc + wp;
-    P.rn[gid] = rc + wr;
+    *(f4 *)(P.vp + q.off) = vp;
+    *(f4 *)(P.vr + q.off) = vr;
+    *(f4 *)(P.pn + q.off) = pn;
+    *(f4 *)(P.rn + q.off) = rn;
 }
 
-// The injected increment enters the new level and its velocity alike.
 __global__ void tti_sparse(float *__restrict__ p, float *__restrict__ r, float *__restrict__ vp,
                            float *__restrict__ vr, const float *__restrict__ inc,
                            const long long *__restrict__ soff, int npts)
@@ -152,7 +216,7 @@ tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const lon
                           int npts, float *rec_row, const long long *roff, int nrid,
                           hipStream_t st)
 {
-    const long long total = (long long)P.nx * P.ny * P.nzp;
+    const long long total = (long long)P.nx * P.ny * (P.nzp / 4);
     if (total == 0) return TB_OK;
     if (r == 2) {
         hipLaunchKernelGGL(tti_rot<2>, dim3(nblocks(total)), dim3(256), 0, st, P);
