@@ -150,6 +150,39 @@ def serve_bench(tb, W, torch, nreq, load, max_active, arena_gb):
     return out
 
 
+def physics_bench(tb, W, torch, which, steps):
+    """GPts/s of the TTI (256^3 SO8, 800 steps, 44 B per point-step) or
+    elastic (256^3 SO8, 600 steps, 84 B per point-step) propagator on one
+    shot, inputs resident; effective bandwidth at those algorithmic bytes."""
+    import numpy as np
+
+    if which == "tti":
+        shot = W.tti_smooth()
+        bpp = 44
+    else:
+        shot = W.elastic_smooth()
+        bpp = 84
+    prop = tb.Propagator(shot)
+    ws = prop.workspace(None)
+    nt = shot.nt
+    shape = (2, nt, prop.nrec) if which == "elastic" else (nt, prop.nrec)
+    rec = torch.empty(shape, dtype=torch.float32, device="cuda")
+    tb.forward(prop.model, prop.sparse, None, ws, rec)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        tb.forward(prop.model, prop.sparse, None, ws, rec)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    N3 = int(np.prod(shot.shape))
+    g = N3 * nt / dt / 1e9
+    prop.close()
+    log(f"{which}: {shot.name}: {dt * 1e3:.1f} ms/shot, {g:.1f} GPts/s")
+    return dict(workload=shot.name, ms_per_shot=round(dt * 1e3, 2), gpts_per_s=round(g, 2),
+                bytes_per_point_step=bpp,
+                effective_hbm_frac=round(g * bpp / HBM_PEAK_GBS, 4), schedule="SB")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -195,11 +228,13 @@ def main(argv=None):
     ap.add_argument("--tile-y", type=int, default=32)
     ap.add_argument("--chunk", type=int, default=64)
     ap.add_argument("--sb-tile-y", type=int, default=32)
-    ap.add_argument("--sb-chunk", type=int, default=0)
+    ap.add_argument("--sb-chunk", type=int, default=128)
     ap.add_argument("--no-sb", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-physics", action="store_true",
+                    help="skip the TTI and elastic measurements")
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-active", type=int, default=4)
@@ -310,6 +345,10 @@ def main(argv=None):
                                           for k, v in errs.items()})
         log(f"parity vs FP64 oracle at {sample.nt} steps: {parity}")
 
+    physics = None
+    if not args.no_physics:
+        physics = {k: physics_bench(tb, W, torch, k, 2) for k in ("tti", "elastic")}
+
     serving = None
     if not args.no_serve:
         serving = serve_bench(tb, W, torch, args.serve_requests, args.serve_load,
@@ -339,6 +378,7 @@ def main(argv=None):
             "parity_rel_l2": parity,
             "inspector_s": round(setup_s, 3),
             "serving": serving,
+            "other_physics": physics,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -177,7 +177,9 @@ tb_status get_lists(const tb_model *m, tb_sparse *s, int adjoint, int T, int til
 tb_status lists_for(const tb_model *m, tb_sparse *s, int adjoint, const SchedChoice &sc, int T,
                     TileLists **out)
 {
-    int chunk = sc.chunk, wgs = m->ncu * sc.wgs_per_cu;
+    // Chunked schedules keep one workgroup per compute unit resident (their
+    // LDS footprint allows no more) and hand each a list of segments.
+    int chunk = sc.chunk, wgs = m->ncu * (sc.chunk > 0 ? 1 : sc.wgs_per_cu);
     for (;;) {
         tb_status st = get_lists(m, s, adjoint, T, sc.tile_y, chunk, wgs, out);
         if (st) return st;

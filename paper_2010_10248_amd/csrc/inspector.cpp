@@ -141,15 +141,42 @@ TileGeom make_geom(int R, int T, int tile_y, int chunk, int wgs, int nx, int ny,
     g.seg_off.assign(1, 0);
     if (nt == 0) return g;
     if (chunk > 0) {
-        // One workgroup per (chunk of x, tile), chunk-major so that the
-        // workgroups running together stream the same x range of
-        // neighbouring tiles.
         g.chunk = std::min(std::min(chunk, nx), kMaxChunk);
-        for (int x0 = 0; x0 < nx; x0 += g.chunk)
-            for (int t = 0; t < nt; t++) {
-                g.segs.push_back(SegDesc{t, x0, std::min(nx, x0 + g.chunk), 0, 0, 0, 0, 0});
-                g.seg_off.push_back((int)g.segs.size());
+        const int nch = (nx + g.chunk - 1) / g.chunk;
+        auto seg = [&](int c, int t) {
+            const int x0 = c * g.chunk;
+            return SegDesc{t, x0, std::min(nx, x0 + g.chunk), 0, 0, 0, 0, 0};
+        };
+        const int W = wgs / 8;  // workgroups per XCD
+        if (W < 1 || (long long)nch * nt <= 8LL * W) {
+            // One workgroup per (chunk of x, tile), chunk-major so that the
+            // workgroups running together stream the same x range of
+            // neighbouring tiles.
+            for (int c = 0; c < nch; c++)
+                for (int t = 0; t < nt; t++) {
+                    g.segs.push_back(seg(c, t));
+                    g.seg_off.push_back((int)g.segs.size());
+                }
+        } else {
+            // XCD slabs. Workgroups are handed to the 8 XCDs round-robin and
+            // the kernel remaps them so that XCD k holds workgroups
+            // [k W, (k+1) W). XCD k owns a contiguous run of tiles (a slab in
+            // y) and its W workgroups take that slab's segments chunk by
+            // chunk in x order, round-robin, so that the workgroups resident
+            // on one XCD stream neighbouring tiles of the same x range, and
+            // the x halo of a chunk is the end of the chunk the same XCD has
+            // just streamed: both share its L2.
+            for (int k = 0; k < 8; k++) {
+                const int t0 = (int)((long long)nt * k / 8), t1 = (int)((long long)nt * (k + 1) / 8);
+                std::vector<SegDesc> list;
+                for (int c = 0; c < nch; c++)
+                    for (int t = t0; t < t1; t++) list.push_back(seg(c, t));
+                for (int j = 0; j < W; j++) {
+                    for (size_t q = j; q < list.size(); q += W) g.segs.push_back(list[q]);
+                    g.seg_off.push_back((int)g.segs.size());
+                }
             }
+        }
     } else {
         // Even partition of the (tile, x) space over `wgs` workgroups: each
         // workgroup streams one contiguous range, split where it crosses a
