@@ -183,6 +183,35 @@ def physics_bench(tb, W, torch, which, steps):
                 effective_hbm_frac=round(g * bpp / HBM_PEAK_GBS, 4), schedule="SB")
 
 
+def density_bench(tb, W, torch, counts, tb_sched, sb_sched, nt):
+    """Section IV-E's source-density experiment on the 512^3 SO8 two-layer
+    grid: TB and SB GPts/s with 1..many sources, uniform in the volume or on
+    one horizontal plane (nt steps per shot; one warm-up and one timed shot
+    per schedule)."""
+    import numpy as np
+
+    out = []
+    for layout in ("volume", "plane"):
+        for k in counts:
+            shot = W.acoustic_source_density(k, layout, nt=nt)
+            t0 = time.perf_counter()
+            prop = tb.Acoustic(shot)
+            torch.cuda.synchronize()
+            insp = time.perf_counter() - t0
+            npts, _ = tb.sparse_counts(prop.sparse)
+            g = {}
+            for name, sc in (("tb", tb_sched), ("sb", sb_sched)):
+                dt, _, _, _, _, _ = time_forward(tb, prop, sc, 1, 1, torch)
+                g[name] = int(np.prod(shot.shape)) * nt / dt / 1e9
+            prop.close()
+            row = dict(layout=layout, sources=k, points=npts, inspector_s=round(insp, 3),
+                       tb_gpts=round(g["tb"], 1), sb_gpts=round(g["sb"], 1),
+                       tb_over_sb=round(g["tb"] / g["sb"], 3))
+            log(f"density {row}")
+            out.append(row)
+    return out
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -233,6 +262,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-density", action="store_true",
+                    help="skip the source-density sweep")
     ap.add_argument("--no-physics", action="store_true",
                     help="skip the TTI and elastic measurements")
     ap.add_argument("--serve-requests", type=int, default=16)
@@ -345,6 +376,10 @@ def main(argv=None):
                                           for k, v in errs.items()})
         log(f"parity vs FP64 oracle at {sample.nt} steps: {parity}")
 
+    density = None
+    if not args.no_density:
+        density = density_bench(tb, W, torch, (1, 64, 1024, 8192), tb_sched, sb_sched, 200)
+
     physics = None
     if not args.no_physics:
         physics = {k: physics_bench(tb, W, torch, k, 2) for k in ("tti", "elastic")}
@@ -379,6 +414,7 @@ def main(argv=None):
             "inspector_s": round(setup_s, 3),
             "serving": serving,
             "other_physics": physics,
+            "source_density": density,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

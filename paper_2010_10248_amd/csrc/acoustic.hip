@@ -113,8 +113,9 @@ tb_status launch_acoustic(const tb_model *m, const TileLists &tl, const AcLaunch
     hipError_t e = hipErrorInvalidValue;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (timing_enabled()) timing_begin(st, &ev0, &ev1);
-    if (m->r == 2) e = launch_acoustic_r2(p, g.T, g.LZ, g.BYE, st);
-    else if (m->r == 4) e = launch_acoustic_r4(p, g.T, g.LZ, g.BYE, st);
+    const bool gl = tl.max_src > kSrcCap || tl.max_rec > kRecCap;
+    if (m->r == 2) e = launch_acoustic_r2(p, g.T, g.LZ, g.BYE, gl, st);
+    else if (m->r == 4) e = launch_acoustic_r4(p, g.T, g.LZ, g.BYE, gl, st);
     if (ev0) timing_end(st, ev0, ev1);
     if (e != hipSuccess) {
         set_error("acoustic kernel launch (R=%d T=%d LZ=%d BYE=%d) failed: %s", m->r, g.T, g.LZ,

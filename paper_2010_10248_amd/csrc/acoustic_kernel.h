@@ -140,11 +140,12 @@ __device__ __forceinline__ float point_update(const AcParams &p, float ctr, cons
 constexpr int cring_slots(int R, int T) { return T > 1 ? R * (T - 1) : 0; }
 constexpr int vring_slots(int R, int T) { return T > 1 ? R + 1 : 0; }
 
-// LDS bytes of one workgroup of acoustic_wavefront<R, T, LZ, BYE>.
-constexpr int wavefront_lds(int R, int T, int LZ, int BYE)
+// LDS bytes of one workgroup of acoustic_wavefront<R, T, LZ, BYE> (GL: the
+// sparse lists are read from global memory instead of being staged).
+constexpr int wavefront_lds(int R, int T, int LZ, int BYE, bool GL = false)
 {
-    return 16 * 2 * T * (BYE + 2 * R) * (LZ + kLdsPad) + kSrcCap * (8 + 4 * T) +
-           kRecCap * (8 + 4 * T) + 4 * kDxCap +
+    return 16 * 2 * T * (BYE + 2 * R) * (LZ + kLdsPad) +
+           (GL ? 0 : kSrcCap * (8 + 4 * T) + kRecCap * (8 + 4 * T)) + 4 * kDxCap +
            16 * LZ * BYE * (cring_slots(R, T) + (T - 1) * vring_slots(R, T));
 }
 
@@ -165,7 +166,10 @@ struct RingIn {
 
 // The kernel body for one job: b is the workgroup's index within the job's
 // grid of p.nwg workgroups.
-template <int R, int T, int LZ, int BYE, int PD>
+// GL selects where the segment's sparse lists are walked: staged in LDS
+// (the common case), or read in place from global memory when a segment
+// holds more entries than the LDS lists (dense sources or receivers).
+template <int R, int T, int LZ, int BYE, int PD, bool GL>
 __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
 {
     constexpr int U = 2 * R + 1;  // window slots: the 2R+1 live planes
@@ -185,10 +189,11 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
     constexpr int NSV = vring_slots(R, T);
 
     __shared__ f4v sh[2][T][LR][LC];
-    __shared__ int2 s_src[kSrcCap];
-    __shared__ float s_val[kSrcCap][T];
-    __shared__ int2 s_rec[kRecCap];
-    __shared__ float s_recv[kRecCap][T];
+    constexpr int SC = GL ? 1 : kSrcCap, RC = GL ? 1 : kRecCap;
+    __shared__ int2 s_src[SC];
+    __shared__ float s_val[SC][T];
+    __shared__ int2 s_rec[RC];
+    __shared__ float s_recv[RC][T];
     __shared__ float s_dx[kDxCap];
     __shared__ f4v s_c[NSC ? NSC : 1][NSC ? NTH : 1];
     __shared__ f4v s_v[T > 1 ? T - 1 : 1][NSV ? NSV : 1][NSV ? NTH : 1];
@@ -264,41 +269,58 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
     for (int k = tid; k < nxd; k += NTH) s_dx[k] = p.dx[xlo + k];
 
     // Stage the segment's injection list (with the decomposed wavelet values
-    // of this pass's T steps) and its receiver list in LDS. The host keeps
-    // every segment within the capacities.
+    // of this pass's T steps) and its receiver list in LDS; the GL variant
+    // reads both lists and the values from global memory instead.
     const int sbeg = sd.sbeg, nsl = sd.sn;
     const int rbeg = sd.rbeg, nrl = sd.rn;
-    for (int k = tid; k < nsl; k += NTH) {
-        const int2 e = p.src[sbeg + k];
-        s_src[k] = e;
+    const int2 *gsrc = p.src + sbeg, *grec = p.rec + rbeg;
+    if constexpr (!GL) {
+        // The host launches this variant only for segments within the LDS
+        // capacities; the bounds keep LDS writes inside the arrays regardless.
+        for (int k = tid; k < nsl && k < kSrcCap; k += NTH) {
+            const int2 e = gsrc[k];
+            s_src[k] = e;
 #pragma unroll
-        for (int s = 0; s < T; s++) s_val[k][s] = p.dcmp[(long long)(p.n0 + s) * p.npts + e.y];
+            for (int s = 0; s < T; s++)
+                s_val[k][s] = p.dcmp[(long long)(p.n0 + s) * p.npts + e.y];
+        }
+        for (int k = tid; k < nrl && k < kRecCap; k += NTH) s_rec[k] = grec[k];
     }
-    for (int k = tid; k < nrl; k += NTH) s_rec[k] = p.rec[rbeg + k];
+    // List accessors (one address space per instantiation).
+    auto skey = [&](int k) -> int {
+        if constexpr (GL) return gsrc[k].x;
+        else return s_src[k].x;
+    };
+    auto rkey = [&](int k) -> int {
+        if constexpr (GL) return grec[k].x;
+        else return s_rec[k].x;
+    };
     lds_barrier();
     // Each lane walks its own entries (sorted by x) with one cursor per stage,
     // so a tick costs one compare per stage unless this lane has a point on
     // the stage's plane.
-    auto first_at = [&](const int2 *lst, int n, int x) {
+    auto first_at = [&](auto key, int n, int x) {
         const int want = tile_key(row, zl, x, 0);  // first entry of this lane at >= x
         int a = 0, b2 = n;
         while (a < b2) {
             const int mid = (a + b2) >> 1;
-            if (lst[mid].x < want) a = mid + 1;
+            if (key(mid) < want) a = mid + 1;
             else b2 = mid;
         }
         return a;
     };
-    auto next_x = [&](const int2 *lst, int n, int k) {
-        return (k < n && (lst[k].x >> 18) == mykey) ? ((lst[k].x >> 2) & 0xffff) : 0x7fffffff;
+    auto next_x = [&](auto key, int n, int k) {
+        if (k >= n) return 0x7fffffff;
+        const int e = key(k);
+        return (e >> 18) == mykey ? ((e >> 2) & 0xffff) : 0x7fffffff;
     };
     int scur[T], snx[T], rcur[T], rnx[T];
 #pragma unroll
     for (int s = 0; s < T; s++) {
-        scur[s] = nsl ? first_at(s_src, nsl, lo[s]) : 0;
-        snx[s] = next_x(s_src, nsl, scur[s]);
-        rcur[s] = nrl ? first_at(s_rec, nrl, lo[s]) : 0;
-        rnx[s] = next_x(s_rec, nrl, rcur[s]);
+        scur[s] = nsl ? first_at(skey, nsl, lo[s]) : 0;
+        snx[s] = next_x(skey, nsl, scur[s]);
+        rcur[s] = nrl ? first_at(rkey, nrl, lo[s]) : 0;
+        rnx[s] = next_x(rkey, nrl, rcur[s]);
     }
 
     f4v q[T][U];
@@ -415,18 +437,22 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
                     // Fused injection at every computed copy (per-tile list).
                     if (snx[s] == cs) {
                         int kk = scur[s];
-                        for (; kk < nsl && (s_src[kk].x >> 18) == mykey &&
-                               ((s_src[kk].x >> 2) & 0xffff) == cs;
+                        for (; kk < nsl && (skey(kk) >> 18) == mykey &&
+                               ((skey(kk) >> 2) & 0xffff) == cs;
                              kk++) {
-                            const int k = s_src[kk].x & 3;
-                            const float add = s_val[kk][s];
+                            const int k = skey(kk) & 3;
+                            float add;
+                            if constexpr (GL)
+                                add = p.dcmp[(long long)(p.n0 + s) * p.npts + gsrc[kk].y];
+                            else
+                                add = s_val[kk][s];
                             v[0] = k == 0 ? v[0] + add : v[0];
                             v[1] = k == 1 ? v[1] + add : v[1];
                             v[2] = k == 2 ? v[2] + add : v[2];
                             v[3] = k == 3 ? v[3] + add : v[3];
                         }
                         scur[s] = kk;
-                        snx[s] = next_x(s_src, nsl, kk);
+                        snx[s] = next_x(skey, nsl, kk);
                     }
 #pragma unroll
                     for (int k = 0; k < 4; k++) un[k] = ctr[k] + v[k];
@@ -434,14 +460,19 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
                     // written out once at the end.
                     if (rnx[s] == cs) {
                         int kk = rcur[s];
-                        for (; kk < nrl && (s_rec[kk].x >> 18) == mykey &&
-                               ((s_rec[kk].x >> 2) & 0xffff) == cs;
+                        for (; kk < nrl && (rkey(kk) >> 18) == mykey &&
+                               ((rkey(kk) >> 2) & 0xffff) == cs;
                              kk++) {
-                            const int k = s_rec[kk].x & 3;
-                            s_recv[kk][s] = k == 0 ? un[0] : k == 1 ? un[1] : k == 2 ? un[2] : un[3];
+                            const int k = rkey(kk) & 3;
+                            const float val =
+                                k == 0 ? un[0] : k == 1 ? un[1] : k == 2 ? un[2] : un[3];
+                            if constexpr (GL)
+                                p.rec_dcmp[(long long)(p.n0 + s + 1) * p.nrid + grec[kk].y] = val;
+                            else
+                                s_recv[kk][s] = val;
                         }
                         rcur[s] = kk;
-                        rnx[s] = next_x(s_rec, nrl, kk);
+                        rnx[s] = next_x(rkey, nrl, kk);
                     }
                 }
                 if constexpr (s + 1 < T) {
@@ -467,9 +498,9 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
             tick++;
         });
     }
-    if (nrl > 0) {
+    if (!GL && nrl > 0) {
         lds_barrier();
-        for (int k = tid; k < nrl; k += NTH) {
+        for (int k = tid; k < nrl && k < kRecCap; k += NTH) {
             const int id = s_rec[k].y;
             // Owned receiver planes lie inside every stage's x range, so each
             // stage recorded every entry.
@@ -481,10 +512,10 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
     }  // segments
 }
 
-template <int R, int T, int LZ, int BYE, int PD>
+template <int R, int T, int LZ, int BYE, int PD, bool GL>
 __global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
 {
-    wavefront_body<R, T, LZ, BYE, PD>(p, blockIdx.x);
+    wavefront_body<R, T, LZ, BYE, PD, GL>(p, blockIdx.x);
 }
 
 // Several jobs (different grids, sparse sets and time levels) in one launch:
@@ -503,7 +534,7 @@ __global__ void __launch_bounds__(LZ *BYE)
     const AcParams &p = jobs[j];
     const int b = bx - wg_off[j];
     if (b >= p.nwg) return;
-    wavefront_body<R, T, LZ, BYE, PD>(p, b);
+    wavefront_body<R, T, LZ, BYE, PD, false>(p, b);
 }
 
 // Prefetch depth (ticks of loads in flight): it must divide the window 2R+1,
@@ -555,11 +586,15 @@ hipError_t dispatch_shape(int T, int LZ, int BYE, F &&f)
 }
 
 template <int R>
-hipError_t launch_r(const AcParams &p, int T, int LZ, int BYE, hipStream_t st)
+hipError_t launch_r(const AcParams &p, int T, int LZ, int BYE, bool gl, hipStream_t st)
 {
     return dispatch_shape<R>(T, LZ, BYE, [&]<int TT, int L, int B>() {
-        hipLaunchKernelGGL((acoustic_wavefront<R, TT, L, B, prefetch_depth<R, TT>()>),
-                           dim3(p.nwg), dim3(L * B), 0, st, p);
+        if (gl)
+            hipLaunchKernelGGL((acoustic_wavefront<R, TT, L, B, prefetch_depth<R, TT>(), true>),
+                               dim3(p.nwg), dim3(L * B), 0, st, p);
+        else
+            hipLaunchKernelGGL((acoustic_wavefront<R, TT, L, B, prefetch_depth<R, TT>(), false>),
+                               dim3(p.nwg), dim3(L * B), 0, st, p);
         return hipGetLastError();
     });
 }

@@ -33,8 +33,12 @@ struct AcParams {
 
 // Launchers of the wave-front kernel for one stencil radius (one translation
 // unit per radius so the instantiations compile in parallel).
-hipError_t launch_acoustic_r2(const AcParams &p, int T, int LZ, int BYE, hipStream_t st);
-hipError_t launch_acoustic_r4(const AcParams &p, int T, int LZ, int BYE, hipStream_t st);
+// gl: the variant that walks the sparse lists in global memory (segments with
+// more entries than the LDS lists hold).
+hipError_t launch_acoustic_r2(const AcParams &p, int T, int LZ, int BYE, bool gl,
+                              hipStream_t st);
+hipError_t launch_acoustic_r4(const AcParams &p, int T, int LZ, int BYE, bool gl,
+                              hipStream_t st);
 // Batched launch: jobs[njobs] in device memory, wg_off[njobs] (device) the
 // first workgroup of each job (multiples of 8), total_wg the grid size.
 hipError_t launch_acoustic_batch_r2(const AcParams *jobs, const int *wg_off, int njobs,

@@ -3,9 +3,10 @@
 
 namespace tbw {
 
-hipError_t launch_acoustic_r2(const AcParams &p, int T, int LZ, int BYE, hipStream_t st)
+hipError_t launch_acoustic_r2(const AcParams &p, int T, int LZ, int BYE, bool gl,
+                              hipStream_t st)
 {
-    return wf::launch_r<2>(p, T, LZ, BYE, st);
+    return wf::launch_r<2>(p, T, LZ, BYE, gl, st);
 }
 
 hipError_t launch_acoustic_batch_r2(const AcParams *jobs, const int *wg_off, int njobs,

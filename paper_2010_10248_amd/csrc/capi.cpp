@@ -172,29 +172,15 @@ tb_status get_lists(const tb_model *m, tb_sparse *s, int adjoint, int T, int til
 
 }  // namespace
 
-// Lists of the schedule with every segment within the kernel's LDS list
-// capacities: denser sparse sets get shorter segments.
+// Lists of the schedule (segments whose lists exceed the LDS capacities are
+// walked in global memory by the kernel).
 tb_status lists_for(const tb_model *m, tb_sparse *s, int adjoint, const SchedChoice &sc, int T,
                     TileLists **out)
 {
     // Chunked schedules keep one workgroup per compute unit resident (their
     // LDS footprint allows no more) and hand each a list of segments.
-    int chunk = sc.chunk, wgs = m->ncu * (sc.chunk > 0 ? 1 : sc.wgs_per_cu);
-    for (;;) {
-        tb_status st = get_lists(m, s, adjoint, T, sc.tile_y, chunk, wgs, out);
-        if (st) return st;
-        if ((*out)->max_src <= kSrcCap && (*out)->max_rec <= kRecCap) return TB_OK;
-        if (chunk > 0) {
-            if (chunk == 1) break;
-            chunk = (chunk + 1) / 2;
-        } else {
-            if (wgs >= m->n[0] * 64) break;
-            wgs *= 2;
-        }
-    }
-    set_error("a single plane of one tile holds more sparse points than the kernel capacity "
-              "(%d / %d)", kSrcCap, kRecCap);
-    return TB_EUNSUPPORTED;
+    const int wgs = m->ncu * (sc.chunk > 0 ? 1 : sc.wgs_per_cu);
+    return get_lists(m, s, adjoint, T, sc.tile_y, sc.chunk, wgs, out);
 }
 
 namespace {
@@ -338,13 +324,14 @@ void image_weights(const tb_model *m, double w[3][5])
 }  // namespace
 
 tb_status pass_params(const tb_model *m, tb_sparse *s, const SchedChoice &sc, const Pass &p,
-                      AcParams *out, const TileGeom **geom)
+                      AcParams *out, const TileGeom **geom, bool *gl)
 {
     TileLists *tl = nullptr;
     tb_status rc = lists_for(m, s, p.adjoint, sc, p.T, &tl);
     if (rc) return rc;
     *out = make_params(m, *tl, to_launch(p));
     if (geom) *geom = &tl->g;
+    if (gl) *gl = tl->max_src > kSrcCap || tl->max_rec > kRecCap;
     return TB_OK;
 }
 

@@ -48,9 +48,11 @@ struct Item {
 };
 using Plan = std::vector<Item>;
 
-// Kernel parameters of a pass (lists resolved for the job's schedule).
+// Kernel parameters of a pass (lists resolved for the job's schedule); *gl
+// is set when a segment's lists exceed the LDS capacities (the pass then
+// needs the global-list kernel and cannot join a batched launch).
 tb_status pass_params(const tb_model *m, tb_sparse *s, const SchedChoice &sc, const Pass &p,
-                      AcParams *out, const TileGeom **geom);
+                      AcParams *out, const TileGeom **geom, bool *gl);
 
 size_t forward_ws_bytes(const tb_model *m, const tb_sparse *s);
 size_t gradient_ws_bytes(const tb_model *m, const tb_sparse *s, const SchedChoice &sc, int every);

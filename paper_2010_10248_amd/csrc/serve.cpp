@@ -93,6 +93,7 @@ struct Arena {
 struct LaunchRec {
     int r, T, LZ, BYE, njobs, total_wg;
     int poff, woff;
+    int round = 0;
 };
 
 }  // namespace
@@ -233,12 +234,28 @@ tb_status ensure_tables(tb_server *sv, int need)
     return TB_OK;
 }
 
-tb_status issue(tb_server *sv, const std::vector<LaunchRec> &L, bool timing)
+tb_status issue(tb_server *sv, const std::vector<LaunchRec> &L,
+                 const std::vector<std::vector<std::pair<Job *, Pass>>> &singles, bool timing)
 {
-    for (const LaunchRec &l : L) {
-        tb_status rc = launch_acoustic_batch(l.r, sv->d_par + l.poff, sv->d_wg + l.woff, l.njobs,
-                                             l.total_wg, l.T, l.LZ, l.BYE, sv->st, timing);
-        if (rc) return rc;
+    size_t k = 0;
+    for (size_t round = 0; round < singles.size(); round++) {
+        for (; k < L.size() && L[k].round == (int)round; k++) {
+            const LaunchRec &l = L[k];
+            tb_status rc = launch_acoustic_batch(l.r, sv->d_par + l.poff, sv->d_wg + l.woff,
+                                                 l.njobs, l.total_wg, l.T, l.LZ, l.BYE, sv->st,
+                                                 timing);
+            if (rc) return rc;
+        }
+        for (const auto &jp : singles[round]) {
+            Plan one;
+            Item it;
+            it.is_pass = true;
+            it.pass = jp.second;
+            one.push_back(it);
+            tb_sparse *s = const_cast<tb_sparse *>(jp.first->rq.sparse);
+            tb_status rc = run_plan(jp.first->rq.model, s, jp.first->sc, one, sv->st);
+            if (rc) return rc;
+        }
     }
     return TB_OK;
 }
@@ -268,6 +285,9 @@ tb_status epoch(tb_server *sv)
     };
     std::vector<LaunchRec> L;
     std::vector<int> key;
+    // Passes whose lists exceed the LDS capacities run as launches of their
+    // own (the global-list kernel), after the batched launches of the round.
+    std::vector<std::vector<std::pair<Job *, Pass>>> singles(P);
     int np = 0;
     for (int round = 0; round < P; round++) {
         std::vector<Entry> ents;
@@ -276,8 +296,13 @@ tb_status epoch(tb_server *sv)
             const Pass &ps = j.plan[j.pos + round].pass;
             Entry e;
             const TileGeom *g = nullptr;
+            bool gl = false;
             tb_sparse *s = const_cast<tb_sparse *>(j.rq.sparse);
-            if ((rc = pass_params(j.rq.model, s, j.sc, ps, &e.p, &g))) return rc;
+            if ((rc = pass_params(j.rq.model, s, j.sc, ps, &e.p, &g, &gl))) return rc;
+            if (gl) {
+                singles[round].push_back({&j, ps});
+                continue;
+            }
             e.r = j.rq.model->r;
             e.T = g->T;
             e.LZ = g->LZ;
@@ -301,23 +326,26 @@ tb_status epoch(tb_server *sv)
             }
             l.njobs = (int)(b - a);
             l.total_wg = wg;
+            l.round = round;
             L.push_back(l);
             for (int v : {l.r, l.T, l.LZ, l.BYE, l.njobs, l.total_wg, l.poff}) key.push_back(v);
             sv->stats[kPassesBatched] += l.njobs;
             a = b;
         }
     }
+    bool any_single = false;
+    for (auto &v : singles) any_single |= !v.empty();
     TB_HIP(hipMemcpyAsync(sv->d_par, sv->h_par, np * sizeof(AcParams), hipMemcpyHostToDevice,
                           sv->st));
     TB_HIP(hipMemcpyAsync(sv->d_wg, sv->h_wg, np * sizeof(int), hipMemcpyHostToDevice, sv->st));
     TB_HIP(hipEventRecord(sv->staged, sv->st));
     sv->staged_pending = true;
-    if (sv->flags & TB_SERVE_GRAPHS) {
+    if ((sv->flags & TB_SERVE_GRAPHS) && !any_single) {
         auto it = sv->graphs.find(key);
         if (it == sv->graphs.end()) {
             hipGraph_t graph = nullptr;
             TB_HIP(hipStreamBeginCapture(sv->st, hipStreamCaptureModeThreadLocal));
-            rc = issue(sv, L, false);
+            rc = issue(sv, L, singles, false);
             hipError_t e = hipStreamEndCapture(sv->st, &graph);
             if (rc) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -334,10 +362,11 @@ tb_status epoch(tb_server *sv)
         TB_HIP(hipGraphLaunch(it->second, sv->st));
         sv->stats[kGraphReplays]++;
     } else {
-        if ((rc = issue(sv, L, true))) return rc;
+        if ((rc = issue(sv, L, singles, true))) return rc;
     }
     for (auto &jp : sv->active) jp->pos += P;
     sv->stats[kLaunches] += (int64_t)L.size();
+    for (auto &v : singles) sv->stats[kLaunches] += (int64_t)v.size();
     sv->stats[kEpochs]++;
     sv->stats[kRounds] += P;
     return TB_OK;

@@ -34,8 +34,8 @@ constexpr int kMaxThreads = 512;
 constexpr int kMaxChunk = 2048;
 // Per-tile list capacities (the lists are staged in LDS); a schedule whose
 // tiles exceed them is run with shorter x chunks.
-constexpr int kSrcCap = 512;
-constexpr int kRecCap = 1024;
+constexpr int kSrcCap = 1024;
+constexpr int kRecCap = 512;
 
 // A list entry: key = ((row*32 + lane) << 18) | (x << 2) | k, with k the z
 // component inside the lane's float4; id = point ID. Sorted by key, so each

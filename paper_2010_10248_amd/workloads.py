@@ -187,6 +187,26 @@ def acoustic_two_layer(seed: int = 10250, n=512, so: int = 8, nt: int = 1000,
                 seed=seed, name=f"acoustic two-layer {shape[0]}^3 SO{so} nt={nt}")
 
 
+def acoustic_source_density(nsrc: int, layout: str = "volume", seed: int = 10254, n=512,
+                            so: int = 8, nt: int = 1000, nbl: int = 40, h: float = 10.0):
+    """The two-layer case with many sources (Section IV-E's stress test):
+    `layout` "volume" draws them uniformly in the interior, "plane" on a
+    horizontal plane at a random off-grid depth (sources on a plane of the
+    blocked y-z tiles). Wavelets are Ricker with f ~ U[8, 15] Hz."""
+    shot = acoustic_two_layer(seed=seed, n=n, so=so, nt=nt, nbl=nbl, h=h, nsrc=1)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    src = _interior_uniform(rng, shot.shape, shot.spacing, shot.origin, nbl, nsrc)
+    if layout == "plane":
+        src[:, 2] = src[0, 2]
+    elif layout != "volume":
+        raise ValueError(f"layout {layout!r}")
+    f = 8.0 + 7.0 * rng.random(nsrc)
+    shot.src_xyz = src
+    shot.src_wav = np.stack([ricker(fi, nt, shot.dt) for fi in f], axis=1)
+    shot.name = f"acoustic two-layer {shot.shape[0]}^3 SO{so} nt={nt}, {nsrc} sources ({layout})"
+    return shot
+
+
 def acoustic_scaled(seed: int, n: int, so: int, nt: int, nbl: int, nsrc: int = 1,
                     nrec: int = 16, layered: bool = True, h: float = 10.0) -> Shot:
     """Small two-layer (or constant) acoustic case for tests."""

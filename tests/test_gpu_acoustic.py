@@ -219,3 +219,14 @@ def test_c2_recipe_full_length_reduced_grid(torch_cuda, orc):
     sources, 512 receivers): traces and final fields against the oracle."""
     s = W.acoustic_two_layer(n=192, nt=1000)
     _check_case(torch_cuda, orc, s, scheds=[("tb", 2, 32, 64), ("sb", 1, 32, 0), ("tb", 2, 0, 0)])
+
+
+@pytest.mark.parametrize("layout", ["plane", "volume"])
+def test_dense_sources(torch_cuda, orc, layout):
+    """A thousand sources (Section IV-E), on one plane of the tiles and
+    uniform in the volume: segments whose lists exceed the LDS capacities run
+    the global-list kernel; parity with the oracle and bitwise identity of
+    the schedules."""
+    s = W.acoustic_source_density(1000, layout, n=(48, 56, 64), nt=40, nbl=6)
+    _check_case(torch_cuda, orc, s, scheds=[("sb", 1, 32, 0), ("tb", 2, 32, 64), ("tb", 2, 32, 0),
+                                            ("tb", 2, 16, 8)])

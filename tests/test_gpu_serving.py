@@ -115,6 +115,42 @@ def test_alone_vs_mix_bit_identical(torch_cuda, graphs):
         p.close()
 
 
+@pytest.mark.parametrize("graphs", [True, False])
+def test_dense_source_request_in_mix(torch_cuda, graphs):
+    """A request with a thousand sources in the volume needs the global-list
+    kernel for some passes; those run as launches of their own beside the
+    batched launches of the other requests, with the same bits as alone."""
+    torch = torch_cuda
+    from paper_2010_10248_amd import tb
+
+    dense = W.acoustic_source_density(1000, "volume", n=(48, 56, 64), nt=40, nbl=6)
+    reqs = [("fwd", dense, None)] + [r for r in _requests() if r[0] == "fwd"][:2]
+    sched = tb.schedule("tb", 2, 32, 64)
+    props, alone = _alone(torch, tb, reqs, sched)
+    sv = tb.Server(arena_bytes=8 << 30, max_active=3, graphs=graphs)
+    outs, pending = {}, {}
+    for i, (kind, shot, _) in enumerate(reqs):
+        o = torch.full((shot.nt, props[i].nrec), float("nan"), device="cuda")
+        pending[sv.submit_forward(props[i], o, sched)] = i
+        outs[i] = o
+    done = set()
+    it = 0
+    while len(done) < len(reqs):
+        sv.step()
+        for rid, _ in sv.poll():
+            done.add(pending[rid])
+        it += 1
+        assert it < 100000
+    st = sv.stats()
+    _say(f"dense mix graphs={graphs} stats {st}")
+    sv.close()
+    for i, (_, ref, _) in enumerate(alone):
+        assert torch.equal(outs[i].view(torch.int32), ref.view(torch.int32)), i
+    assert st["completed"] == len(reqs)
+    for p in props:
+        p.close()
+
+
 def test_server_rejects_oversized_request(torch_cuda):
     torch = torch_cuda
     from paper_2010_10248_amd import tb
