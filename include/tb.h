@@ -95,15 +95,18 @@ typedef struct {
  * Schedule of the time loop (Section II-B; the wave-front loop nest of the
  * last listing). mode TB_SCHED_SB runs one step per pass; TB_SCHED_TB runs
  * time_tile steps per pass with a wave-front along x and overlapped y-z
- * halos. time_tile is 1..4 at space order 4 and 1..3 at space order 8.
+ * halos. time_tile is 1..4 at space order 4 (3 and 4 with tile_y 16) and
+ * 1..2 at space order 8.
  *  tile_y   y rows one workgroup holds: 16 or 32 (16 lanes x 4 z per row),
- *           or 0 for the shape whose tile owns 64 z (16 + halo/2 lanes).
- *  chunk_x  x planes one work segment streams: 1..n, each (chunk, tile) pair
- *           one workgroup, dispatched chunk-major; 0 splits the tile-x space
- *           evenly over two workgroups per compute unit.
+ *           or 0 for 32 where that shape fits the depth, else 16.
+ *  chunk_x  x planes one work segment streams: 1..2048. Each (chunk, tile)
+ *           pair is one segment; one workgroup per compute unit streams the
+ *           segments of a slab of neighbouring tiles, chunk by chunk, with
+ *           the slabs spread over the XCDs. 0 splits the tile-x space evenly
+ *           over two workgroups per compute unit.
  * Every schedule gives bit-identical results. Passing NULL where a schedule
- * is accepted selects the default: TB, time_tile 2, tile_y 32, chunk_x 64
- * when nx >= 256, else 0.
+ * is accepted selects the tuned choice for the model if tb_autotune cached
+ * one, else TB, time_tile 2, tile_y 32, chunk_x 64 when nx >= 256, else 0.
  */
 typedef struct {
     int32_t mode;

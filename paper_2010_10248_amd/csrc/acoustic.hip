@@ -86,6 +86,8 @@ AcParams make_params(const tb_model *m, const TileLists &tl, const AcLaunch &a)
         p.wy[j] = (float)(wj * ihy);
         p.wz[j] = (float)(wj * ihz);
     }
+    p.iso = 1;
+    for (int j = 0; j < 4; j++) p.iso &= p.wx[j] == p.wy[j] && p.wx[j] == p.wz[j];
     p.nx = m->n[0];
     p.ny = m->n[1];
     p.nz = m->n[2];

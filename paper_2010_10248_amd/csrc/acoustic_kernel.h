@@ -52,10 +52,48 @@ constexpr int kRsrcWord3 = 0x00020000;
 // Byte offset beyond any buffer: loads return 0, stores are discarded.
 constexpr unsigned kNoLane = 0x80000000u;
 
-// LDS row: the lanes, two z-ring columns (and padding) in float4.
-constexpr int kLdsPad = 2;
+// DPP controls (16-lane rows): lane l takes lane l-1 / l+1 of its row; the
+// lane at the row's end keeps the value passed as `old`.
+constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppRowShl1 = 0x101;
 // Damping values of the chunk's x range (chunk plus halo) staged in LDS.
 constexpr int kDxCap = kMaxChunk + 32;
+
+// z neighbours from the adjacent lanes of the same tile row (a tile row is
+// one 16-lane DPP row), with `edge` supplying the lane at the row's end.
+// The operands are passed as named scalars: with vector-element operands
+// indexed in a loop the compiler merged the four moves into one.
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float edge, float v)
+{
+    const int e = __builtin_bit_cast(int, edge);
+    const int x = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(e, x, CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ f4v row_shift(f4v edge, f4v v)
+{
+    return f4v{lane_shift<CTRL>(edge.x, v.x), lane_shift<CTRL>(edge.y, v.y),
+               lane_shift<CTRL>(edge.z, v.z), lane_shift<CTRL>(edge.w, v.w)};
+}
+// The same with 0 at the row's end (no edge operand to set up).
+template <int CTRL>
+__device__ __forceinline__ float lane_shift0(float v)
+{
+    const int x = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ f4v row_shift0(f4v v)
+{
+    return f4v{lane_shift0<CTRL>(v.x), lane_shift0<CTRL>(v.y), lane_shift0<CTRL>(v.z),
+               lane_shift0<CTRL>(v.w)};
+}
+
+__device__ __forceinline__ float uniform(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes)
 {
@@ -105,28 +143,43 @@ __device__ __forceinline__ void static_for(F &&f)
 // steps each of the two changes removes most of the drift from the FP64
 // definition. Without damping (d == 0, beta == 1) the fast path evaluates
 // the same expression with identical rounding.
-template <int R, bool DAMP>
+//
+// With equal spacing on all axes (ISO) the three axes share one weight per
+// offset and the Laplacian is sum_j w_j (((x-j + x+j) + (z-j + z+j)) +
+// (y-j + y+j) - 6u): seven operations per offset instead of nine, still
+// exactly zero on a constant field (the neighbour sum and 6u round the same
+// exact value 6u).
+template <int R, bool DAMP, bool ISO>
 __device__ __forceinline__ float point_update(const AcParams &p, float ctr, const float *xm,
                                               const float *xp, const float *ym, const float *yp,
                                               const float *zm, const float *zp, float vold,
                                               float cc, float d)
 {
-    // x terms (register window) first, so LDS reads of the y/z neighbours
-    // overlap with arithmetic.
-    const float t2 = 2.0f * ctr;
     float lap = 0.0f;
+    if constexpr (ISO) {
+        const float t6 = 6.0f * ctr;
 #pragma unroll
-    for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wx[j], (xm[j] + xp[j]) - t2, lap);
+        for (int j = 0; j < R; j++)
+            lap = __builtin_fmaf(p.wx[j], (((xm[j] + xp[j]) + (zm[j] + zp[j])) + (ym[j] + yp[j])) - t6,
+                                 lap);
+    } else {
+        // x terms (register window) first, so LDS reads of the y/z
+        // neighbours overlap with arithmetic.
+        const float t2 = 2.0f * ctr;
 #pragma unroll
-    for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wz[j], (zm[j] + zp[j]) - t2, lap);
+        for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wx[j], (xm[j] + xp[j]) - t2, lap);
 #pragma unroll
-    for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wy[j], (ym[j] + yp[j]) - t2, lap);
+        for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wz[j], (zm[j] + zp[j]) - t2, lap);
+#pragma unroll
+        for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wy[j], (ym[j] + yp[j]) - t2, lap);
+    }
     if constexpr (DAMP) {
+        // 1/alpha by the hardware reciprocal (exact for alpha == 1, so an
+        // undamped point gives the fast path's bits).
         const float dd = d * p.hdt;
         const float beta = 1.0f - dd;
-        float r = __builtin_fmaf(cc, lap, beta * vold);
-        if (d != 0.0f) r = r / (1.0f + dd);
-        return r;
+        const float r = __builtin_fmaf(cc, lap, beta * vold);
+        return r * __builtin_amdgcn_rcpf(1.0f + dd);
     } else {
         return __builtin_fmaf(cc, lap, vold);
     }
@@ -140,14 +193,6 @@ __device__ __forceinline__ float point_update(const AcParams &p, float ctr, cons
 constexpr int cring_slots(int R, int T) { return T > 1 ? R * (T - 1) : 0; }
 constexpr int vring_slots(int R, int T) { return T > 1 ? R + 1 : 0; }
 
-// LDS bytes of one workgroup of acoustic_wavefront<R, T, LZ, BYE> (GL: the
-// sparse lists are read from global memory instead of being staged).
-constexpr int wavefront_lds(int R, int T, int LZ, int BYE, bool GL = false)
-{
-    return 16 * 2 * T * (BYE + 2 * R) * (LZ + kLdsPad) +
-           (GL ? 0 : kSrcCap * (8 + 4 * T) + kRecCap * (8 + 4 * T)) + 4 * kDxCap +
-           16 * LZ * BYE * (cring_slots(R, T) + (T - 1) * vring_slots(R, T));
-}
 
 // Side inputs of one tick, loaded PD ticks ahead into a register ring: the
 // newest u^n plane, and v^n and c at the stage-0 centre plane.
@@ -164,13 +209,39 @@ struct RingIn {
     f4v yr;
 };
 
+// LDS of one workgroup (one instance shared by the body's variants).
+template <int R, int T, int LZ, int BYE, bool GL>
+struct WfLds {
+    static constexpr int LR = BYE + 2 * R;  // LDS rows per stage (with the y ring)
+    static constexpr int NTH = LZ * BYE;
+    static constexpr int NSC = cring_slots(R, T), NSV = vring_slots(R, T);
+    static constexpr int SC = GL ? 1 : kSrcCap, RC = GL ? 1 : kRecCap;
+    f4v sh[2][T][LR][LZ];
+    int2 s_src[SC];
+    float s_val[SC][T];
+    int2 s_rec[RC];
+    float s_recv[RC][T];
+    float s_dx[kDxCap];
+    f4v s_c[NSC ? NSC : 1][NSC ? NTH : 1];
+    f4v s_v[T > 1 ? T - 1 : 1][NSV ? NSV : 1][NSV ? NTH : 1];
+};
+
+// LDS bytes of one workgroup of acoustic_wavefront<R, T, LZ, BYE> (GL: the
+// sparse lists are read from global memory instead of being staged).
+template <int R, int T, int LZ, int BYE, bool GL = false>
+constexpr int wavefront_lds()
+{
+    return (int)sizeof(WfLds<R, T, LZ, BYE, GL>);
+}
+
 // The kernel body for one job: b is the workgroup's index within the job's
 // grid of p.nwg workgroups.
 // GL selects where the segment's sparse lists are walked: staged in LDS
 // (the common case), or read in place from global memory when a segment
 // holds more entries than the LDS lists (dense sources or receivers).
-template <int R, int T, int LZ, int BYE, int PD, bool GL>
-__device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
+template <int R, int T, int LZ, int BYE, int PD, bool GL, bool ISO>
+__device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
+                                               WfLds<R, T, LZ, BYE, GL> &lds)
 {
     constexpr int U = 2 * R + 1;  // window slots: the 2R+1 live planes
     static_assert(U % PD == 0, "prefetch ring must divide the window");
@@ -179,31 +250,27 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
     constexpr int OY = BYE - 2 * HY;
     constexpr int OZ = 4 * LZ - 2 * HZ;
     constexpr int LR = BYE + 2 * R;  // LDS rows per stage (with the y ring)
-    // LDS row: LZ lane columns, then the left and right z ring, padded.
-    constexpr int LC = LZ + kLdsPad;
+    // LDS row: the LZ lane columns (z neighbours move between lanes by DPP).
+    constexpr int LC = LZ;
     constexpr int NTH = LZ * BYE;
     static_assert(OY > 0 && OZ > 0, "tile too small for this depth");
     static_assert(R >= 1 && R <= 4, "radius must be 1..4");
-    static_assert(NTH <= kMaxThreads && LZ <= 32 && BYE <= 32, "workgroup shape");
+    static_assert(NTH <= kMaxThreads && LZ == 16 && BYE <= 32, "workgroup shape");
     constexpr int NSC = cring_slots(R, T);
     constexpr int NSV = vring_slots(R, T);
 
-    __shared__ f4v sh[2][T][LR][LC];
-    constexpr int SC = GL ? 1 : kSrcCap, RC = GL ? 1 : kRecCap;
-    __shared__ int2 s_src[SC];
-    __shared__ float s_val[SC][T];
-    __shared__ int2 s_rec[RC];
-    __shared__ float s_recv[RC][T];
-    __shared__ float s_dx[kDxCap];
-    __shared__ f4v s_c[NSC ? NSC : 1][NSC ? NTH : 1];
-    __shared__ f4v s_v[T > 1 ? T - 1 : 1][NSV ? NSV : 1][NSV ? NTH : 1];
+    auto &sh = lds.sh;
+    auto &s_src = lds.s_src;
+    auto &s_val = lds.s_val;
+    auto &s_rec = lds.s_rec;
+    auto &s_recv = lds.s_recv;
+    auto &s_dx = lds.s_dx;
+    auto &s_c = lds.s_c;
+    auto &s_v = lds.s_v;
 
     const int tid = threadIdx.x;
     const int zl = tid % LZ;
     const int row = tid / LZ;
-    const int rg_col = zl == 0 ? LZ : LZ + 1;
-    const int col_l = zl == 0 ? LZ : zl - 1;  // left z neighbour (or ring)
-    const int col_r = zl == LZ - 1 ? LZ + 1 : zl + 1;
     const bool has_rg = zl == 0 || zl == LZ - 1;
     const bool has_yr = tid < 2 * R * LZ;
     const int yr_lds = row < R ? row : BYE + row;
@@ -376,7 +443,7 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
             const int buf = tick & 1;
 #pragma unroll
             for (int s = 0; s < T; s++) sh[buf][s][row + R][zl] = q[s][CTR];
-            if (has_rg) sh[buf][0][row + R][rg_col] = rgn.rg;
+            const f4v rg_now = rgn.rg;
             if (has_yr) sh[buf][0][yr_lds][zl] = rgn.yr;
             lds_barrier();
             fetch_ring(i + 1, rgn);
@@ -398,8 +465,17 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
                         const int sl = cslot - R * s;                      // tick - R s
                         cf = s_c[sl < 0 ? sl + NSC : sl][tid];
                     }
-                    const f4v zl4 = sh[buf][s][row + R][col_l];
-                    const f4v zr4 = sh[buf][s][row + R][col_r];
+                    // Stage 0 takes the tile's outer z values from the ring;
+                    // later stages do not need them (their edge lanes lie
+                    // in the halo, which they need not compute correctly).
+                    f4v zl4, zr4;
+                    if constexpr (s == 0) {
+                        zl4 = row_shift<kDppRowShr1>(rg_now, ctr);
+                        zr4 = row_shift<kDppRowShl1>(rg_now, ctr);
+                    } else {
+                        zl4 = row_shift0<kDppRowShr1>(ctr);
+                        zr4 = row_shift0<kDppRowShl1>(ctr);
+                    }
                     float zw[12];
 #pragma unroll
                     for (int k = 0; k < 4; k++) {
@@ -413,7 +489,7 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
                         ym[j - 1] = sh[buf][s][row + R - j][zl];
                         yp[j - 1] = sh[buf][s][row + R + j][zl];
                     }
-                    const float dxs = s_dx[cs - xlo];
+                    const float dxs = uniform(s_dx[cs - xlo]);
                     auto compute = [&](auto DC) {
                         constexpr bool DAMP = decltype(DC)::value;
 #pragma unroll
@@ -428,14 +504,14 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
                                 zm[j - 1] = zw[4 + k - j];
                                 zp[j - 1] = zw[4 + k + j];
                             }
-                            v[k] = point_update<R, DAMP>(p, ctr[k], xm, xp, a, bb, zm, zp,
+                            v[k] = point_update<R, DAMP, ISO>(p, ctr[k], xm, xp, a, bb, zm, zp,
                                                          vold[k], cf[k], dxs + dyz[k]);
                         }
                     };
                     if (dxs != 0.0f || wave_dyz) compute(std::true_type{});
                     else compute(std::false_type{});
                     // Fused injection at every computed copy (per-tile list).
-                    if (snx[s] == cs) {
+                    if (__builtin_amdgcn_ballot_w64(snx[s] == cs) && snx[s] == cs) {
                         int kk = scur[s];
                         for (; kk < nsl && (skey(kk) >> 18) == mykey &&
                                ((skey(kk) >> 2) & 0xffff) == cs;
@@ -458,7 +534,7 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
                     for (int k = 0; k < 4; k++) un[k] = ctr[k] + v[k];
                     // Receiver points (owned copy only), buffered in LDS and
                     // written out once at the end.
-                    if (rnx[s] == cs) {
+                    if (__builtin_amdgcn_ballot_w64(rnx[s] == cs) && rnx[s] == cs) {
                         int kk = rcur[s];
                         for (; kk < nrl && (rkey(kk) >> 18) == mykey &&
                                ((rkey(kk) >> 2) & 0xffff) == cs;
@@ -515,7 +591,9 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b)
 template <int R, int T, int LZ, int BYE, int PD, bool GL>
 __global__ void __launch_bounds__(LZ *BYE) acoustic_wavefront(const AcParams p)
 {
-    wavefront_body<R, T, LZ, BYE, PD, GL>(p, blockIdx.x);
+    __shared__ WfLds<R, T, LZ, BYE, GL> lds;
+    if (p.iso) wavefront_body<R, T, LZ, BYE, PD, GL, true>(p, blockIdx.x, lds);
+    else wavefront_body<R, T, LZ, BYE, PD, GL, false>(p, blockIdx.x, lds);
 }
 
 // Several jobs (different grids, sparse sets and time levels) in one launch:
@@ -534,7 +612,9 @@ __global__ void __launch_bounds__(LZ *BYE)
     const AcParams &p = jobs[j];
     const int b = bx - wg_off[j];
     if (b >= p.nwg) return;
-    wavefront_body<R, T, LZ, BYE, PD, false>(p, b);
+    __shared__ WfLds<R, T, LZ, BYE, false> lds;
+    if (p.iso) wavefront_body<R, T, LZ, BYE, PD, false, true>(p, b, lds);
+    else wavefront_body<R, T, LZ, BYE, PD, false, false>(p, b, lds);
 }
 
 // Prefetch depth (ticks of loads in flight): it must divide the window 2R+1,
@@ -549,12 +629,11 @@ constexpr int prefetch_depth()
 }
 static_assert((2 * 4 + 1) % 3 == 0 && (2 * 2 + 1) % 5 == 0, "depth must divide the window");
 
-// Instantiated shapes: 16-lane tiles of 16 or 32 rows (the shape a schedule
-// may request), and the default shape for (R, T), whose tile owns 64 z.
+// Instantiated shapes: 16-lane tiles of 16 or 32 rows.
 template <int R, int T, int LZ, int BYE>
 constexpr bool wavefront_fits()
 {
-    return BYE - 2 * R * (T - 1) > 0 && wavefront_lds(R, T, LZ, BYE) <= 160 * 1024 &&
+    return BYE - 2 * R * (T - 1) > 0 && wavefront_lds<R, T, LZ, BYE>() <= 160 * 1024 &&
            LZ * BYE <= kMaxThreads;
 }
 
@@ -563,16 +642,10 @@ template <int R, class F>
 hipError_t dispatch_shape(int T, int LZ, int BYE, F &&f)
 {
     auto rt = [&]<int TT>() -> hipError_t {
-        constexpr int HZ = ((R * (TT - 1) + 3) / 4) * 4;
-        constexpr int DLZ = 16 + HZ / 2;                // default lanes per row
-        constexpr int DBYE = (kMaxThreads / DLZ) & ~3;  // default rows
         if (LZ == 16 && BYE == 16) {
             if constexpr (wavefront_fits<R, TT, 16, 16>()) return f.template operator()<TT, 16, 16>();
         } else if (LZ == 16 && BYE == 32) {
             if constexpr (wavefront_fits<R, TT, 16, 32>()) return f.template operator()<TT, 16, 32>();
-        } else if (LZ == DLZ && BYE == DBYE) {
-            if constexpr (DLZ != 16 && wavefront_fits<R, TT, DLZ, DBYE>())
-                return f.template operator()<TT, DLZ, DBYE>();
         }
         return hipErrorInvalidValue;
     };

@@ -18,6 +18,7 @@ struct AcParams {
     const float *__restrict__ dz;
     float hdt;  // dt / 2
     float wx[4], wy[4], wz[4];  // off-centre weights per axis (h^-2 scaled)
+    int iso;                    // wx == wy == wz (equal spacing on all axes)
     int nx, ny, nz, nzp;
     long long sx;  // plane stride ny * nzp
     int tiles_z, nwg;

@@ -114,14 +114,8 @@ static void node_xyz(int64_t r, const int n[3], int *x, int *y, int *z)
 // covered without a ragged last tile); rows fill one 512-thread workgroup.
 void tile_shape(int R, int T, int tile_y, int *LZ, int *BYE)
 {
-    const int HZ = ((R * (T - 1) + 3) / 4) * 4;
-    if (tile_y > 0) {
-        *LZ = 16;
-        *BYE = tile_y;
-    } else {
-        *LZ = 16 + HZ / 2;
-        *BYE = (kMaxThreads / *LZ) & ~3;
-    }
+    *LZ = 16;
+    *BYE = tile_y > 0 ? tile_y : (acoustic_shape_ok(R, T, 16, 32) ? 32 : 16);
 }
 
 TileGeom make_geom(int R, int T, int tile_y, int chunk, int wgs, int nx, int ny, int nz)

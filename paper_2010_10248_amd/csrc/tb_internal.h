@@ -65,8 +65,8 @@ struct TileGeom {
     std::vector<int> seg_off;   // per workgroup: [seg_off[b], seg_off[b+1])
     int ntiles() const { return tiles_y * tiles_z; }
 };
-// Tile shape: tile_y == 0 picks the default for (R, T) (a tile owns 64 z);
-// otherwise 16 lanes and tile_y rows. chunk > 0 gives one workgroup per
+// Tile shape: 16 lanes (64 z) and tile_y rows; tile_y == 0 picks 32 rows
+// where that shape fits the kernel's LDS for (R, T), else 16. chunk > 0 gives one workgroup per
 // (tile, chunk of x); chunk == 0 partitions the tile-x space evenly over
 // `wgs` workgroups.
 TileGeom make_geom(int R, int T, int tile_y, int chunk, int wgs, int nx, int ny, int nz);
