@@ -101,15 +101,20 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes)
                                              kRsrcWord3);
 }
 
+// Cache policy of the buffer instructions: 2 marks the access streaming
+// (non-temporal), so it does not displace lines other workgroups reuse.
+constexpr int kTemporal = 0, kStreaming = 2;
+
+template <int POLICY = kTemporal>
 __device__ __forceinline__ f4v bload(rsrc_t r, unsigned off)
 {
-    return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+    return __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, POLICY));
 }
 
 __device__ __forceinline__ void bstore(rsrc_t r, unsigned off, f4v v)
 {
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v),
-                                           r, (int)off, 0, 0);
+                                           r, (int)off, 0, kStreaming);
 }
 
 // Workgroup barrier that orders LDS only. __syncthreads() also fences global
@@ -407,11 +412,15 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
     };
     // Inputs of tick i: the newest plane i of u^n, and v^n and c at the
     // stage-0 centre plane (later stages take c and v from the LDS rings).
+    // v and c are read once per point in a pass except where tiles overlap
+    // (T > 1), whose neighbours then find them in L2; with T == 1 they
+    // stream past L2.
+    constexpr int VC = T > 1 ? kTemporal : kStreaming;
     auto fetch_far = [&](int i, FarIn &f) {
         const int c0 = i - R;
         f.u = bload(plane(p.u, i), off_c);
-        f.v = bload(plane(p.v, c0), off_c);
-        f.c = bload(plane(p.c, (c0 >= lo[0] && c0 < hi[0]) ? c0 : -1), off_c);
+        f.v = bload<VC>(plane(p.v, c0), off_c);
+        f.c = bload<VC>(plane(p.c, (c0 >= lo[0] && c0 < hi[0]) ? c0 : -1), off_c);
     };
     auto fetch_ring = [&](int i, RingIn &f) {
         const rsrc_t ru = plane(p.u, i - R);
