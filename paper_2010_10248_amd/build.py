@@ -18,7 +18,7 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++20", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
-SOURCES = ["acoustic_r4.hip", "acoustic_r2.hip", "acoustic.hip", "imaging.hip", "capi.cpp",
+SOURCES = ["acoustic_r4.hip", "acoustic_r6.hip", "acoustic_r2.hip", "acoustic.hip", "imaging.hip", "capi.cpp",
            "inspector.cpp", "autotune.cpp", "serve.cpp", "tti.hip", "elastic.hip"]
 
 

@@ -77,17 +77,19 @@ AcParams make_params(const tb_model *m, const TileLists &tl, const AcLaunch &a)
     // to differences from the centre, so the centre weight is not needed.
     static const double w4[3] = {-5.0 / 2.0, 4.0 / 3.0, -1.0 / 12.0};
     static const double w8[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
-    const double *w = m->so == 4 ? w4 : w8;
+    static const double w12[7] = {-5369.0 / 1800.0, 12.0 / 7.0, -15.0 / 56.0, 10.0 / 189.0,
+                                  -1.0 / 112.0,     2.0 / 1925.0, -1.0 / 16632.0};
+    const double *w = m->so == 4 ? w4 : (m->so == 8 ? w8 : w12);
     const double ihx = 1.0 / (m->h[0] * m->h[0]), ihy = 1.0 / (m->h[1] * m->h[1]),
                  ihz = 1.0 / (m->h[2] * m->h[2]);
-    for (int j = 0; j < 4; j++) {
+    for (int j = 0; j < 6; j++) {
         const double wj = j < m->r ? w[j + 1] : 0.0;
         p.wx[j] = (float)(wj * ihx);
         p.wy[j] = (float)(wj * ihy);
         p.wz[j] = (float)(wj * ihz);
     }
     p.iso = 1;
-    for (int j = 0; j < 4; j++) p.iso &= p.wx[j] == p.wy[j] && p.wx[j] == p.wz[j];
+    for (int j = 0; j < 6; j++) p.iso &= p.wx[j] == p.wy[j] && p.wx[j] == p.wz[j];
     p.nx = m->n[0];
     p.ny = m->n[1];
     p.nz = m->n[2];
@@ -118,6 +120,7 @@ tb_status launch_acoustic(const tb_model *m, const TileLists &tl, const AcLaunch
     const bool gl = tl.max_src > kSrcCap || tl.max_rec > kRecCap;
     if (m->r == 2) e = launch_acoustic_r2(p, g.T, g.LZ, g.BYE, gl, st);
     else if (m->r == 4) e = launch_acoustic_r4(p, g.T, g.LZ, g.BYE, gl, st);
+    else if (m->r == 6) e = launch_acoustic_r6(p, g.T, g.LZ, g.BYE, gl, st);
     if (ev0) timing_end(st, ev0, ev1);
     if (e != hipSuccess) {
         set_error("acoustic kernel launch (R=%d T=%d LZ=%d BYE=%d) failed: %s", m->r, g.T, g.LZ,
@@ -129,8 +132,18 @@ tb_status launch_acoustic(const tb_model *m, const TileLists &tl, const AcLaunch
 
 bool acoustic_shape_ok(int R, int T, int LZ, int BYE)
 {
-    return R == 2 ? acoustic_shape_ok_r2(T, LZ, BYE)
-                  : (R == 4 ? acoustic_shape_ok_r4(T, LZ, BYE) : false);
+    return R == 2   ? acoustic_shape_ok_r2(T, LZ, BYE)
+           : R == 4 ? acoustic_shape_ok_r4(T, LZ, BYE)
+           : R == 6 ? acoustic_shape_ok_r6(T, LZ, BYE)
+                    : false;
+}
+
+bool acoustic_lists_in_lds(int R, int T, int LZ, int BYE)
+{
+    return R == 2   ? acoustic_lists_in_lds_r2(T, LZ, BYE)
+           : R == 4 ? acoustic_lists_in_lds_r4(T, LZ, BYE)
+           : R == 6 ? acoustic_lists_in_lds_r6(T, LZ, BYE)
+                    : false;
 }
 
 tb_status launch_acoustic_batch(int r, const AcParams *d_jobs, const int *d_wgoff, int njobs,
@@ -143,6 +156,7 @@ tb_status launch_acoustic_batch(int r, const AcParams *d_jobs, const int *d_wgof
     if (allow_timing && timing_enabled()) timing_begin(st, &ev0, &ev1);
     if (r == 2) e = launch_acoustic_batch_r2(d_jobs, d_wgoff, njobs, total_wg, T, LZ, BYE, st);
     else if (r == 4) e = launch_acoustic_batch_r4(d_jobs, d_wgoff, njobs, total_wg, T, LZ, BYE, st);
+    else if (r == 6) e = launch_acoustic_batch_r6(d_jobs, d_wgoff, njobs, total_wg, T, LZ, BYE, st);
     if (ev0) timing_end(st, ev0, ev1);
     if (e != hipSuccess) {
         set_error("batched acoustic kernel launch (R=%d T=%d LZ=%d BYE=%d, %d jobs) failed: %s", r,

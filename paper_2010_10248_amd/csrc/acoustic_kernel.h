@@ -56,6 +56,8 @@ constexpr unsigned kNoLane = 0x80000000u;
 // lane at the row's end keeps the value passed as `old`.
 constexpr int kDppRowShr1 = 0x111;
 constexpr int kDppRowShl1 = 0x101;
+constexpr int kDppRowShr2 = 0x112;
+constexpr int kDppRowShl2 = 0x102;
 // Damping values of the chunk's x range (chunk plus halo) staged in LDS.
 constexpr int kDxCap = kMaxChunk + 32;
 
@@ -259,7 +261,9 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
     constexpr int LC = LZ;
     constexpr int NTH = LZ * BYE;
     static_assert(OY > 0 && OZ > 0, "tile too small for this depth");
-    static_assert(R >= 1 && R <= 4, "radius must be 1..4");
+    static_assert(R >= 1 && R <= 6, "radius must be 1..6");
+    // z neighbours span one float4 on each side (R <= 4) or two (R <= 6).
+    constexpr int ZB = R <= 4 ? 4 : 8;
     static_assert(NTH <= kMaxThreads && LZ == 16 && BYE <= 32, "workgroup shape");
     constexpr int NSC = cring_slots(R, T);
     constexpr int NSV = vring_slots(R, T);
@@ -276,7 +280,9 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
     const int tid = threadIdx.x;
     const int zl = tid % LZ;
     const int row = tid / LZ;
-    const bool has_rg = zl == 0 || zl == LZ - 1;
+    // Lanes that load the tile's outer z values for stage 0: the first and
+    // last ZB/4 lanes of a row, each the float4 ZB before / after its own.
+    const bool has_rg = zl < ZB / 4 || zl >= LZ - ZB / 4;
     const bool has_yr = tid < 2 * R * LZ;
     const int yr_lds = row < R ? row : BYE + row;
     const bool own_rc = row >= HY && row < HY + OY && zl >= HZ / 4 && zl < (HZ + OZ) / 4;
@@ -304,7 +310,7 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
     const unsigned off_own = own_rc ? off_c : kNoLane;
     // z ring of stage 0: lane 0 of each row loads z0-4..z0-1, lane LZ-1 loads
     // the float4 after the tile (one float4 covers the radius).
-    const int zr = zl == 0 ? z - 4 : z + 4;
+    const int zr = zl < LZ / 2 ? z - ZB : z + ZB;
     const bool rgok = yin && has_rg && zr >= 0 && zr < p.nzp;
     const unsigned off_rg = rgok ? (unsigned)((y * p.nzp + zr) * 4) : kNoLane;
     // y ring of stage 0: rows y0-R..y0-1 and y0+BYE..y0+BYE+R-1.
@@ -477,20 +483,42 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
                     // Stage 0 takes the tile's outer z values from the ring;
                     // later stages do not need them (their edge lanes lie
                     // in the halo, which they need not compute correctly).
+                    // zw: the float4s of lanes l-2 (ZB == 8), l-1, l, l+1,
+                    // l+2 (ZB == 8), i.e. z - ZB .. z + 4 + ZB.
+                    float zw[4 + 2 * ZB];
                     f4v zl4, zr4;
-                    if constexpr (s == 0) {
+                    if constexpr (s == 0 && ZB == 4) {
                         zl4 = row_shift<kDppRowShr1>(rg_now, ctr);
                         zr4 = row_shift<kDppRowShl1>(rg_now, ctr);
+                    } else if constexpr (s == 0) {
+                        // Lane 0's left float4 is lane 1's ring value, lane
+                        // 15's right float4 lane 14's.
+                        zl4 = row_shift<kDppRowShr1>(row_shift0<kDppRowShl1>(rg_now), ctr);
+                        zr4 = row_shift<kDppRowShl1>(row_shift0<kDppRowShr1>(rg_now), ctr);
                     } else {
                         zl4 = row_shift0<kDppRowShr1>(ctr);
                         zr4 = row_shift0<kDppRowShl1>(ctr);
                     }
-                    float zw[12];
 #pragma unroll
                     for (int k = 0; k < 4; k++) {
-                        zw[k] = zl4[k];
-                        zw[4 + k] = ctr[k];
-                        zw[8 + k] = zr4[k];
+                        zw[ZB - 4 + k] = zl4[k];
+                        zw[ZB + k] = ctr[k];
+                        zw[ZB + 4 + k] = zr4[k];
+                    }
+                    if constexpr (ZB == 8) {
+                        f4v zl8, zr8;
+                        if constexpr (s == 0) {
+                            zl8 = row_shift<kDppRowShr2>(rg_now, ctr);
+                            zr8 = row_shift<kDppRowShl2>(rg_now, ctr);
+                        } else {
+                            zl8 = row_shift0<kDppRowShr2>(ctr);
+                            zr8 = row_shift0<kDppRowShl2>(ctr);
+                        }
+#pragma unroll
+                        for (int k = 0; k < 4; k++) {
+                            zw[k] = zl8[k];
+                            zw[16 + k] = zr8[k];
+                        }
                     }
                     f4v ym[R], yp[R];
 #pragma unroll
@@ -510,8 +538,8 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
                                 xp[j - 1] = q[s][(P + R + j) % U][k];
                                 a[j - 1] = ym[j - 1][k];
                                 bb[j - 1] = yp[j - 1][k];
-                                zm[j - 1] = zw[4 + k - j];
-                                zp[j - 1] = zw[4 + k + j];
+                                zm[j - 1] = zw[ZB + k - j];
+                                zp[j - 1] = zw[ZB + k + j];
                             }
                             v[k] = point_update<R, DAMP, ISO>(p, ctr[k], xm, xp, a, bb, zm, zp,
                                                          vold[k], cf[k], dxs + dyz[k]);
@@ -634,16 +662,24 @@ constexpr int prefetch_depth()
 {
     if constexpr (R == 4) return 3;
     else if constexpr (R == 2) return T <= 2 ? 5 : 1;
-    else return 1;
+    else return 1;  // R = 6: the window of 13 planes is prime
 }
 static_assert((2 * 4 + 1) % 3 == 0 && (2 * 2 + 1) % 5 == 0, "depth must divide the window");
 
-// Instantiated shapes: 16-lane tiles of 16 or 32 rows.
-template <int R, int T, int LZ, int BYE>
+// Instantiated shapes: 16-lane tiles of 16 or 32 rows whose LDS fits one
+// workgroup, at least without the staged lists (GL).
+template <int R, int T, int LZ, int BYE, bool GL = true>
 constexpr bool wavefront_fits()
 {
-    return BYE - 2 * R * (T - 1) > 0 && wavefront_lds<R, T, LZ, BYE>() <= 160 * 1024 &&
+    return BYE - 2 * R * (T - 1) > 0 && wavefront_lds<R, T, LZ, BYE, GL>() <= 160 * 1024 &&
            LZ * BYE <= kMaxThreads;
+}
+// Whether the shape also fits with the sparse lists staged in LDS (the
+// common variant and the batched entry); otherwise only GL runs it.
+template <int R, int T, int LZ, int BYE>
+constexpr bool lists_in_lds()
+{
+    return wavefront_fits<R, T, LZ, BYE, false>();
 }
 
 // Calls f.template operator()<T, LZ, BYE>() for an instantiated shape.
@@ -671,12 +707,16 @@ template <int R>
 hipError_t launch_r(const AcParams &p, int T, int LZ, int BYE, bool gl, hipStream_t st)
 {
     return dispatch_shape<R>(T, LZ, BYE, [&]<int TT, int L, int B>() {
-        if (gl)
-            hipLaunchKernelGGL((acoustic_wavefront<R, TT, L, B, prefetch_depth<R, TT>(), true>),
-                               dim3(p.nwg), dim3(L * B), 0, st, p);
-        else
-            hipLaunchKernelGGL((acoustic_wavefront<R, TT, L, B, prefetch_depth<R, TT>(), false>),
-                               dim3(p.nwg), dim3(L * B), 0, st, p);
+        if constexpr (lists_in_lds<R, TT, L, B>()) {
+            if (!gl) {
+                hipLaunchKernelGGL(
+                    (acoustic_wavefront<R, TT, L, B, prefetch_depth<R, TT>(), false>),
+                    dim3(p.nwg), dim3(L * B), 0, st, p);
+                return hipGetLastError();
+            }
+        }
+        hipLaunchKernelGGL((acoustic_wavefront<R, TT, L, B, prefetch_depth<R, TT>(), true>),
+                           dim3(p.nwg), dim3(L * B), 0, st, p);
         return hipGetLastError();
     });
 }
@@ -686,9 +726,13 @@ hipError_t launch_batch_r(const AcParams *jobs, const int *wg_off, int njobs, in
                           int LZ, int BYE, hipStream_t st)
 {
     return dispatch_shape<R>(T, LZ, BYE, [&]<int TT, int L, int B>() {
-        hipLaunchKernelGGL((acoustic_wavefront_batch<R, TT, L, B, prefetch_depth<R, TT>()>),
-                           dim3(total_wg), dim3(L * B), 0, st, jobs, wg_off, njobs);
-        return hipGetLastError();
+        if constexpr (lists_in_lds<R, TT, L, B>()) {
+            hipLaunchKernelGGL((acoustic_wavefront_batch<R, TT, L, B, prefetch_depth<R, TT>()>),
+                               dim3(total_wg), dim3(L * B), 0, st, jobs, wg_off, njobs);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
     });
 }
 

@@ -17,7 +17,7 @@ struct AcParams {
     const float *__restrict__ dy;
     const float *__restrict__ dz;
     float hdt;  // dt / 2
-    float wx[4], wy[4], wz[4];  // off-centre weights per axis (h^-2 scaled)
+    float wx[6], wy[6], wz[6];  // off-centre weights per axis (h^-2 scaled)
     int iso;                    // wx == wy == wz (equal spacing on all axes)
     int nx, ny, nz, nzp;
     long long sx;  // plane stride ny * nzp
@@ -40,15 +40,26 @@ hipError_t launch_acoustic_r2(const AcParams &p, int T, int LZ, int BYE, bool gl
                               hipStream_t st);
 hipError_t launch_acoustic_r4(const AcParams &p, int T, int LZ, int BYE, bool gl,
                               hipStream_t st);
+hipError_t launch_acoustic_r6(const AcParams &p, int T, int LZ, int BYE, bool gl,
+                              hipStream_t st);
 // Batched launch: jobs[njobs] in device memory, wg_off[njobs] (device) the
 // first workgroup of each job (multiples of 8), total_wg the grid size.
 hipError_t launch_acoustic_batch_r2(const AcParams *jobs, const int *wg_off, int njobs,
                                     int total_wg, int T, int LZ, int BYE, hipStream_t st);
 hipError_t launch_acoustic_batch_r4(const AcParams *jobs, const int *wg_off, int njobs,
                                     int total_wg, int T, int LZ, int BYE, hipStream_t st);
+hipError_t launch_acoustic_batch_r6(const AcParams *jobs, const int *wg_off, int njobs,
+                                    int total_wg, int T, int LZ, int BYE, hipStream_t st);
 
 bool acoustic_shape_ok_r2(int T, int LZ, int BYE);
 bool acoustic_shape_ok_r4(int T, int LZ, int BYE);
+bool acoustic_shape_ok_r6(int T, int LZ, int BYE);
+// Whether a shape also runs with its sparse lists staged in LDS (and so has a
+// batched entry); a shape without is run by the global-list variant alone.
+bool acoustic_lists_in_lds(int R, int T, int LZ, int BYE);
+bool acoustic_lists_in_lds_r2(int T, int LZ, int BYE);
+bool acoustic_lists_in_lds_r4(int T, int LZ, int BYE);
+bool acoustic_lists_in_lds_r6(int T, int LZ, int BYE);
 
 // Kernel parameters of one pass of one job.
 AcParams make_params(const tb_model *m, const TileLists &tl, const AcLaunch &a);

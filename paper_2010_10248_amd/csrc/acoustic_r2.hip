@@ -21,4 +21,11 @@ bool acoustic_shape_ok_r2(int T, int LZ, int BYE)
            hipSuccess;
 }
 
+bool acoustic_lists_in_lds_r2(int T, int LZ, int BYE)
+{
+    return wf::dispatch_shape<2>(T, LZ, BYE, []<int TT, int L, int B>() {
+               return wf::lists_in_lds<2, TT, L, B>() ? hipSuccess : hipErrorInvalidValue;
+           }) == hipSuccess;
+}
+
 }  // namespace tbw

@@ -21,4 +21,11 @@ bool acoustic_shape_ok_r4(int T, int LZ, int BYE)
            hipSuccess;
 }
 
+bool acoustic_lists_in_lds_r4(int T, int LZ, int BYE)
+{
+    return wf::dispatch_shape<4>(T, LZ, BYE, []<int TT, int L, int B>() {
+               return wf::lists_in_lds<4, TT, L, B>() ? hipSuccess : hipErrorInvalidValue;
+           }) == hipSuccess;
+}
+
 }  // namespace tbw

@@ -85,7 +85,7 @@ tb_status tb_autotune(const tb_model *m, const tb_sparse *s_, int32_t steps, voi
     TB_HIP(hipEventCreate(&e0.e));
     TB_HIP(hipEventCreate(&e1.e));
 
-    const int Tmax = m->r == 4 ? 3 : 4;
+    const int Tmax = m->r >= 4 ? 3 : 4;
     const int tiles[3] = {32, 16, 0};
     const int chunks[4] = {0, 32, 64, 128};
     SchedChoice bestc{};

@@ -38,13 +38,34 @@ tb_sparse::~tb_sparse()
 
 namespace {
 
-// Centred second-derivative weights (Fornberg rationals) for the stability
-// bound; the kernels tabulate the same rationals.
+// Finite-difference weights on unit spacing, exact rationals (Fornberg 1988)
+// for space orders 4, 8 and 12; the kernels take them rounded to FP32.
+// Centred second derivative, offsets 0..r.
 const double *d2_weights(int so)
 {
     static const double w4[3] = {-5.0 / 2.0, 4.0 / 3.0, -1.0 / 12.0};
     static const double w8[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
-    return so == 4 ? w4 : (so == 8 ? w8 : nullptr);
+    static const double w12[7] = {-5369.0 / 1800.0, 12.0 / 7.0, -15.0 / 56.0, 10.0 / 189.0,
+                                  -1.0 / 112.0,     2.0 / 1925.0, -1.0 / 16632.0};
+    return so == 4 ? w4 : (so == 8 ? w8 : (so == 12 ? w12 : nullptr));
+}
+// Centred first derivative, offsets 1..r (offset -j has the opposite sign).
+const double *d1_weights(int so)
+{
+    static const double w4[2] = {2.0 / 3.0, -1.0 / 12.0};
+    static const double w8[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+    static const double w12[6] = {6.0 / 7.0, -15.0 / 56.0, 5.0 / 63.0,
+                                  -1.0 / 56.0, 1.0 / 385.0, -1.0 / 5544.0};
+    return so == 4 ? w4 : (so == 8 ? w8 : (so == 12 ? w12 : nullptr));
+}
+// Staggered first derivative, offsets 1/2 .. r-1/2.
+const double *stag_weights(int so)
+{
+    static const double w4[2] = {9.0 / 8.0, -1.0 / 24.0};
+    static const double w8[4] = {1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0, -5.0 / 7168.0};
+    static const double w12[6] = {160083.0 / 131072.0, -12705.0 / 131072.0, 22869.0 / 1310720.0,
+                                  -5445.0 / 1835008.0, 847.0 / 2359296.0,   -63.0 / 2883584.0};
+    return so == 4 ? w4 : (so == 8 ? w8 : (so == 12 ? w12 : nullptr));
 }
 
 // Damping profile along one axis: d0 (k/nbl)^2 with k the depth into the
@@ -110,8 +131,8 @@ tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice 
         set_error("time_tile %d not in 1..4", c.T);
         return TB_EUNSUPPORTED;
     }
-    if (m->r == 4 && c.T > 3) {
-        set_error("time_tile %d exceeds 3 at space order 8", c.T);
+    if (m->r >= 4 && c.T > 3) {
+        set_error("time_tile %d exceeds 3 at space order %d", c.T, m->so);
         return TB_EUNSUPPORTED;
     }
     if (c.tile_y != 0 && c.tile_y != 16 && c.tile_y != 32) {
@@ -314,11 +335,11 @@ GradLayout grad_layout(const tb_model *m, const tb_sparse *s, const SchedChoice 
 }
 
 // Centred second-derivative weights per axis scaled by h^-2 (FP64).
-void image_weights(const tb_model *m, double w[3][5])
+void image_weights(const tb_model *m, double w[3][7])
 {
     const double *d2 = d2_weights(m->so);
     for (int a = 0; a < 3; a++)
-        for (int j = 0; j < 5; j++) w[a][j] = j <= m->r ? d2[j] / (m->h[a] * m->h[a]) : 0.0;
+        for (int j = 0; j < 7; j++) w[a][j] = j <= m->r ? d2[j] / (m->h[a] * m->h[a]) : 0.0;
 }
 
 }  // namespace
@@ -331,7 +352,9 @@ tb_status pass_params(const tb_model *m, tb_sparse *s, const SchedChoice &sc, co
     if (rc) return rc;
     *out = make_params(m, *tl, to_launch(p));
     if (geom) *geom = &tl->g;
-    if (gl) *gl = tl->max_src > kSrcCap || tl->max_rec > kRecCap;
+    if (gl)
+        *gl = tl->max_src > kSrcCap || tl->max_rec > kRecCap ||
+              !acoustic_lists_in_lds(m->r, tl->g.T, tl->g.LZ, tl->g.BYE);
     return TB_OK;
 }
 
@@ -386,12 +409,10 @@ tb_status plan_forward_tti(const tb_model *m, tb_sparse *s, void *ws, float *rec
     P.dz = m->d_damp + m->n[0] + m->n[1];
     P.hdt = (float)(m->dt / 2.0);
     // Centred weights on unit spacing (Fornberg rationals).
-    static const double d1_4[2] = {2.0 / 3.0, -1.0 / 12.0};
-    static const double d1_8[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
-    const double *d1 = m->so == 4 ? d1_4 : d1_8;
+    const double *d1 = d1_weights(m->so);
     const double *d2 = d2_weights(m->so);
-    for (int j = 0; j < 4; j++) P.w1[j] = j < m->r ? (float)d1[j] : 0.0f;
-    for (int j = 0; j < 5; j++) P.w2[j] = j <= m->r ? (float)d2[j] : 0.0f;
+    for (int j = 0; j < 6; j++) P.w1[j] = j < m->r ? (float)d1[j] : 0.0f;
+    for (int j = 0; j < 7; j++) P.w2[j] = j <= m->r ? (float)d2[j] : 0.0f;
     for (int a = 0; a < 3; a++) {
         P.ih[a] = (float)(1.0 / m->h[a]);
         P.ih2[a] = (float)(1.0 / (m->h[a] * m->h[a]));
@@ -467,10 +488,8 @@ tb_status plan_forward_elastic(const tb_model *m, tb_sparse *s, void *ws, float 
     P.dy = m->d_damp + m->n[0];
     P.dz = m->d_damp + m->n[0] + m->n[1];
     P.hdt = (float)(m->dt / 2.0);
-    static const double s4[2] = {9.0 / 8.0, -1.0 / 24.0};
-    static const double s8[4] = {1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0, -5.0 / 7168.0};
-    const double *sw = m->so == 4 ? s4 : s8;
-    for (int j = 0; j < 4; j++) P.w[j] = j < m->r ? (float)sw[j] : 0.0f;
+    const double *sw = stag_weights(m->so);
+    for (int j = 0; j < 6; j++) P.w[j] = j < m->r ? (float)sw[j] : 0.0f;
     for (int a = 0; a < 3; a++) P.ih[a] = (float)(1.0 / m->h[a]);
     P.nx = m->n[0];
     P.ny = m->n[1];
@@ -796,8 +815,8 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
         set_error("TTI needs epsilon, delta, theta and phi");
         return TB_EINVAL;
     }
-    if (d->space_order != 4 && d->space_order != 8) {
-        set_error("space order %d not supported (4 or 8)", d->space_order);
+    if (d->space_order != 4 && d->space_order != 8 && d->space_order != 12) {
+        set_error("space order %d not supported (4, 8 or 12)", d->space_order);
         return TB_EUNSUPPORTED;
     }
     for (int a = 0; a < 3; a++) {
@@ -930,10 +949,7 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
     for (int j = 1; j <= m->r; j++) sym += 2.0 * w[j] * ((j & 1) ? -1.0 : 1.0);
     sym = std::fabs(sym);
     if (d->physics == TB_ELASTIC) {
-        static const double s4[2] = {9.0 / 8.0, -1.0 / 24.0};
-        static const double s8[4] = {1225.0 / 1024.0, -245.0 / 3072.0, 49.0 / 5120.0,
-                                     -5.0 / 7168.0};
-        const double *sw = m->so == 4 ? s4 : s8;
+        const double *sw = stag_weights(m->so);
         double a = 0.0;
         for (int j = 0; j < m->r; j++) a += 2.0 * std::fabs(sw[j]);
         sym = a * a;

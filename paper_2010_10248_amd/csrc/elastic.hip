@@ -17,8 +17,9 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Each thread takes 4 consecutive z (float4 accesses); neighbours along x and
-// y are float4 loads, along z they come from the 12-value window [z4-4,
-// z4+8). Reads outside the grid give 0; the z padding holds 0 in every field.
+// y are float4 loads, along z they come from the window [z4-ZB, z4+4+ZB),
+// ZB = 4 up to radius 4 and 8 up to radius 6. Reads outside the grid give 0;
+// the z padding holds 0 in every field.
 struct Site {
     int x, y, z4;
     long long off, sx, sy;
@@ -52,16 +53,21 @@ __device__ __forceinline__ f4 dstg(const float *__restrict__ f, const ElParams &
 {
     f4 s = f4{0.f, 0.f, 0.f, 0.f};
     if constexpr (AX == 2) {
-        const f4 a = ld4(f, q.off - 4, q.z4 >= 4), b = ld4(f, q.off, true),
-                 c = ld4(f, q.off + 4, q.z4 + 4 < P.nzp);
-        const float w[12] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3],
-                             c[0], c[1], c[2], c[3]};
+        static_assert(R >= 1 && R <= 6, "radius must be 1..6");
+        constexpr int ZB = R <= 4 ? 4 : 8;
+        float w[4 + 2 * ZB];
+#pragma unroll
+        for (int o = -ZB; o <= ZB; o += 4) {
+            const f4 a = ld4(f, q.off + o, q.z4 + o >= 0 && q.z4 + o < P.nzp);
+#pragma unroll
+            for (int k = 0; k < 4; k++) w[ZB + o + k] = a[k];
+        }
 #pragma unroll
         for (int k = 0; k < 4; k++)
 #pragma unroll
             for (int m = 0; m < R; m++) {
                 const int up = FWD ? m + 1 : m, dn = FWD ? -m : -m - 1;
-                s[k] = __builtin_fmaf(P.w[m], w[4 + k + up] - w[4 + k + dn], s[k]);
+                s[k] = __builtin_fmaf(P.w[m], w[ZB + k + up] - w[ZB + k + dn], s[k]);
             }
     } else {
         const int c = AX == 0 ? q.x : q.y, n = AX == 0 ? P.nx : P.ny;
@@ -196,6 +202,9 @@ tb_status launch_elastic_step(const ElParams &P, int r, const float *inc, const 
     } else if (r == 4) {
         hipLaunchKernelGGL(el_vel<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
         hipLaunchKernelGGL(el_str<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
+    } else if (r == 6) {
+        hipLaunchKernelGGL(el_vel<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL(el_str<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
     } else {
         set_error("elastic radius %d not built", r);
         return TB_EUNSUPPORTED;

@@ -13,7 +13,7 @@ struct ElParams {
     const float *ms[3];       // dt * mu at the txy, txz, tyz points
     const float *dx, *dy, *dz;  // damping per axis
     float hdt;                // dt / 2
-    float w[4];               // staggered first derivative, unit spacing
+    float w[6];               // staggered first derivative, unit spacing
     float ih[3];              // 1/h per axis
     int nx, ny, nz, nzp;
 };

@@ -53,8 +53,8 @@ __global__ void __launch_bounds__(kLossThreads)
 }
 
 // g += nu * c * L(u) for one or two levels; each thread takes 4 consecutive z
-// (float4 loads of the fields; the z neighbours come from the float4 on each
-// side), z padding skipped.
+// (float4 loads of the fields; the z neighbours come from the two float4 on
+// each side, enough for radius 6), z padding skipped.
 __global__ void __launch_bounds__(256) image_kernel(const ImageArgs a)
 {
     const int nz4 = a.nzp / 4;
@@ -81,11 +81,15 @@ __global__ void __launch_bounds__(256) image_kernel(const ImageArgs a)
         // A zero adjoint level adds +0 to a finite g: skip its stencil.
         if (nu[0] == 0.0f && nu[1] == 0.0f && nu[2] == 0.0f && nu[3] == 0.0f) continue;
         const float *u = a.u[l];
+        // z window [z4-8, z4+12): two float4 on each side cover radius 6.
         const f4 uc = ld4(u, off, true);
-        const f4 zl = ld4(u, off - 4, z4 >= 4);
-        const f4 zr = ld4(u, off + 4, z4 + 4 < a.nzp);
-        const float zw[12] = {zl[0], zl[1], zl[2], zl[3], uc[0], uc[1], uc[2], uc[3],
-                              zr[0], zr[1], zr[2], zr[3]};
+        float zw[20];
+#pragma unroll
+        for (int o = -8; o <= 8; o += 4) {
+            const f4 t = o == 0 ? uc : ld4(u, off + o, z4 + o >= 0 && z4 + o < a.nzp);
+#pragma unroll
+            for (int k = 0; k < 4; k++) zw[8 + o + k] = t[k];
+        }
         double lx[4], ly[4], lz[4];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
@@ -102,7 +106,7 @@ __global__ void __launch_bounds__(256) image_kernel(const ImageArgs a)
             for (int k = 0; k < 4; k++) {
                 lx[k] += a.w[0][j] * ((double)xm[k] + (double)xp[k]);
                 ly[k] += a.w[1][j] * ((double)ym[k] + (double)yp[k]);
-                lz[k] += a.w[2][j] * ((double)zw[4 + k - j] + (double)zw[4 + k + j]);
+                lz[k] += a.w[2][j] * ((double)zw[8 + k - j] + (double)zw[8 + k + j]);
             }
         }
         double *g = a.g + off;

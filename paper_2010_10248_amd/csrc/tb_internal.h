@@ -212,7 +212,7 @@ struct ImageArgs {
     const float *c;
     double *g;
     int nx, ny, nz, nzp, r;
-    double w[3][5];  // centred second-derivative weights per axis, scaled by h^-2
+    double w[3][7];  // centred second-derivative weights per axis, scaled by h^-2
 };
 tb_status launch_residual_loss(const float *d, const float *dobs, long long n, float *res,
                                double *loss, hipStream_t st);

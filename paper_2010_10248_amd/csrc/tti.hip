@@ -23,9 +23,15 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 // Each thread takes 4 consecutive z (float4 accesses); neighbours along x and
-// y are float4 loads, neighbours along z come from the 12-value window
-// [z4-4, z4+8) of three float4 loads. Reads outside the grid give 0; the z
-// padding holds 0 in every field.
+// y are float4 loads, neighbours along z come from the window [z4-ZB,
+// z4+4+ZB) of float4 loads, ZB = 4 up to radius 4 and 8 up to radius 6.
+// Reads outside the grid give 0; the z padding holds 0 in every field.
+template <int R>
+constexpr int zspan()
+{
+    static_assert(R >= 1 && R <= 6, "radius must be 1..6");
+    return R <= 4 ? 4 : 8;
+}
 struct Site {
     int x, y, z4;
     long long off, sx, sy;
@@ -51,15 +57,14 @@ __device__ __forceinline__ f4 ld4(const float *f, long long o, bool in)
     return in ? *(const f4 *)(f + o) : f4{0.f, 0.f, 0.f, 0.f};
 }
 
-__device__ __forceinline__ void zwin(const float *f, const Site &q, int nzp, float w[12])
+template <int ZB>
+__device__ __forceinline__ void zwin(const float *f, const Site &q, int nzp, float *w)
 {
-    const f4 a = ld4(f, q.off - 4, q.z4 >= 4), b = ld4(f, q.off, true),
-             c = ld4(f, q.off + 4, q.z4 + 4 < nzp);
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-        w[k] = a[k];
-        w[4 + k] = b[k];
-        w[8 + k] = c[k];
+    for (int o = -ZB; o <= ZB; o += 4) {
+        const f4 a = ld4(f, q.off + o, q.z4 + o >= 0 && q.z4 + o < nzp);
+#pragma unroll
+        for (int k = 0; k < 4; k++) w[ZB + o + k] = a[k];
     }
 }
 
@@ -84,9 +89,10 @@ __global__ void __launch_bounds__(256) tti_rot(const TtiParams P)
 {
     Site q;
     if (!locate4(P, q)) return;
-    float zp[12], zr[12];
-    zwin(P.p, q, P.nzp, zp);
-    zwin(P.r, q, P.nzp, zr);
+    constexpr int ZB = zspan<R>();
+    float zp[4 + 2 * ZB], zr[4 + 2 * ZB];
+    zwin<ZB>(P.p, q, P.nzp, zp);
+    zwin<ZB>(P.r, q, P.nzp, zr);
     const f4 gpx = d1xy<R>(P.p, P, q, 0), gpy = d1xy<R>(P.p, P, q, 1);
     const f4 grx = d1xy<R>(P.r, P, q, 0), gry = d1xy<R>(P.r, P, q, 1);
     const f4 ax = ld4(P.ax, q.off, true), ay = ld4(P.ay, q.off, true), az = ld4(P.az, q.off, true);
@@ -96,8 +102,8 @@ __global__ void __launch_bounds__(256) tti_rot(const TtiParams P)
         float gpz = 0.0f, grz = 0.0f;
 #pragma unroll
         for (int m = 1; m <= R; m++) {
-            gpz = __builtin_fmaf(P.w1[m - 1], zp[4 + k + m] - zp[4 + k - m], gpz);
-            grz = __builtin_fmaf(P.w1[m - 1], zr[4 + k + m] - zr[4 + k - m], grz);
+            gpz = __builtin_fmaf(P.w1[m - 1], zp[ZB + k + m] - zp[ZB + k - m], gpz);
+            grz = __builtin_fmaf(P.w1[m - 1], zr[ZB + k + m] - zr[ZB + k - m], grz);
         }
         qp[k] = ax[k] * (gpx[k] * P.ih[0]) + ay[k] * (gpy[k] * P.ih[1]) + az[k] * (gpz * P.ih[2]);
         qr[k] = ax[k] * (grx[k] * P.ih[0]) + ay[k] * (gry[k] * P.ih[1]) + az[k] * (grz * P.ih[2]);
@@ -111,13 +117,14 @@ __global__ void __launch_bounds__(256) tti_update(const TtiParams P)
 {
     Site q;
     if (!locate4(P, q)) return;
-    float zp[12];
-    zwin(P.p, q, P.nzp, zp);
+    constexpr int ZB = zspan<R>();
+    float zp[4 + 2 * ZB];
+    zwin<ZB>(P.p, q, P.nzp, zp);
     // Products a_z q along z for the z part of Hz.
-    float zaz[12], zqp[12], zqr[12];
-    zwin(P.az, q, P.nzp, zaz);
-    zwin(P.qp, q, P.nzp, zqp);
-    zwin(P.qr, q, P.nzp, zqr);
+    float zaz[4 + 2 * ZB], zqp[4 + 2 * ZB], zqr[4 + 2 * ZB];
+    zwin<ZB>(P.az, q, P.nzp, zaz);
+    zwin<ZB>(P.qp, q, P.nzp, zqp);
+    zwin<ZB>(P.qr, q, P.nzp, zqr);
     f4 lx = f4{0.f, 0.f, 0.f, 0.f}, ly = lx, hpx = lx, hpy = lx, hrx = lx, hry = lx;
     const f4 pc = ld4(P.p, q.off, true);
 #pragma unroll
@@ -154,11 +161,11 @@ __global__ void __launch_bounds__(256) tti_update(const TtiParams P)
         float lz = 0.0f, hpz = 0.0f, hrz = 0.0f;
 #pragma unroll
         for (int m = 1; m <= R; m++) {
-            lz = __builtin_fmaf(P.w2[m], (zp[4 + k + m] + zp[4 + k - m]) - p2, lz);
-            hpz = __builtin_fmaf(P.w1[m - 1], zaz[4 + k + m] * zqp[4 + k + m] -
-                                                  zaz[4 + k - m] * zqp[4 + k - m], hpz);
-            hrz = __builtin_fmaf(P.w1[m - 1], zaz[4 + k + m] * zqr[4 + k + m] -
-                                                  zaz[4 + k - m] * zqr[4 + k - m], hrz);
+            lz = __builtin_fmaf(P.w2[m], (zp[ZB + k + m] + zp[ZB + k - m]) - p2, lz);
+            hpz = __builtin_fmaf(P.w1[m - 1], zaz[ZB + k + m] * zqp[ZB + k + m] -
+                                                  zaz[ZB + k - m] * zqp[ZB + k - m], hpz);
+            hrz = __builtin_fmaf(P.w1[m - 1], zaz[ZB + k + m] * zqr[ZB + k + m] -
+                                                  zaz[ZB + k - m] * zqr[ZB + k - m], hrz);
         }
         const float lap = lx[k] * P.ih2[0] + ly[k] * P.ih2[1] + lz * P.ih2[2];
         const float hzp = hpx[k] * P.ih[0] + hpy[k] * P.ih[1] + hpz * P.ih[2];
@@ -224,6 +231,9 @@ tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const lon
     } else if (r == 4) {
         hipLaunchKernelGGL(tti_rot<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
         hipLaunchKernelGGL(tti_update<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
+    } else if (r == 6) {
+        hipLaunchKernelGGL(tti_rot<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL(tti_update<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
     } else {
         set_error("TTI radius %d not built", r);
         return TB_EUNSUPPORTED;

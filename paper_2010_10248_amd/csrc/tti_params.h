@@ -15,8 +15,8 @@ struct TtiParams {
     const float *c;             // dt^2 vp^2
     const float *dx, *dy, *dz;  // damping per axis
     float hdt;                  // dt / 2
-    float w1[4];                // centred first derivative, unit spacing
-    float w2[5];                // centred second derivative, unit spacing
+    float w1[6];                // centred first derivative, unit spacing
+    float w2[7];                // centred second derivative, unit spacing
     float ih[3], ih2[3];        // 1/h and 1/h^2 per axis
     int nx, ny, nz, nzp;
 };

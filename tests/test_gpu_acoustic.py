@@ -101,6 +101,20 @@ def test_sources_on_tile_boundaries(torch_cuda, orc):
                                             ("tb", 2, 0, 40), ("tb", 2, 16, 17)])
 
 
+def test_parity_so12(torch_cuda, orc):
+    """Space order 12 (radius 6, two float4 of z neighbours on each side): a
+    ragged two-layer case with sources on the z seams of the 16-lane tiles;
+    spatial blocking and T = 2 (whose 32-row tile fits LDS only without the
+    staged lists, so the global-list kernel runs it)."""
+    s = W.acoustic_scaled(31, (57, 62, 70), 12, 50, 6, nsrc=3, nrec=16, layered=True)
+    h = s.spacing[0]
+    s.src_xyz[0] = np.array([20.5, 30.25, 47.5]) * h   # T=2 z seam (owned 48 per tile)
+    s.src_xyz[1] = np.array([36.7, 19.6, 8.2]) * h     # inside the z halo of a tile
+    s.rec_xyz[:2] = s.src_xyz[:2] + 0.3 * h
+    _check_case(torch_cuda, orc, s, scheds=[("sb", 1, 32, 0), ("sb", 1, 16, 24), ("tb", 2, 32, 0),
+                                            ("tb", 2, 32, 24), ("tb", 2, 16, 0), ("tb", 2, 0, 17)])
+
+
 def test_zero_source_is_exactly_zero(torch_cuda):
     from paper_2010_10248_amd import tb
 

@@ -28,7 +28,8 @@ def torch_cuda():
     return torch
 
 
-@pytest.mark.parametrize("so,n,nt", [(8, (40, 44, 48), 70), (4, (35, 30, 33), 60)])
+@pytest.mark.parametrize("so,n,nt", [(8, (40, 44, 48), 70), (4, (35, 30, 33), 60),
+                                     (12, (37, 42, 41), 60)])
 def test_elastic_parity_with_oracle(torch_cuda, orc, so, n, nt):
     from paper_2010_10248_amd import tb
 

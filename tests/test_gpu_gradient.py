@@ -51,7 +51,7 @@ def _dobs(orc, shot, vp_true, vmax):
     return orc.acoustic_forward(shot, vp=vp_true, vmax_damp=vmax)["traces"]
 
 
-@pytest.mark.parametrize("so,data", [(4, "zero"), (8, "zero"), (8, "blob")])
+@pytest.mark.parametrize("so,data", [(4, "zero"), (8, "zero"), (8, "blob"), (12, "zero")])
 def test_gradient_matches_oracle_and_is_schedule_independent(torch_cuda, orc, so, data):
     """d_obs = 0 (J = 1/2 |d|^2, residual = traces) at the forward tolerance;
     d_obs from a model with a +5% velocity blob at the tolerance scaled by

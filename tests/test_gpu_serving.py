@@ -151,6 +151,51 @@ def test_dense_source_request_in_mix(torch_cuda, graphs):
         p.close()
 
 
+def test_so12_request_in_mix(torch_cuda):
+    """A space-order-12 shot at T = 2 (a shape that only the global-list
+    kernel runs, so it gets launches of its own) and a gradient at space
+    order 12 served beside space-order-8 shots: bits as alone."""
+    torch = torch_cuda
+    from paper_2010_10248_amd import tb
+
+    reqs = []
+    for k, (n, nt, so, kind) in enumerate([(40, 33, 12, "fwd"), (36, 40, 8, "fwd"),
+                                           (34, 29, 12, "grad"), (44, 35, 8, "fwd")]):
+        rng = np.random.Generator(np.random.PCG64(900 + k))
+        shot, vp_true = W.serving_request(rng, sizes=(n,), nt_range=(nt, nt), so=so, nbl=5)
+        reqs.append((kind, shot, vp_true))
+    sched = tb.schedule("tb", 2, 32)
+    props, alone = _alone(torch, tb, reqs, sched)
+    sv = tb.Server(arena_bytes=4 << 30, max_active=4)
+    outs, pending = {}, {}
+    for i, (kind, shot, _) in enumerate(reqs):
+        if kind == "fwd":
+            o = torch.full((shot.nt, props[i].nrec), float("nan"), device="cuda")
+            rid = sv.submit_forward(props[i], o, sched)
+        else:
+            o = torch.full(shot.shape, float("nan"), device="cuda")
+            rid = sv.submit_gradient(props[i], alone[i][2][1], o, sched, 5)
+        outs[i] = o
+        pending[rid] = i
+    done = {}
+    it = 0
+    while len(done) < len(reqs):
+        sv.step()
+        for rid, loss in sv.poll():
+            done[pending[rid]] = loss
+        it += 1
+        assert it < 100000
+    st = sv.stats()
+    _say(f"so12 mix stats {st}")
+    sv.close()
+    for i, (kind, ref, extra) in enumerate(alone):
+        assert torch.equal(outs[i].view(torch.int32), ref.view(torch.int32)), (i, kind)
+        if kind == "grad":
+            assert done[i] == extra[0]
+    for p in props:
+        p.close()
+
+
 def test_server_rejects_oversized_request(torch_cuda):
     torch = torch_cuda
     from paper_2010_10248_amd import tb

@@ -33,7 +33,8 @@ def torch_cuda():
     return torch
 
 
-@pytest.mark.parametrize("so,n,nt", [(8, (40, 44, 48), 70), (4, (33, 30, 37), 60)])
+@pytest.mark.parametrize("so,n,nt", [(8, (40, 44, 48), 70), (4, (33, 30, 37), 60),
+                                     (12, (38, 41, 45), 60)])
 def test_tti_parity_with_oracle(torch_cuda, orc, so, n, nt):
     from paper_2010_10248_amd import tb
 

@@ -70,7 +70,8 @@ def test_fd_d2_exact_to_order(orc, so):
     assert abs(s - e) > 1e-3
 
 
-@pytest.mark.parametrize("kind,so", [("d1", 4), ("d1", 8), ("d1s", 4), ("d1s", 8)])
+@pytest.mark.parametrize("kind,so", [("d1", 4), ("d1", 8), ("d1", 12), ("d1s", 4), ("d1s", 8),
+                                     ("d1s", 12)])
 def test_fd_d1_exact_to_order(orc, kind, so):
     w = orc.weights_d1(so) if kind == "d1" else orc.weights_d1_staggered(so)
     for p in range(0, so + 1):
