@@ -183,6 +183,38 @@ def physics_bench(tb, W, torch, which, steps):
                 effective_hbm_frac=round(g * bpp / HBM_PEAK_GBS, 4), schedule="SB")
 
 
+def space_order_bench(tb, W, torch, nt):
+    """Table 1's space-order axis on the 512^3 two-layer grid: GPts/s of the
+    fastest spatially blocked schedule and of the temporally blocked ones
+    built for each order (nt steps per shot; one warm-up, one timed shot)."""
+    import numpy as np
+
+    cands = {4: [("tb", 2, 32, 64), ("tb", 3, 16, 64), ("tb", 4, 16, 64)],
+             8: [("tb", 2, 32, 64)],
+             12: [("tb", 2, 32, 64), ("tb", 2, 16, 64)]}
+    out = []
+    for so in (4, 8, 12):
+        shot = W.acoustic_two_layer(so=so, nt=nt)
+        prop = tb.Acoustic(shot)
+        N = int(np.prod(shot.shape)) * nt
+        row = dict(space_order=so, nt=nt)
+        dt, _, _, _, _, _ = time_forward(tb, prop, tb.schedule("sb", 1, 32, 128), 1, 1, torch)
+        row["sb_gpts"] = round(N / dt / 1e9, 1)
+        best = None
+        for c in cands[so]:
+            sc = tb.schedule(*c)
+            dt, _, _, _, _, _ = time_forward(tb, prop, sc, 1, 1, torch)
+            g = N / dt / 1e9
+            if best is None or g > best[0]:
+                best = (g, repr(sc))
+        row["tb_gpts"], row["tb_schedule"] = round(best[0], 1), best[1]
+        row["tb_over_sb"] = round(best[0] / row["sb_gpts"], 3)
+        prop.close()
+        log(f"space order {row}")
+        out.append(row)
+    return out
+
+
 def density_bench(tb, W, torch, counts, tb_sched, sb_sched, nt):
     """Section IV-E's source-density experiment on the 512^3 SO8 two-layer
     grid: TB and SB GPts/s with 1..many sources, uniform in the volume or on
@@ -262,6 +294,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-orders", action="store_true",
+                    help="skip the space-order sweep (SO 4, 8, 12)")
     ap.add_argument("--no-density", action="store_true",
                     help="skip the source-density sweep")
     ap.add_argument("--no-physics", action="store_true",
@@ -376,6 +410,9 @@ def main(argv=None):
                                           for k, v in errs.items()})
         log(f"parity vs FP64 oracle at {sample.nt} steps: {parity}")
 
+    orders = None
+    if not args.no_orders:
+        orders = space_order_bench(tb, W, torch, 200)
     density = None
     if not args.no_density:
         density = density_bench(tb, W, torch, (1, 64, 1024, 8192), tb_sched, sb_sched, 200)
@@ -415,6 +452,7 @@ def main(argv=None):
             "serving": serving,
             "other_physics": physics,
             "source_density": density,
+            "space_orders": orders,
         },
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -142,7 +142,7 @@ __device__ __forceinline__ void static_for(F &&f)
 // The per-point update shared by every schedule (fixed operation order), in
 // the velocity form of the leapfrog recursion, v^n = u^n - u^{n-1}:
 //   lap = sum_j wx_j ((x-j + x+j) - 2u) + (same in z) + (same in y)
-//   v'  = (c lap + beta v) / alpha       (the division only where d != 0)
+//   v'  = (c lap + beta v) / alpha
 // and then u' = u + v' (after the injection into v'). With differences from
 // the centre the Laplacian of a constant is exactly zero whatever the FP32
 // rounding of the weights, and carrying v instead of u^{n-1} keeps the
@@ -155,31 +155,12 @@ __device__ __forceinline__ void static_for(F &&f)
 // offset and the Laplacian is sum_j w_j (((x-j + x+j) + (z-j + z+j)) +
 // (y-j + y+j) - 6u): seven operations per offset instead of nine, still
 // exactly zero on a constant field (the neighbour sum and 6u round the same
-// exact value 6u).
-template <int R, bool DAMP, bool ISO>
-__device__ __forceinline__ float point_update(const AcParams &p, float ctr, const float *xm,
-                                              const float *xp, const float *ym, const float *yp,
-                                              const float *zm, const float *zp, float vold,
-                                              float cc, float d)
+// exact value 6u). The Laplacian is evaluated in the kernel body, the
+// velocity update here.
+template <bool DAMP>
+__device__ __forceinline__ float vel_update(const AcParams &p, float lap, float vold, float cc,
+                                            float d)
 {
-    float lap = 0.0f;
-    if constexpr (ISO) {
-        const float t6 = 6.0f * ctr;
-#pragma unroll
-        for (int j = 0; j < R; j++)
-            lap = __builtin_fmaf(p.wx[j], (((xm[j] + xp[j]) + (zm[j] + zp[j])) + (ym[j] + yp[j])) - t6,
-                                 lap);
-    } else {
-        // x terms (register window) first, so LDS reads of the y/z
-        // neighbours overlap with arithmetic.
-        const float t2 = 2.0f * ctr;
-#pragma unroll
-        for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wx[j], (xm[j] + xp[j]) - t2, lap);
-#pragma unroll
-        for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wz[j], (zm[j] + zp[j]) - t2, lap);
-#pragma unroll
-        for (int j = 0; j < R; j++) lap = __builtin_fmaf(p.wy[j], (ym[j] + yp[j]) - t2, lap);
-    }
     if constexpr (DAMP) {
         // 1/alpha by the hardware reciprocal (exact for alpha == 1, so an
         // undamped point gives the fast path's bits).
@@ -520,30 +501,82 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
                             zw[16 + k] = zr8[k];
                         }
                     }
-                    f4v ym[R], yp[R];
+                    // Laplacian of the 4 points, one offset at a time; per
+                    // point the operations are those of the per-point
+                    // definition above, in the same order.
+                    float lap[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    // y rows of each offset: read together up front (their LDS
+                    // latency overlaps) up to radius 4; at radius 6, where
+                    // registers are short, where they are used.
+                    constexpr bool YPRE = R <= 4;
+                    f4v yrow[YPRE ? 2 * R : 1];
+                    if constexpr (YPRE) {
 #pragma unroll
-                    for (int j = 1; j <= R; j++) {
-                        ym[j - 1] = sh[buf][s][row + R - j][zl];
-                        yp[j - 1] = sh[buf][s][row + R + j][zl];
+                        for (int j = 1; j <= R; j++) {
+                            yrow[2 * j - 2] = sh[buf][s][row + R - j][zl];
+                            yrow[2 * j - 1] = sh[buf][s][row + R + j][zl];
+                        }
+                    }
+                    auto yrows = [&](int j, f4v &ym_, f4v &yp_) {
+                        if constexpr (YPRE) {
+                            ym_ = yrow[2 * j - 2];
+                            yp_ = yrow[2 * j - 1];
+                        } else {
+                            ym_ = sh[buf][s][row + R - j][zl];
+                            yp_ = sh[buf][s][row + R + j][zl];
+                        }
+                    };
+                    if constexpr (ISO) {
+                        float t6[4];
+#pragma unroll
+                        for (int k = 0; k < 4; k++) t6[k] = 6.0f * ctr[k];
+#pragma unroll
+                        for (int j = 1; j <= R; j++) {
+                            const f4v xmj = q[s][(P + R - j) % U], xpj = q[s][(P + R + j) % U];
+                            f4v ymj, ypj;
+                            yrows(j, ymj, ypj);
+#pragma unroll
+                            for (int k = 0; k < 4; k++)
+                                lap[k] = __builtin_fmaf(
+                                    p.wx[j - 1],
+                                    (((xmj[k] + xpj[k]) + (zw[ZB + k - j] + zw[ZB + k + j])) +
+                                     (ymj[k] + ypj[k])) - t6[k],
+                                    lap[k]);
+                        }
+                    } else {
+                        float t2[4];
+#pragma unroll
+                        for (int k = 0; k < 4; k++) t2[k] = 2.0f * ctr[k];
+#pragma unroll
+                        for (int j = 1; j <= R; j++) {
+                            const f4v xmj = q[s][(P + R - j) % U], xpj = q[s][(P + R + j) % U];
+#pragma unroll
+                            for (int k = 0; k < 4; k++)
+                                lap[k] = __builtin_fmaf(p.wx[j - 1], (xmj[k] + xpj[k]) - t2[k],
+                                                        lap[k]);
+                        }
+#pragma unroll
+                        for (int j = 1; j <= R; j++)
+#pragma unroll
+                            for (int k = 0; k < 4; k++)
+                                lap[k] = __builtin_fmaf(
+                                    p.wz[j - 1], (zw[ZB + k - j] + zw[ZB + k + j]) - t2[k], lap[k]);
+#pragma unroll
+                        for (int j = 1; j <= R; j++) {
+                            f4v ymj, ypj;
+                            yrows(j, ymj, ypj);
+#pragma unroll
+                            for (int k = 0; k < 4; k++)
+                                lap[k] = __builtin_fmaf(p.wy[j - 1], (ymj[k] + ypj[k]) - t2[k],
+                                                        lap[k]);
+                        }
                     }
                     const float dxs = uniform(s_dx[cs - xlo]);
                     auto compute = [&](auto DC) {
                         constexpr bool DAMP = decltype(DC)::value;
 #pragma unroll
-                        for (int k = 0; k < 4; k++) {
-                            float xm[R], xp[R], a[R], bb[R], zm[R], zp[R];
-#pragma unroll
-                            for (int j = 1; j <= R; j++) {
-                                xm[j - 1] = q[s][(P + R - j) % U][k];
-                                xp[j - 1] = q[s][(P + R + j) % U][k];
-                                a[j - 1] = ym[j - 1][k];
-                                bb[j - 1] = yp[j - 1][k];
-                                zm[j - 1] = zw[ZB + k - j];
-                                zp[j - 1] = zw[ZB + k + j];
-                            }
-                            v[k] = point_update<R, DAMP, ISO>(p, ctr[k], xm, xp, a, bb, zm, zp,
-                                                         vold[k], cf[k], dxs + dyz[k]);
-                        }
+                        for (int k = 0; k < 4; k++)
+                            v[k] = vel_update<DAMP>(p, lap[k], vold[k], cf[k], dxs + dyz[k]);
                     };
                     if (dxs != 0.0f || wave_dyz) compute(std::true_type{});
                     else compute(std::false_type{});
