@@ -38,7 +38,9 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "oracle_tti.c", "oracle_elastic.c")]
+        if not os.path.exists(_LIB_PATH) or any(
+                os.path.getmtime(f) > os.path.getmtime(_LIB_PATH) for f in srcs if os.path.exists(f)):
             build()
         L = ctypes.CDLL(_LIB_PATH)
         c_int, c_double = ctypes.c_int, ctypes.c_double
@@ -66,6 +68,10 @@ def lib():
             L.or_tti_forward.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int,
                                          _dp, _dp, _dp, _dp, _dp, c_double,
                                          c_int, _dp, _dp, c_int, _dp, vp, vp, vp, vp, vp]
+        if hasattr(L, "or_tti_adjoint"):
+            L.or_tti_adjoint.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int,
+                                         _dp, _dp, _dp, _dp, _dp, c_double,
+                                         c_int, _dp, c_int, _dp, _dp, vp]
         if hasattr(L, "or_tti_operators"):
             L.or_tti_operators.argtypes = [_ip, _dp, c_int, _dp, _dp, _dp, vp, vp]
         if hasattr(L, "or_elastic_forward"):
@@ -248,6 +254,22 @@ def tti_forward(shot, vp=None, vmax_damp: float = 0.0, src_wav=None, epsilon=Non
                               _ptr(out["r_last"]), _ptr(out["r_prev"]))
     _check(st, "tti_forward")
     return out
+
+
+def tti_adjoint(shot, res: np.ndarray, vmax_damp: float = 0.0):
+    """Adjoint of the TTI map q -> d driven by ``res[nt][nrec]``; returns
+    qhat[nt][nsrc]."""
+    n = np.asarray(shot.shape, dtype=np.int32)
+    sx = _f64(shot.src_xyz)
+    rx = _f64(shot.rec_xyz)
+    qhat = np.zeros((shot.nt, sx.shape[0]))
+    st = lib().or_tti_adjoint(n, _f64(shot.spacing), _f64(shot.origin), shot.space_order,
+                              shot.nbl, float(shot.dt), shot.nt, _f64(shot.vp),
+                              _f64(shot.epsilon), _f64(shot.delta), _f64(shot.theta),
+                              _f64(shot.phi), float(vmax_damp), sx.shape[0], sx, rx.shape[0], rx,
+                              _f64(res), _ptr(qhat))
+    _check(st, "tti_adjoint")
+    return qhat
 
 
 def tti_operators(u, spacing, so: int, theta, phi):

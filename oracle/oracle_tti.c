@@ -272,3 +272,126 @@ done:
     free(buf);
     return st;
 }
+
+/*
+ * Exact discrete adjoint of the linear map q -> d of or_tti_forward. With
+ * w = (p, r), the forward is
+ *   w^k = (c/alpha) A w^{k-1} + (2/alpha) w^{k-1} - (beta/alpha) w^{k-2} + s^{k-1},
+ *   A = [[e H0, s Hz], [s H0, Hz]] = D H,  D = [[e, s], [s, 1]] per node,
+ *   H = diag(H0, Hz),  s^n = c P_s^T q^n added to both fields,  d^k = P_r p^k,
+ * with e = 1 + 2 eps, s = sqrt(1 + 2 min(del, eps)). H0 and Hz are symmetric
+ * (Hz = -D^T D with zero outside the grid; L symmetric), so A^T = H D, and
+ * the multiplier obeys, backwards from lambda^{nt} = lambda^{nt+1} = 0,
+ *   y = (c/alpha) lambda^{k+1}
+ *   lambda^k = H (D y) + (2/alpha) lambda^{k+1} - (beta/alpha) lambda^{k+2}
+ *              + (P_r^T res^k, 0),                           k = nt-1 .. 0,
+ * and the adjoint of the source map is
+ *   qhat_s^n = P_s (c (lambda_p^{n+1} + lambda_r^{n+1})).
+ * res[nt][nrec] is any data-space vector; output qhat[nt][nsrc].
+ */
+int or_tti_adjoint(const int *n, const double *h, const double *o, int so, int nbl, double dt,
+                   int nt, const double *vp, const double *eps, const double *del,
+                   const double *theta, const double *phi, double vmax_damp, int nsrc,
+                   const double *src_xyz, int nrec, const double *rec_xyz, const double *res,
+                   double *qhat)
+{
+    tgrid G;
+    int st = tgrid_init(&G, n, h, so);
+    if (st) return st;
+    const i64 N = (i64)n[0] * n[1] * n[2];
+    const int NB = 18;
+    double *buf = calloc((size_t)NB * N, sizeof(double));
+    if (!buf) return OR_ENOMEM;
+    double *ax = buf, *ay = buf + N, *az = buf + 2 * N;
+    double *c = buf + 3 * N, *alpha = buf + 4 * N, *beta = buf + 5 * N;
+    double *e1 = buf + 6 * N, *sd = buf + 7 * N;
+    double *p0 = buf + 8 * N, *p1 = buf + 9 * N, *p2 = buf + 10 * N; /* lambda_p k+2, k+1, k */
+    double *r0 = buf + 11 * N, *r1 = buf + 12 * N, *r2 = buf + 13 * N;
+    double *zp = buf + 14 * N, *zr = buf + 15 * N, *hzp = buf + 16 * N, *hzr = buf + 17 * N;
+    double *wx = malloc(sizeof(double) * 3 * N);
+    if (!wx) {
+        free(buf);
+        return OR_ENOMEM;
+    }
+    double *wy = wx + N, *wz = wx + 2 * N;
+    axis_of(theta, phi, N, ax, ay, az);
+    double vmax = vmax_damp;
+    if (!(vmax > 0.0)) {
+        vmax = 0.0;
+        for (i64 q = 0; q < N; q++)
+            if (vp[q] > vmax) vmax = vp[q];
+    }
+    or_damping(n, h, nbl, vmax, alpha); /* alpha holds d for now */
+    for (i64 q = 0; q < N; q++) {
+        const double d = alpha[q];
+        c[q] = dt * dt * vp[q] * vp[q];
+        alpha[q] = 1.0 + d * dt / 2.0;
+        beta[q] = 1.0 - d * dt / 2.0;
+        const double dl = del[q] < eps[q] ? del[q] : eps[q];
+        e1[q] = 1.0 + 2.0 * eps[q];
+        sd[q] = sqrt(1.0 + 2.0 * dl);
+    }
+    if (qhat) memset(qhat, 0, sizeof(double) * (size_t)nt * nsrc);
+    for (int k = nt - 1; k >= 0; k--) {
+        /* qhat^k from lambda^{k+1}. */
+        for (int s = 0; qhat && s < nsrc; s++) {
+            int nodes[24];
+            double w[8];
+            int cnt = or_trilinear(src_xyz + 3 * s, o, G.h, G.n, nodes, w);
+            if (cnt < 0) {
+                st = cnt;
+                goto done;
+            }
+            double acc = 0.0;
+            for (int q = 0; q < cnt; q++) {
+                const i64 qi = ((i64)nodes[3 * q] * n[1] + nodes[3 * q + 1]) * n[2] +
+                               nodes[3 * q + 2];
+                acc += w[q] * c[qi] * (p1[qi] + r1[qi]);
+            }
+            qhat[(i64)k * nsrc + s] = acc;
+        }
+        /* D y with y = (c/alpha) lambda^{k+1}. */
+        for (i64 q = 0; q < N; q++) {
+            const double yp = c[q] / alpha[q] * p1[q], yr = c[q] / alpha[q] * r1[q];
+            zp[q] = e1[q] * yp + sd[q] * yr;
+            zr[q] = sd[q] * yp + yr;
+        }
+        apply_hz(&G, ax, ay, az, zp, hzp, wx, wy, wz);
+        apply_hz(&G, ax, ay, az, zr, hzr, wx, wy, wz);
+#pragma omp parallel for schedule(static)
+        for (i64 i = 0; i < n[0]; i++)
+            for (i64 j = 0; j < n[1]; j++)
+                for (i64 kk = 0; kk < n[2]; kk++) {
+                    const i64 q = (i * n[1] + j) * n[2] + kk;
+                    const double h0 = lap(&G, zp, i, j, kk) - hzp[q];
+                    p2[q] = h0 + (2.0 * p1[q] - beta[q] * p0[q]) / alpha[q];
+                    r2[q] = hzr[q] + (2.0 * r1[q] - beta[q] * r0[q]) / alpha[q];
+                }
+        /* Residual: (P_r^T res^k) into the p component. */
+        for (int rr = 0; rr < nrec; rr++) {
+            int nodes[24];
+            double w[8];
+            int cnt = or_trilinear(rec_xyz + 3 * rr, o, G.h, G.n, nodes, w);
+            if (cnt < 0) {
+                st = cnt;
+                goto done;
+            }
+            const double rv = res[(i64)k * nrec + rr];
+            for (int q = 0; q < cnt; q++)
+                p2[((i64)nodes[3 * q] * n[1] + nodes[3 * q + 1]) * n[2] + nodes[3 * q + 2]] +=
+                    w[q] * rv;
+        }
+        double *tp = p0;
+        p0 = p1;
+        p1 = p2;
+        p2 = tp;
+        tp = r0;
+        r0 = r1;
+        r1 = r2;
+        r2 = tp;
+    }
+done:
+    free(wx);
+    free(buf);
+    return st;
+}

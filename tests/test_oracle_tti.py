@@ -124,3 +124,54 @@ def test_elliptic_kinematics(orc):
         t_pk = (i + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)) * dt
         want = t0 + R * math.sqrt(math.sin(psi) ** 2 / vx ** 2 + math.cos(psi) ** 2 / vp ** 2)
         assert abs(t_pk - want) <= 0.01 * (want - t0), (psi, t_pk, want)
+
+
+# --------------------------------------------------------------------------
+# Adjoint of the TTI map q -> d (or_tti_adjoint): the dot-product identity
+# against the oracle's own forward, with smooth random eps, delta, tilt and
+# azimuth (delta equal to eps somewhere, so the coupling matrix is singular
+# at some nodes), damping on, SO4 and SO8; a one-sample time shift and a
+# different coupling both break it.
+# --------------------------------------------------------------------------
+def _tti_adj_shot(so, seed=41):
+    return W.tti_smooth(seed=seed, n=(20, 22, 24), so=so, nt=40, nbl=4, nsrc=2, nrec=6,
+                        sigma=3.0)
+
+
+@pytest.mark.parametrize("so", [4, 8])
+def test_tti_adjoint_dot_product(orc, so):
+    s = _tti_adj_shot(so)
+    # delta = eps at some nodes (where the drawn delta exceeded eps), which
+    # makes the coupling matrix D singular there.
+    assert np.any(s.delta == s.epsilon)
+    rng = np.random.Generator(np.random.PCG64(7))
+    q = rng.standard_normal(s.src_wav.shape)
+    dp = rng.standard_normal((s.nt, s.rec_xyz.shape[0]))
+    Fq = orc.tti_forward(s, src_wav=q)["traces"]
+    FTd = orc.tti_adjoint(s, dp)
+    lhs = float(np.sum(Fq * dp))
+    rhs = float(np.sum(q * FTd))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), abs(rhs)), (lhs, rhs)
+    assert np.all(FTd[-1] == 0.0)
+    # Control: a one-sample shift of the adjoint output breaks the identity.
+    shifted = float(np.sum(q[1:] * FTd[:-1]))
+    assert abs(lhs - shifted) > 1e-3 * abs(lhs)
+
+
+def test_tti_adjoint_detects_untransposed_coupling(orc):
+    """The coupling matrix is not symmetric as an operator (A = D H, A^T =
+    H D): the adjoint of a model whose s field is replaced by the e field
+    (a different D) must fail the identity against the original forward, so
+    the test sees the coupling."""
+    s = _tti_adj_shot(8, seed=43)
+    rng = np.random.Generator(np.random.PCG64(8))
+    q = rng.standard_normal(s.src_wav.shape)
+    dp = rng.standard_normal((s.nt, s.rec_xyz.shape[0]))
+    Fq = orc.tti_forward(s, src_wav=q)["traces"]
+    lhs = float(np.sum(Fq * dp))
+    import copy
+
+    s2 = copy.copy(s)
+    s2.delta = np.zeros_like(s.delta)
+    FTd2 = orc.tti_adjoint(s2, dp)
+    assert abs(lhs - float(np.sum(q * FTd2))) > 1e-4 * abs(lhs)
