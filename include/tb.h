@@ -190,10 +190,16 @@ tb_status tb_forward(const tb_model *m, const tb_sparse *s, const tb_schedule *s
                      void *stream);
 
 /*
- * Exact discrete adjoint of the linear map q -> d of tb_forward (the same
- * update run backward in time, driven by rec_in[nt][nrec] at the receiver
- * points). Output src_out[nt][nsrc] (device). Used for the dot-product test
- * and for imaging. Acoustic only.
+ * Exact discrete adjoint of the linear map q -> d of tb_forward, driven by
+ * rec_in[nt][nrec] at the receiver points; output src_out[nt][nsrc] (device).
+ * Used for the dot-product test and for imaging. Acoustic: the forward update
+ * run backward in time in the scaled multiplier c lambda / alpha (any
+ * schedule). TTI (spatially blocked): the multiplier recursion with the
+ * transposed coupling, lambda^k = H D (c/alpha) lambda^{k+1} + (2/alpha)
+ * lambda^{k+1} - (beta/alpha) lambda^{k+2} + (P_r^T rec_in^k, 0), H =
+ * diag(H0, Hz), D = [[1+2 eps, s], [s, 1]] (the forward couples through D H),
+ * and src_out^n = P_s (c (lambda_p + lambda_r)^{n+1}). Elastic returns
+ * TB_EUNSUPPORTED.
  */
 tb_status tb_adjoint(const tb_model *m, const tb_sparse *s, const tb_schedule *sched, void *ws,
                      size_t ws_bytes, const float *rec_in, float *src_out, void *stream);

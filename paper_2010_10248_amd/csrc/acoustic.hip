@@ -39,7 +39,8 @@ __global__ void unpad_kernel(const float *__restrict__ src, float *__restrict__ 
     dst[g] = src[xy * nzp + zz];
 }
 
-// Adjoint source term: dcmp_out[tau][rid] = scale[rid] * sum W res[nt-1-tau][rec].
+// Adjoint source term: dcmp_out[tau][rid] = scale[rid] * sum W res[nt-1-tau][rec]
+// (scale 1 where rid_scale is NULL).
 __global__ void adj_inject_kernel(const float *__restrict__ res, int nt, int nrec, int nrid,
                                   const int *__restrict__ rr_ptr, const int *__restrict__ rr_rec,
                                   const float *__restrict__ rr_w,
@@ -52,7 +53,7 @@ __global__ void adj_inject_kernel(const float *__restrict__ res, int nt, int nre
     float acc = 0.0f;
     for (int k = rr_ptr[rid]; k < rr_ptr[rid + 1]; k++)
         acc = __builtin_fmaf(rr_w[k], rv[rr_rec[k]], acc);
-    dcmp_out[g] = rid_scale[rid] * acc;
+    dcmp_out[g] = rid_scale ? rid_scale[rid] * acc : acc;
 }
 
 }  // namespace

@@ -384,19 +384,10 @@ size_t forward_ws_bytes(const tb_model *m, const tb_sparse *s)
 
 namespace {
 
-// TTI forward (SB): p (two levels), r (two levels), w_p, w_r, q_p, q_r, then
-// rec_dcmp.
-tb_status plan_forward_tti(const tb_model *m, tb_sparse *s, void *ws, float *rec_out,
-                           float *field_out, float *field_prev_out, Plan *plan)
+// Model part of the TTI kernel parameters (forward and adjoint).
+TtiParams tti_params(const tb_model *m)
 {
-    const size_t fb = field_bytes(m), fe = m->field_elems();
-    char *base = (char *)ws;
-    float *F[8];
-    for (int k = 0; k < 8; k++) F[k] = (float *)(base + k * fb);
-    float *rec = (float *)(base + 8 * fb);
-    for (int k = 0; k < 8; k++) plan->push_back(fill_item(F[k], fe));
-    const int nrid = s->nrid, npts = s->npts, nt = m->nt;
-    if (nrid > 0) plan->push_back(fill_item(rec, (size_t)nrid));
+    const size_t fe = m->field_elems();
     TtiParams P{};
     P.ax = m->d_tti;
     P.ay = m->d_tti + fe;
@@ -421,6 +412,23 @@ tb_status plan_forward_tti(const tb_model *m, tb_sparse *s, void *ws, float *rec
     P.ny = m->n[1];
     P.nz = m->n[2];
     P.nzp = m->nzp;
+    return P;
+}
+
+// TTI forward (SB): p (two levels), r (two levels), w_p, w_r, q_p, q_r, then
+// rec_dcmp.
+tb_status plan_forward_tti(const tb_model *m, tb_sparse *s, void *ws, float *rec_out,
+                           float *field_out, float *field_prev_out, Plan *plan)
+{
+    const size_t fb = field_bytes(m), fe = m->field_elems();
+    char *base = (char *)ws;
+    float *F[8];
+    for (int k = 0; k < 8; k++) F[k] = (float *)(base + k * fb);
+    float *rec = (float *)(base + 8 * fb);
+    for (int k = 0; k < 8; k++) plan->push_back(fill_item(F[k], fe));
+    const int nrid = s->nrid, npts = s->npts, nt = m->nt;
+    if (nrid > 0) plan->push_back(fill_item(rec, (size_t)nrid));
+    TtiParams P = tti_params(m);
     P.vp = F[4];
     P.vr = F[5];
     P.qp = F[6];
@@ -754,6 +762,57 @@ tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, 
 }
 
 // Adjoint time loop (tb_adjoint): nt updates from zero state in F[0..3].
+// Adjoint of the TTI map q -> d (spatially blocked), backwards in time from
+// lambda = psi = 0: the decomposed residual of each step enters the p
+// component; the source-point samples c (lambda_p + lambda_r)^{k+1} / alpha,
+// reduced with the weights W alpha, give qhat^k.
+tb_status tti_adjoint(const tb_model *m, tb_sparse *s, void *ws, const float *rec_in,
+                      float *src_out, hipStream_t strm)
+{
+    const size_t fb = field_bytes(m), fe = m->field_elems();
+    const size_t nt1 = (size_t)m->nt + 1;
+    const int nt = m->nt, npts = s->npts, nrid = s->nrid;
+    char *base = (char *)ws;
+    float *F[10];
+    for (int k = 0; k < 10; k++) F[k] = (float *)(base + k * fb);
+    float *srec = (float *)(base + 10 * fb);
+    float *adj = (float *)(base + 10 * fb + align256(nt1 * std::max(npts, 1) * sizeof(float)));
+    tb_status st;
+    for (int k = 0; k < 10; k++)
+        if ((st = launch_fill(F[k], fe, 0.0f, strm))) return st;
+    if (nrid > 0 && nt > 0)
+        if ((st = launch_adj_inject(rec_in, nt, s->nrec, nrid, s->d_rr_ptr, s->d_rr_rec,
+                                    s->d_rr_w, nullptr, adj, strm)))
+            return st;
+    TtiParams P = tti_params(m);
+    P.vp = F[4];
+    P.vr = F[5];
+    P.zp = F[6];
+    P.zr = F[7];
+    P.p = F[6];
+    P.r = F[7];
+    P.qp = F[8];
+    P.qr = F[9];
+    int lc = 0, ln = 1;  // lambda_p^{k+1} in F[lc], lambda_r^{k+1} in F[lc + 2]
+    for (int tau = 0; tau < nt; tau++) {
+        TtiParams Q = P;
+        Q.lp = F[lc];
+        Q.lr = F[lc + 2];
+        Q.pn = F[ln];
+        Q.rn = F[ln + 2];
+        if ((st = launch_tti_adjoint_step(Q, m->r, adj + (size_t)tau * std::max(nrid, 1),
+                                          s->d_rid_off, nrid, srec + (size_t)tau * npts,
+                                          s->d_src_off, s->d_src_alpha, npts, strm)))
+            return st;
+        std::swap(lc, ln);
+    }
+    if (src_out && s->nsrc > 0 && nt > 0)
+        if ((st = launch_trace_reduce(srec, npts, nt, s->d_sc_ptr, s->d_sc_id, s->d_sc_w, s->nsrc,
+                                      src_out, 1, strm)))
+            return st;
+    return TB_OK;
+}
+
 tb_status time_loop(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int adjoint,
                     float *F[4], const float *dcmp, int ninj, float *rec_dcmp, int nrecp,
                     hipStream_t st)
@@ -1120,7 +1179,11 @@ tb_status tb_workspace_size(const tb_model *m, const tb_sparse *s, const tb_sche
         *bytes = forward_ws_bytes(m, s);
         return TB_OK;
     case TB_OP_ADJOINT:
-        *bytes = 4 * fb + align256(nt1 * std::max(s->npts, 1) * sizeof(float)) +
+        // Acoustic: u, v (two levels each); TTI: lambda_p, lambda_r (two
+        // levels each), psi_p, psi_r, z_p, z_r, q_p, q_r. Then the samples at
+        // the source points and the decomposed residual.
+        *bytes = (m->physics == TB_TTI ? 10 : 4) * fb +
+                 align256(nt1 * std::max(s->npts, 1) * sizeof(float)) +
                  align256((size_t)m->nt * std::max(s->nrid, 1) * sizeof(float));
         return TB_OK;
     case TB_OP_GRADIENT:
@@ -1163,8 +1226,8 @@ tb_status tb_adjoint(const tb_model *m, const tb_sparse *s_, const tb_schedule *
         set_error("tb_adjoint: invalid argument");
         return TB_EINVAL;
     }
-    if (m->physics != TB_ACOUSTIC) {
-        set_error("the adjoint is built for the acoustic propagator only");
+    if (m->physics == TB_ELASTIC) {
+        set_error("the adjoint is built for the acoustic and TTI propagators only");
         return TB_EUNSUPPORTED;
     }
     SchedChoice sc;
@@ -1177,6 +1240,7 @@ tb_status tb_adjoint(const tb_model *m, const tb_sparse *s_, const tb_schedule *
         return TB_EWORKSPACE;
     }
     hipStream_t strm = (hipStream_t)stream;
+    if (m->physics == TB_TTI) return tti_adjoint(m, s, ws, rec_in, src_out, strm);
     const size_t fb = field_bytes(m);
     const size_t nt1 = (size_t)m->nt + 1;
     char *base = (char *)ws;

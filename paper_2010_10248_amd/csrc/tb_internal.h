@@ -199,6 +199,7 @@ tb_status launch_trace_reduce(const float *rec_dcmp, int nrid, int nt, const int
                               int reverse, hipStream_t st);
 tb_status launch_unpad(const float *src, float *dst, int nx, int ny, int nz, int nzp,
                        hipStream_t st);
+// rid_scale NULL: unit scale.
 tb_status launch_adj_inject(const float *res, int nt, int nrec, int nrid, const int *rr_ptr,
                             const int *rr_rec, const float *rr_w, const float *rid_scale,
                             float *dcmp_out, hipStream_t st);

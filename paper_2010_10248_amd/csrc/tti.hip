@@ -112,7 +112,10 @@ __global__ void __launch_bounds__(256) tti_rot(const TtiParams P)
     *(f4 *)(P.qr + q.off) = qr;
 }
 
-template <int R>
+// ADJ: the adjoint update. The operator input (p, r) is then the mixed
+// field z; the rates are psi = (H0 z_p, Hz z_r) + (beta/alpha) psi, and the
+// levels advance from lambda^{k+1} (lp, lr).
+template <int R, bool ADJ>
 __global__ void __launch_bounds__(256) tti_update(const TtiParams P)
 {
     Site q;
@@ -151,8 +154,11 @@ __global__ void __launch_bounds__(256) tti_update(const TtiParams P)
             hry[k] = __builtin_fmaf(w1, ayp[k] * qryp[k] - aym[k] * qrym[k], hry[k]);
         }
     }
-    const f4 rc = ld4(P.r, q.off, true);
-    const f4 e1 = ld4(P.e1, q.off, true), sd = ld4(P.sd, q.off, true), cc = ld4(P.c, q.off, true);
+    const f4 zero = f4{0.f, 0.f, 0.f, 0.f};
+    const f4 rc = ADJ ? ld4(P.lr, q.off, true) : ld4(P.r, q.off, true);
+    const f4 lpc = ADJ ? ld4(P.lp, q.off, true) : pc;
+    const f4 e1 = ADJ ? zero : ld4(P.e1, q.off, true), sd = ADJ ? zero : ld4(P.sd, q.off, true),
+             cc = ADJ ? zero : ld4(P.c, q.off, true);
     f4 vp = ld4(P.vp, q.off, true), vr = ld4(P.vr, q.off, true), pn, rn;
     const float dxy = P.dx[q.x] + P.dy[q.y];
 #pragma unroll
@@ -171,21 +177,27 @@ __global__ void __launch_bounds__(256) tti_update(const TtiParams P)
         const float hzp = hpx[k] * P.ih[0] + hpy[k] * P.ih[1] + hpz * P.ih[2];
         const float hzr = hrx[k] * P.ih[0] + hry[k] * P.ih[1] + hrz * P.ih[2];
         const float h0p = lap - hzp;
-        const float rhs_p = __builtin_fmaf(e1[k], h0p, sd[k] * hzr);
-        const float rhs_r = __builtin_fmaf(sd[k], h0p, hzr);
         const int z = q.z4 + k;
         const float d = dxy + (z < P.nz ? P.dz[z] : 0.0f);
         const float dd = d * P.hdt;
         const float beta = 1.0f - dd;
-        float wp = __builtin_fmaf(cc[k], rhs_p, beta * vp[k]);
-        float wr = __builtin_fmaf(cc[k], rhs_r, beta * vr[k]);
-        if (d != 0.0f) {
-            wp = wp / (1.0f + dd);
-            wr = wr / (1.0f + dd);
+        float wp, wr;
+        if constexpr (ADJ) {
+            wp = d != 0.0f ? __builtin_fmaf(beta / (1.0f + dd), vp[k], h0p) : h0p + vp[k];
+            wr = d != 0.0f ? __builtin_fmaf(beta / (1.0f + dd), vr[k], hzr) : hzr + vr[k];
+        } else {
+            const float rhs_p = __builtin_fmaf(e1[k], h0p, sd[k] * hzr);
+            const float rhs_r = __builtin_fmaf(sd[k], h0p, hzr);
+            wp = __builtin_fmaf(cc[k], rhs_p, beta * vp[k]);
+            wr = __builtin_fmaf(cc[k], rhs_r, beta * vr[k]);
+            if (d != 0.0f) {
+                wp = wp / (1.0f + dd);
+                wr = wr / (1.0f + dd);
+            }
         }
         vp[k] = wp;
         vr[k] = wr;
-        pn[k] = pc[k] + wp;
+        pn[k] = lpc[k] + wp;
         rn[k] = rc[k] + wr;
     }
     *(f4 *)(P.vp + q.off) = vp;
@@ -215,6 +227,53 @@ __global__ void tti_record(const float *__restrict__ p, float *__restrict__ rec_
     if (i < nrid) rec_row[i] = p[roff[i]];
 }
 
+// z = (c/alpha) D lambda with D = [[1+2 eps, s], [s, 1]] per node.
+__global__ void __launch_bounds__(256) tti_adj_mix(const TtiParams P)
+{
+    Site q;
+    if (!locate4(P, q)) return;
+    const f4 lp = ld4(P.lp, q.off, true), lr = ld4(P.lr, q.off, true);
+    const f4 cc = ld4(P.c, q.off, true), e1 = ld4(P.e1, q.off, true), sd = ld4(P.sd, q.off, true);
+    const float dxy = P.dx[q.x] + P.dy[q.y];
+    f4 zp, zr;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int z = q.z4 + k;
+        const float d = dxy + (z < P.nz ? P.dz[z] : 0.0f);
+        const float ca = d != 0.0f ? cc[k] / (1.0f + d * P.hdt) : cc[k];
+        const float yp = ca * lp[k], yr = ca * lr[k];
+        zp[k] = __builtin_fmaf(e1[k], yp, sd[k] * yr);
+        zr[k] = __builtin_fmaf(sd[k], yp, yr);
+    }
+    *(f4 *)(P.zp + q.off) = zp;
+    *(f4 *)(P.zr + q.off) = zr;
+}
+
+// The residual enters the p component of lambda and of its rate.
+__global__ void tti_adj_inject(float *__restrict__ lam, float *__restrict__ rate,
+                               const float *__restrict__ inc, const long long *__restrict__ off,
+                               int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const long long o = off[i];
+        lam[o] += inc[i];
+        rate[o] += inc[i];
+    }
+}
+
+// c (lambda_p + lambda_r) / alpha at the source points.
+__global__ void tti_adj_record(const float *__restrict__ lp, const float *__restrict__ lr,
+                               const float *__restrict__ c, const long long *__restrict__ off,
+                               const double *__restrict__ alpha, int n, float *__restrict__ row)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const long long o = off[i];
+        row[i] = (float)((double)c[o] * ((double)lp[o] + (double)lr[o]) / alpha[i]);
+    }
+}
+
 unsigned nblocks(long long n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -227,13 +286,13 @@ tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const lon
     if (total == 0) return TB_OK;
     if (r == 2) {
         hipLaunchKernelGGL(tti_rot<2>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL(tti_update<2>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<2, false>), dim3(nblocks(total)), dim3(256), 0, st, P);
     } else if (r == 4) {
         hipLaunchKernelGGL(tti_rot<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL(tti_update<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<4, false>), dim3(nblocks(total)), dim3(256), 0, st, P);
     } else if (r == 6) {
         hipLaunchKernelGGL(tti_rot<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL(tti_update<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<6, false>), dim3(nblocks(total)), dim3(256), 0, st, P);
     } else {
         set_error("TTI radius %d not built", r);
         return TB_EUNSUPPORTED;
@@ -247,6 +306,41 @@ tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const lon
     if (nrid > 0) {
         hipLaunchKernelGGL(tti_record, dim3(nblocks(nrid)), dim3(256), 0, st, P.pn, rec_row, roff,
                            nrid);
+        TB_HIP(hipGetLastError());
+    }
+    return TB_OK;
+}
+
+tb_status launch_tti_adjoint_step(const TtiParams &P, int r, const float *inc,
+                                  const long long *roff, int nrid, float *src_row,
+                                  const long long *soff, const double *src_alpha, int npts,
+                                  hipStream_t st)
+{
+    const long long total = (long long)P.nx * P.ny * (P.nzp / 4);
+    if (total == 0) return TB_OK;
+    if (npts > 0) {
+        hipLaunchKernelGGL(tti_adj_record, dim3(nblocks(npts)), dim3(256), 0, st, P.lp, P.lr, P.c,
+                           soff, src_alpha, npts, src_row);
+        TB_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(tti_adj_mix, dim3(nblocks(total)), dim3(256), 0, st, P);
+    if (r == 2) {
+        hipLaunchKernelGGL(tti_rot<2>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<2, true>), dim3(nblocks(total)), dim3(256), 0, st, P);
+    } else if (r == 4) {
+        hipLaunchKernelGGL(tti_rot<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<4, true>), dim3(nblocks(total)), dim3(256), 0, st, P);
+    } else if (r == 6) {
+        hipLaunchKernelGGL(tti_rot<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<6, true>), dim3(nblocks(total)), dim3(256), 0, st, P);
+    } else {
+        set_error("TTI radius %d not built", r);
+        return TB_EUNSUPPORTED;
+    }
+    TB_HIP(hipGetLastError());
+    if (nrid > 0) {
+        hipLaunchKernelGGL(tti_adj_inject, dim3(nblocks(nrid)), dim3(256), 0, st, P.pn, P.vp, inc,
+                           roff, nrid);
         TB_HIP(hipGetLastError());
     }
     return TB_OK;

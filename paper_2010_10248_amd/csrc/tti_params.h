@@ -19,6 +19,10 @@ struct TtiParams {
     float w2[7];                // centred second derivative, unit spacing
     float ih[3], ih2[3];        // 1/h and 1/h^2 per axis
     int nx, ny, nz, nzp;
+    // Adjoint step only: lambda^{k+1} (lp, lr) and the mixed fields
+    // z = (c/alpha) D lambda^{k+1} (zp, zr), which p and r then point to.
+    const float *lp, *lr;
+    float *zp, *zr;
 };
 
 // One step: rotated gradients, coupled update (velocity form), injection of
@@ -27,5 +31,19 @@ struct TtiParams {
 tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const long long *soff,
                           int npts, float *rec_row, const long long *roff, int nrid,
                           hipStream_t st);
+
+// One step of the adjoint of q -> d, backwards: lambda^{k+1} in (P.lp, P.lr),
+// psi^{k+1} = lambda^{k+1} - lambda^{k+2} in (P.vp, P.vr) (updated in place
+// to psi^k), lambda^k into (P.pn, P.rn). First src_row[npts] receives
+// c (lambda_p + lambda_r)^{k+1} / alpha at the source points (soff, alpha per
+// point), then z = (c/alpha) D lambda^{k+1} goes to (P.zp, P.zr), and
+//   psi^k = H z + (beta/alpha) psi^{k+1} + (P_r^T res^k, 0),
+//   lambda^k = lambda^{k+1} + psi^k,
+// with H = diag(L - Hz, Hz) and res^k decomposed at the receiver points as
+// inc[nrid] (added at roff).
+tb_status launch_tti_adjoint_step(const TtiParams &P, int r, const float *inc,
+                                  const long long *roff, int nrid, float *src_row,
+                                  const long long *soff, const double *src_alpha, int npts,
+                                  hipStream_t st);
 
 }  // namespace tbw

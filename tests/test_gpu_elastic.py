@@ -61,6 +61,9 @@ def test_elastic_zero_source_and_unsupported_paths(torch_cuda):
     with pytest.raises(tb.TbError) as e:
         prop.forward(tb.schedule("tb", 2, 32))
     assert e.value.status == tb.EUNSUPPORTED
+    with pytest.raises(tb.TbError) as e:
+        prop.adjoint(torch.zeros((s.nt, s.rec_xyz.shape[0]), device="cuda"))
+    assert e.value.status == tb.EUNSUPPORTED
     prop.close()
 
 
