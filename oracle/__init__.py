@@ -67,11 +67,12 @@ def lib():
         if hasattr(L, "or_tti_forward"):
             L.or_tti_forward.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int,
                                          _dp, _dp, _dp, _dp, _dp, c_double,
-                                         c_int, _dp, _dp, c_int, _dp, vp, vp, vp, vp, vp]
+                                         c_int, _dp, _dp, c_int, _dp, vp, vp, vp, vp, vp,
+                                         vp, vp]
         if hasattr(L, "or_tti_adjoint"):
             L.or_tti_adjoint.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int,
                                          _dp, _dp, _dp, _dp, _dp, c_double,
-                                         c_int, _dp, c_int, _dp, _dp, vp]
+                                         c_int, _dp, vp, c_int, _dp, _dp, vp, vp, vp, vp]
         if hasattr(L, "or_tti_operators"):
             L.or_tti_operators.argtypes = [_ip, _dp, c_int, _dp, _dp, _dp, vp, vp]
         if hasattr(L, "or_elastic_forward"):
@@ -233,9 +234,10 @@ def acoustic_gradient(shot, dobs: np.ndarray, vp=None, vmax_damp: float = 0.0):
 
 
 def tti_forward(shot, vp=None, vmax_damp: float = 0.0, src_wav=None, epsilon=None, delta=None,
-                theta=None, phi=None):
+                theta=None, phi=None, want_history: bool = False):
     """FP64 pseudo-acoustic TTI forward of a ``workloads.Shot`` (zero initial
-    state). Returns dict(traces[nt][nrec] of p, p_last, p_prev, r_last, r_prev)."""
+    state). Returns dict(traces[nt][nrec] of p, p_last, p_prev, r_last, r_prev
+    and, with want_history, p_hist, r_hist [nt][N] (levels 0..nt-1))."""
     n = np.asarray(shot.shape, dtype=np.int32)
     f = lambda a, b: _f64(b if a is None else a)
     vp = f(vp, shot.vp)
@@ -247,29 +249,48 @@ def tti_forward(shot, vp=None, vmax_damp: float = 0.0, src_wav=None, epsilon=Non
     out = dict(traces=np.zeros((shot.nt, rx.shape[0])))
     for k in ("p_last", "p_prev", "r_last", "r_prev"):
         out[k] = np.zeros(shot.shape)
+    ph_, rh_ = None, None
+    if want_history:
+        ph_ = out["p_hist"] = np.zeros((shot.nt,) + tuple(shot.shape))
+        rh_ = out["r_hist"] = np.zeros((shot.nt,) + tuple(shot.shape))
     st = lib().or_tti_forward(n, _f64(shot.spacing), _f64(shot.origin), shot.space_order,
                               shot.nbl, float(shot.dt), shot.nt, vp, eps, dl, th, ph,
                               float(vmax_damp), sx.shape[0], sx, wav, rx.shape[0], rx,
                               _ptr(out["traces"]), _ptr(out["p_last"]), _ptr(out["p_prev"]),
-                              _ptr(out["r_last"]), _ptr(out["r_prev"]))
+                              _ptr(out["r_last"]), _ptr(out["r_prev"]), _ptr(ph_), _ptr(rh_))
     _check(st, "tti_forward")
     return out
 
 
-def tti_adjoint(shot, res: np.ndarray, vmax_damp: float = 0.0):
+def tti_adjoint(shot, res: np.ndarray, vmax_damp: float = 0.0, vp=None, hist=None):
     """Adjoint of the TTI map q -> d driven by ``res[nt][nrec]``; returns
-    qhat[nt][nsrc]."""
+    qhat[nt][nsrc], or (qhat, grad) when ``hist`` = (p_hist, r_hist) of the
+    forward is given (grad of 1/2 |P_r p - dobs|^2 w.r.t. m = 1/vp^2 for
+    res = P_r p - dobs)."""
     n = np.asarray(shot.shape, dtype=np.int32)
     sx = _f64(shot.src_xyz)
     rx = _f64(shot.rec_xyz)
     qhat = np.zeros((shot.nt, sx.shape[0]))
+    grad = np.zeros(shot.shape) if hist is not None else None
+    ph_, rh_ = (None, None) if hist is None else (_f64(hist[0]), _f64(hist[1]))
     st = lib().or_tti_adjoint(n, _f64(shot.spacing), _f64(shot.origin), shot.space_order,
-                              shot.nbl, float(shot.dt), shot.nt, _f64(shot.vp),
+                              shot.nbl, float(shot.dt), shot.nt, _f64(shot.vp if vp is None else vp),
                               _f64(shot.epsilon), _f64(shot.delta), _f64(shot.theta),
-                              _f64(shot.phi), float(vmax_damp), sx.shape[0], sx, rx.shape[0], rx,
-                              _f64(res), _ptr(qhat))
+                              _f64(shot.phi), float(vmax_damp), sx.shape[0], sx,
+                              _ptr(_f64(shot.src_wav)), rx.shape[0], rx, _f64(res), _ptr(ph_),
+                              _ptr(rh_), _ptr(grad), _ptr(qhat))
     _check(st, "tti_adjoint")
-    return qhat
+    return qhat if hist is None else (qhat, grad)
+
+
+def tti_gradient(shot, dobs: np.ndarray, vp=None, vmax_damp: float = 0.0):
+    """J(m) and dJ/dm (m = 1/vp^2) of the TTI propagator for
+    J = 1/2 sum_k |P_r p^k - dobs^k|^2."""
+    fw = tti_forward(shot, vp=vp, vmax_damp=vmax_damp, want_history=True)
+    res = fw["traces"] - _f64(dobs)
+    J = 0.5 * float(np.sum(res * res))
+    _, g = tti_adjoint(shot, res, vmax_damp=vmax_damp, vp=vp, hist=(fw["p_hist"], fw["r_hist"]))
+    return J, g
 
 
 def tti_operators(u, spacing, so: int, theta, phi):

@@ -192,14 +192,15 @@ static int gather(const tgrid *G, const double *o, const double *u, int nrec, co
 /*
  * Forward run from zero state. Inputs as or_acoustic_forward plus eps, del,
  * theta, phi [N]. Outputs (any may be NULL): traces[nt][nrec] (d^n = P_r p^n),
- * p^{nt}, p^{nt-1}, r^{nt}, r^{nt-1}.
+ * p^{nt}, p^{nt-1}, r^{nt}, r^{nt-1}, and the histories p^0..p^{nt-1},
+ * r^0..r^{nt-1} ([nt][N] each) for the gradient.
  */
 int or_tti_forward(const int *n, const double *h, const double *o, int so, int nbl, double dt,
                    int nt, const double *vp, const double *eps, const double *del,
                    const double *theta, const double *phi, double vmax_damp, int nsrc,
                    const double *src_xyz, const double *src_wav, int nrec, const double *rec_xyz,
                    double *traces, double *p_last, double *p_prev, double *r_last,
-                   double *r_prev)
+                   double *r_prev, double *p_hist, double *r_hist)
 {
     tgrid G;
     int st = tgrid_init(&G, n, h, so);
@@ -238,6 +239,8 @@ int or_tti_forward(const int *n, const double *h, const double *o, int so, int n
         sd[q] = sqrt(1.0 + 2.0 * dl);
     }
     for (int t = 0; t < nt; t++) {
+        if (p_hist) memcpy(p_hist + (i64)t * N, p1, sizeof(double) * N);
+        if (r_hist) memcpy(r_hist + (i64)t * N, r1, sizeof(double) * N);
         apply_hz(&G, ax, ay, az, p1, hzp, wx, wy, wz);
         apply_hz(&G, ax, ay, az, r1, hzr, wx, wy, wz);
 #pragma omp parallel for schedule(static)
@@ -288,18 +291,30 @@ done:
  * and the adjoint of the source map is
  *   qhat_s^n = P_s (c (lambda_p^{n+1} + lambda_r^{n+1})).
  * res[nt][nrec] is any data-space vector; output qhat[nt][nsrc].
+ *
+ * With the forward histories p_hist, r_hist ([nt][N], levels 0..nt-1) and
+ * the wavelets src_wav, grad[N] receives the gradient with respect to
+ * m = 1/vp^2 of J = 1/2 sum_k |P_r p^k - dobs^k|^2 when res = P_r p - dobs
+ * (eps, delta, the axis and the damping held fixed). Differentiating the
+ * alpha-scaled forward equation, where c = dt^2/m enters A w^{k-1} and the
+ * injection c P_s^T q^{k-1}, gives
+ *   grad = -(1/dt^2) sum_{k=1}^{nt-1} sum_{f = p, r} y_f^k (c (A w^{k-1})_f + alpha s^{k-1}),
+ *   y^k = (c/alpha) lambda^k,  s^{k-1} = c P_s^T q^{k-1},
+ * the acoustic formula with the coupled operator.
  */
 int or_tti_adjoint(const int *n, const double *h, const double *o, int so, int nbl, double dt,
                    int nt, const double *vp, const double *eps, const double *del,
                    const double *theta, const double *phi, double vmax_damp, int nsrc,
-                   const double *src_xyz, int nrec, const double *rec_xyz, const double *res,
+                   const double *src_xyz, const double *src_wav, int nrec, const double *rec_xyz,
+                   const double *res, const double *p_hist, const double *r_hist, double *grad,
                    double *qhat)
 {
     tgrid G;
     int st = tgrid_init(&G, n, h, so);
     if (st) return st;
     const i64 N = (i64)n[0] * n[1] * n[2];
-    const int NB = 18;
+    const int NB = 21;
+    if (grad && (!p_hist || !r_hist || !src_wav)) return OR_EINVAL;
     double *buf = calloc((size_t)NB * N, sizeof(double));
     if (!buf) return OR_ENOMEM;
     double *ax = buf, *ay = buf + N, *az = buf + 2 * N;
@@ -308,6 +323,7 @@ int or_tti_adjoint(const int *n, const double *h, const double *o, int so, int n
     double *p0 = buf + 8 * N, *p1 = buf + 9 * N, *p2 = buf + 10 * N; /* lambda_p k+2, k+1, k */
     double *r0 = buf + 11 * N, *r1 = buf + 12 * N, *r2 = buf + 13 * N;
     double *zp = buf + 14 * N, *zr = buf + 15 * N, *hzp = buf + 16 * N, *hzr = buf + 17 * N;
+    double *hfp = buf + 18 * N, *hfr = buf + 19 * N, *sk = buf + 20 * N; /* Hz p^k, Hz r^k, s^k */
     double *wx = malloc(sizeof(double) * 3 * N);
     if (!wx) {
         free(buf);
@@ -332,7 +348,29 @@ int or_tti_adjoint(const int *n, const double *h, const double *o, int so, int n
         sd[q] = sqrt(1.0 + 2.0 * dl);
     }
     if (qhat) memset(qhat, 0, sizeof(double) * (size_t)nt * nsrc);
+    if (grad) memset(grad, 0, sizeof(double) * N);
     for (int k = nt - 1; k >= 0; k--) {
+        /* Gradient term of level k+1: y^{k+1} = (c/alpha) lambda^{k+1} against
+         * c A w^k + alpha s^k, for k <= nt-2 (lambda^{nt} = 0). */
+        if (grad && k <= nt - 2) {
+            const double *pk = p_hist + (i64)k * N, *rk = r_hist + (i64)k * N;
+            apply_hz(&G, ax, ay, az, pk, hfp, wx, wy, wz);
+            apply_hz(&G, ax, ay, az, rk, hfr, wx, wy, wz);
+            memset(sk, 0, sizeof(double) * N);
+            if ((st = scatter(&G, o, sk, c, nsrc, src_xyz, src_wav, k))) goto done;
+#pragma omp parallel for schedule(static)
+            for (i64 i = 0; i < n[0]; i++)
+                for (i64 j = 0; j < n[1]; j++)
+                    for (i64 kk = 0; kk < n[2]; kk++) {
+                        const i64 q = (i * n[1] + j) * n[2] + kk;
+                        const double h0 = lap(&G, pk, i, j, kk) - hfp[q];
+                        const double ap = e1[q] * h0 + sd[q] * hfr[q];
+                        const double ar = sd[q] * h0 + hfr[q];
+                        const double yp = c[q] / alpha[q] * p1[q], yr = c[q] / alpha[q] * r1[q];
+                        grad[q] += yp * (c[q] * ap + alpha[q] * sk[q]) +
+                                   yr * (c[q] * ar + alpha[q] * sk[q]);
+                    }
+        }
         /* qhat^k from lambda^{k+1}. */
         for (int s = 0; qhat && s < nsrc; s++) {
             int nodes[24];
@@ -390,6 +428,8 @@ int or_tti_adjoint(const int *n, const double *h, const double *o, int so, int n
         r1 = r2;
         r2 = tp;
     }
+    if (grad)
+        for (i64 q = 0; q < N; q++) grad[q] *= -1.0 / (dt * dt);
 done:
     free(wx);
     free(buf);

@@ -175,3 +175,33 @@ def test_tti_adjoint_detects_untransposed_coupling(orc):
     s2.delta = np.zeros_like(s.delta)
     FTd2 = orc.tti_adjoint(s2, dp)
     assert abs(lhs - float(np.sum(q * FTd2))) > 1e-4 * abs(lhs)
+
+
+def test_tti_gradient_taylor(orc):
+    """Gradient of the TTI misfit w.r.t. m = 1/vp^2 (or_tti_adjoint with the
+    forward history): the first-order Taylor remainder falls as h^2 over
+    halvings of a smooth perturbation; any error in the gradient's direction
+    leaves an O(h) remainder instead."""
+    s = W.tti_smooth(seed=47, n=(20, 22, 24), so=8, nt=50, nbl=4, nsrc=2, nrec=8, sigma=3.0)
+    vmax = 4500.0
+    m0 = 1.0 / s.vp ** 2
+    n = s.shape
+    X, Y, Z = np.meshgrid(*[np.arange(k, dtype=float) for k in n], indexing="ij")
+    blob = np.exp(-((X - n[0] / 2) ** 2 + (Y - n[1] / 2) ** 2 + (Z - n[2] / 2) ** 2) / 18.0)
+    dobs = orc.tti_forward(s, vp=s.vp * (1.0 + 0.05 * blob), vmax_damp=vmax)["traces"]
+    J0, g = orc.tti_gradient(s, dobs, vmax_damp=vmax)
+    rng = np.random.Generator(np.random.PCG64(10))
+    from scipy.ndimage import gaussian_filter
+
+    dm = gaussian_filter(rng.standard_normal(n), 2.0)
+    dm *= 0.02 * np.abs(m0).max() / np.abs(dm).max()
+    gd = float(np.sum(g * dm))
+    errs = []
+    for k in range(5):
+        hstep = 2.0 ** (-k)
+        tr = orc.tti_forward(s, vp=1.0 / np.sqrt(m0 + hstep * dm), vmax_damp=vmax)["traces"]
+        Jh = 0.5 * float(np.sum((tr - dobs) ** 2))
+        errs.append(abs(Jh - J0 - hstep * gd))
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    assert all(3.5 < r < 4.6 for r in ratios), ratios
+    assert abs(gd) > 4 * errs[0]
