@@ -222,6 +222,12 @@ tb_status tb_adjoint(const tb_model *m, const tb_sparse *s, const tb_schedule *s
  * loss_out host (may be NULL; when given, the call synchronises the stream to
  * write it). ws must hold tb_gradient_workspace_size(checkpoint_every) bytes
  * (tb_workspace_size(TB_OP_GRADIENT) is the size for checkpoint_every = 0).
+ * TTI (spatially blocked; J on the traces of p): with y^k = (c/alpha)
+ * lambda^k, lambda the multiplier of tb_adjoint driven by the residual,
+ *   dJ/dm = -(1/dt^2) sum_{k=1}^{nt-1} sum_{f=p,r} y_f^k (c (A w^{k-1})_f
+ *           + alpha s^{k-1}),  A = D H the coupled operator,
+ * eps, delta and the axis held fixed; checkpoints of (p, r, w_p, w_r) every K
+ * levels (0 = ceil(sqrt(nt))). Elastic returns TB_EUNSUPPORTED.
  * Errors: TB_EINVAL, TB_EWORKSPACE, TB_EUNSUPPORTED, TB_EHIP.
  */
 tb_status tb_gradient(const tb_model *m, const tb_sparse *s, const tb_schedule *sched, void *ws,

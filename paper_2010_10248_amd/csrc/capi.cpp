@@ -543,8 +543,49 @@ tb_status plan_forward_elastic(const tb_model *m, tb_sparse *s, void *ws, float 
 
 }  // namespace
 
+// TTI gradient workspace: forward state (p, r two levels each, w_p, w_r,
+// q_p, q_r), adjoint state (lambda_p, lambda_r two levels each, psi_p,
+// psi_r, z_p, z_r; q shared), K level slots of (p, r), a checkpoint of
+// (p, r, w_p, w_r) at the start of every segment, then the FP64 image and
+// the per-step rows.
+struct TtiGradLayout {
+    int K = 1, nseg = 0;
+    size_t F = 0, A = 0, slots = 0, cps = 0, g = 0, gs = 0, rec = 0, traces = 0, res = 0,
+           adj = 0, srec = 0, loss = 0, total = 0;
+};
+
+TtiGradLayout tti_grad_layout(const tb_model *m, const tb_sparse *s, int every)
+{
+    TtiGradLayout L;
+    const int nt = m->nt;
+    L.K = every > 0 ? every : ceil_sqrt(std::max(nt, 1));
+    L.nseg = (nt + L.K - 1) / L.K;
+    const size_t fb = field_bytes(m), nt1 = (size_t)nt + 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    L.F = take(8 * fb);
+    L.A = take(8 * fb);
+    L.slots = take(2 * (size_t)L.K * fb);
+    L.cps = take(4 * (size_t)L.nseg * fb);
+    L.g = take(m->field_elems() * sizeof(double));
+    L.gs = take((size_t)std::max(s->npts, 1) * sizeof(double));
+    L.rec = take(nt1 * std::max(s->nrid, 1) * sizeof(float));
+    L.traces = take((size_t)nt * std::max(s->nrec, 1) * sizeof(float));
+    L.res = take((size_t)nt * std::max(s->nrec, 1) * sizeof(float));
+    L.adj = take((size_t)nt * std::max(s->nrid, 1) * sizeof(float));
+    L.srec = take(nt1 * std::max(s->npts, 1) * sizeof(float));
+    L.loss = take(sizeof(double));
+    L.total = o;
+    return L;
+}
+
 size_t gradient_ws_bytes(const tb_model *m, const tb_sparse *s, const SchedChoice &sc, int every)
 {
+    if (m->physics == TB_TTI) return tti_grad_layout(m, s, every).total;
     return grad_layout(m, s, sc, every).total;
 }
 
@@ -598,7 +639,7 @@ tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, 
                         void *ws, const float *d_obs, float *grad_m, double *loss_dst, Plan *plan)
 {
     if (m->physics != TB_ACOUSTIC) {
-        set_error("the gradient is built for the acoustic propagator only");
+        set_error("this gradient plan is built for the acoustic propagator only");
         return TB_EUNSUPPORTED;
     }
     const GradLayout L = grad_layout(m, s, sc, every);
@@ -811,6 +852,139 @@ tb_status tti_adjoint(const tb_model *m, tb_sparse *s, void *ws, const float *re
                                       src_out, 1, strm)))
             return st;
     return TB_OK;
+}
+
+// Gradient of J = 1/2 sum_k |P_r p^k - d_obs^k|^2 of the TTI propagator with
+// respect to m = 1/vp^2, by checkpointing with recomputation:
+//   grad = -(1/dt^2) sum_{k=0}^{nt-2} sum_f y_f^{k+1} (c (A w^k)_f + alpha s^k),
+//   y^{k+1} = (c/alpha) lambda^{k+1},
+// with lambda the multiplier of tti_adjoint driven by the residual. The
+// forward run stores (p, r, w_p, w_r) at the start of every segment of K
+// levels; the backward run recomputes a segment's levels into the slots,
+// then images each level against the multiplier and takes the adjoint step.
+tb_status tti_gradient(const tb_model *m, tb_sparse *s, int every, void *ws, const float *d_obs,
+                       float *grad_m, double *loss_out, hipStream_t strm)
+{
+    const TtiGradLayout L = tti_grad_layout(m, s, every);
+    const size_t fb = field_bytes(m), fe = m->field_elems();
+    const int nt = m->nt, npts = s->npts, nrid = s->nrid, nrec = s->nrec, K = L.K;
+    char *base = (char *)ws;
+    auto fld = [&](size_t off, int k) { return (float *)(base + off + (size_t)k * fb); };
+    float *rec = (float *)(base + L.rec), *traces = (float *)(base + L.traces);
+    float *res = (float *)(base + L.res), *adj = (float *)(base + L.adj);
+    float *srec = (float *)(base + L.srec);
+    double *g = (double *)(base + L.g), *gs = (double *)(base + L.gs);
+    double *loss = (double *)(base + L.loss);
+    tb_status st;
+    for (int k = 0; k < 8; k++) {
+        if ((st = launch_fill(fld(L.F, k), fe, 0.0f, strm))) return st;
+        if ((st = launch_fill(fld(L.A, k), fe, 0.0f, strm))) return st;
+    }
+    if (nrid > 0 && (st = launch_fill(rec, (size_t)nrid, 0.0f, strm))) return st;
+    if ((st = launch_zero64(g, fe, strm)) || (st = launch_zero64(gs, std::max(npts, 1), strm)))
+        return st;
+    const TtiParams P0 = tti_params(m);
+    // Forward: p in F0/F1, r in F2/F3, w_p F4, w_r F5, q F6/F7.
+    TtiParams P = P0;
+    P.vp = fld(L.F, 4);
+    P.vr = fld(L.F, 5);
+    P.qp = fld(L.F, 6);
+    P.qr = fld(L.F, 7);
+    const long long *soff = s->d_src_off, *roff = s->d_rid_off;
+    int pc = 0, pp = 1;
+    for (int n = 0; n < nt; n++) {
+        if (n % K == 0) {
+            const int j = n / K;
+            const float *src4[4] = {fld(L.F, pc), fld(L.F, pc + 2), P.vp, P.vr};
+            for (int f = 0; f < 4; f++)
+                TB_HIP(hipMemcpyAsync(fld(L.cps, 4 * j + f), src4[f], fb, hipMemcpyDeviceToDevice,
+                                      strm));
+        }
+        TtiParams Q = P;
+        Q.p = fld(L.F, pc);
+        Q.pn = fld(L.F, pp);
+        Q.r = fld(L.F, pc + 2);
+        Q.rn = fld(L.F, pp + 2);
+        if ((st = launch_tti_step(Q, m->r, s->d_dcmp + (size_t)n * npts, soff, npts,
+                                  rec + (size_t)(n + 1) * nrid, roff, nrid, strm)))
+            return st;
+        std::swap(pc, pp);
+    }
+    if (nt > 0 && nrec > 0) {
+        if ((st = launch_trace_reduce(rec, nrid, nt, s->d_rc_ptr, s->d_rc_id, s->d_rc_w, nrec,
+                                      traces, 0, strm)))
+            return st;
+    }
+    if ((st = launch_residual_loss(traces, d_obs, (long long)nt * nrec, res, loss, strm)))
+        return st;
+    if (loss_out)
+        TB_HIP(hipMemcpyAsync(loss_out, loss, sizeof(double), hipMemcpyDeviceToHost, strm));
+    if (nrid > 0 && nt > 0)
+        if ((st = launch_adj_inject(res, nt, nrec, nrid, s->d_rr_ptr, s->d_rr_rec, s->d_rr_w,
+                                    nullptr, adj, strm)))
+            return st;
+    // Backward. Adjoint: lambda_p A0/A1, lambda_r A2/A3, psi A4/A5, z A6/A7.
+    TtiParams PA = P0;
+    PA.vp = fld(L.A, 4);
+    PA.vr = fld(L.A, 5);
+    PA.zp = fld(L.A, 6);
+    PA.zr = fld(L.A, 7);
+    PA.p = PA.zp;
+    PA.r = PA.zr;
+    PA.qp = P.qp;
+    PA.qr = P.qr;
+    int lc = 0, ln = 1;
+    for (int j = L.nseg - 1; j >= 0; j--) {
+        const int k0 = j * K, k1 = std::min(nt, k0 + K);
+        // Recompute levels k0 .. k1-1 into the slots (p in slot 2i, r in 2i+1).
+        TB_HIP(hipMemcpyAsync(fld(L.slots, 0), fld(L.cps, 4 * j), fb, hipMemcpyDeviceToDevice,
+                              strm));
+        TB_HIP(hipMemcpyAsync(fld(L.slots, 1), fld(L.cps, 4 * j + 1), fb,
+                              hipMemcpyDeviceToDevice, strm));
+        TB_HIP(hipMemcpyAsync(P.vp, fld(L.cps, 4 * j + 2), fb, hipMemcpyDeviceToDevice, strm));
+        TB_HIP(hipMemcpyAsync(P.vr, fld(L.cps, 4 * j + 3), fb, hipMemcpyDeviceToDevice, strm));
+        for (int k = k0; k + 1 < k1; k++) {
+            const int i = k - k0;
+            TtiParams Q = P;
+            Q.p = fld(L.slots, 2 * i);
+            Q.r = fld(L.slots, 2 * i + 1);
+            Q.pn = fld(L.slots, 2 * i + 2);
+            Q.rn = fld(L.slots, 2 * i + 3);
+            if ((st = launch_tti_step(Q, m->r, s->d_dcmp + (size_t)k * npts, soff, npts, nullptr,
+                                      roff, 0, strm)))
+                return st;
+        }
+        for (int k = k1 - 1; k >= k0; k--) {
+            const int tau = nt - 1 - k, i = k - k0;
+            TtiParams Q = PA;
+            Q.lp = fld(L.A, lc);
+            Q.lr = fld(L.A, lc + 2);
+            Q.pn = fld(L.A, ln);
+            Q.rn = fld(L.A, ln + 2);
+            if (k <= nt - 2) {
+                TtiParams I = P0;
+                I.p = fld(L.slots, 2 * i);
+                I.r = fld(L.slots, 2 * i + 1);
+                I.qp = P.qp;
+                I.qr = P.qr;
+                I.lp = Q.lp;
+                I.lr = Q.lr;
+                if ((st = launch_tti_image(I, m->r, g, strm))) return st;
+            }
+            float *srow = srec + (size_t)tau * npts;
+            if ((st = launch_tti_adjoint_step(Q, m->r, adj + (size_t)tau * nrid, roff, nrid, srow,
+                                              soff, s->d_src_alpha, npts, strm)))
+                return st;
+            if (k <= nt - 2 && npts > 0)
+                if ((st = launch_tti_image_sparse(srow, s->d_src_alpha,
+                                                  s->d_dcmp + (size_t)k * npts, npts, gs, strm)))
+                    return st;
+            std::swap(lc, ln);
+        }
+    }
+    if ((st = launch_image_merge(gs, npts, soff, g, strm))) return st;
+    return launch_finish_grad(g, grad_m, m->n[0], m->n[1], m->n[2], m->nzp,
+                              -1.0 / (m->dt * m->dt), strm);
 }
 
 tb_status time_loop(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int adjoint,
@@ -1287,6 +1461,10 @@ tb_status tb_gradient(const tb_model *m, const tb_sparse *s_, const tb_schedule 
         set_error("tb_gradient: invalid argument");
         return TB_EINVAL;
     }
+    if (m->physics == TB_ELASTIC) {
+        set_error("the gradient is built for the acoustic and TTI propagators only");
+        return TB_EUNSUPPORTED;
+    }
     SchedChoice sc;
     tb_status st = resolve_schedule(m, sched, &sc);
     if (st) return st;
@@ -1296,6 +1474,12 @@ tb_status tb_gradient(const tb_model *m, const tb_sparse *s_, const tb_schedule 
         return TB_EWORKSPACE;
     }
     hipStream_t strm = (hipStream_t)stream;
+    if (m->physics == TB_TTI) {
+        if ((st = tti_gradient(m, s, checkpoint_every, ws, d_obs, grad_m, loss_out, strm)))
+            return st;
+        if (loss_out) TB_HIP(hipStreamSynchronize(strm));
+        return TB_OK;
+    }
     Plan plan;
     if ((st = plan_gradient(m, s, sc, checkpoint_every, ws, d_obs, grad_m, loss_out, &plan)))
         return st;

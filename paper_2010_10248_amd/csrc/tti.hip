@@ -112,12 +112,17 @@ __global__ void __launch_bounds__(256) tti_rot(const TtiParams P)
     *(f4 *)(P.qr + q.off) = qr;
 }
 
-// ADJ: the adjoint update. The operator input (p, r) is then the mixed
-// field z; the rates are psi = (H0 z_p, Hz z_r) + (beta/alpha) psi, and the
-// levels advance from lambda^{k+1} (lp, lr).
-template <int R, bool ADJ>
-__global__ void __launch_bounds__(256) tti_update(const TtiParams P)
+// Modes: kForward, the update above; kAdjoint, the adjoint update, whose
+// operator input (p, r) is the mixed field z, with rates psi = (H0 z_p,
+// Hz z_r) + (beta/alpha) psi and levels advancing from lambda^{k+1} (lp,
+// lr); kImage, the gradient's imaging term of a forward level w = (p, r):
+// g += sum_f y_f c (A w)_f with y = (c/alpha) lambda^{k+1} (lp, lr), in FP64.
+enum { kForward = 0, kAdjoint = 1, kImage = 2 };
+
+template <int R, int MODE>
+__global__ void __launch_bounds__(256) tti_update(const TtiParams P, double *__restrict__ g)
 {
+    constexpr bool ADJ = MODE == kAdjoint;
     Site q;
     if (!locate4(P, q)) return;
     constexpr int ZB = zspan<R>();
@@ -155,10 +160,11 @@ __global__ void __launch_bounds__(256) tti_update(const TtiParams P)
         }
     }
     const f4 zero = f4{0.f, 0.f, 0.f, 0.f};
-    const f4 rc = ADJ ? ld4(P.lr, q.off, true) : ld4(P.r, q.off, true);
-    const f4 lpc = ADJ ? ld4(P.lp, q.off, true) : pc;
+    const f4 rc = MODE != kForward ? ld4(P.lr, q.off, true) : ld4(P.r, q.off, true);
+    const f4 lpc = MODE != kForward ? ld4(P.lp, q.off, true) : pc;
     const f4 e1 = ADJ ? zero : ld4(P.e1, q.off, true), sd = ADJ ? zero : ld4(P.sd, q.off, true),
              cc = ADJ ? zero : ld4(P.c, q.off, true);
+    (void)zero;
     f4 vp = ld4(P.vp, q.off, true), vr = ld4(P.vr, q.off, true), pn, rn;
     const float dxy = P.dx[q.x] + P.dy[q.y];
 #pragma unroll
@@ -182,7 +188,16 @@ __global__ void __launch_bounds__(256) tti_update(const TtiParams P)
         const float dd = d * P.hdt;
         const float beta = 1.0f - dd;
         float wp, wr;
-        if constexpr (ADJ) {
+        if constexpr (MODE == kImage) {
+            if (z < P.nz) {
+                const float rhs_p = __builtin_fmaf(e1[k], h0p, sd[k] * hzr);
+                const float rhs_r = __builtin_fmaf(sd[k], h0p, hzr);
+                const double ca = (double)cc[k] / (1.0 + (double)dd);
+                g[q.off + k] += ca * ((double)lpc[k] * ((double)cc[k] * rhs_p) +
+                                      (double)rc[k] * ((double)cc[k] * rhs_r));
+            }
+            continue;
+        } else if constexpr (ADJ) {
             wp = d != 0.0f ? __builtin_fmaf(beta / (1.0f + dd), vp[k], h0p) : h0p + vp[k];
             wr = d != 0.0f ? __builtin_fmaf(beta / (1.0f + dd), vr[k], hzr) : hzr + vr[k];
         } else {
@@ -200,10 +215,12 @@ __global__ void __launch_bounds__(256) tti_update(const TtiParams P)
         pn[k] = lpc[k] + wp;
         rn[k] = rc[k] + wr;
     }
-    *(f4 *)(P.vp + q.off) = vp;
-    *(f4 *)(P.vr + q.off) = vr;
-    *(f4 *)(P.pn + q.off) = pn;
-    *(f4 *)(P.rn + q.off) = rn;
+    if constexpr (MODE != kImage) {
+        *(f4 *)(P.vp + q.off) = vp;
+        *(f4 *)(P.vr + q.off) = vr;
+        *(f4 *)(P.pn + q.off) = pn;
+        *(f4 *)(P.rn + q.off) = rn;
+    }
 }
 
 __global__ void tti_sparse(float *__restrict__ p, float *__restrict__ r, float *__restrict__ vp,
@@ -262,6 +279,15 @@ __global__ void tti_adj_inject(float *__restrict__ lam, float *__restrict__ rate
     }
 }
 
+// Source-point imaging term: gs[i] += row[i] alpha[i] s[i], with row the
+// samples c (lambda_p + lambda_r)^{k+1} / alpha and s the injected increment.
+__global__ void tti_image_sparse(const float *__restrict__ row, const double *__restrict__ alpha,
+                                 const float *__restrict__ inc, int n, double *__restrict__ gs)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) gs[i] += (double)row[i] * (alpha[i] * (double)inc[i]);
+}
+
 // c (lambda_p + lambda_r) / alpha at the source points.
 __global__ void tti_adj_record(const float *__restrict__ lp, const float *__restrict__ lr,
                                const float *__restrict__ c, const long long *__restrict__ off,
@@ -286,13 +312,16 @@ tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const lon
     if (total == 0) return TB_OK;
     if (r == 2) {
         hipLaunchKernelGGL(tti_rot<2>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL((tti_update<2, false>), dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<2, kForward>), dim3(nblocks(total)), dim3(256), 0, st, P,
+                           nullptr);
     } else if (r == 4) {
         hipLaunchKernelGGL(tti_rot<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL((tti_update<4, false>), dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<4, kForward>), dim3(nblocks(total)), dim3(256), 0, st, P,
+                           nullptr);
     } else if (r == 6) {
         hipLaunchKernelGGL(tti_rot<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL((tti_update<6, false>), dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<6, kForward>), dim3(nblocks(total)), dim3(256), 0, st, P,
+                           nullptr);
     } else {
         set_error("TTI radius %d not built", r);
         return TB_EUNSUPPORTED;
@@ -326,13 +355,16 @@ tb_status launch_tti_adjoint_step(const TtiParams &P, int r, const float *inc,
     hipLaunchKernelGGL(tti_adj_mix, dim3(nblocks(total)), dim3(256), 0, st, P);
     if (r == 2) {
         hipLaunchKernelGGL(tti_rot<2>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL((tti_update<2, true>), dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<2, kAdjoint>), dim3(nblocks(total)), dim3(256), 0, st, P,
+                           nullptr);
     } else if (r == 4) {
         hipLaunchKernelGGL(tti_rot<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL((tti_update<4, true>), dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<4, kAdjoint>), dim3(nblocks(total)), dim3(256), 0, st, P,
+                           nullptr);
     } else if (r == 6) {
         hipLaunchKernelGGL(tti_rot<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL((tti_update<6, true>), dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<6, kAdjoint>), dim3(nblocks(total)), dim3(256), 0, st, P,
+                           nullptr);
     } else {
         set_error("TTI radius %d not built", r);
         return TB_EUNSUPPORTED;
@@ -343,6 +375,37 @@ tb_status launch_tti_adjoint_step(const TtiParams &P, int r, const float *inc,
                            roff, nrid);
         TB_HIP(hipGetLastError());
     }
+    return TB_OK;
+}
+
+tb_status launch_tti_image(const TtiParams &P, int r, double *g, hipStream_t st)
+{
+    const long long total = (long long)P.nx * P.ny * (P.nzp / 4);
+    if (total == 0) return TB_OK;
+    if (r == 2) {
+        hipLaunchKernelGGL(tti_rot<2>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<2, kImage>), dim3(nblocks(total)), dim3(256), 0, st, P, g);
+    } else if (r == 4) {
+        hipLaunchKernelGGL(tti_rot<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<4, kImage>), dim3(nblocks(total)), dim3(256), 0, st, P, g);
+    } else if (r == 6) {
+        hipLaunchKernelGGL(tti_rot<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL((tti_update<6, kImage>), dim3(nblocks(total)), dim3(256), 0, st, P, g);
+    } else {
+        set_error("TTI radius %d not built", r);
+        return TB_EUNSUPPORTED;
+    }
+    TB_HIP(hipGetLastError());
+    return TB_OK;
+}
+
+tb_status launch_tti_image_sparse(const float *row, const double *alpha, const float *inc,
+                                  int npts, double *gs, hipStream_t st)
+{
+    if (npts == 0) return TB_OK;
+    hipLaunchKernelGGL(tti_image_sparse, dim3(nblocks(npts)), dim3(256), 0, st, row, alpha, inc,
+                       npts, gs);
+    TB_HIP(hipGetLastError());
     return TB_OK;
 }
 

@@ -41,6 +41,15 @@ tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const lon
 //   lambda^k = lambda^{k+1} + psi^k,
 // with H = diag(L - Hz, Hz) and res^k decomposed at the receiver points as
 // inc[nrid] (added at roff).
+// Imaging term of the gradient for a forward level w = (P.p, P.r) against
+// the multiplier lambda^{k+1} = (P.lp, P.lr): the rotated gradients of w go
+// to (P.qp, P.qr), then g += sum_f y_f c (A w)_f with y = (c/alpha) lambda
+// (g in FP64, padded layout).
+tb_status launch_tti_image(const TtiParams &P, int r, double *g, hipStream_t st);
+// gs[i] += row[i] alpha[i] inc[i] at the source points.
+tb_status launch_tti_image_sparse(const float *row, const double *alpha, const float *inc,
+                                  int npts, double *gs, hipStream_t st);
+
 tb_status launch_tti_adjoint_step(const TtiParams &P, int r, const float *inc,
                                   const long long *roff, int nrid, float *src_row,
                                   const long long *soff, const double *src_alpha, int npts,

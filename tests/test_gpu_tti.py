@@ -149,3 +149,45 @@ def test_tti_long_run(torch_cuda, orc):
              p_prev=_rel(out["u_prev"].cpu().numpy(), ref["p_prev"]))
     _say(f"TTI 600 steps: {e}")
     assert all(v <= TOL for v in e.values()), e
+
+
+@pytest.mark.parametrize("so,data", [(8, "zero"), (8, "blob"), (4, "zero")])
+def test_tti_gradient_matches_oracle(torch_cuda, orc, so, data):
+    """Gradient of the TTI misfit w.r.t. m = 1/vp^2 against the FP64 oracle
+    (pinned by its Taylor test): d_obs = 0 at the forward tolerance, d_obs
+    from a +5% velocity blob at the tolerance scaled by the residual's
+    conditioning; the result does not depend on the checkpoint spacing
+    (recomputed levels are bit-identical), bitwise."""
+    import torch
+
+    from paper_2010_10248_amd import tb
+
+    s = W.tti_smooth(seed=95 + so, n=(34, 36, 38), so=so, nt=60, nbl=5, nsrc=2, nrec=16,
+                     sigma=3.0)
+    vmax = 4500.0
+    n = s.shape
+    X, Y, Z = np.meshgrid(*[np.arange(k, dtype=float) for k in n], indexing="ij")
+    blob = np.exp(-((X - n[0] / 2) ** 2 + (Y - n[1] / 2) ** 2 + (Z - n[2] / 2) ** 2) / 18.0)
+    if data == "zero":
+        dobs = np.zeros((s.nt, s.rec_xyz.shape[0]))
+    else:
+        dobs = orc.tti_forward(s, vp=s.vp * (1.0 + 0.05 * blob), vmax_damp=vmax)["traces"]
+    J_ref, g_ref = orc.tti_gradient(s, dobs, vmax_damp=vmax)
+    tr = orc.tti_forward(s, vmax_damp=vmax)["traces"]
+    kappa = float(np.linalg.norm(tr) / np.linalg.norm(tr - dobs))
+    prop = tb.Propagator(s, damp_vmax=vmax)
+    d = torch.as_tensor(dobs.astype(np.float32), device="cuda")
+    base = None
+    for every in (0, 1, 7, 60):
+        J, g = prop.gradient(d, None, every)
+        g = g.cpu().numpy()
+        e = _rel(g, g_ref)
+        _say(f"TTI SO{so} gradient {data} every={every}: J {J:.9e} oracle {J_ref:.9e} "
+             f"rel {abs(J - J_ref) / J_ref:.2e} grad relL2 {e:.3e} kappa {kappa:.2f}")
+        assert abs(J - J_ref) <= 2 * TOL * kappa * abs(J_ref)
+        assert e <= TOL * kappa
+        if base is None:
+            base = g
+        else:
+            assert np.array_equal(g.view(np.uint32), base.view(np.uint32)), every
+    prop.close()
