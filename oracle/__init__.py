@@ -75,6 +75,10 @@ def lib():
                                          c_int, _dp, vp, c_int, _dp, _dp, vp, vp, vp, vp]
         if hasattr(L, "or_tti_operators"):
             L.or_tti_operators.argtypes = [_ip, _dp, c_int, _dp, _dp, _dp, vp, vp]
+        if hasattr(L, "or_elastic_adjoint"):
+            L.or_elastic_adjoint.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int,
+                                             _dp, _dp, _dp, c_double, c_int, _dp, c_int, _dp,
+                                             _dp, vp]
         if hasattr(L, "or_elastic_forward"):
             L.or_elastic_forward.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int,
                                              _dp, _dp, _dp, c_double,
@@ -306,6 +310,21 @@ def tti_operators(u, spacing, so: int, theta, phi):
 
 
 ELASTIC_FIELDS = ("vx", "vy", "vz", "txx", "tyy", "tzz", "txy", "txz", "tyz")
+
+
+def elastic_adjoint(shot, res: np.ndarray, vmax_damp: float = 0.0):
+    """Adjoint of the elastic map q -> (vz, P) traces driven by
+    ``res[2][nt][nrec]`` (vz block, then P); returns qhat[nt][nsrc]."""
+    n = np.asarray(shot.shape, dtype=np.int32)
+    sx = _f64(shot.src_xyz)
+    rx = _f64(shot.rec_xyz)
+    qhat = np.zeros((shot.nt, sx.shape[0]))
+    st = lib().or_elastic_adjoint(n, _f64(shot.spacing), _f64(shot.origin), shot.space_order,
+                                  shot.nbl, float(shot.dt), shot.nt, _f64(shot.vp),
+                                  _f64(shot.vs), _f64(shot.rho), float(vmax_damp), sx.shape[0],
+                                  sx, rx.shape[0], rx, _f64(res), _ptr(qhat))
+    _check(st, "elastic_adjoint")
+    return qhat
 
 
 def elastic_forward(shot, vmax_damp: float = 0.0, src_wav=None, vp=None, vs=None, rho=None,

@@ -245,3 +245,159 @@ done:
     free(P);
     return st;
 }
+
+/*
+ * Exact discrete adjoint of the linear map q -> (vz, P) traces of
+ * or_elastic_forward. A step is two passes, v' = (beta v + dt b (D t)) / alpha
+ * then t' = (beta t + dt C E v') / alpha (+ the source), with D the
+ * divergence and E the strain operator of the staggered derivatives; with
+ * every field zero outside the grid the staggered derivatives satisfy
+ * (d_fwd)^T = -d_bwd, so D^T = -E and E^T = -D on these arrays, and C
+ * (lambda, mu, the averaged mu) is symmetric. Backwards from zero multipliers
+ * (vh, th) of the final state, for t = nt-1 .. 0:
+ *   qhat^t = dt P_s (thxx + thyy + thzz)               (the source entered t^{t+1})
+ *   s = th / alpha;  vh += -dt D(C s);  th = (beta/alpha) th     (stress pass)
+ *   u = dt b vh / alpha;  th += -E(u);  vh = (beta/alpha) vh     (velocity pass)
+ *   vh_z += P_vz^T res_vz^t;  th_ii += P^T res_P^t / 3           (receivers)
+ * res[2][nt][nrec] (vz block, then P block); qhat[nt][nsrc].
+ */
+int or_elastic_adjoint(const int *n, const double *h, const double *o, int so, int nbl,
+                       double dt, int nt, const double *vp, const double *vs, const double *rho,
+                       double vmax_damp, int nsrc, const double *src_xyz, int nrec,
+                       const double *rec_xyz, const double *res, double *qhat)
+{
+    egrid G;
+    memcpy(G.n, n, sizeof(int) * 3);
+    memcpy(G.h, h, sizeof(double) * 3);
+    G.r = so / 2;
+    if (so < 2 || so > 16 || so % 2 || or_weights_d1_staggered(so, G.w)) return OR_EINVAL;
+    const i64 N = (i64)n[0] * n[1] * n[2];
+    double *F = calloc((size_t)NF * N, sizeof(double)); /* multipliers */
+    double *S = calloc(6 * (size_t)N, sizeof(double));  /* C s, then u */
+    double *P = calloc((size_t)10 * N, sizeof(double));
+    if (!F || !S || !P) {
+        free(F); free(S); free(P);
+        return OR_ENOMEM;
+    }
+    double *b = P, *lam = P + N, *mu = P + 2 * N, *bx = P + 3 * N, *by = P + 4 * N,
+           *bz = P + 5 * N, *mxy = P + 6 * N, *mxz = P + 7 * N, *myz = P + 8 * N, *dmp = P + 9 * N;
+    double vmax = vmax_damp;
+    if (!(vmax > 0.0)) {
+        vmax = 0.0;
+        for (i64 q = 0; q < N; q++)
+            if (vp[q] > vmax) vmax = vp[q];
+    }
+    or_damping(n, h, nbl, vmax, dmp);
+    for (i64 q = 0; q < N; q++) {
+        b[q] = 1.0 / rho[q];
+        mu[q] = rho[q] * vs[q] * vs[q];
+        lam[q] = rho[q] * (vp[q] * vp[q] - 2.0 * vs[q] * vs[q]);
+    }
+    for (i64 i = 0; i < n[0]; i++)
+        for (i64 j = 0; j < n[1]; j++)
+            for (i64 k = 0; k < n[2]; k++) {
+                i64 q = idx(&G, i, j, k);
+                bx[q] = 0.5 * (clampv(&G, b, i, j, k) + clampv(&G, b, i + 1, j, k));
+                by[q] = 0.5 * (clampv(&G, b, i, j, k) + clampv(&G, b, i, j + 1, k));
+                bz[q] = 0.5 * (clampv(&G, b, i, j, k) + clampv(&G, b, i, j, k + 1));
+                mxy[q] = 0.25 * (clampv(&G, mu, i, j, k) + clampv(&G, mu, i + 1, j, k) +
+                                 clampv(&G, mu, i, j + 1, k) + clampv(&G, mu, i + 1, j + 1, k));
+                mxz[q] = 0.25 * (clampv(&G, mu, i, j, k) + clampv(&G, mu, i + 1, j, k) +
+                                 clampv(&G, mu, i, j, k + 1) + clampv(&G, mu, i + 1, j, k + 1));
+                myz[q] = 0.25 * (clampv(&G, mu, i, j, k) + clampv(&G, mu, i, j + 1, k) +
+                                 clampv(&G, mu, i, j, k + 1) + clampv(&G, mu, i, j + 1, k + 1));
+            }
+    double *vx = F + VX * N, *vy = F + VY * N, *vz = F + VZ * N;
+    double *txx = F + TXX * N, *tyy = F + TYY * N, *tzz = F + TZZ * N;
+    double *txy = F + TXY * N, *txz = F + TXZ * N, *tyz = F + TYZ * N;
+    double *sxx = S, *syy = S + N, *szz = S + 2 * N, *sxy = S + 3 * N, *sxz = S + 4 * N,
+           *syz = S + 5 * N;
+    double ovz[3] = {o[0], o[1], o[2] + 0.5 * h[2]};
+    int st = OR_OK;
+    if (qhat) memset(qhat, 0, sizeof(double) * (size_t)nt * nsrc);
+    for (int t = nt - 1; t >= 0; t--) {
+        for (int s = 0; qhat && s < nsrc; s++) {
+            int nodes[24];
+            double w[8];
+            int cnt = or_trilinear(src_xyz + 3 * s, o, h, n, nodes, w);
+            if (cnt < 0) { st = cnt; goto done; }
+            double acc = 0.0;
+            for (int c = 0; c < cnt; c++) {
+                i64 q = idx(&G, nodes[3 * c], nodes[3 * c + 1], nodes[3 * c + 2]);
+                acc += dt * w[c] * (txx[q] + tyy[q] + tzz[q]);
+            }
+            qhat[(i64)t * nsrc + s] = acc;
+        }
+        /* Adjoint of the stress pass. */
+        for (i64 q = 0; q < N; q++) {
+            const double al = 1.0 + dmp[q] * dt / 2.0, be = 1.0 - dmp[q] * dt / 2.0;
+            const double a = txx[q] / al, bb = tyy[q] / al, c = tzz[q] / al;
+            const double tr = a + bb + c;
+            sxx[q] = lam[q] * tr + 2.0 * mu[q] * a;
+            syy[q] = lam[q] * tr + 2.0 * mu[q] * bb;
+            szz[q] = lam[q] * tr + 2.0 * mu[q] * c;
+            sxy[q] = mxy[q] * txy[q] / al;
+            sxz[q] = mxz[q] * txz[q] / al;
+            syz[q] = myz[q] * tyz[q] / al;
+            for (int f = TXX; f <= TYZ; f++) F[f * N + q] *= be / al;
+        }
+#pragma omp parallel for schedule(static)
+        for (i64 i = 0; i < n[0]; i++)
+            for (i64 j = 0; j < n[1]; j++)
+                for (i64 k = 0; k < n[2]; k++) {
+                    i64 q = idx(&G, i, j, k);
+                    vx[q] -= dt * (dst(&G, sxx, i, j, k, 0, 1) + dst(&G, sxy, i, j, k, 1, 0) +
+                                   dst(&G, sxz, i, j, k, 2, 0));
+                    vy[q] -= dt * (dst(&G, sxy, i, j, k, 0, 0) + dst(&G, syy, i, j, k, 1, 1) +
+                                   dst(&G, syz, i, j, k, 2, 0));
+                    vz[q] -= dt * (dst(&G, sxz, i, j, k, 0, 0) + dst(&G, syz, i, j, k, 1, 0) +
+                                   dst(&G, szz, i, j, k, 2, 1));
+                }
+        /* Adjoint of the velocity pass: u = dt b vh / alpha into S[0..2]. */
+        for (i64 q = 0; q < N; q++) {
+            const double al = 1.0 + dmp[q] * dt / 2.0, be = 1.0 - dmp[q] * dt / 2.0;
+            sxx[q] = dt * bx[q] * vx[q] / al;
+            syy[q] = dt * by[q] * vy[q] / al;
+            szz[q] = dt * bz[q] * vz[q] / al;
+            vx[q] *= be / al;
+            vy[q] *= be / al;
+            vz[q] *= be / al;
+        }
+#pragma omp parallel for schedule(static)
+        for (i64 i = 0; i < n[0]; i++)
+            for (i64 j = 0; j < n[1]; j++)
+                for (i64 k = 0; k < n[2]; k++) {
+                    i64 q = idx(&G, i, j, k);
+                    txx[q] -= dst(&G, sxx, i, j, k, 0, 0);
+                    tyy[q] -= dst(&G, syy, i, j, k, 1, 0);
+                    tzz[q] -= dst(&G, szz, i, j, k, 2, 0);
+                    txy[q] -= dst(&G, sxx, i, j, k, 1, 1) + dst(&G, syy, i, j, k, 0, 1);
+                    txz[q] -= dst(&G, sxx, i, j, k, 2, 1) + dst(&G, szz, i, j, k, 0, 1);
+                    tyz[q] -= dst(&G, syy, i, j, k, 2, 1) + dst(&G, szz, i, j, k, 1, 1);
+                }
+        /* Receivers of step t (they read v^{t-1/2} and t^t). */
+        for (int r = 0; r < nrec; r++) {
+            int nodes[24];
+            double w[8];
+            int cnt = or_trilinear(rec_xyz + 3 * r, ovz, h, n, nodes, w);
+            if (cnt < 0) { st = cnt; goto done; }
+            const double rv = res[(i64)t * nrec + r];
+            for (int c = 0; c < cnt; c++)
+                vz[idx(&G, nodes[3 * c], nodes[3 * c + 1], nodes[3 * c + 2])] += w[c] * rv;
+            cnt = or_trilinear(rec_xyz + 3 * r, o, h, n, nodes, w);
+            if (cnt < 0) { st = cnt; goto done; }
+            const double rp = res[((i64)nt + t) * nrec + r] / 3.0;
+            for (int c = 0; c < cnt; c++) {
+                i64 q = idx(&G, nodes[3 * c], nodes[3 * c + 1], nodes[3 * c + 2]);
+                txx[q] += w[c] * rp;
+                tyy[q] += w[c] * rp;
+                tzz[q] += w[c] * rp;
+            }
+        }
+    }
+done:
+    free(F);
+    free(S);
+    free(P);
+    return st;
+}

@@ -86,3 +86,29 @@ def test_p_wave_speed(orc):
     for a, b in ((0, 1), (2, 3)):
         got = tpk(b) - tpk(a)
         assert abs(got - want) <= 0.02 * want, (a, b, got, want)
+
+
+# --------------------------------------------------------------------------
+# Adjoint of the elastic map q -> (vz, P) (or_elastic_adjoint): the FP64
+# dot-product identity against the oracle forward, SO4 and SO8, damping on;
+# a one-sample time shift breaks it, and so does a model whose shear modulus
+# differs (the adjoint must carry the same C).
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("so", [4, 8])
+def test_elastic_adjoint_dot_product(orc, so):
+    s = W.elastic_smooth(seed=51, n=(18, 20, 22), so=so, nt=36, nbl=4, nrec=6, sigma=3.0)
+    rng = np.random.Generator(np.random.PCG64(13))
+    q = rng.standard_normal(s.src_wav.shape)
+    dp = rng.standard_normal((2, s.nt, s.rec_xyz.shape[0]))
+    fw = orc.elastic_forward(s, src_wav=q)
+    lhs = float(np.sum(fw["vz"] * dp[0]) + np.sum(fw["p"] * dp[1]))
+    FTd = orc.elastic_adjoint(s, dp)
+    rhs = float(np.sum(q * FTd))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), abs(rhs)), (lhs, rhs)
+    assert np.all(FTd[-1] == 0.0)
+    assert abs(lhs - float(np.sum(q[1:] * FTd[:-1]))) > 1e-3 * abs(lhs)
+    import copy
+
+    s2 = copy.copy(s)
+    s2.vs = s.vs * 0.9
+    assert abs(lhs - float(np.sum(q * orc.elastic_adjoint(s2, dp)))) > 1e-4 * abs(lhs)
