@@ -198,8 +198,11 @@ tb_status tb_forward(const tb_model *m, const tb_sparse *s, const tb_schedule *s
  * transposed coupling, lambda^k = H D (c/alpha) lambda^{k+1} + (2/alpha)
  * lambda^{k+1} - (beta/alpha) lambda^{k+2} + (P_r^T rec_in^k, 0), H =
  * diag(H0, Hz), D = [[1+2 eps, s], [s, 1]] (the forward couples through D H),
- * and src_out^n = P_s (c (lambda_p + lambda_r)^{n+1}). Elastic returns
- * TB_EUNSUPPORTED.
+ * and src_out^n = P_s (c (lambda_p + lambda_r)^{n+1}). Elastic (spatially
+ * blocked; rec_in is [2][nt][nrec], the vz block then the P block): the two
+ * passes of each step reversed with transposed staggered operators (D^T =
+ * -E, E^T = -D for the divergence D and strain E with zero outside the
+ * grid), and src_out^n = dt P_s (tr of the stress multiplier)^{n+1}.
  */
 tb_status tb_adjoint(const tb_model *m, const tb_sparse *s, const tb_schedule *sched, void *ws,
                      size_t ws_bytes, const float *rec_in, float *src_out, void *stream);

@@ -32,7 +32,8 @@ tb_sparse::~tb_sparse()
                     (void *)d_sc_ptr, (void *)d_sc_id, (void *)d_sc_w, (void *)d_rr_ptr,
                     (void *)d_rr_rec, (void *)d_rr_w, (void *)d_rid_scale, (void *)d_src_off,
                     (void *)d_src_alpha, (void *)d_rid_off, (void *)d_rc2_ptr, (void *)d_rc2_id,
-                    (void *)d_rc2_w, (void *)d_rid2_off})
+                    (void *)d_rc2_w, (void *)d_rid2_off, (void *)d_rr2_ptr, (void *)d_rr2_rec,
+                    (void *)d_rr2_w})
         if (p) (void)hipFree(p);
 }
 
@@ -854,6 +855,68 @@ tb_status tti_adjoint(const tb_model *m, tb_sparse *s, void *ws, const float *re
     return TB_OK;
 }
 
+// Adjoint of the elastic map q -> (vz, P) (spatially blocked), backwards from
+// zero multipliers; rec_in is [2][nt][nrec] (vz block, then P). The samples
+// dt tr(th) / alpha at the source points, reduced with the weights W alpha,
+// give qhat.
+tb_status elastic_adjoint(const tb_model *m, tb_sparse *s, void *ws, const float *rec_in,
+                          float *src_out, hipStream_t strm)
+{
+    const size_t fb = field_bytes(m), fe = m->field_elems();
+    const size_t nt1 = (size_t)m->nt + 1;
+    const int nt = m->nt, npts = s->npts, nrid = s->nrid, nrid2 = s->nrid2, nrec = s->nrec;
+    char *base = (char *)ws;
+    float *F[15];
+    for (int k = 0; k < 15; k++) F[k] = (float *)(base + k * fb);
+    float *srec = (float *)(base + 15 * fb);
+    float *adjP = (float *)(base + 15 * fb + align256(nt1 * std::max(npts, 1) * sizeof(float)));
+    float *adjV = adjP + (size_t)nt * nrid;
+    tb_status st;
+    for (int k = 0; k < 9; k++)
+        if ((st = launch_fill(F[k], fe, 0.0f, strm))) return st;
+    if (nt > 0 && nrec > 0) {
+        if (nrid > 0 && (st = launch_adj_inject(rec_in + (size_t)nt * nrec, nt, nrec, nrid,
+                                                s->d_rr_ptr, s->d_rr_rec, s->d_rr_w, nullptr, adjP,
+                                                strm)))
+            return st;
+        if (nrid2 > 0 && (st = launch_adj_inject(rec_in, nt, nrec, nrid2, s->d_rr2_ptr,
+                                                 s->d_rr2_rec, s->d_rr2_w, nullptr, adjV, strm)))
+            return st;
+    }
+    ElParams P{};
+    for (int k = 0; k < 3; k++) P.v[k] = F[k];
+    for (int k = 0; k < 6; k++) P.t[k] = F[3 + k];
+    for (int k = 0; k < 3; k++) P.bq[k] = m->d_el + k * fe;
+    P.lam = m->d_el + 3 * fe;
+    P.mu = m->d_el + 4 * fe;
+    for (int k = 0; k < 3; k++) P.ms[k] = m->d_el + (5 + k) * fe;
+    P.dx = m->d_damp;
+    P.dy = m->d_damp + m->n[0];
+    P.dz = m->d_damp + m->n[0] + m->n[1];
+    P.hdt = (float)(m->dt / 2.0);
+    const double *sw = stag_weights(m->so);
+    for (int j = 0; j < 6; j++) P.w[j] = j < m->r ? (float)sw[j] : 0.0f;
+    for (int a = 0; a < 3; a++) P.ih[a] = (float)(1.0 / m->h[a]);
+    P.nx = m->n[0];
+    P.ny = m->n[1];
+    P.nz = m->n[2];
+    P.nzp = m->nzp;
+    ElScratch S{};
+    for (int k = 0; k < 6; k++) S.f[k] = F[9 + k];
+    for (int tau = 0; tau < nt; tau++) {
+        if ((st = launch_elastic_adjoint_step(P, S, m->r, adjP + (size_t)tau * nrid, s->d_rid_off,
+                                              nrid, adjV + (size_t)tau * nrid2, s->d_rid2_off,
+                                              nrid2, srec + (size_t)tau * npts, s->d_src_off,
+                                              s->d_src_alpha, m->dt, npts, strm)))
+            return st;
+    }
+    if (src_out && s->nsrc > 0 && nt > 0)
+        if ((st = launch_trace_reduce(srec, npts, nt, s->d_sc_ptr, s->d_sc_id, s->d_sc_w, s->nsrc,
+                                      src_out, 1, strm)))
+            return st;
+    return TB_OK;
+}
+
 // Gradient of J = 1/2 sum_k |P_r p^k - d_obs^k|^2 of the TTI propagator with
 // respect to m = 1/vp^2, by checkpointing with recomputation:
 //   grad = -(1/dt^2) sum_{k=0}^{nt-2} sum_f y_f^{k+1} (c (A w^k)_f + alpha s^k),
@@ -1318,6 +1381,22 @@ tb_status tb_inspect_sparse(const tb_model *m, int32_t nsrc, const double *src_x
         if ((st = upload(&s->d_rc2_ptr, s->rc2_ptr)) || (st = upload(&s->d_rc2_id, s->rc2_id)) ||
             (st = upload(&s->d_rc2_w, w2)) || (st = upload(&s->d_rid2_off, roff2)))
             return st;
+        // Transposed vz mirror (adjoint injection at the vz points).
+        std::vector<int> c2(s->nrid2 + 1, 0);
+        for (size_t k = 0; k < s->rc2_id.size(); k++) c2[s->rc2_id[k] + 1]++;
+        for (int i = 0; i < s->nrid2; i++) c2[i + 1] += c2[i];
+        std::vector<int> rr2_rec(s->rc2_id.size());
+        std::vector<float> rr2_w(s->rc2_id.size());
+        std::vector<int> fill2(c2.begin(), c2.end() - 1);
+        for (int r = 0; r < nrec; r++)
+            for (int k = s->rc2_ptr[r]; k < s->rc2_ptr[r + 1]; k++) {
+                const int pos = fill2[s->rc2_id[k]]++;
+                rr2_rec[pos] = r;
+                rr2_w[pos] = (float)s->rc2_w[k];
+            }
+        if ((st = upload(&s->d_rr2_ptr, c2)) || (st = upload(&s->d_rr2_rec, rr2_rec)) ||
+            (st = upload(&s->d_rr2_w, rr2_w)))
+            return st;
     }
     *out = s.release();
     return TB_OK;
@@ -1356,9 +1435,11 @@ tb_status tb_workspace_size(const tb_model *m, const tb_sparse *s, const tb_sche
         // Acoustic: u, v (two levels each); TTI: lambda_p, lambda_r (two
         // levels each), psi_p, psi_r, z_p, z_r, q_p, q_r. Then the samples at
         // the source points and the decomposed residual.
-        *bytes = (m->physics == TB_TTI ? 10 : 4) * fb +
+        // Elastic: the nine multipliers and six scratch fields; its residual
+        // rows cover both receiver mirrors.
+        *bytes = (m->physics == TB_TTI ? 10 : (m->physics == TB_ELASTIC ? 15 : 4)) * fb +
                  align256(nt1 * std::max(s->npts, 1) * sizeof(float)) +
-                 align256((size_t)m->nt * std::max(s->nrid, 1) * sizeof(float));
+                 align256((size_t)m->nt * std::max(s->nrid + s->nrid2, 1) * sizeof(float));
         return TB_OK;
     case TB_OP_GRADIENT:
         *bytes = gradient_ws_bytes(m, s, sc, 0);
@@ -1400,10 +1481,6 @@ tb_status tb_adjoint(const tb_model *m, const tb_sparse *s_, const tb_schedule *
         set_error("tb_adjoint: invalid argument");
         return TB_EINVAL;
     }
-    if (m->physics == TB_ELASTIC) {
-        set_error("the adjoint is built for the acoustic and TTI propagators only");
-        return TB_EUNSUPPORTED;
-    }
     SchedChoice sc;
     tb_status st = resolve_schedule(m, sched, &sc);
     if (st) return st;
@@ -1415,6 +1492,7 @@ tb_status tb_adjoint(const tb_model *m, const tb_sparse *s_, const tb_schedule *
     }
     hipStream_t strm = (hipStream_t)stream;
     if (m->physics == TB_TTI) return tti_adjoint(m, s, ws, rec_in, src_out, strm);
+    if (m->physics == TB_ELASTIC) return elastic_adjoint(m, s, ws, rec_in, src_out, strm);
     const size_t fb = field_bytes(m);
     const size_t nt1 = (size_t)m->nt + 1;
     char *base = (char *)ws;

@@ -186,6 +186,138 @@ __global__ void el_rec(const float *__restrict__ txx, const float *__restrict__ 
     }
 }
 
+// ---- Adjoint (multipliers vh in P.v, th in P.t; six scratch fields S). ----
+// Stress-pass adjoint, pointwise part: S = C (th / alpha) with C = dt
+// (lambda, mu, the averaged mu), then th = (beta / alpha) th.
+__global__ void __launch_bounds__(256) el_adj_pre_str(const ElParams P, ElScratch S)
+{
+    Site q;
+    if (!locate4(P, q)) return;
+    f4 t[6];
+#pragma unroll
+    for (int c = 0; c < 6; c++) t[c] = ld4(P.t[c], q.off, true);
+    const f4 lam = ld4(P.lam, q.off, true), mu = ld4(P.mu, q.off, true);
+    const f4 m0 = ld4(P.ms[0], q.off, true), m1 = ld4(P.ms[1], q.off, true),
+             m2 = ld4(P.ms[2], q.off, true);
+    f4 o[6];
+    const float dxy = P.dx[q.x] + P.dy[q.y];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int z = q.z4 + k;
+        const float d = dxy + (z < P.nz ? P.dz[z] : 0.0f);
+        const float dd = d * P.hdt;
+        const float ia = d != 0.0f ? 1.0f / (1.0f + dd) : 1.0f;
+        const float a = t[0][k] * ia, b = t[1][k] * ia, c = t[2][k] * ia;
+        const float tr = a + b + c;
+        o[0][k] = __builtin_fmaf(lam[k], tr, 2.0f * mu[k] * a);
+        o[1][k] = __builtin_fmaf(lam[k], tr, 2.0f * mu[k] * b);
+        o[2][k] = __builtin_fmaf(lam[k], tr, 2.0f * mu[k] * c);
+        o[3][k] = m0[k] * (t[3][k] * ia);
+        o[4][k] = m1[k] * (t[4][k] * ia);
+        o[5][k] = m2[k] * (t[5][k] * ia);
+        const float g = (1.0f - dd) * ia;
+#pragma unroll
+        for (int f = 0; f < 6; f++) t[f][k] *= g;
+    }
+#pragma unroll
+    for (int c = 0; c < 6; c++) {
+        *(f4 *)(S.f[c] + q.off) = o[c];
+        *(f4 *)(P.t[c] + q.off) = t[c];
+    }
+}
+
+// vh -= div S (the divergence of the velocity pass).
+template <int R>
+__global__ void __launch_bounds__(256) el_adj_vel(const ElParams P, ElScratch S)
+{
+    Site q;
+    if (!locate4(P, q)) return;
+    const f4 fx = dstg<R, 0, true>(S.f[0], P, q) + dstg<R, 1, false>(S.f[3], P, q) +
+                  dstg<R, 2, false>(S.f[4], P, q);
+    const f4 fy = dstg<R, 0, false>(S.f[3], P, q) + dstg<R, 1, true>(S.f[1], P, q) +
+                  dstg<R, 2, false>(S.f[5], P, q);
+    const f4 fz = dstg<R, 0, false>(S.f[4], P, q) + dstg<R, 1, false>(S.f[5], P, q) +
+                  dstg<R, 2, true>(S.f[2], P, q);
+    const f4 f3[3] = {fx, fy, fz};
+#pragma unroll
+    for (int c = 0; c < 3; c++) *(f4 *)(P.v[c] + q.off) = ld4(P.v[c], q.off, true) - f3[c];
+}
+
+// Velocity-pass adjoint, pointwise part: S[0..2] = (dt b / alpha) vh, then
+// vh = (beta / alpha) vh.
+__global__ void __launch_bounds__(256) el_adj_pre_vel(const ElParams P, ElScratch S)
+{
+    Site q;
+    if (!locate4(P, q)) return;
+    const float dxy = P.dx[q.x] + P.dy[q.y];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        f4 v = ld4(P.v[c], q.off, true);
+        const f4 b = ld4(P.bq[c], q.off, true);
+        f4 u;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int z = q.z4 + k;
+            const float d = dxy + (z < P.nz ? P.dz[z] : 0.0f);
+            const float dd = d * P.hdt;
+            const float ia = d != 0.0f ? 1.0f / (1.0f + dd) : 1.0f;
+            u[k] = b[k] * (v[k] * ia);
+            v[k] *= (1.0f - dd) * ia;
+        }
+        *(f4 *)(S.f[c] + q.off) = u;
+        *(f4 *)(P.v[c] + q.off) = v;
+    }
+}
+
+// th -= strain(S[0..2]) (the strain operator of the stress pass).
+template <int R>
+__global__ void __launch_bounds__(256) el_adj_str(const ElParams P, ElScratch S)
+{
+    Site q;
+    if (!locate4(P, q)) return;
+    const f4 e[6] = {dstg<R, 0, false>(S.f[0], P, q), dstg<R, 1, false>(S.f[1], P, q),
+                     dstg<R, 2, false>(S.f[2], P, q),
+                     dstg<R, 1, true>(S.f[0], P, q) + dstg<R, 0, true>(S.f[1], P, q),
+                     dstg<R, 2, true>(S.f[0], P, q) + dstg<R, 0, true>(S.f[2], P, q),
+                     dstg<R, 2, true>(S.f[1], P, q) + dstg<R, 1, true>(S.f[2], P, q)};
+#pragma unroll
+    for (int c = 0; c < 6; c++) *(f4 *)(P.t[c] + q.off) = ld4(P.t[c], q.off, true) - e[c];
+}
+
+// Receiver adjoint of one step: th_ii += inc_p / 3 at the node points, vh_z
+// += inc_v at the vz points.
+__global__ void el_adj_inject(float *__restrict__ txx, float *__restrict__ tyy,
+                              float *__restrict__ tzz, float *__restrict__ vz,
+                              const float *__restrict__ inc_p, const long long *__restrict__ roff,
+                              int nrid, const float *__restrict__ inc_v,
+                              const long long *__restrict__ roff2, int nrid2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nrid) {
+        const long long o = roff[i];
+        const float a = inc_p[i] / 3.0f;
+        txx[o] += a;
+        tyy[o] += a;
+        tzz[o] += a;
+    } else if (i < nrid + nrid2) {
+        const int j = i - nrid;
+        vz[roff2[j]] += inc_v[j];
+    }
+}
+
+// dt (thxx + thyy + thzz) / alpha at the source points.
+__global__ void el_adj_record(const float *__restrict__ txx, const float *__restrict__ tyy,
+                              const float *__restrict__ tzz, const long long *__restrict__ off,
+                              const double *__restrict__ alpha, double dt, int n,
+                              float *__restrict__ row)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const long long o = off[i];
+        row[i] = (float)(dt * ((double)txx[o] + (double)tyy[o] + (double)tzz[o]) / alpha[i]);
+    }
+}
+
 unsigned nblocks(long long n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -218,6 +350,41 @@ tb_status launch_elastic_step(const ElParams &P, int r, const float *inc, const 
     if (nrid + nrid2 > 0) {
         hipLaunchKernelGGL(el_rec, dim3(nblocks(nrid + nrid2)), dim3(256), 0, st, P.t[0], P.t[1],
                            P.t[2], P.v[2], row_p, roff, nrid, row_v, roff2, nrid2);
+        TB_HIP(hipGetLastError());
+    }
+    return TB_OK;
+}
+
+tb_status launch_elastic_adjoint_step(const ElParams &P, const ElScratch &S, int r,
+                                      const float *inc_p, const long long *roff, int nrid,
+                                      const float *inc_v, const long long *roff2, int nrid2,
+                                      float *src_row, const long long *soff,
+                                      const double *src_alpha, double dt, int npts,
+                                      hipStream_t st)
+{
+    const long long total = (long long)P.nx * P.ny * (P.nzp / 4);
+    if (total == 0) return TB_OK;
+    if (npts > 0) {
+        hipLaunchKernelGGL(el_adj_record, dim3(nblocks(npts)), dim3(256), 0, st, P.t[0], P.t[1],
+                           P.t[2], soff, src_alpha, dt, npts, src_row);
+        TB_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(el_adj_pre_str, dim3(nblocks(total)), dim3(256), 0, st, P, S);
+    if (r == 2) hipLaunchKernelGGL(el_adj_vel<2>, dim3(nblocks(total)), dim3(256), 0, st, P, S);
+    else if (r == 4) hipLaunchKernelGGL(el_adj_vel<4>, dim3(nblocks(total)), dim3(256), 0, st, P, S);
+    else if (r == 6) hipLaunchKernelGGL(el_adj_vel<6>, dim3(nblocks(total)), dim3(256), 0, st, P, S);
+    else {
+        set_error("elastic radius %d not built", r);
+        return TB_EUNSUPPORTED;
+    }
+    hipLaunchKernelGGL(el_adj_pre_vel, dim3(nblocks(total)), dim3(256), 0, st, P, S);
+    if (r == 2) hipLaunchKernelGGL(el_adj_str<2>, dim3(nblocks(total)), dim3(256), 0, st, P, S);
+    else if (r == 4) hipLaunchKernelGGL(el_adj_str<4>, dim3(nblocks(total)), dim3(256), 0, st, P, S);
+    else hipLaunchKernelGGL(el_adj_str<6>, dim3(nblocks(total)), dim3(256), 0, st, P, S);
+    TB_HIP(hipGetLastError());
+    if (nrid + nrid2 > 0) {
+        hipLaunchKernelGGL(el_adj_inject, dim3(nblocks(nrid + nrid2)), dim3(256), 0, st, P.t[0],
+                           P.t[1], P.t[2], P.v[2], inc_p, roff, nrid, inc_v, roff2, nrid2);
         TB_HIP(hipGetLastError());
     }
     return TB_OK;

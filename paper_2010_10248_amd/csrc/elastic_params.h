@@ -18,6 +18,25 @@ struct ElParams {
     int nx, ny, nz, nzp;
 };
 
+// Six scratch fields of the adjoint step.
+struct ElScratch {
+    float *f[6];
+};
+
+// One step of the adjoint of q -> (vz, P), backwards: multipliers of the
+// velocities in P.v and of the stresses in P.t (in place). First src_row
+// receives dt (thxx + thyy + thzz) / alpha at the source points (soff, alpha
+// per point); then the stress-pass adjoint (S = C th / alpha, vh -= div S,
+// th *= beta/alpha), the velocity-pass adjoint (S = dt b vh / alpha,
+// th -= strain S, vh *= beta/alpha), and the receivers of the step (th_ii +=
+// inc_p / 3 at roff, vh_z += inc_v at roff2).
+tb_status launch_elastic_adjoint_step(const ElParams &P, const ElScratch &S, int r,
+                                      const float *inc_p, const long long *roff, int nrid,
+                                      const float *inc_v, const long long *roff2, int nrid2,
+                                      float *src_row, const long long *soff,
+                                      const double *src_alpha, double dt, int npts,
+                                      hipStream_t st);
+
 // One step: velocity and stress passes (in place), injection of inc[npts] at
 // soff into the three normal stresses, gather of P into row_p[nrid] at roff
 // and of vz into row_v[nrid2] at roff2.

@@ -157,6 +157,9 @@ struct tb_sparse {
     int *d_rc2_ptr = nullptr, *d_rc2_id = nullptr;
     float *d_rc2_w = nullptr;
     long long *d_rid2_off = nullptr;
+    // Transposed vz mirror for the adjoint: rid2 -> (receiver, W).
+    int *d_rr2_ptr = nullptr, *d_rr2_rec = nullptr;
+    float *d_rr2_w = nullptr;
     std::mutex mu;
     std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<tbw::TileLists>> tiles;
     ~tb_sparse();

@@ -61,9 +61,40 @@ def test_elastic_zero_source_and_unsupported_paths(torch_cuda):
     with pytest.raises(tb.TbError) as e:
         prop.forward(tb.schedule("tb", 2, 32))
     assert e.value.status == tb.EUNSUPPORTED
+    qh = prop.adjoint(torch.zeros((2, s.nt, s.rec_xyz.shape[0]), device="cuda"))
+    assert torch.count_nonzero(qh) == 0
     with pytest.raises(tb.TbError) as e:
-        prop.adjoint(torch.zeros((s.nt, s.rec_xyz.shape[0]), device="cuda"))
+        prop.gradient(torch.zeros((2, s.nt, s.rec_xyz.shape[0]), device="cuda"))
     assert e.value.status == tb.EUNSUPPORTED
+    prop.close()
+
+
+@pytest.mark.parametrize("so,n", [(4, (30, 28, 33)), (8, (34, 36, 32)), (12, (36, 35, 38))])
+def test_elastic_adjoint_dot_product_and_oracle(torch_cuda, orc, so, n):
+    """Adjoint of q -> (vz, P): the dot-product identity between the GPU
+    forward and the GPU adjoint, and the adjoint's output against the FP64
+    oracle's adjoint (pinned by the FP64 identity)."""
+    import torch
+
+    from paper_2010_10248_amd import tb
+
+    s = W.elastic_smooth(seed=60 + so, n=n, so=so, nt=40, nbl=5, nrec=10, sigma=3.0)
+    rng = np.random.Generator(np.random.PCG64(14))
+    q = rng.standard_normal(s.src_wav.shape)
+    dp = rng.standard_normal((2, s.nt, s.rec_xyz.shape[0]))
+    prop = tb.Propagator(s, src_wav=q)
+    Fq = prop.forward(tb.schedule("sb"))["traces"].double().cpu().numpy()
+    FTd = prop.adjoint(torch.as_tensor(dp.astype(np.float32), device="cuda"))
+    FTd = FTd.double().cpu().numpy()
+    lhs = float(np.sum(Fq * dp))
+    rhs = float(np.sum(q * FTd))
+    ref = orc.elastic_adjoint(s, dp)
+    e = _rel(FTd, ref)
+    print(f"elastic SO{so} adjoint: dot {lhs:.9e} {rhs:.9e} rel {abs(lhs - rhs) / abs(lhs):.2e}; "
+          f"vs oracle {e:.2e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    assert e <= TOL
+    assert np.all(FTd[-1] == 0.0)
     prop.close()
 
 
