@@ -78,11 +78,11 @@ def lib():
         if hasattr(L, "or_elastic_adjoint"):
             L.or_elastic_adjoint.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int,
                                              _dp, _dp, _dp, c_double, c_int, _dp, c_int, _dp,
-                                             _dp, vp]
+                                             _dp, vp, vp, vp]
         if hasattr(L, "or_elastic_forward"):
             L.or_elastic_forward.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int,
                                              _dp, _dp, _dp, c_double,
-                                             c_int, _dp, _dp, c_int, _dp, vp, vp, vp]
+                                             c_int, _dp, _dp, c_int, _dp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -312,23 +312,41 @@ def tti_operators(u, spacing, so: int, theta, phi):
 ELASTIC_FIELDS = ("vx", "vy", "vz", "txx", "tyy", "tzz", "txy", "txz", "tyz")
 
 
-def elastic_adjoint(shot, res: np.ndarray, vmax_damp: float = 0.0):
+def elastic_adjoint(shot, res: np.ndarray, vmax_damp: float = 0.0, vp=None, vs=None, rho=None,
+                    hist=None):
     """Adjoint of the elastic map q -> (vz, P) traces driven by
-    ``res[2][nt][nrec]`` (vz block, then P); returns qhat[nt][nsrc]."""
+    ``res[2][nt][nrec]`` (vz block, then P); returns qhat[nt][nsrc], or
+    (qhat, grad[3][...]) w.r.t. (lambda, mu, b = 1/rho) when the forward
+    history ``hist`` is given and res = traces - dobs."""
     n = np.asarray(shot.shape, dtype=np.int32)
+    f = lambda a, b: _f64(b if a is None else a)
     sx = _f64(shot.src_xyz)
     rx = _f64(shot.rec_xyz)
     qhat = np.zeros((shot.nt, sx.shape[0]))
+    grad = np.zeros((3,) + tuple(shot.shape)) if hist is not None else None
     st = lib().or_elastic_adjoint(n, _f64(shot.spacing), _f64(shot.origin), shot.space_order,
-                                  shot.nbl, float(shot.dt), shot.nt, _f64(shot.vp),
-                                  _f64(shot.vs), _f64(shot.rho), float(vmax_damp), sx.shape[0],
-                                  sx, rx.shape[0], rx, _f64(res), _ptr(qhat))
+                                  shot.nbl, float(shot.dt), shot.nt, f(vp, shot.vp),
+                                  f(vs, shot.vs), f(rho, shot.rho), float(vmax_damp),
+                                  sx.shape[0], sx, rx.shape[0], rx, _f64(res),
+                                  _ptr(None if hist is None else _f64(hist)), _ptr(grad),
+                                  _ptr(qhat))
     _check(st, "elastic_adjoint")
-    return qhat
+    return qhat if hist is None else (qhat, grad)
+
+
+def elastic_gradient(shot, dobs: np.ndarray, vmax_damp: float = 0.0, vp=None, vs=None, rho=None):
+    """J and dJ/d(lambda, mu, b) [3][...] of J = 1/2 |traces - dobs|^2 for
+    the elastic propagator (traces [2][nt][nrec]: vz, then P)."""
+    fw = elastic_forward(shot, vmax_damp=vmax_damp, vp=vp, vs=vs, rho=rho, want_history=True)
+    res = np.stack([fw["vz"], fw["p"]]) - _f64(dobs)
+    J = 0.5 * float(np.sum(res * res))
+    _, g = elastic_adjoint(shot, res, vmax_damp=vmax_damp, vp=vp, vs=vs, rho=rho,
+                           hist=fw["hist"])
+    return J, g
 
 
 def elastic_forward(shot, vmax_damp: float = 0.0, src_wav=None, vp=None, vs=None, rho=None,
-                    want_energy: bool = False):
+                    want_energy: bool = False, want_history: bool = False):
     """FP64 elastic velocity-stress forward of a ``workloads.Shot`` (zero
     initial state). Returns dict(vz[nt][nrec], p[nt][nrec] traces, the nine
     final fields by name (vz as "vz_field"), energy[nt] if asked)."""
@@ -342,15 +360,18 @@ def elastic_forward(shot, vmax_damp: float = 0.0, src_wav=None, vp=None, vs=None
     traces = np.zeros((2, shot.nt, nrec))
     state = np.zeros((9,) + tuple(shot.shape))
     energy = np.zeros(shot.nt) if want_energy else None
+    hist = np.zeros((shot.nt, 9) + tuple(shot.shape)) if want_history else None
     st = lib().or_elastic_forward(n, _f64(shot.spacing), _f64(shot.origin), shot.space_order,
                                   shot.nbl, float(shot.dt), shot.nt, vp, vs, rho,
                                   float(vmax_damp), sx.shape[0], sx, wav, nrec, rx,
-                                  _ptr(traces), _ptr(state), _ptr(energy))
+                                  _ptr(traces), _ptr(state), _ptr(energy), _ptr(hist))
     _check(st, "elastic_forward")
     out = {k if k != "vz" else "vz_field": state[i] for i, k in enumerate(ELASTIC_FIELDS)}
     out.update(vz=traces[0], p=traces[1])
     if want_energy:
         out["energy"] = energy
+    if want_history:
+        out["hist"] = hist
     return out
 
 

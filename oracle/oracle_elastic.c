@@ -102,13 +102,15 @@ static int interp(const egrid *G, const double *o, const double *u, const double
  * t^{nt} in the order vx vy vz txx tyy tzz txy txz tyz. energy[nt]
  * (optional): E^{n+1/2} = 1/2 sum_v |v^{n+1/2}|^2 / b + 1/2 <t^{n+1}, C^-1 t^n>
  * after step n (needs mu > 0 everywhere; exactly conserved by the scheme
- * without damping and source).
+ * without damping and source). hist[nt][9][N] (optional, for the gradient):
+ * per step t the velocities after its velocity pass, v^{t+1/2}, then the
+ * stresses it started from, t^t.
  */
 int or_elastic_forward(const int *n, const double *h, const double *o, int so, int nbl,
                        double dt, int nt, const double *vp, const double *vs, const double *rho,
                        double vmax_damp, int nsrc, const double *src_xyz, const double *src_wav,
                        int nrec, const double *rec_xyz, double *traces, double *state,
-                       double *energy)
+                       double *energy, double *hist)
 {
     egrid G;
     memcpy(G.n, n, sizeof(int) * 3);
@@ -170,6 +172,7 @@ int or_elastic_forward(const int *n, const double *h, const double *o, int so, i
             }
         }
         if (energy) memcpy(Fold, F + TXX * N, sizeof(double) * 6 * N);
+        if (hist) memcpy(hist + ((i64)t * NF + TXX) * N, F + TXX * N, sizeof(double) * 6 * N);
         /* Velocity pass. */
 #pragma omp parallel for schedule(static)
         for (i64 i = 0; i < n[0]; i++)
@@ -187,6 +190,7 @@ int or_elastic_forward(const int *n, const double *h, const double *o, int so, i
                     vy[q] = (be * vy[q] + dt * by[q] * fy) / al;
                     vz[q] = (be * vz[q] + dt * bz[q] * fz) / al;
                 }
+        if (hist) memcpy(hist + (i64)t * NF * N, F, sizeof(double) * 3 * N);
         /* Stress pass. */
 #pragma omp parallel for schedule(static)
         for (i64 i = 0; i < n[0]; i++)
@@ -260,11 +264,52 @@ done:
  *   u = dt b vh / alpha;  th += -E(u);  vh = (beta/alpha) vh     (velocity pass)
  *   vh_z += P_vz^T res_vz^t;  th_ii += P^T res_P^t / 3           (receivers)
  * res[2][nt][nrec] (vz block, then P block); qhat[nt][nsrc].
+ *
+ * With the forward history (hist of or_elastic_forward), grad[3][N]
+ * receives the gradient of J = 1/2 |traces - dobs|^2 (res = traces - dobs)
+ * with respect to lambda, mu and b = 1/rho at the nodes, damping held fixed.
+ * The stress pass of step t contributes, with s = th^{t+1} / alpha and e the
+ * strain of v^{t+1/2},
+ *   dJ/dlambda += dt tr(s) tr(e),  dJ/dmu += 2 dt sum_i s_ii e_ii  (nodes),
+ *   dt s_xy e_xy (and xz, yz) at each shear point, shared 1/4 by the four
+ *   nodes whose mean gives mu there;
+ * the velocity pass, with vh the multiplier of v^{t+1/2} after the stress
+ * pass's adjoint and D t^t the divergence of the forward stress,
+ *   dt vh_a (D t^t)_a / alpha at each velocity point, shared 1/2 by the two
+ *   nodes whose mean gives b there (a node beyond the grid is the nearest
+ *   inside one, as in the means).
  */
+static void share4(const egrid *G, double *g, i64 i, i64 j, i64 k, int a1, int a2, double c)
+{
+    for (int u = 0; u < 2; u++)
+        for (int v = 0; v < 2; v++) {
+            i64 ii = i, jj = j, kk = k;
+            if (u) {
+                if (a1 == 0) ii = ii + 1 < G->n[0] ? ii + 1 : G->n[0] - 1;
+                if (a1 == 1) jj = jj + 1 < G->n[1] ? jj + 1 : G->n[1] - 1;
+            }
+            if (v) {
+                if (a2 == 1) jj = jj + 1 < G->n[1] ? jj + 1 : G->n[1] - 1;
+                if (a2 == 2) kk = kk + 1 < G->n[2] ? kk + 1 : G->n[2] - 1;
+            }
+            g[idx(G, ii, jj, kk)] += 0.25 * c;
+        }
+}
+
+static void share2(const egrid *G, double *g, i64 i, i64 j, i64 k, int ax, double c)
+{
+    g[idx(G, i, j, k)] += 0.5 * c;
+    if (ax == 0) i = i + 1 < G->n[0] ? i + 1 : G->n[0] - 1;
+    if (ax == 1) j = j + 1 < G->n[1] ? j + 1 : G->n[1] - 1;
+    if (ax == 2) k = k + 1 < G->n[2] ? k + 1 : G->n[2] - 1;
+    g[idx(G, i, j, k)] += 0.5 * c;
+}
+
 int or_elastic_adjoint(const int *n, const double *h, const double *o, int so, int nbl,
                        double dt, int nt, const double *vp, const double *vs, const double *rho,
                        double vmax_damp, int nsrc, const double *src_xyz, int nrec,
-                       const double *rec_xyz, const double *res, double *qhat)
+                       const double *rec_xyz, const double *res, const double *hist,
+                       double *grad, double *qhat)
 {
     egrid G;
     memcpy(G.n, n, sizeof(int) * 3);
@@ -315,7 +360,36 @@ int or_elastic_adjoint(const int *n, const double *h, const double *o, int so, i
     double ovz[3] = {o[0], o[1], o[2] + 0.5 * h[2]};
     int st = OR_OK;
     if (qhat) memset(qhat, 0, sizeof(double) * (size_t)nt * nsrc);
+    if (grad && !hist) {
+        st = OR_EINVAL;
+        goto done;
+    }
+    if (grad) memset(grad, 0, sizeof(double) * 3 * N);
     for (int t = nt - 1; t >= 0; t--) {
+        if (grad) {
+            /* Stress-pass terms: s = th^{t+1} / alpha against e(v^{t+1/2}). */
+            const double *hv = hist + (i64)t * NF * N;
+            const double *hvx = hv, *hvy = hv + N, *hvz = hv + 2 * N;
+            double *gl = grad, *gm = grad + N;
+            for (i64 i = 0; i < n[0]; i++)
+                for (i64 j = 0; j < n[1]; j++)
+                    for (i64 k = 0; k < n[2]; k++) {
+                        i64 q = idx(&G, i, j, k);
+                        const double al = 1.0 + dmp[q] * dt / 2.0;
+                        const double exx = dst(&G, hvx, i, j, k, 0, 0),
+                                     eyy = dst(&G, hvy, i, j, k, 1, 0),
+                                     ezz = dst(&G, hvz, i, j, k, 2, 0);
+                        const double a = txx[q] / al, bb = tyy[q] / al, c = tzz[q] / al;
+                        gl[q] += dt * (a + bb + c) * (exx + eyy + ezz);
+                        gm[q] += 2.0 * dt * (a * exx + bb * eyy + c * ezz);
+                        const double gxy = dst(&G, hvx, i, j, k, 1, 1) + dst(&G, hvy, i, j, k, 0, 1);
+                        const double gxz = dst(&G, hvx, i, j, k, 2, 1) + dst(&G, hvz, i, j, k, 0, 1);
+                        const double gyz = dst(&G, hvy, i, j, k, 2, 1) + dst(&G, hvz, i, j, k, 1, 1);
+                        share4(&G, gm, i, j, k, 0, 1, dt * txy[q] / al * gxy);
+                        share4(&G, gm, i, j, k, 0, 2, dt * txz[q] / al * gxz);
+                        share4(&G, gm, i, j, k, 1, 2, dt * tyz[q] / al * gyz);
+                    }
+        }
         for (int s = 0; qhat && s < nsrc; s++) {
             int nodes[24];
             double w[8];
@@ -353,6 +427,28 @@ int or_elastic_adjoint(const int *n, const double *h, const double *o, int so, i
                     vz[q] -= dt * (dst(&G, sxz, i, j, k, 0, 0) + dst(&G, syz, i, j, k, 1, 0) +
                                    dst(&G, szz, i, j, k, 2, 1));
                 }
+        if (grad) {
+            /* Velocity-pass terms: vh (now complete) against D t^t. */
+            const double *ht = hist + ((i64)t * NF + TXX) * N;
+            const double *hxx = ht, *hyy = ht + N, *hzz = ht + 2 * N, *hxy = ht + 3 * N,
+                         *hxz = ht + 4 * N, *hyz = ht + 5 * N;
+            double *gb = grad + 2 * N;
+            for (i64 i = 0; i < n[0]; i++)
+                for (i64 j = 0; j < n[1]; j++)
+                    for (i64 k = 0; k < n[2]; k++) {
+                        i64 q = idx(&G, i, j, k);
+                        const double al = 1.0 + dmp[q] * dt / 2.0;
+                        const double fx = dst(&G, hxx, i, j, k, 0, 1) + dst(&G, hxy, i, j, k, 1, 0) +
+                                          dst(&G, hxz, i, j, k, 2, 0);
+                        const double fy = dst(&G, hxy, i, j, k, 0, 0) + dst(&G, hyy, i, j, k, 1, 1) +
+                                          dst(&G, hyz, i, j, k, 2, 0);
+                        const double fz = dst(&G, hxz, i, j, k, 0, 0) + dst(&G, hyz, i, j, k, 1, 0) +
+                                          dst(&G, hzz, i, j, k, 2, 1);
+                        share2(&G, gb, i, j, k, 0, dt * vx[q] / al * fx);
+                        share2(&G, gb, i, j, k, 1, dt * vy[q] / al * fy);
+                        share2(&G, gb, i, j, k, 2, dt * vz[q] / al * fz);
+                    }
+        }
         /* Adjoint of the velocity pass: u = dt b vh / alpha into S[0..2]. */
         for (i64 q = 0; q < N; q++) {
             const double al = 1.0 + dmp[q] * dt / 2.0, be = 1.0 - dmp[q] * dt / 2.0;

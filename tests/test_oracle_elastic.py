@@ -112,3 +112,51 @@ def test_elastic_adjoint_dot_product(orc, so):
     s2 = copy.copy(s)
     s2.vs = s.vs * 0.9
     assert abs(lhs - float(np.sum(q * orc.elastic_adjoint(s2, dp)))) > 1e-4 * abs(lhs)
+
+
+@pytest.mark.parametrize("which", [0, 1, 2])
+def test_elastic_gradient_taylor(orc, which):
+    """Gradient of the elastic misfit w.r.t. lambda, mu and b = 1/rho at the
+    nodes (or_elastic_adjoint with the forward history): perturbing one of
+    them along a smooth direction, the first-order Taylor remainder falls as
+    h^2 over halvings. The model passes through (vp, vs, rho), so the test
+    also checks the chain through the two- and four-node means."""
+    s = W.elastic_smooth(seed=53, n=(16, 18, 20), so=8, nt=40, nbl=4, nrec=6, sigma=3.0)
+    vmax = 4000.0
+    rho0 = s.rho
+    lam0 = rho0 * (s.vp ** 2 - 2 * s.vs ** 2)
+    mu0 = rho0 * s.vs ** 2
+    b0 = 1.0 / rho0
+    n = s.shape
+    X, Y, Z = np.meshgrid(*[np.arange(k, dtype=float) for k in n], indexing="ij")
+    blob = np.exp(-((X - n[0] / 2) ** 2 + (Y - n[1] / 2) ** 2 + (Z - n[2] / 2) ** 2) / 12.0)
+    fw = orc.elastic_forward(s, vmax_damp=vmax, vs=s.vs * (1.0 + 0.04 * blob),
+                             vp=s.vp * (1.0 + 0.03 * blob))
+    dobs = np.stack([fw["vz"], fw["p"]])
+
+    def model(lam, mu, b):
+        rho = 1.0 / b
+        return dict(vp=np.sqrt((lam + 2 * mu) * b), vs=np.sqrt(mu * b), rho=rho)
+
+    J0, g = orc.elastic_gradient(s, dobs, vmax_damp=vmax)
+    rng = np.random.Generator(np.random.PCG64(20 + which))
+    from scipy.ndimage import gaussian_filter
+
+    base = (lam0, mu0, b0)
+    dp = gaussian_filter(rng.standard_normal(n), 2.0)
+    dp *= 0.005 * np.abs(base[which]).max() / np.abs(dp).max()
+    gd = float(np.sum(g[which] * dp))
+    errs = []
+    for k in range(5):
+        hstep = 2.0 ** (-k)
+        p = [x.copy() for x in base]
+        p[which] = p[which] + hstep * dp
+        f2 = orc.elastic_forward(s, vmax_damp=vmax, **model(*p))
+        Jh = 0.5 * float(np.sum((np.stack([f2["vz"], f2["p"]]) - dobs) ** 2))
+        errs.append(abs(Jh - J0 - hstep * gd))
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    assert all(3.4 < r < 4.7 for r in ratios), ratios
+    # The first-order term dominates the remainder at the smallest step (a
+    # random smooth direction can be nearly orthogonal to the gradient, so
+    # the largest step is not used for this).
+    assert abs(2.0 ** (-4) * gd) > 4 * errs[-1]
