@@ -230,7 +230,15 @@ tb_status tb_adjoint(const tb_model *m, const tb_sparse *s, const tb_schedule *s
  *   dJ/dm = -(1/dt^2) sum_{k=1}^{nt-1} sum_{f=p,r} y_f^k (c (A w^{k-1})_f
  *           + alpha s^{k-1}),  A = D H the coupled operator,
  * eps, delta and the axis held fixed; checkpoints of (p, r, w_p, w_r) every K
- * levels (0 = ceil(sqrt(nt))). Elastic returns TB_EUNSUPPORTED.
+ * levels (0 = ceil(sqrt(nt))). Elastic (spatially blocked): J on both
+ * trace blocks (d_obs [2][nt][nrec], vz then P), gradient with respect to
+ * lambda, mu and b = 1/rho at the nodes into grad_m [3][nx][ny][nz], the
+ * stress-pass terms (dt tr(s) tr(e), 2 dt s_ii e_ii, and dt s_c e_c at each
+ * shear point shared 1/4 by the four nodes of its mean of mu) and the
+ * velocity-pass terms (dt vh_a (div t)_a / alpha at each velocity point,
+ * shared 1/2 by the two nodes of its mean of b), s the stress multiplier over
+ * alpha and e the strain of the forward velocities; checkpoints of the nine
+ * fields every K steps.
  * Errors: TB_EINVAL, TB_EWORKSPACE, TB_EUNSUPPORTED, TB_EHIP.
  */
 tb_status tb_gradient(const tb_model *m, const tb_sparse *s, const tb_schedule *sched, void *ws,

@@ -584,9 +584,48 @@ TtiGradLayout tti_grad_layout(const tb_model *m, const tb_sparse *s, int every)
     return L;
 }
 
+// Elastic gradient workspace: the forward state (9 fields), the multipliers
+// and scratch (15), K level slots of (v^{t+1/2}, t^t) (9 each), a checkpoint
+// of the 9 fields at the start of every segment, nine FP64 accumulators, the
+// per-step rows, traces, residual and loss.
+struct ElGradLayout {
+    int K = 1, nseg = 0;
+    size_t F = 0, A = 0, slots = 0, cps = 0, acc = 0, rec = 0, traces = 0, res = 0, adj = 0,
+           loss = 0, total = 0;
+};
+
+ElGradLayout el_grad_layout(const tb_model *m, const tb_sparse *s, int every)
+{
+    ElGradLayout L;
+    const int nt = m->nt;
+    L.K = every > 0 ? every : ceil_sqrt(std::max(nt, 1));
+    L.nseg = (nt + L.K - 1) / L.K;
+    const size_t fb = field_bytes(m), nt1 = (size_t)nt + 1;
+    const size_t nr = (size_t)std::max(s->nrid + s->nrid2, 1);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    L.F = take(9 * fb);
+    L.A = take(15 * fb);
+    L.slots = take(9 * (size_t)L.K * fb);
+    L.cps = take(9 * (size_t)L.nseg * fb);
+    L.acc = take(9 * m->field_elems() * sizeof(double));
+    L.rec = take(nt1 * nr * sizeof(float));
+    L.traces = take(2 * (size_t)nt * std::max(s->nrec, 1) * sizeof(float));
+    L.res = take(2 * (size_t)nt * std::max(s->nrec, 1) * sizeof(float));
+    L.adj = take((size_t)nt * nr * sizeof(float));
+    L.loss = take(sizeof(double));
+    L.total = o;
+    return L;
+}
+
 size_t gradient_ws_bytes(const tb_model *m, const tb_sparse *s, const SchedChoice &sc, int every)
 {
     if (m->physics == TB_TTI) return tti_grad_layout(m, s, every).total;
+    if (m->physics == TB_ELASTIC) return el_grad_layout(m, s, every).total;
     return grad_layout(m, s, sc, every).total;
 }
 
@@ -853,6 +892,135 @@ tb_status tti_adjoint(const tb_model *m, tb_sparse *s, void *ws, const float *re
                                       src_out, 1, strm)))
             return st;
     return TB_OK;
+}
+
+// Model part of the elastic kernel parameters, with the nine fields at F.
+ElParams el_params(const tb_model *m, float *const *F)
+{
+    const size_t fe = m->field_elems();
+    ElParams P{};
+    for (int k = 0; k < 3; k++) P.v[k] = F[k];
+    for (int k = 0; k < 6; k++) P.t[k] = F[3 + k];
+    for (int k = 0; k < 3; k++) P.bq[k] = m->d_el + k * fe;
+    P.lam = m->d_el + 3 * fe;
+    P.mu = m->d_el + 4 * fe;
+    for (int k = 0; k < 3; k++) P.ms[k] = m->d_el + (5 + k) * fe;
+    P.dx = m->d_damp;
+    P.dy = m->d_damp + m->n[0];
+    P.dz = m->d_damp + m->n[0] + m->n[1];
+    P.hdt = (float)(m->dt / 2.0);
+    const double *sw = stag_weights(m->so);
+    for (int j = 0; j < 6; j++) P.w[j] = j < m->r ? (float)sw[j] : 0.0f;
+    for (int a = 0; a < 3; a++) P.ih[a] = (float)(1.0 / m->h[a]);
+    P.nx = m->n[0];
+    P.ny = m->n[1];
+    P.nz = m->n[2];
+    P.nzp = m->nzp;
+    return P;
+}
+
+// Gradient of J = 1/2 |traces - d_obs|^2 (traces [2][nt][nrec]: vz, then P)
+// of the elastic propagator with respect to lambda, mu and b = 1/rho at the
+// nodes, by checkpointing with recomputation: the forward run stores the nine
+// fields at the start of every segment of K steps; the backward run
+// recomputes a segment's levels (v^{t+1/2}, t^t) into the slots, then for
+// each step images them against the multipliers and takes the adjoint step
+// (elastic_adjoint's recursion). grad_out is [3][nx][ny][nz].
+tb_status elastic_gradient(const tb_model *m, tb_sparse *s, int every, void *ws,
+                           const float *d_obs, float *grad_out, double *loss_out, hipStream_t strm)
+{
+    const ElGradLayout L = el_grad_layout(m, s, every);
+    const size_t fb = field_bytes(m), fe = m->field_elems();
+    const int nt = m->nt, npts = s->npts, nrid = s->nrid, nrid2 = s->nrid2, nrec = s->nrec;
+    const int K = L.K, stride = nrid + nrid2;
+    char *base = (char *)ws;
+    auto fld = [&](size_t off, size_t k) { return (float *)(base + off + k * fb); };
+    float *rec = (float *)(base + L.rec), *traces = (float *)(base + L.traces);
+    float *res = (float *)(base + L.res);
+    float *adjP = (float *)(base + L.adj), *adjV = adjP + (size_t)nt * nrid;
+    double *loss = (double *)(base + L.loss);
+    tb_status st;
+    float *Ff[9], *Af[9];
+    for (int k = 0; k < 9; k++) {
+        Ff[k] = fld(L.F, k);
+        Af[k] = fld(L.A, k);
+        if ((st = launch_fill(Ff[k], fe, 0.0f, strm)) || (st = launch_fill(Af[k], fe, 0.0f, strm)))
+            return st;
+    }
+    ElGradAcc G{};
+    double *acc = (double *)(base + L.acc);
+    if ((st = launch_zero64(acc, 9 * fe, strm))) return st;
+    G.lam = acc;
+    G.mu = acc + fe;
+    for (int c = 0; c < 3; c++) {
+        G.sh[c] = acc + (2 + c) * fe;
+        G.bv[c] = acc + (5 + c) * fe;
+    }
+    if (stride > 0 && (st = launch_fill(rec, (size_t)stride, 0.0f, strm))) return st;
+    const ElParams PF = el_params(m, Ff), PA = el_params(m, Af);
+    const long long *soff = s->d_src_off, *roff = s->d_rid_off, *roff2 = s->d_rid2_off;
+    for (int t = 0; t < nt; t++) {
+        if (t % K == 0)
+            for (int f = 0; f < 9; f++)
+                TB_HIP(hipMemcpyAsync(fld(L.cps, 9 * (size_t)(t / K) + f), Ff[f], fb,
+                                      hipMemcpyDeviceToDevice, strm));
+        float *row = rec + (size_t)(t + 1) * stride;
+        if ((st = launch_elastic_step(PF, m->r, s->d_dcmp + (size_t)t * npts, soff, npts, row, roff,
+                                      nrid, row + nrid, roff2, nrid2, strm)))
+            return st;
+    }
+    if (nt > 0 && nrec > 0) {
+        if ((st = launch_trace_reduce(rec + nrid, stride, nt, s->d_rc2_ptr, s->d_rc2_id,
+                                      s->d_rc2_w, nrec, traces, 0, strm)) ||
+            (st = launch_trace_reduce(rec, stride, nt, s->d_rc_ptr, s->d_rc_id, s->d_rc_w, nrec,
+                                      traces + (size_t)nt * nrec, 0, strm)))
+            return st;
+    }
+    if ((st = launch_residual_loss(traces, d_obs, 2LL * nt * nrec, res, loss, strm))) return st;
+    if (loss_out)
+        TB_HIP(hipMemcpyAsync(loss_out, loss, sizeof(double), hipMemcpyDeviceToHost, strm));
+    if (nt > 0 && nrec > 0) {
+        if (nrid > 0 && (st = launch_adj_inject(res + (size_t)nt * nrec, nt, nrec, nrid,
+                                                s->d_rr_ptr, s->d_rr_rec, s->d_rr_w, nullptr, adjP,
+                                                strm)))
+            return st;
+        if (nrid2 > 0 && (st = launch_adj_inject(res, nt, nrec, nrid2, s->d_rr2_ptr, s->d_rr2_rec,
+                                                 s->d_rr2_w, nullptr, adjV, strm)))
+            return st;
+    }
+    ElScratch S{};
+    for (int k = 0; k < 6; k++) S.f[k] = fld(L.A, 9 + k);
+    for (int j = L.nseg - 1; j >= 0; j--) {
+        const int k0 = j * K, k1 = std::min(nt, k0 + K);
+        for (int f = 0; f < 9; f++)
+            TB_HIP(hipMemcpyAsync(Ff[f], fld(L.cps, 9 * (size_t)j + f), fb,
+                                  hipMemcpyDeviceToDevice, strm));
+        for (int t = k0; t < k1; t++) {
+            float *sl = fld(L.slots, 9 * (size_t)(t - k0));
+            for (int f = 0; f < 6; f++)
+                TB_HIP(hipMemcpyAsync(sl + (3 + f) * (fb / sizeof(float)), Ff[3 + f], fb,
+                                      hipMemcpyDeviceToDevice, strm));
+            if ((st = launch_elastic_step(PF, m->r, s->d_dcmp + (size_t)t * npts, soff, npts,
+                                          nullptr, roff, 0, nullptr, roff2, 0, strm)))
+                return st;
+            for (int f = 0; f < 3; f++)
+                TB_HIP(hipMemcpyAsync(sl + f * (fb / sizeof(float)), Ff[f], fb,
+                                      hipMemcpyDeviceToDevice, strm));
+        }
+        for (int t = k1 - 1; t >= k0; t--) {
+            const int tau = nt - 1 - t;
+            float *sl = fld(L.slots, 9 * (size_t)(t - k0));
+            ElScratch fv{}, ft{};
+            for (int f = 0; f < 3; f++) fv.f[f] = sl + f * (fb / sizeof(float));
+            for (int f = 0; f < 6; f++) ft.f[f] = sl + (3 + f) * (fb / sizeof(float));
+            if ((st = launch_elastic_gradient_step(PA, S, fv, ft, G, m->r,
+                                                   adjP + (size_t)tau * nrid, roff, nrid,
+                                                   adjV + (size_t)tau * nrid2, roff2, nrid2,
+                                                   m->dt, strm)))
+                return st;
+        }
+    }
+    return launch_elastic_grad_finish(PA, G, grad_out, strm);
 }
 
 // Adjoint of the elastic map q -> (vz, P) (spatially blocked), backwards from
@@ -1539,10 +1707,6 @@ tb_status tb_gradient(const tb_model *m, const tb_sparse *s_, const tb_schedule 
         set_error("tb_gradient: invalid argument");
         return TB_EINVAL;
     }
-    if (m->physics == TB_ELASTIC) {
-        set_error("the gradient is built for the acoustic and TTI propagators only");
-        return TB_EUNSUPPORTED;
-    }
     SchedChoice sc;
     tb_status st = resolve_schedule(m, sched, &sc);
     if (st) return st;
@@ -1552,8 +1716,11 @@ tb_status tb_gradient(const tb_model *m, const tb_sparse *s_, const tb_schedule 
         return TB_EWORKSPACE;
     }
     hipStream_t strm = (hipStream_t)stream;
-    if (m->physics == TB_TTI) {
-        if ((st = tti_gradient(m, s, checkpoint_every, ws, d_obs, grad_m, loss_out, strm)))
+    if (m->physics == TB_TTI || m->physics == TB_ELASTIC) {
+        if ((st = m->physics == TB_TTI
+                      ? tti_gradient(m, s, checkpoint_every, ws, d_obs, grad_m, loss_out, strm)
+                      : elastic_gradient(m, s, checkpoint_every, ws, d_obs, grad_m, loss_out,
+                                         strm)))
             return st;
         if (loss_out) TB_HIP(hipStreamSynchronize(strm));
         return TB_OK;

@@ -318,6 +318,126 @@ __global__ void el_adj_record(const float *__restrict__ txx, const float *__rest
     }
 }
 
+// ---- Gradient w.r.t. (lambda, mu, b) at the nodes (FP64 accumulators,
+// padded layout; z < nz only). ----
+// Stress-pass terms of one step: with s = th / alpha (th the multiplier of
+// t^{t+1}) and e the strain of the forward v^{t+1/2} (fv),
+//   glam += dt tr(s) tr(e),  gmu += 2 dt sum_i s_ii e_ii,
+//   sh[c] += dt s_c e_c at the shear points (spread onto the nodes at the end).
+template <int R>
+__global__ void __launch_bounds__(256) el_img_str(const ElParams P, ElGradAcc G, ElScratch fv,
+                                                  double dt)
+{
+    Site q;
+    if (!locate4(P, q)) return;
+    const f4 e[6] = {dstg<R, 0, false>(fv.f[0], P, q), dstg<R, 1, false>(fv.f[1], P, q),
+                     dstg<R, 2, false>(fv.f[2], P, q),
+                     dstg<R, 1, true>(fv.f[0], P, q) + dstg<R, 0, true>(fv.f[1], P, q),
+                     dstg<R, 2, true>(fv.f[0], P, q) + dstg<R, 0, true>(fv.f[2], P, q),
+                     dstg<R, 2, true>(fv.f[1], P, q) + dstg<R, 1, true>(fv.f[2], P, q)};
+    f4 t[6];
+#pragma unroll
+    for (int c = 0; c < 6; c++) t[c] = ld4(P.t[c], q.off, true);
+    const float dxy = P.dx[q.x] + P.dy[q.y];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int z = q.z4 + k;
+        if (z >= P.nz) continue;
+        const double ia = 1.0 / (1.0 + (double)((dxy + P.dz[z]) * P.hdt));
+        const long long o = q.off + k;
+        const double sxx = t[0][k] * ia, syy = t[1][k] * ia, szz = t[2][k] * ia;
+        const double exx = e[0][k], eyy = e[1][k], ezz = e[2][k];
+        G.lam[o] += dt * (sxx + syy + szz) * (exx + eyy + ezz);
+        G.mu[o] += 2.0 * dt * (sxx * exx + syy * eyy + szz * ezz);
+#pragma unroll
+        for (int c = 0; c < 3; c++) G.sh[c][o] += dt * (t[3 + c][k] * ia) * (double)e[3 + c][k];
+    }
+}
+
+// Velocity-pass terms: bv[a] += dt vh_a (div t^t)_a / alpha at the velocity
+// points (vh the complete multiplier of v^{t+1/2}, ft the forward t^t).
+template <int R>
+__global__ void __launch_bounds__(256) el_img_vel(const ElParams P, ElGradAcc G, ElScratch ft,
+                                                  double dt)
+{
+    Site q;
+    if (!locate4(P, q)) return;
+    const f4 fx = dstg<R, 0, true>(ft.f[0], P, q) + dstg<R, 1, false>(ft.f[3], P, q) +
+                  dstg<R, 2, false>(ft.f[4], P, q);
+    const f4 fy = dstg<R, 0, false>(ft.f[3], P, q) + dstg<R, 1, true>(ft.f[1], P, q) +
+                  dstg<R, 2, false>(ft.f[5], P, q);
+    const f4 fz = dstg<R, 0, false>(ft.f[4], P, q) + dstg<R, 1, false>(ft.f[5], P, q) +
+                  dstg<R, 2, true>(ft.f[2], P, q);
+    const f4 f3[3] = {fx, fy, fz};
+    const float dxy = P.dx[q.x] + P.dy[q.y];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const f4 v = ld4(P.v[c], q.off, true);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int z = q.z4 + k;
+            if (z >= P.nz) continue;
+            const double ia = 1.0 / (1.0 + (double)((dxy + P.dz[z]) * P.hdt));
+            G.bv[c][q.off + k] += dt * (double)v[k] * ia * (double)f3[c][k];
+        }
+    }
+}
+
+// Spreads the per-element terms onto the nodes (the transposes of the
+// means): gmu gets 1/4 of each shear point's term at its four nodes, gb 1/2
+// of each velocity point's term at its two nodes; a node index beyond the
+// grid is the last node inside (so the last node collects that share too).
+// Then out[0..2] = (glam, gmu, gb) unpadded.
+__global__ void el_grad_finish(const ElParams P, ElGradAcc G, float *__restrict__ out)
+{
+    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long N = (long long)P.nx * P.ny * P.nz;
+    if (gid >= N) return;
+    const int z = (int)(gid % P.nz);
+    const long long xy = gid / P.nz;
+    const int y = (int)(xy % P.ny), x = (int)(xy / P.ny);
+    const int n3[3] = {P.nx, P.ny, P.nz};
+    const int c3[3] = {x, y, z};
+    auto at = [&](const double *f, int i, int j, int k) {
+        return f[((long long)i * P.ny + j) * P.nzp + k];
+    };
+    // Weights of the element indices a = c and a = c - 1 along an axis.
+    auto w0 = [&](int ax) { return c3[ax] == n3[ax] - 1 ? 2.0 : 1.0; };
+    auto w1 = [&](int ax) { return c3[ax] >= 1 ? 1.0 : 0.0; };
+    auto shifted = [&](int ax, int d, int *ijk) {
+        ijk[0] = x;
+        ijk[1] = y;
+        ijk[2] = z;
+        ijk[ax] -= d;
+    };
+    double gmu = at(G.mu, x, y, z);
+    const int pairs[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int c = 0; c < 3; c++) {
+        const int a1 = pairs[c][0], a2 = pairs[c][1];
+        for (int d1 = 0; d1 < 2; d1++)
+            for (int d2 = 0; d2 < 2; d2++) {
+                const double w = (d1 ? w1(a1) : w0(a1)) * (d2 ? w1(a2) : w0(a2));
+                if (w == 0.0) continue;
+                int ijk[3];
+                shifted(a1, d1, ijk);
+                ijk[a2] -= d2;
+                gmu += 0.25 * w * at(G.sh[c], ijk[0], ijk[1], ijk[2]);
+            }
+    }
+    double gb = 0.0;
+    for (int a = 0; a < 3; a++)
+        for (int d = 0; d < 2; d++) {
+            const double w = d ? w1(a) : w0(a);
+            if (w == 0.0) continue;
+            int ijk[3];
+            shifted(a, d, ijk);
+            gb += 0.5 * w * at(G.bv[a], ijk[0], ijk[1], ijk[2]);
+        }
+    out[gid] = (float)at(G.lam, x, y, z);
+    out[N + gid] = (float)gmu;
+    out[2 * N + gid] = (float)gb;
+}
+
 unsigned nblocks(long long n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -387,6 +507,52 @@ tb_status launch_elastic_adjoint_step(const ElParams &P, const ElScratch &S, int
                            P.t[1], P.t[2], P.v[2], inc_p, roff, nrid, inc_v, roff2, nrid2);
         TB_HIP(hipGetLastError());
     }
+    return TB_OK;
+}
+
+tb_status launch_elastic_gradient_step(const ElParams &P, const ElScratch &S,
+                                       const ElScratch &fv, const ElScratch &ft,
+                                       const ElGradAcc &G, int r, const float *inc_p,
+                                       const long long *roff, int nrid, const float *inc_v,
+                                       const long long *roff2, int nrid2, double dt,
+                                       hipStream_t st)
+{
+    const long long total = (long long)P.nx * P.ny * (P.nzp / 4);
+    if (total == 0) return TB_OK;
+    const dim3 grid(nblocks(total)), blk(256);
+#define TBW_EL_R(KERNEL, ...)                                                    \
+    do {                                                                         \
+        if (r == 2) hipLaunchKernelGGL(KERNEL<2>, grid, blk, 0, st, __VA_ARGS__); \
+        else if (r == 4) hipLaunchKernelGGL(KERNEL<4>, grid, blk, 0, st, __VA_ARGS__); \
+        else hipLaunchKernelGGL(KERNEL<6>, grid, blk, 0, st, __VA_ARGS__);       \
+    } while (0)
+    if (r != 2 && r != 4 && r != 6) {
+        set_error("elastic radius %d not built", r);
+        return TB_EUNSUPPORTED;
+    }
+    TBW_EL_R(el_img_str, P, G, fv, dt);
+    hipLaunchKernelGGL(el_adj_pre_str, grid, blk, 0, st, P, S);
+    TBW_EL_R(el_adj_vel, P, S);
+    TBW_EL_R(el_img_vel, P, G, ft, dt);
+    hipLaunchKernelGGL(el_adj_pre_vel, grid, blk, 0, st, P, S);
+    TBW_EL_R(el_adj_str, P, S);
+#undef TBW_EL_R
+    TB_HIP(hipGetLastError());
+    if (nrid + nrid2 > 0) {
+        hipLaunchKernelGGL(el_adj_inject, dim3(nblocks(nrid + nrid2)), dim3(256), 0, st, P.t[0],
+                           P.t[1], P.t[2], P.v[2], inc_p, roff, nrid, inc_v, roff2, nrid2);
+        TB_HIP(hipGetLastError());
+    }
+    return TB_OK;
+}
+
+tb_status launch_elastic_grad_finish(const ElParams &P, const ElGradAcc &G, float *out,
+                                     hipStream_t st)
+{
+    const long long N = (long long)P.nx * P.ny * P.nz;
+    if (N == 0) return TB_OK;
+    hipLaunchKernelGGL(el_grad_finish, dim3(nblocks(N)), dim3(256), 0, st, P, G, out);
+    TB_HIP(hipGetLastError());
     return TB_OK;
 }
 

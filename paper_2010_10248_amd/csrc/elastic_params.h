@@ -18,10 +18,34 @@ struct ElParams {
     int nx, ny, nz, nzp;
 };
 
-// Six scratch fields of the adjoint step.
+// Six scratch fields of the adjoint step (also used to pass a forward
+// level: v in f[0..2], or t in f[0..5]).
 struct ElScratch {
     float *f[6];
 };
+
+// FP64 gradient accumulators (padded layout): node terms of lambda and mu,
+// per-shear-point and per-velocity-point terms before their spread onto the
+// nodes.
+struct ElGradAcc {
+    double *lam, *mu;
+    double *sh[3];  // xy, xz, yz
+    double *bv[3];  // x, y, z
+};
+
+// One backward step of the gradient: the stress-pass imaging against the
+// forward v^{t+1/2} (fv), the stress-pass adjoint, the velocity-pass imaging
+// against the forward t^t (ft), the velocity-pass adjoint, the receivers.
+tb_status launch_elastic_gradient_step(const ElParams &P, const ElScratch &S,
+                                       const ElScratch &fv, const ElScratch &ft,
+                                       const ElGradAcc &G, int r, const float *inc_p,
+                                       const long long *roff, int nrid, const float *inc_v,
+                                       const long long *roff2, int nrid2, double dt,
+                                       hipStream_t st);
+// Spreads the element terms onto the nodes and writes out[3][nx][ny][nz] =
+// (dJ/dlambda, dJ/dmu, dJ/db).
+tb_status launch_elastic_grad_finish(const ElParams &P, const ElGradAcc &G, float *out,
+                                     hipStream_t st);
 
 // One step of the adjoint of q -> (vz, P), backwards: multipliers of the
 // velocities in P.v and of the stresses in P.t (in place). First src_row

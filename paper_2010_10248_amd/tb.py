@@ -378,6 +378,7 @@ class Propagator:
             self.vp = torch.as_tensor(np.ascontiguousarray(vp, dtype=np.float32),
                                       device=self.device)
         physics = getattr(shot, "physics", ACOUSTIC)
+        self.physics = physics
         extra = {}
         names = {TTI: ("epsilon", "delta", "theta", "phi"), ELASTIC: ("vs", "rho")}
         if physics in names:
@@ -451,7 +452,10 @@ class Propagator:
             self._ws = {k: v for k, v in self._ws.items() if not (isinstance(k, tuple))}
             ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
             self._ws[key] = ws
-        g = torch.empty(self.shot.shape, dtype=torch.float32, device=self.device)
+        shape = tuple(self.shot.shape)
+        if self.physics == ELASTIC:
+            shape = (3,) + shape  # d/dlambda, d/dmu, d/db
+        g = torch.empty(shape, dtype=torch.float32, device=self.device)
         J = gradient(self.model, self.sparse, sched, ws, d_obs.contiguous(), g, checkpoint_every,
                      stream)
         return J, g
