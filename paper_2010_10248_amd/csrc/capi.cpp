@@ -416,6 +416,31 @@ TtiParams tti_params(const tb_model *m)
     return P;
 }
 
+// Model part of the elastic kernel parameters, with the nine fields at F.
+ElParams el_params(const tb_model *m, float *const *F)
+{
+    const size_t fe = m->field_elems();
+    ElParams P{};
+    for (int k = 0; k < 3; k++) P.v[k] = F[k];
+    for (int k = 0; k < 6; k++) P.t[k] = F[3 + k];
+    for (int k = 0; k < 3; k++) P.bq[k] = m->d_el + k * fe;
+    P.lam = m->d_el + 3 * fe;
+    P.mu = m->d_el + 4 * fe;
+    for (int k = 0; k < 3; k++) P.ms[k] = m->d_el + (5 + k) * fe;
+    P.dx = m->d_damp;
+    P.dy = m->d_damp + m->n[0];
+    P.dz = m->d_damp + m->n[0] + m->n[1];
+    P.hdt = (float)(m->dt / 2.0);
+    const double *sw = stag_weights(m->so);
+    for (int j = 0; j < 6; j++) P.w[j] = j < m->r ? (float)sw[j] : 0.0f;
+    for (int a = 0; a < 3; a++) P.ih[a] = (float)(1.0 / m->h[a]);
+    P.nx = m->n[0];
+    P.ny = m->n[1];
+    P.nz = m->n[2];
+    P.nzp = m->nzp;
+    return P;
+}
+
 // TTI forward (SB): p (two levels), r (two levels), w_p, w_r, q_p, q_r, then
 // rec_dcmp.
 tb_status plan_forward_tti(const tb_model *m, tb_sparse *s, void *ws, float *rec_out,
@@ -486,24 +511,7 @@ tb_status plan_forward_elastic(const tb_model *m, tb_sparse *s, void *ws, float 
     float *rec = (float *)(base + 9 * fb);  // row k: P at nrid points, vz at nrid2
     for (int k = 0; k < 9; k++) plan->push_back(fill_item(F[k], fe));
     if (stride > 0) plan->push_back(fill_item(rec, (size_t)stride));
-    ElParams P{};
-    for (int k = 0; k < 3; k++) P.v[k] = F[k];
-    for (int k = 0; k < 6; k++) P.t[k] = F[3 + k];
-    for (int k = 0; k < 3; k++) P.bq[k] = m->d_el + k * fe;
-    P.lam = m->d_el + 3 * fe;
-    P.mu = m->d_el + 4 * fe;
-    for (int k = 0; k < 3; k++) P.ms[k] = m->d_el + (5 + k) * fe;
-    P.dx = m->d_damp;
-    P.dy = m->d_damp + m->n[0];
-    P.dz = m->d_damp + m->n[0] + m->n[1];
-    P.hdt = (float)(m->dt / 2.0);
-    const double *sw = stag_weights(m->so);
-    for (int j = 0; j < 6; j++) P.w[j] = j < m->r ? (float)sw[j] : 0.0f;
-    for (int a = 0; a < 3; a++) P.ih[a] = (float)(1.0 / m->h[a]);
-    P.nx = m->n[0];
-    P.ny = m->n[1];
-    P.nz = m->n[2];
-    P.nzp = m->nzp;
+    const ElParams P = el_params(m, F);
     const int r = m->r;
     const float *dcmp = s->d_dcmp;
     const long long *soff = s->d_src_off, *roff = s->d_rid_off, *roff2 = s->d_rid2_off;
@@ -894,30 +902,6 @@ tb_status tti_adjoint(const tb_model *m, tb_sparse *s, void *ws, const float *re
     return TB_OK;
 }
 
-// Model part of the elastic kernel parameters, with the nine fields at F.
-ElParams el_params(const tb_model *m, float *const *F)
-{
-    const size_t fe = m->field_elems();
-    ElParams P{};
-    for (int k = 0; k < 3; k++) P.v[k] = F[k];
-    for (int k = 0; k < 6; k++) P.t[k] = F[3 + k];
-    for (int k = 0; k < 3; k++) P.bq[k] = m->d_el + k * fe;
-    P.lam = m->d_el + 3 * fe;
-    P.mu = m->d_el + 4 * fe;
-    for (int k = 0; k < 3; k++) P.ms[k] = m->d_el + (5 + k) * fe;
-    P.dx = m->d_damp;
-    P.dy = m->d_damp + m->n[0];
-    P.dz = m->d_damp + m->n[0] + m->n[1];
-    P.hdt = (float)(m->dt / 2.0);
-    const double *sw = stag_weights(m->so);
-    for (int j = 0; j < 6; j++) P.w[j] = j < m->r ? (float)sw[j] : 0.0f;
-    for (int a = 0; a < 3; a++) P.ih[a] = (float)(1.0 / m->h[a]);
-    P.nx = m->n[0];
-    P.ny = m->n[1];
-    P.nz = m->n[2];
-    P.nzp = m->nzp;
-    return P;
-}
 
 // Gradient of J = 1/2 |traces - d_obs|^2 (traces [2][nt][nrec]: vz, then P)
 // of the elastic propagator with respect to lambda, mu and b = 1/rho at the
@@ -1051,24 +1035,7 @@ tb_status elastic_adjoint(const tb_model *m, tb_sparse *s, void *ws, const float
                                                  s->d_rr2_rec, s->d_rr2_w, nullptr, adjV, strm)))
             return st;
     }
-    ElParams P{};
-    for (int k = 0; k < 3; k++) P.v[k] = F[k];
-    for (int k = 0; k < 6; k++) P.t[k] = F[3 + k];
-    for (int k = 0; k < 3; k++) P.bq[k] = m->d_el + k * fe;
-    P.lam = m->d_el + 3 * fe;
-    P.mu = m->d_el + 4 * fe;
-    for (int k = 0; k < 3; k++) P.ms[k] = m->d_el + (5 + k) * fe;
-    P.dx = m->d_damp;
-    P.dy = m->d_damp + m->n[0];
-    P.dz = m->d_damp + m->n[0] + m->n[1];
-    P.hdt = (float)(m->dt / 2.0);
-    const double *sw = stag_weights(m->so);
-    for (int j = 0; j < 6; j++) P.w[j] = j < m->r ? (float)sw[j] : 0.0f;
-    for (int a = 0; a < 3; a++) P.ih[a] = (float)(1.0 / m->h[a]);
-    P.nx = m->n[0];
-    P.ny = m->n[1];
-    P.nz = m->n[2];
-    P.nzp = m->nzp;
+    const ElParams P = el_params(m, F);
     ElScratch S{};
     for (int k = 0; k < 6; k++) S.f[k] = F[9 + k];
     for (int tau = 0; tau < nt; tau++) {
