@@ -118,7 +118,7 @@ tb_status launch_acoustic(const tb_model *m, const TileLists &tl, const AcLaunch
     hipError_t e = hipErrorInvalidValue;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (timing_enabled()) timing_begin(st, &ev0, &ev1);
-    const bool gl = tl.max_src > kSrcCap || tl.max_rec > kRecCap;
+    const bool gl = tl.max_src > kSrcCap;
     if (m->r == 2) e = launch_acoustic_r2(p, g.T, g.LZ, g.BYE, gl, st);
     else if (m->r == 4) e = launch_acoustic_r4(p, g.T, g.LZ, g.BYE, gl, st);
     else if (m->r == 6) e = launch_acoustic_r6(p, g.T, g.LZ, g.BYE, gl, st);

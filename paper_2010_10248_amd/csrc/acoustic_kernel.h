@@ -197,21 +197,20 @@ struct RingIn {
     f4v yr;
 };
 
-// LDS of one workgroup (one instance shared by the body's variants).
+// LDS of one workgroup (one instance shared by the body's variants). The
+// 16-byte arrays come first, so the struct has no padding inside.
 template <int R, int T, int LZ, int BYE, bool GL>
 struct WfLds {
     static constexpr int LR = BYE + 2 * R;  // LDS rows per stage (with the y ring)
     static constexpr int NTH = LZ * BYE;
     static constexpr int NSC = cring_slots(R, T), NSV = vring_slots(R, T);
-    static constexpr int SC = GL ? 1 : kSrcCap, RC = GL ? 1 : kRecCap;
+    static constexpr int SC = GL ? 1 : kSrcCap;
     f4v sh[2][T][LR][LZ];
-    int2 s_src[SC];
-    float s_val[SC][T];
-    int2 s_rec[RC];
-    float s_recv[RC][T];
-    float s_dx[kDxCap];
     f4v s_c[NSC ? NSC : 1][NSC ? NTH : 1];
     f4v s_v[T > 1 ? T - 1 : 1][NSV ? NSV : 1][NSV ? NTH : 1];
+    int s_src[SC];  // injection-list keys (the point IDs stay in global memory)
+    float s_val[SC][T];
+    float s_dx[kDxCap];
 };
 
 // LDS bytes of one workgroup of acoustic_wavefront<R, T, LZ, BYE> (GL: the
@@ -252,8 +251,6 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
     auto &sh = lds.sh;
     auto &s_src = lds.s_src;
     auto &s_val = lds.s_val;
-    auto &s_rec = lds.s_rec;
-    auto &s_recv = lds.s_recv;
     auto &s_dx = lds.s_dx;
     auto &s_c = lds.s_c;
     auto &s_v = lds.s_v;
@@ -328,8 +325,8 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
     for (int k = tid; k < nxd; k += NTH) s_dx[k] = p.dx[xlo + k];
 
     // Stage the segment's injection list (with the decomposed wavelet values
-    // of this pass's T steps) and its receiver list in LDS; the GL variant
-    // reads both lists and the values from global memory instead.
+    // of this pass's T steps) in LDS; the GL variant reads the list and the
+    // values from global memory instead.
     const int sbeg = sd.sbeg, nsl = sd.sn;
     const int rbeg = sd.rbeg, nrl = sd.rn;
     const int2 *gsrc = p.src + sbeg, *grec = p.rec + rbeg;
@@ -338,21 +335,16 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
         // capacities; the bounds keep LDS writes inside the arrays regardless.
         for (int k = tid; k < nsl && k < kSrcCap; k += NTH) {
             const int2 e = gsrc[k];
-            s_src[k] = e;
+            s_src[k] = e.x;
 #pragma unroll
             for (int s = 0; s < T; s++)
                 s_val[k][s] = p.dcmp[(long long)(p.n0 + s) * p.npts + e.y];
         }
-        for (int k = tid; k < nrl && k < kRecCap; k += NTH) s_rec[k] = grec[k];
     }
     // List accessors (one address space per instantiation).
     auto skey = [&](int k) -> int {
         if constexpr (GL) return gsrc[k].x;
-        else return s_src[k].x;
-    };
-    auto rkey = [&](int k) -> int {
-        if constexpr (GL) return grec[k].x;
-        else return s_rec[k].x;
+        else return s_src[k];
     };
     lds_barrier();
     // Each lane walks its own entries (sorted by x) with one cursor per stage,
@@ -373,13 +365,36 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
         const int e = key(k);
         return (e >> 18) == mykey ? ((e >> 2) & 0xffff) : 0x7fffffff;
     };
-    int scur[T], snx[T], rcur[T], rnx[T];
+    int scur[T], snx[T];
 #pragma unroll
     for (int s = 0; s < T; s++) {
         scur[s] = nsl ? first_at(skey, nsl, lo[s]) : 0;
         snx[s] = next_x(skey, nsl, scur[s]);
-        rcur[s] = nrl ? first_at(rkey, nrl, lo[s]) : 0;
-        rnx[s] = next_x(rkey, nrl, rcur[s]);
+    }
+    // Receivers record from the owned copy. Stage s publishes level n0 + s
+    // of plane i - R(s+1) to LDS in tick i, so wave 0 records levels
+    // n0+1 .. n0+T-1 from there. The segment's entries are sorted by x; for
+    // each such level wave 0 holds two batches of 64 in registers (the next
+    // batch is read when the current one is used up, 64 entries ahead of
+    // its use). Level n0+T is read back from this segment's own stores of
+    // out_u when the segment ends.
+    constexpr int TG = T > 1 ? T - 1 : 1;
+    const bool wave0 = tid < 64;
+    int gbase[TG];    // list index of batch A's first entry (uniform)
+    int goff[TG];     // entries of batch A already recorded (uniform)
+    int2 gA[TG], gB[TG];  // entries gbase + lane and gbase + 64 + lane
+    auto gload = [&](int at) {
+        const int k = at + tid;
+        return k < nrl ? grec[k] : make_int2(0x7fffffff, 0);
+    };
+#pragma unroll
+    for (int g = 0; g < TG; g++) {
+        gbase[g] = 0;
+        goff[g] = 0;
+        if (T > 1 && wave0) {
+            gA[g] = gload(0);
+            gB[g] = gload(64);
+        }
     }
 
     f4v q[T][U];
@@ -447,6 +462,29 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
             static_for<0, T>([&](auto SC) {
                 constexpr int s = SC.value;
                 const int cs = i - R * (s + 1);
+                if constexpr (s > 0) {
+                    // Level n0+s at plane cs, from this tick's LDS plane.
+                    constexpr int g = s - 1;
+                    if (wave0) {
+                        // Past the list end the entries hold x = 2^20 - 1.
+                        while ((__builtin_amdgcn_readlane(gA[g].x, goff[g]) >> 11) == cs) {
+                            const int e = gA[g].x;
+                            const bool hit = tid >= goff[g] && (e >> 11) == cs;
+                            if (hit) {
+                                const float *cell =
+                                    (const float *)&sh[buf][s][((e >> 6) & 31) + R][(e >> 2) & 15];
+                                p.rec_dcmp[(long long)(p.n0 + s) * p.nrid + gA[g].y] = cell[e & 3];
+                            }
+                            goff[g] += __builtin_popcountll(__builtin_amdgcn_ballot_w64(hit));
+                            if (goff[g] == 64) {
+                                gA[g] = gB[g];
+                                gbase[g] += 64;
+                                goff[g] = 0;
+                                gB[g] = gload(gbase[g] + 64);
+                            }
+                        }
+                    }
+                }
                 f4v v = f4v{0.f, 0.f, 0.f, 0.f};   // v^{n+s+1}
                 f4v un = f4v{0.f, 0.f, 0.f, 0.f};  // u^{n+s+1}
                 if (cs >= lo[s] && cs < hi[s]) {
@@ -602,24 +640,6 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
                     }
 #pragma unroll
                     for (int k = 0; k < 4; k++) un[k] = ctr[k] + v[k];
-                    // Receiver points (owned copy only), buffered in LDS and
-                    // written out once at the end.
-                    if (__builtin_amdgcn_ballot_w64(rnx[s] == cs) && rnx[s] == cs) {
-                        int kk = rcur[s];
-                        for (; kk < nrl && (rkey(kk) >> 18) == mykey &&
-                               ((rkey(kk) >> 2) & 0xffff) == cs;
-                             kk++) {
-                            const int k = rkey(kk) & 3;
-                            const float val =
-                                k == 0 ? un[0] : k == 1 ? un[1] : k == 2 ? un[2] : un[3];
-                            if constexpr (GL)
-                                p.rec_dcmp[(long long)(p.n0 + s + 1) * p.nrid + grec[kk].y] = val;
-                            else
-                                s_recv[kk][s] = val;
-                        }
-                        rcur[s] = kk;
-                        rnx[s] = next_x(rkey, nrl, kk);
-                    }
                 }
                 if constexpr (s + 1 < T) {
                     q[s + 1 < T ? s + 1 : 0][NEW] = un;
@@ -644,15 +664,15 @@ __device__ __forceinline__ void wavefront_body(const AcParams &p, const int b,
             tick++;
         });
     }
-    if (!GL && nrl > 0) {
-        lds_barrier();
-        for (int k = tid; k < nrl && k < kRecCap; k += NTH) {
-            const int id = s_rec[k].y;
-            // Owned receiver planes lie inside every stage's x range, so each
-            // stage recorded every entry.
-#pragma unroll
-            for (int s = 0; s < T; s++)
-                p.rec_dcmp[(long long)(p.n0 + s + 1) * p.nrid + id] = s_recv[k][s];
+    if (nrl > 0) {
+        // Level n0+T: this segment stored every owned point of its planes;
+        // the barrier makes those stores visible to the whole workgroup.
+        __syncthreads();
+        for (int k = tid; k < nrl; k += NTH) {
+            const int2 e = grec[k];
+            const int y = y0 + ((e.x >> 6) & 31), z = z0 + 4 * ((e.x >> 2) & 15) + (e.x & 3);
+            const long long at = (long long)(e.x >> 11) * p.sx + (long long)y * p.nzp + z;
+            p.rec_dcmp[(long long)(p.n0 + T) * p.nrid + e.y] = p.out_u[at];
         }
     }
     }  // segments
@@ -704,10 +724,10 @@ static_assert((2 * 4 + 1) % 3 == 0 && (2 * 2 + 1) % 5 == 0, "depth must divide t
 template <int R, int T, int LZ, int BYE, bool GL = true>
 constexpr bool wavefront_fits()
 {
-    return BYE - 2 * R * (T - 1) > 0 && wavefront_lds<R, T, LZ, BYE, GL>() <= 160 * 1024 &&
+    return BYE - 2 * R * (T - 1) > 0 && wavefront_lds<R, T, LZ, BYE, GL>() <= kLdsBytes &&
            LZ * BYE <= kMaxThreads;
 }
-// Whether the shape also fits with the sparse lists staged in LDS (the
+// Whether the shape also fits with the injection list staged in LDS (the
 // common variant and the batched entry); otherwise only GL runs it.
 template <int R, int T, int LZ, int BYE>
 constexpr bool lists_in_lds()

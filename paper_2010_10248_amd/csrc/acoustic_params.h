@@ -54,8 +54,9 @@ hipError_t launch_acoustic_batch_r6(const AcParams *jobs, const int *wg_off, int
 bool acoustic_shape_ok_r2(int T, int LZ, int BYE);
 bool acoustic_shape_ok_r4(int T, int LZ, int BYE);
 bool acoustic_shape_ok_r6(int T, int LZ, int BYE);
-// Whether a shape also runs with its sparse lists staged in LDS (and so has a
-// batched entry); a shape without is run by the global-list variant alone.
+// Whether a shape also runs with its injection list staged in LDS (and so
+// has a batched entry); a shape without is run by the global-list variant
+// alone.
 bool acoustic_lists_in_lds(int R, int T, int LZ, int BYE);
 bool acoustic_lists_in_lds_r2(int T, int LZ, int BYE);
 bool acoustic_lists_in_lds_r4(int T, int LZ, int BYE);

@@ -87,7 +87,7 @@ tb_status tb_autotune(const tb_model *m, const tb_sparse *s_, int32_t steps, voi
 
     const int Tmax = m->r >= 4 ? 3 : 4;
     const int tiles[3] = {32, 16, 0};
-    const int chunks[4] = {0, 32, 64, 128};
+    const int chunks[5] = {0, 32, 64, 128, kMaxChunk};
     SchedChoice bestc{};
     double best_ms = INFINITY;
     for (int T = 1; T <= Tmax; T++)

@@ -354,8 +354,7 @@ tb_status pass_params(const tb_model *m, tb_sparse *s, const SchedChoice &sc, co
     *out = make_params(m, *tl, to_launch(p));
     if (geom) *geom = &tl->g;
     if (gl)
-        *gl = tl->max_src > kSrcCap || tl->max_rec > kRecCap ||
-              !acoustic_lists_in_lds(m->r, tl->g.T, tl->g.LZ, tl->g.BYE);
+        *gl = tl->max_src > kSrcCap || !acoustic_lists_in_lds(m->r, tl->g.T, tl->g.LZ, tl->g.BYE);
     return TB_OK;
 }
 

@@ -109,9 +109,8 @@ static void node_xyz(int64_t r, const int n[3], int *x, int *y, int *z)
     *x = (int)(q / n[1]);
 }
 
-// Default tile width for (R, T): enough lanes that a tile owns 64 z after
-// removing its halo of HZ columns on each side (so 64-multiples of nz are
-// covered without a ragged last tile); rows fill one 512-thread workgroup.
+// Tile shape for (R, T): 16 lanes (64 z) per row; 32 rows when that shape
+// has a kernel (its LDS fits), else 16, unless the schedule names the rows.
 void tile_shape(int R, int T, int tile_y, int *LZ, int *BYE)
 {
     *LZ = 16;
@@ -142,7 +141,27 @@ TileGeom make_geom(int R, int T, int tile_y, int chunk, int wgs, int nx, int ny,
             return SegDesc{t, x0, std::min(nx, x0 + g.chunk), 0, 0, 0, 0, 0};
         };
         const int W = wgs / 8;  // workgroups per XCD
-        if (W < 1 || (long long)nch * nt <= 8LL * W) {
+        if (nch == 1 && nt < wgs && nx > 1) {
+            // Whole x per tile, with fewer tiles than resident workgroups.
+            // Tile t streams x in [0, s) on workgroup t, so neighbouring
+            // tiles stream the same planes together (their halo re-reads
+            // meet in L2); the wgs - nt spare workgroups take the tails
+            // [s, nx) of tiles j, j + ns, ... (neighbouring tails again run
+            // together). s balances the two: a head costs s + R T planes
+            // of the stream, a spare k tails of nx - s + 2 R T each.
+            const int ns = wgs - nt;
+            const int k = (nt + ns - 1) / ns;
+            const int H = R * T;
+            const int s = std::max(1, std::min(nx - 1, (k * (nx + 2 * H) - H) / (k + 1)));
+            for (int t = 0; t < nt; t++) {
+                g.segs.push_back(SegDesc{t, 0, s, 0, 0, 0, 0, 0});
+                g.seg_off.push_back((int)g.segs.size());
+            }
+            for (int j = 0; j < ns; j++) {
+                for (int t = j; t < nt; t += ns) g.segs.push_back(SegDesc{t, s, nx, 0, 0, 0, 0, 0});
+                g.seg_off.push_back((int)g.segs.size());
+            }
+        } else if (W < 1 || (long long)nch * nt <= 8LL * W) {
             // One workgroup per (chunk of x, tile), chunk-major so that the
             // workgroups running together stream the same x range of
             // neighbouring tiles.
@@ -207,7 +226,8 @@ static inline int tile_index(const TileGeom &g, int ty, int tz) { return ty * g.
 
 // Bin points by tile: inj points into every tile whose extended region
 // (rows [0, BYE), columns [0, 4 LZ)) holds them, rec points into the tile
-// that owns them. Entries carry x in the key; segments select by x later.
+// that owns them. Entries carry x in the key (tile_key for injection,
+// rec_key for receivers); segments select by x later.
 static void bin_points(const TileGeom &g, const int n[3], const std::vector<int64_t> &nodes,
                        bool owned_only, std::vector<std::vector<int2>> *bins)
 {
@@ -235,8 +255,9 @@ static void bin_points(const TileGeom &g, const int n[3], const std::vector<int6
                 const int col = z - (tz * g.OZ - g.HZ);
                 if (owned_only ? (col < g.HZ || col >= g.HZ + g.OZ) : (col < 0 || col >= EZ))
                     continue;
-                (*bins)[tile_index(g, ty, tz)].push_back(
-                    make_int2(tile_key(row, col >> 2, x, col & 3), (int)id));
+                const int key = owned_only ? rec_key(row, col >> 2, x, col & 3)
+                                           : tile_key(row, col >> 2, x, col & 3);
+                (*bins)[tile_index(g, ty, tz)].push_back(make_int2(key, (int)id));
             }
         }
     }
@@ -275,7 +296,7 @@ tb_status build_tile_lists(const tb_model *m, const std::vector<int64_t> &inj,
         sd.sn = (int)sflat.size() - sd.sbeg;
         sd.rbeg = (int)rflat.size();
         for (const int2 &e : rb[sd.tile]) {
-            const int x = (e.x >> 2) & 0xffff;
+            const int x = e.x >> 11;
             if (x >= sd.xs && x < sd.xe) rflat.push_back(e);
         }
         sd.rn = (int)rflat.size() - sd.rbeg;

@@ -28,21 +28,30 @@ void set_error(const char *fmt, ...);
     } while (0)
 
 // Each lane of the acoustic kernels holds 4 consecutive z as one float4; a
-// tile row has LZ lanes (16, 18 or 20).
+// tile row has 16 lanes (one DPP row).
 constexpr int kMaxThreads = 512;
-// Longest x chunk one workgroup streams (its damping values sit in LDS).
-constexpr int kMaxChunk = 2048;
-// Per-tile list capacities (the lists are staged in LDS); a schedule whose
-// tiles exceed them is run with shorter x chunks.
+// LDS of one workgroup on gfx950.
+constexpr int kLdsBytes = 160 * 1024;
+// Longest x range one work segment streams (its damping values sit in LDS).
+constexpr int kMaxChunk = 1024;
+// Injection entries one segment can stage in LDS; a segment with more runs
+// the variant that walks its injection list in global memory. (Receiver
+// lists stay in global memory: they are read a few entries ahead.)
 constexpr int kSrcCap = 1024;
-constexpr int kRecCap = 512;
 
-// A list entry: key = ((row*32 + lane) << 18) | (x << 2) | k, with k the z
-// component inside the lane's float4; id = point ID. Sorted by key, so each
-// lane's entries are contiguous and ordered by x.
+// An injection-list entry: key = ((row*32 + lane) << 18) | (x << 2) | k,
+// with k the z component inside the lane's float4; id = point ID. Sorted by
+// key, so each lane's entries are contiguous and ordered by x.
 __host__ __device__ inline int tile_key(int row, int lane, int x, int k)
 {
     return ((row * 32 + lane) << 18) | (x << 2) | k;
+}
+// A receiver-list entry: key = (x << 11) | (row << 6) | (lane << 2) | k
+// (row < 32, lane < 16); sorted by key, so the entries of one plane are
+// contiguous and the planes come in x order.
+__host__ __device__ inline int rec_key(int row, int lane, int x, int k)
+{
+    return (x << 11) | (row << 6) | (lane << 2) | k;
 }
 
 // One unit of work of a workgroup: tile `tile` over planes [xs, xe), with the

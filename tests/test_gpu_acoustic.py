@@ -43,9 +43,11 @@ def _say(msg):
 
 
 # Time tiles of 3 and 4 exist at space order 4 with 16-row tiles only (LDS).
+# chunk_x 2048 streams whole x per tile, with the tails of the tiles on the
+# spare workgroups.
 SCHEDS = [("sb", 1, 32, 0), ("sb", 1, 16, 24), ("tb", 2, 32, 0), ("tb", 2, 16, 0),
           ("tb", 3, 16, 0), ("tb", 4, 16, 40), ("tb", 2, 32, 24), ("tb", 3, 16, 17),
-          ("tb", 2, 0, 0)]
+          ("tb", 2, 0, 0), ("tb", 2, 32, 2048), ("sb", 1, 32, 2048)]
 
 
 def _check_case(torch_cuda, orc, shot, scheds=SCHEDS, tol=TOL):
@@ -206,11 +208,12 @@ def test_full_size_c2_first_steps_and_schedule_identity(torch_cuda, orc):
 
     from paper_2010_10248_amd import tb
 
-    tb_s, sb_s = tb.schedule("tb", 2, 32, 64), tb.schedule("sb", 1, 32, 0)
+    tb_s, sb_s = tb.schedule("tb", 2, 32, 2048), tb.schedule("sb", 1, 32, 0)
+    tb_c = tb.schedule("tb", 2, 32, 64)
     s8 = W.acoustic_two_layer(n=512, nt=8)
     ref = orc.acoustic_forward(s8)
     prop = tb.Acoustic(s8)
-    for sc in (tb_s, sb_s):
+    for sc in (tb_s, sb_s, tb_c):
         out = _run(tb, prop, sc)
         e = (_rel(out["u_last"], ref["u_last"]), _rel(out["u_prev"], ref["u_prev"]))
         _say(f"512^3 first 8 steps {sc}: relL2 u {e[0]:.3e} u_prev {e[1]:.3e}")
@@ -225,6 +228,11 @@ def test_full_size_c2_first_steps_and_schedule_identity(torch_cuda, orc):
     for k in ("traces", "u_last", "u_prev"):
         assert torch.equal(a[k].view(torch.int32), b[k].view(torch.int32)), k
     assert float(a["traces"].abs().max()) > 0
+    del b
+    c = prop.forward(tb_c)
+    torch.cuda.synchronize()
+    for k in ("traces", "u_last", "u_prev"):
+        assert torch.equal(a[k].view(torch.int32), c[k].view(torch.int32)), k
     prop.close()
 
 
@@ -232,7 +240,20 @@ def test_c2_recipe_full_length_reduced_grid(torch_cuda, orc):
     """The two-layer SO8 recipe with all 1000 steps on a 192^3 grid (8
     sources, 512 receivers): traces and final fields against the oracle."""
     s = W.acoustic_two_layer(n=192, nt=1000)
-    _check_case(torch_cuda, orc, s, scheds=[("tb", 2, 32, 64), ("sb", 1, 32, 0), ("tb", 2, 0, 0)])
+    _check_case(torch_cuda, orc, s, scheds=[("tb", 2, 32, 64), ("sb", 1, 32, 0), ("tb", 2, 0, 0),
+                                            ("tb", 2, 32, 2048)])
+
+
+def test_long_segments_dense_receiver_line(torch_cuda, orc):
+    """Whole-x segments on a long x axis with a dense receiver line (600
+    receivers over 320 planes, four nodes per plane): a segment on the line
+    holds more receiver entries than the smallest LDS list, fewer than the
+    32-row two-step shape stages; parity with the oracle and bitwise identity
+    with chunked and spatially blocked schedules."""
+    s = W.acoustic_two_layer(seed=41, n=(320, 40, 48), nt=60, nbl=6, nrec=600)
+    _check_case(torch_cuda, orc, s, scheds=[("sb", 1, 32, 0), ("tb", 2, 32, 2048),
+                                            ("sb", 1, 32, 2048), ("tb", 2, 32, 64),
+                                            ("tb", 2, 16, 2048)])
 
 
 @pytest.mark.parametrize("layout", ["plane", "volume"])
