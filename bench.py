@@ -185,21 +185,28 @@ def physics_bench(tb, W, torch, which, steps):
 
 def space_order_bench(tb, W, torch, nt):
     """Table 1's space-order axis on the 512^3 two-layer grid: GPts/s of the
-    fastest spatially blocked schedule and of the temporally blocked ones
-    built for each order (nt steps per shot; one warm-up, one timed shot)."""
+    fastest spatially blocked schedule and the fastest temporally blocked
+    one built for each order (nt steps per shot; one warm-up, one timed
+    shot each)."""
     import numpy as np
 
-    cands = {4: [("tb", 2, 32, 64), ("tb", 3, 16, 64), ("tb", 4, 16, 64)],
-             8: [("tb", 2, 32, 64)],
-             12: [("tb", 2, 32, 64), ("tb", 2, 16, 64)]}
+    cands = {4: [("tb", 2, 32, 2048), ("tb", 2, 32, 64), ("tb", 3, 16, 64), ("tb", 4, 16, 64)],
+             8: [("tb", 2, 32, 2048), ("tb", 2, 32, 64)],
+             12: [("tb", 2, 32, 64), ("tb", 2, 32, 2048), ("tb", 2, 16, 64)]}
+    sb_cands = [("sb", 1, 16, 2048), ("sb", 1, 32, 128), ("sb", 1, 16, 128)]
     out = []
     for so in (4, 8, 12):
         shot = W.acoustic_two_layer(so=so, nt=nt)
         prop = tb.Acoustic(shot)
         N = int(np.prod(shot.shape)) * nt
         row = dict(space_order=so, nt=nt)
-        dt, _, _, _, _, _ = time_forward(tb, prop, tb.schedule("sb", 1, 32, 128), 1, 1, torch)
-        row["sb_gpts"] = round(N / dt / 1e9, 1)
+        sb_best = None
+        for c in sb_cands:
+            sc = tb.schedule(*c)
+            dt, _, _, _, _, _ = time_forward(tb, prop, sc, 1, 1, torch)
+            if sb_best is None or N / dt > sb_best[0]:
+                sb_best = (N / dt, repr(sc))
+        row["sb_gpts"], row["sb_schedule"] = round(sb_best[0] / 1e9, 1), sb_best[1]
         best = None
         for c in cands[so]:
             sc = tb.schedule(*c)
@@ -287,9 +294,11 @@ def main(argv=None):
     ap.add_argument("--nt", type=int, default=1000)
     ap.add_argument("--T", type=int, default=2)
     ap.add_argument("--tile-y", type=int, default=32)
-    ap.add_argument("--chunk", type=int, default=64)
-    ap.add_argument("--sb-tile-y", type=int, default=32)
-    ap.add_argument("--sb-chunk", type=int, default=128)
+    # chunk 2048 (>= nx): each tile streams whole x, the spare workgroups take
+    # the tails (the fastest TB and SB schedules at 512^3 SO8).
+    ap.add_argument("--chunk", type=int, default=2048)
+    ap.add_argument("--sb-tile-y", type=int, default=16)
+    ap.add_argument("--sb-chunk", type=int, default=2048)
     ap.add_argument("--no-sb", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")

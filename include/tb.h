@@ -99,14 +99,22 @@ typedef struct {
  * 1..2 at space order 8.
  *  tile_y   y rows one workgroup holds: 16 or 32 (16 lanes x 4 z per row),
  *           or 0 for 32 where that shape fits the depth, else 16.
- *  chunk_x  x planes one work segment streams: 1..2048. Each (chunk, tile)
- *           pair is one segment; one workgroup per compute unit streams the
- *           segments of a slab of neighbouring tiles, chunk by chunk, with
- *           the slabs spread over the XCDs. 0 splits the tile-x space evenly
- *           over two workgroups per compute unit.
+ *  chunk_x  x planes one work segment streams (at most 1024 are used).
+ *           Below nx: each (chunk, tile) pair is one segment; one workgroup
+ *           per compute unit streams the segments of a slab of neighbouring
+ *           tiles, chunk by chunk, with the slabs spread over the XCDs.
+ *           nx or more (up to 1024): whole x per tile; with fewer tiles than
+ *           compute units, each tile streams a head [0, s) on its own
+ *           workgroup and the spare workgroups stream the tails [s, nx), s
+ *           chosen to balance the two. 0 splits the tile-x space evenly
+ *           over two workgroups per compute unit. A segment whose injection
+ *           list exceeds the staged capacity is streamed as consecutive
+ *           pieces.
  * Every schedule gives bit-identical results. Passing NULL where a schedule
  * is accepted selects the tuned choice for the model if tb_autotune cached
- * one, else TB, time_tile 2, tile_y 32, chunk_x 64 when nx >= 256, else 0.
+ * one, else TB, time_tile 2, tile_y 32, with whole x when nx <= 1024 and the
+ * tiles fill at least half the compute units but not all of them, else
+ * chunk_x 64 when nx >= 256, else 0.
  */
 typedef struct {
     int32_t mode;

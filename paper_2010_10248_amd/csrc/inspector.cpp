@@ -157,7 +157,8 @@ TileGeom make_geom(int R, int T, int tile_y, int chunk, int wgs, int nx, int ny,
                 g.segs.push_back(SegDesc{t, 0, s, 0, 0, 0, 0, 0});
                 g.seg_off.push_back((int)g.segs.size());
             }
-            for (int j = 0; j < ns; j++) {
+            // (Spares beyond nt would get no tail: none is launched.)
+            for (int j = 0; j < std::min(ns, nt); j++) {
                 for (int t = j; t < nt; t += ns) g.segs.push_back(SegDesc{t, s, nx, 0, 0, 0, 0, 0});
                 g.seg_off.push_back((int)g.segs.size());
             }
@@ -274,6 +275,50 @@ static tb_status upload_vec(T **d, const std::vector<T> &v)
     return TB_OK;
 }
 
+// Splits every segment whose injection list (entries with x in [xs - halo,
+// xe + halo)) would exceed the LDS capacity into consecutive pieces on the
+// same workgroup, each within the capacity where one plane allows it; the
+// workgroup streams the pieces one after the other (each with its own x
+// warm-up), so the staged-list kernel runs instead of the global-list one.
+static void split_dense_segments(TileGeom &g, int nx, const std::vector<std::vector<int2>> &sb,
+                                 int halo_x)
+{
+    std::vector<std::vector<int>> pre(sb.size());  // per tile: prefix counts over x
+    auto prefix = [&](int t) -> const std::vector<int> & {
+        std::vector<int> &P = pre[t];
+        if (P.empty()) {
+            P.assign(nx + 1, 0);
+            for (const int2 &e : sb[t]) P[((e.x >> 2) & 0xffff) + 1]++;
+            for (int x = 0; x < nx; x++) P[x + 1] += P[x];
+        }
+        return P;
+    };
+    std::vector<SegDesc> segs;
+    std::vector<int> off(1, 0);
+    for (size_t w = 0; w + 1 < g.seg_off.size(); w++) {
+        for (int k = g.seg_off[w]; k < g.seg_off[w + 1]; k++) {
+            const SegDesc &sd = g.segs[k];
+            if ((int)sb[sd.tile].size() <= kSrcCap) {
+                segs.push_back(sd);
+                continue;
+            }
+            const std::vector<int> &P = prefix(sd.tile);
+            auto count = [&](int a, int b) {  // entries of the piece [a, b)
+                return P[std::min(nx, b + halo_x)] - P[std::max(0, a - halo_x)];
+            };
+            for (int a = sd.xs; a < sd.xe;) {
+                int b = a + 1;
+                while (b < sd.xe && count(a, b + 1) <= kSrcCap) b++;
+                segs.push_back(SegDesc{sd.tile, a, b, 0, 0, 0, 0, 0});
+                a = b;
+            }
+        }
+        off.push_back((int)segs.size());
+    }
+    g.segs.swap(segs);
+    g.seg_off.swap(off);
+}
+
 // Per-segment lists: the tile's entries whose x lies in the segment's range
 // (extended by the x halo for injection points), kept in key order.
 tb_status build_tile_lists(const tb_model *m, const std::vector<int64_t> &inj,
@@ -285,6 +330,7 @@ tb_status build_tile_lists(const tb_model *m, const std::vector<int64_t> &inj,
     bin_points(g, m->n, inj, false, &sb);
     bin_points(g, m->n, rec, true, &rb);
     const int halo_x = g.R * (g.T - 1);
+    split_dense_segments(g, m->n[0], sb, halo_x);
     std::vector<int2> sflat, rflat;
     out->max_src = out->max_rec = 0;
     for (SegDesc &sd : g.segs) {
