@@ -173,6 +173,27 @@ tb_status tb_inspect_host(const int32_t shape[3], const double spacing[3], const
                           const double *src_xyz, const double *src_wavelet, int32_t *npts,
                           int32_t *nodes, float *dcmp);
 
+/*
+ * Host-only view of how an acoustic schedule splits the wave-front loop nest
+ * of Section II-B into work (no device memory touched): for a grid `shape`
+ * at `space_order` (4, 8 or 12), the schedule `s` (not NULL; mode SB means
+ * time_tile 1) and `wgs` resident workgroups (the device launches one per
+ * compute unit for chunk_x > 0, two for chunk_x 0). tile[4] receives the
+ * tile's rows, its z width, and the rows and z columns it owns (the rest is
+ * the overlapped halo). On input *nseg holds the capacity of seg[cap][5]; on
+ * return the number of work segments (TB_EWORKSPACE if it exceeds the
+ * capacity; seg is then not written). Segment k, in launch order, is
+ * seg[k] = {workgroup, tile index along y, tile index along z, xs, xe}: that
+ * workgroup streams planes [xs, xe) of that tile (with its x halo). The
+ * pieces into which the inspector splits segments with dense injection lists
+ * depend on the sparse set and are not shown. Errors: TB_EINVAL (NULL
+ * pointer, wgs < 1, shape below 1), TB_EUNSUPPORTED (space order, or no
+ * kernel of that shape).
+ */
+tb_status tb_schedule_segments_host(const int32_t shape[3], int32_t space_order,
+                                    const tb_schedule *s, int32_t wgs, int32_t tile[4],
+                                    int32_t *nseg, int32_t *seg);
+
 /* Bytes of caller workspace needed by an operation (TB_OP_*). */
 tb_status tb_workspace_size(const tb_model *m, const tb_sparse *s, const tb_schedule *sched,
                             int32_t op, size_t *bytes);

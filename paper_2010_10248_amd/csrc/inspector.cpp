@@ -442,3 +442,56 @@ tb_status inspect_into(tb_sparse *s, int nsrc, const double *src_xyz, const doub
     return TB_OK;
 }
 }  // namespace tbw
+
+extern "C" tb_status tb_schedule_segments_host(const int32_t shape[3], int32_t space_order,
+                                               const tb_schedule *s, int32_t wgs, int32_t tile[4],
+                                               int32_t *nseg, int32_t *seg)
+{
+    if (!shape || !s || !tile || !nseg || wgs < 1 || shape[0] < 1 || shape[1] < 1 ||
+        shape[2] < 1) {
+        tbw::set_error("tb_schedule_segments_host: invalid argument");
+        return TB_EINVAL;
+    }
+    if (space_order != 4 && space_order != 8 && space_order != 12) {
+        tbw::set_error("tb_schedule_segments_host: space order %d not in {4, 8, 12}", space_order);
+        return TB_EUNSUPPORTED;
+    }
+    const int R = space_order / 2;
+    const int T = s->mode == TB_SCHED_SB ? 1 : s->time_tile;
+    int lz = 0, bye = 0;
+    if (T < 1 || T > 4 || s->chunk_x < 0 ||
+        (s->tile_y != 0 && s->tile_y != 16 && s->tile_y != 32)) {
+        tbw::set_error("tb_schedule_segments_host: schedule out of range");
+        return TB_EINVAL;
+    }
+    tbw::tile_shape(R, T, s->tile_y, &lz, &bye);
+    if (!tbw::acoustic_shape_ok(R, T, lz, bye)) {
+        tbw::set_error("tb_schedule_segments_host: no kernel for radius %d, depth %d, %d rows", R,
+                       T, bye);
+        return TB_EUNSUPPORTED;
+    }
+    const tbw::TileGeom g = tbw::make_geom(R, T, s->tile_y, s->chunk_x, wgs, shape[0], shape[1],
+                                           shape[2]);
+    tile[0] = g.BYE;
+    tile[1] = 4 * g.LZ;
+    tile[2] = g.OY;
+    tile[3] = g.OZ;
+    const int n = (int)g.segs.size();
+    const int cap = *nseg;
+    *nseg = n;
+    if (n > cap || (n > 0 && !seg)) {
+        tbw::set_error("tb_schedule_segments_host: %d segments exceed capacity %d", n, cap);
+        return TB_EWORKSPACE;
+    }
+    for (int w = 0; w < g.nwg; w++)
+        for (int k = g.seg_off[w]; k < g.seg_off[w + 1]; k++) {
+            const tbw::SegDesc &d = g.segs[k];
+            int32_t *o = seg + 5 * k;
+            o[0] = w;
+            o[1] = d.tile / g.tiles_z;
+            o[2] = d.tile % g.tiles_z;
+            o[3] = d.xs;
+            o[4] = d.xe;
+        }
+    return TB_OK;
+}

@@ -84,6 +84,8 @@ _SIGNATURES = {
     "tb_sparse_counts": (ctypes.c_int32, [_vp, _ip, _ip]),
     "tb_inspect_host": (ctypes.c_int32, [_ip, _dp, _dp, ctypes.c_double, ctypes.c_int32, _fp,
                                          ctypes.c_int32, _dp, _dp, _ip, _ip, _fp]),
+    "tb_schedule_segments_host": (ctypes.c_int32, [_ip, ctypes.c_int32, ctypes.POINTER(Schedule),
+                                                   ctypes.c_int32, _ip, _ip, _ip]),
     "tb_workspace_size": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(Schedule), ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_size_t)]),
     "tb_forward": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(Schedule), _vp, ctypes.c_size_t,
@@ -239,6 +241,27 @@ def inspect_host(shape, spacing, origin, dt, nt, vp_host, src_xyz, src_wavelet):
                                  dcmp.ctypes.data_as(_fp)), "tb_inspect_host")
     k = n.value
     return nodes[:k].copy(), dcmp[:nt, :k].copy()
+
+
+def schedule_segments(shape, space_order: int, sched: Schedule, wgs: int):
+    """Host-only work decomposition of an acoustic schedule: (tile, segs) with
+    tile = (rows, z width, owned rows, owned z) and segs[k] = (workgroup,
+    tile y index, tile z index, xs, xe) in launch order."""
+    shp = np.asarray(shape, dtype=np.int32)
+    tile = np.zeros(4, dtype=np.int32)
+    n = ctypes.c_int32(0)
+    st = lib().tb_schedule_segments_host(shp.ctypes.data_as(_ip), int(space_order),
+                                         ctypes.byref(sched), int(wgs), tile.ctypes.data_as(_ip),
+                                         ctypes.byref(n), None)
+    if st not in (0, EWORKSPACE):
+        _check(st, "tb_schedule_segments_host")
+    segs = np.zeros((max(n.value, 1), 5), dtype=np.int32)
+    cap = ctypes.c_int32(segs.shape[0])
+    _check(lib().tb_schedule_segments_host(shp.ctypes.data_as(_ip), int(space_order),
+                                           ctypes.byref(sched), int(wgs), tile.ctypes.data_as(_ip),
+                                           ctypes.byref(cap), segs.ctypes.data_as(_ip)),
+           "tb_schedule_segments_host")
+    return tuple(int(v) for v in tile), segs[:cap.value].copy()
 
 
 def workspace_size(model, sparse, sched: Optional[Schedule], op: int = OP_FORWARD) -> int:
