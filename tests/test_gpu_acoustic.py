@@ -265,3 +265,22 @@ def test_dense_sources(torch_cuda, orc, layout):
     s = W.acoustic_source_density(1000, layout, n=(48, 56, 64), nt=40, nbl=6)
     _check_case(torch_cuda, orc, s, scheds=[("sb", 1, 32, 0), ("tb", 2, 32, 64), ("tb", 2, 32, 0),
                                             ("tb", 2, 16, 8)])
+
+
+def test_dense_x_plane_runs_the_global_list_kernel(torch_cuda, orc):
+    """2000 sources on one x-plane of a 40x40x64 grid: the corner planes
+    hold ~2000 injection entries per tile, more than the 1024 a segment can
+    stage in LDS even for a single plane, so those passes run the variant
+    that walks the lists in global memory; parity with the oracle and
+    bitwise identity with the other schedules."""
+    s = W.acoustic_two_layer(seed=77, n=(40, 40, 64), nt=30, nbl=4, nsrc=1, nrec=16)
+    rng = np.random.Generator(np.random.PCG64(78))
+    k = 2000
+    src = np.empty((k, 3))
+    src[:, 0] = 20.3 * s.spacing[0]
+    src[:, 1] = rng.uniform(5, 34, k) * s.spacing[1]
+    src[:, 2] = rng.uniform(5, 58, k) * s.spacing[2]
+    s.src_xyz = src
+    s.src_wav = np.stack([W.ricker(10.0 + 0.001 * i, s.nt, s.dt) for i in range(k)], axis=1)
+    _check_case(torch_cuda, orc, s, scheds=[("sb", 1, 32, 0), ("tb", 2, 32, 2048),
+                                            ("tb", 2, 32, 64), ("sb", 1, 16, 2048)])
