@@ -190,7 +190,7 @@ def space_order_bench(tb, W, torch, nt):
     shot each)."""
     import numpy as np
 
-    cands = {4: [("tb", 2, 32, 2048), ("tb", 2, 32, 64), ("tb", 3, 16, 64), ("tb", 4, 16, 64)],
+    cands = {4: [("tb", 3, 32, 2048), ("tb", 3, 32, 64), ("tb", 2, 32, 2048), ("tb", 4, 16, 64)],
              8: [("tb", 2, 32, 2048), ("tb", 2, 32, 64)],
              12: [("tb", 2, 32, 64), ("tb", 2, 32, 2048), ("tb", 2, 16, 64)]}
     sb_cands = [("sb", 1, 16, 2048), ("sb", 1, 32, 128), ("sb", 1, 16, 128)]

@@ -95,8 +95,8 @@ typedef struct {
  * Schedule of the time loop (Section II-B; the wave-front loop nest of the
  * last listing). mode TB_SCHED_SB runs one step per pass; TB_SCHED_TB runs
  * time_tile steps per pass with a wave-front along x and overlapped y-z
- * halos. time_tile is 1..4 at space order 4 (3 and 4 with tile_y 16) and
- * 1..2 at space order 8.
+ * halos. time_tile is 1..4 at space order 4 (4 with tile_y 16 only) and
+ * 1..2 at space orders 8 and 12.
  *  tile_y   y rows one workgroup holds: 16 or 32 (16 lanes x 4 z per row),
  *           or 0 for 32 where that shape fits the depth, else 16.
  *  chunk_x  x planes one work segment streams (at most 1024 are used).

@@ -42,12 +42,13 @@ def _say(msg):
     sys.stdout.flush()
 
 
-# Time tiles of 3 and 4 exist at space order 4 with 16-row tiles only (LDS).
+# Time tiles of 3 and 4 exist at space order 4 only (4 with 16-row tiles).
 # chunk_x 2048 streams whole x per tile, with the tails of the tiles on the
 # spare workgroups.
 SCHEDS = [("sb", 1, 32, 0), ("sb", 1, 16, 24), ("tb", 2, 32, 0), ("tb", 2, 16, 0),
           ("tb", 3, 16, 0), ("tb", 4, 16, 40), ("tb", 2, 32, 24), ("tb", 3, 16, 17),
-          ("tb", 2, 0, 0), ("tb", 2, 32, 2048), ("sb", 1, 32, 2048)]
+          ("tb", 2, 0, 0), ("tb", 2, 32, 2048), ("sb", 1, 32, 2048), ("tb", 3, 32, 2048),
+          ("tb", 3, 32, 24)]
 
 
 def _check_case(torch_cuda, orc, shot, scheds=SCHEDS, tol=TOL):
