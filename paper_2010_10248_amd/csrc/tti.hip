@@ -75,7 +75,7 @@ __device__ __forceinline__ f4 d1xy(const float *f, const TtiParams &P, const Sit
     f4 s = f4{0.f, 0.f, 0.f, 0.f};
     const long long st = ax == 0 ? q.sx : q.sy;
     const int c = ax == 0 ? q.x : q.y, n = ax == 0 ? P.nx : P.ny;
-#pragma unroll 1
+#pragma unroll
     for (int m = 1; m <= R; m++) {
         const f4 up = ld4(f, q.off + m * st, c + m < n), dn = ld4(f, q.off - m * st, c - m >= 0);
 #pragma unroll
