@@ -185,7 +185,8 @@ def test_adjoint_dot_product_and_oracle(torch_cuda, orc, so):
     q = rng.standard_normal(s.src_wav.shape)
     dp = rng.standard_normal((s.nt, s.rec_xyz.shape[0]))
     prop = tb.Acoustic(s, src_wav=q)
-    for sc in (tb.schedule("sb"), tb.schedule("tb", 2, 32), tb.schedule("tb", 2, 16, 20)):
+    for sc in (tb.schedule("sb"), tb.schedule("tb", 2, 32), tb.schedule("tb", 2, 16, 20),
+               tb.schedule("tb", 2, 32, 2048)):
         _say(f"adjoint so{so} {sc}")
         Fq = prop.forward(sc)["traces"].double().cpu().numpy()
         FTd = prop.adjoint(torch.as_tensor(dp.astype(np.float32), device="cuda"), sc)

@@ -73,7 +73,8 @@ def test_gradient_matches_oracle_and_is_schedule_independent(torch_cuda, orc, so
     base = None
     for sc, every in ((tb.schedule("sb"), 0), (tb.schedule("tb", 2, 32), 0),
                       (tb.schedule("tb", 2, 32), 1), (tb.schedule("tb", 2, 16, 9), 7),
-                      (tb.schedule("tb", 2, 0, 0), 5), (tb.schedule("sb"), 70)):
+                      (tb.schedule("tb", 2, 0, 0), 5), (tb.schedule("sb"), 70),
+                      (tb.schedule("tb", 2, 32, 2048), 3)):
         _say(f"gradient so{so} {data} {sc} checkpoint_every={every}")
         J, g = prop.gradient(d, sc, every)
         g = g.cpu().numpy()
