@@ -286,3 +286,27 @@ def test_dense_x_plane_runs_the_global_list_kernel(torch_cuda, orc):
     s.src_wav = np.stack([W.ricker(10.0 + 0.001 * i, s.nt, s.dt) for i in range(k)], axis=1)
     _check_case(torch_cuda, orc, s, scheds=[("sb", 1, 32, 0), ("tb", 2, 32, 2048),
                                             ("tb", 2, 32, 64), ("sb", 1, 16, 2048)])
+
+
+@pytest.mark.skipif(not __import__("os").environ.get("TB_FULL_PARITY"),
+                    reason="full-length 512^3 oracle run (about 2 minutes of FP64 on 16 threads); "
+                           "set TB_FULL_PARITY=1")
+def test_full_size_c2_all_steps(torch_cuda, orc):
+    """The 512^3 SO8 two-layer workload over all 1000 steps in the launch
+    configurations the benchmark times: TB (whole x) bitwise equal to SB, and
+    traces and final fields against the FP64 oracle."""
+    from paper_2010_10248_amd import tb
+
+    s = W.acoustic_two_layer(n=512, nt=1000)
+    prop = tb.Acoustic(s)
+    a = _run(tb, prop, tb.schedule("tb", 2, 32, 2048))
+    b = _run(tb, prop, tb.schedule("sb", 1, 16, 2048))
+    prop.close()
+    for k in ("traces", "u_last", "u_prev"):
+        assert np.array_equal(a[k].view(np.uint32), b[k].view(np.uint32)), k
+    _say("512^3 1000 steps: TB == SB bitwise; running the oracle")
+    ref = orc.acoustic_forward(s)
+    e = {k: _rel(a[k], ref[k]) for k in ("traces", "u_last", "u_prev")}
+    _say(f"512^3 1000 steps vs oracle: {e}")
+    assert np.abs(ref["traces"]).max() > 0
+    assert all(v <= TOL for v in e.values()), e
