@@ -131,9 +131,10 @@ typedef struct {
 /*
  * Create a model: validates the description, computes c = dt^2 vp^2 (FP64,
  * rounded once to FP32) and the damping profile into library-owned device
- * memory on the current device. Errors: TB_EINVAL, TB_EUNSUPPORTED (physics
- * or space order), TB_EUNSTABLE (vp_max dt exceeds the leapfrog bound of the
- * chosen weights), TB_ENOMEM, TB_EHIP. *out is NULL on failure.
+ * memory on the current device. Errors: TB_EINVAL, TB_EUNSUPPORTED (physics,
+ * space order, or nx above 65535: the sparse-list keys hold x in 16 bits),
+ * TB_EUNSTABLE (vp_max dt exceeds the leapfrog bound of the chosen weights),
+ * TB_ENOMEM, TB_EHIP. *out is NULL on failure.
  */
 tb_status tb_create_model(const tb_model_desc *desc, tb_model **out);
 void tb_destroy_model(tb_model *m);

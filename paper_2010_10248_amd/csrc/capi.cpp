@@ -1269,6 +1269,10 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
         set_error("grid too large");
         return TB_EINVAL;
     }
+    if (nx > 65535) {
+        set_error("nx %d above 65535 (the sparse-list keys hold x in 16 bits)", nx);
+        return TB_EUNSUPPORTED;
+    }
     auto m = std::make_unique<tb_model>();
     m->physics = d->physics;
     std::memcpy(m->n, d->shape, sizeof m->n);

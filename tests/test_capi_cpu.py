@@ -49,6 +49,12 @@ def test_invalid_arguments_fail_without_touching_the_gpu():
     d.physics = 7
     assert L.tb_create_model(ctypes.byref(d), ctypes.byref(h)) == tb.EUNSUPPORTED
     d.physics = tb.ACOUSTIC
+    d.shape[:] = [70000, 4, 4]
+    d.vp = ctypes.c_void_p(16)  # never dereferenced: the shape is rejected first
+    assert L.tb_create_model(ctypes.byref(d), ctypes.byref(h)) == tb.EUNSUPPORTED
+    assert "65535" in tb.last_error()
+    d.vp = None
+    d.shape[:] = [16, 16, 16]
     d.spacing[1] = -1.0
     assert L.tb_create_model(ctypes.byref(d), ctypes.byref(h)) == tb.EINVAL
     assert L.tb_sparse_counts(None, None, None) == tb.EINVAL
