@@ -245,6 +245,35 @@ tb_status launch_fill(float *ptr, size_t n, float v, hipStream_t st)
     return TB_OK;
 }
 
+__global__ void c_from_vp_kernel(const float *__restrict__ vp, float *__restrict__ c, int ny,
+                                 int nz, int nzp, long long n, double dt)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int z = (int)(i % nzp);
+        const long long xy = i / nzp;
+        float out = 0.0f;
+        if (z < nz) {
+            const double v = (double)vp[xy * nz + z];
+            out = (float)(dt * dt * v * v);
+        }
+        c[i] = out;
+    }
+}
+
+tb_status launch_c_from_vp(const float *vp, float *c, int nx, int ny, int nz, int nzp, double dt,
+                           hipStream_t st)
+{
+    const long long n = (long long)nx * ny * nzp;
+    if (n == 0) return TB_OK;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(c_from_vp_kernel, dim3((unsigned)blocks), dim3(256), 0, st, vp, c, ny, nz,
+                       nzp, n, dt);
+    TB_HIP(hipGetLastError());
+    return TB_OK;
+}
+
 tb_status launch_trace_reduce(const float *rec_dcmp, int nrid, int nt, const int *ptr,
                               const int *id, const float *w, int nrec, float *out, int reverse,
                               hipStream_t st)

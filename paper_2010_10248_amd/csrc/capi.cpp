@@ -1400,25 +1400,19 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
                   2.0 / (vstab * std::sqrt(rho)), vstab);
         return TB_EUNSTABLE;
     }
-    m->c64.resize(N);
-    std::vector<float> cpad(m->field_elems(), 0.0f);
-    for (size_t x = 0; x < (size_t)nx; x++)
-        for (size_t y = 0; y < (size_t)ny; y++)
-            for (size_t z = 0; z < (size_t)nz; z++) {
-                const size_t i = (x * ny + y) * nz + z;
-                const double v = (double)vp[i];
-                const double c = m->dt * m->dt * v * v;
-                // The inspector scales injected values by c64: dt^2/m for the
-                // second-order systems, dt for the stress injection.
-                m->c64[i] = d->physics == TB_ELASTIC ? m->dt : c;
-                cpad[(x * ny + y) * m->nzp + z] = (float)c;
-            }
     m->damp.assign((size_t)nx + ny + m->nzp, 0.0f);
     damping_axis(nx, m->nbl, m->h[0], m->vmax, m->damp.data());
     damping_axis(ny, m->nbl, m->h[1], m->vmax, m->damp.data() + nx);
     damping_axis(nz, m->nbl, m->h[2], m->vmax, m->damp.data() + nx + ny);
+    // c = dt^2 vp^2 on the device from the caller's vp (the same FP64
+    // expression the inspector evaluates at its points from the host copy).
     TB_HIP(hipMalloc(&m->d_c, m->field_elems() * sizeof(float)));
-    TB_HIP(hipMemcpy(m->d_c, cpad.data(), cpad.size() * sizeof(float), hipMemcpyHostToDevice));
+    {
+        tb_status rc = launch_c_from_vp(d->vp, m->d_c, nx, ny, nz, m->nzp, m->dt, nullptr);
+        if (rc) return rc;
+        TB_HIP(hipDeviceSynchronize());
+    }
+    m->vp_host = std::move(vp);
     TB_HIP(hipMalloc(&m->d_zero, 256));
     TB_HIP(hipMemset(m->d_zero, 0, 256));
     if (!el_host.empty()) {
@@ -1494,7 +1488,7 @@ tb_status tb_inspect_sparse(const tb_model *m, int32_t nsrc, const double *src_x
         }
     std::vector<float> scale(s->nrid);
     for (int i = 0; i < s->nrid; i++)
-        scale[i] = (float)(m->c64[s->rid_nodes[i]] / alpha_at(s->rid_nodes[i]));
+        scale[i] = (float)(m->inj_coef(s->rid_nodes[i]) / alpha_at(s->rid_nodes[i]));
     if ((st = upload(&s->d_rr_ptr, cnt)) || (st = upload(&s->d_rr_rec, rr_rec)) ||
         (st = upload(&s->d_rr_w, rr_w)) || (st = upload(&s->d_rid_scale, scale)))
         return st;

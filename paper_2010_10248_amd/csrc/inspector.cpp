@@ -421,7 +421,7 @@ tb_status inspect_into(tb_sparse *s, int nsrc, const double *src_xyz, const doub
     s->sc_id = ss.id;
     s->sc_w = ss.w;
     std::vector<double> cn(ss.nodes.size());
-    for (size_t i = 0; i < ss.nodes.size(); i++) cn[i] = m->c64[ss.nodes[i]];
+    for (size_t i = 0; i < ss.nodes.size(); i++) cn[i] = m->inj_coef(ss.nodes[i]);
     decompose(ss, nsrc, m->nt, wav, cn, &s->dcmp);
     s->nrid = (int)rs.nodes.size();
     s->rid_nodes = rs.nodes;
