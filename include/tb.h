@@ -112,9 +112,9 @@ typedef struct {
  *           pieces.
  * Every schedule gives bit-identical results. Passing NULL where a schedule
  * is accepted selects the tuned choice for the model if tb_autotune cached
- * one, else TB, time_tile 2, tile_y 32, with whole x when nx <= 1024 and the
- * tiles fill at least half the compute units but not all of them, else
- * chunk_x 64 when nx >= 256, else 0.
+ * one, else TB, time_tile 3 at space order 4 and 2 otherwise, tile_y 32,
+ * with whole x when nx <= 1024 and the tiles fill at least half the compute
+ * units but not all of them, else chunk_x 64 when nx >= 256, else 0.
  */
 typedef struct {
     int32_t mode;

@@ -104,15 +104,17 @@ size_t field_bytes(const tb_model *m) { return align256(m->field_elems() * sizeo
 
 tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice *out)
 {
-    // Default: two steps per pass on 32-row tiles. When the tiles fill at
-    // least half the CUs but not all, each tile streams whole x (neighbouring
-    // tiles in step, sharing their halo reads in L2) and the spare workgroups
-    // take the tails; otherwise long x axes use 64-plane chunks dispatched
-    // chunk-major, short ones the even partition of the tile-x space. A
-    // schedule tuned for the model's shape (tb_autotune) replaces the default.
-    SchedChoice c{2, 32, m->n[0] >= 256 ? 64 : 0, 2};
+    // Default: three steps per pass at space order 4, two otherwise, on 32-row
+    // tiles. When the tiles fill at least half the CUs but not all, each tile
+    // streams whole x (neighbouring tiles in step, sharing their halo reads in
+    // L2) and the spare workgroups take the tails; otherwise long x axes use
+    // 64-plane chunks dispatched chunk-major, short ones the even partition of
+    // the tile-x space. A schedule tuned for the model's shape (tb_autotune)
+    // replaces the default.
+    const int T0 = m->r == 2 && acoustic_shape_ok(2, 3, 16, 32) ? 3 : 2;
+    SchedChoice c{T0, 32, m->n[0] >= 256 ? 64 : 0, 2};
     if (m->n[0] <= kMaxChunk) {
-        const int nt = make_geom(m->r, 2, 32, kMaxChunk, m->ncu, m->n[0], m->n[1], m->n[2]).ntiles();
+        const int nt = make_geom(m->r, T0, 32, kMaxChunk, m->ncu, m->n[0], m->n[1], m->n[2]).ntiles();
         if (2 * nt >= m->ncu && nt < m->ncu) c.chunk = kMaxChunk;
     }
     if (s) {

@@ -310,3 +310,19 @@ def test_full_size_c2_all_steps(torch_cuda, orc):
     _say(f"512^3 1000 steps vs oracle: {e}")
     assert np.abs(ref["traces"]).max() > 0
     assert all(v <= TOL for v in e.values()), e
+
+
+@pytest.mark.parametrize("so", [4, 8])
+def test_default_schedule_is_bitwise_sb(torch_cuda, so):
+    """A NULL schedule (three steps per pass at space order 4, two at 8, with
+    whole x where the tiles fill the CUs) gives the spatially blocked bits."""
+    from paper_2010_10248_amd import tb
+
+    s = W.acoustic_scaled(31 + so, (96, 70, 130), so, 40, 6, nsrc=2, nrec=20, layered=True)
+    prop = tb.Acoustic(s)
+    a = _run(tb, prop, None)
+    b = _run(tb, prop, tb.schedule("sb"))
+    prop.close()
+    for k in ("traces", "u_last", "u_prev"):
+        assert np.array_equal(a[k].view(np.uint32), b[k].view(np.uint32)), k
+    assert np.abs(a["u_last"]).max() > 0
