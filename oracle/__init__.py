@@ -79,6 +79,9 @@ def lib():
             L.or_elastic_adjoint.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int,
                                              _dp, _dp, _dp, c_double, c_int, _dp, c_int, _dp,
                                              _dp, vp, vp, vp]
+        if hasattr(L, "or_elastic_passes"):
+            L.or_elastic_passes.argtypes = [_ip, _dp, c_int, c_int, c_double, _dp, _dp, _dp,
+                                            c_double, c_int, _dp]
         if hasattr(L, "or_elastic_forward"):
             L.or_elastic_forward.argtypes = [_ip, _dp, _dp, c_int, c_int, c_double, c_int,
                                              _dp, _dp, _dp, c_double,
@@ -373,6 +376,20 @@ def elastic_forward(shot, vmax_damp: float = 0.0, src_wav=None, vp=None, vs=None
     if want_history:
         out["hist"] = hist
     return out
+
+
+def elastic_passes(state, spacing, so: int, dt: float, vp, vs, rho, which: int = 3,
+                   nbl: int = 0, vmax_damp: float = 0.0) -> np.ndarray:
+    """Apply one velocity pass (which & 1) and/or one stress pass (which & 2)
+    of the elastic oracle to ``state[9][...]`` (vx vy vz txx tyy tzz txy txz
+    tyz); returns the new state."""
+    F = np.array(state, dtype=np.float64, order="C", copy=True)
+    shape = F.shape[1:]
+    b = lambda a: _f64(np.broadcast_to(a, shape))
+    _check(lib().or_elastic_passes(np.asarray(shape, dtype=np.int32), _f64(spacing), so, int(nbl),
+                                   float(dt), b(vp), b(vs), b(rho), float(vmax_damp), int(which),
+                                   F), "elastic_passes")
+    return F
 
 
 def misfit(d, dobs) -> float:

@@ -96,6 +96,126 @@ static int interp(const egrid *G, const double *o, const double *u, const double
     return OR_OK;
 }
 
+/* Material parameters at the nodes (b = 1/rho, lambda, mu) and their means:
+ * b at the three velocity points (2 nodes), mu at the three shear points
+ * (4 nodes, a node beyond the grid taken as the nearest inside one). */
+static void set_params(const egrid *G, const double *vp, const double *vs, const double *rho,
+                       double *P)
+{
+    const i64 N = (i64)G->n[0] * G->n[1] * G->n[2];
+    double *b = P, *lam = P + N, *mu = P + 2 * N, *bx = P + 3 * N, *by = P + 4 * N,
+           *bz = P + 5 * N, *mxy = P + 6 * N, *mxz = P + 7 * N, *myz = P + 8 * N;
+    for (i64 q = 0; q < N; q++) {
+        b[q] = 1.0 / rho[q];
+        mu[q] = rho[q] * vs[q] * vs[q];
+        lam[q] = rho[q] * (vp[q] * vp[q] - 2.0 * vs[q] * vs[q]);
+    }
+    for (i64 i = 0; i < G->n[0]; i++)
+        for (i64 j = 0; j < G->n[1]; j++)
+            for (i64 k = 0; k < G->n[2]; k++) {
+                i64 q = idx(G, i, j, k);
+                bx[q] = 0.5 * (clampv(G, b, i, j, k) + clampv(G, b, i + 1, j, k));
+                by[q] = 0.5 * (clampv(G, b, i, j, k) + clampv(G, b, i, j + 1, k));
+                bz[q] = 0.5 * (clampv(G, b, i, j, k) + clampv(G, b, i, j, k + 1));
+                mxy[q] = 0.25 * (clampv(G, mu, i, j, k) + clampv(G, mu, i + 1, j, k) +
+                                 clampv(G, mu, i, j + 1, k) + clampv(G, mu, i + 1, j + 1, k));
+                mxz[q] = 0.25 * (clampv(G, mu, i, j, k) + clampv(G, mu, i + 1, j, k) +
+                                 clampv(G, mu, i, j, k + 1) + clampv(G, mu, i + 1, j, k + 1));
+                myz[q] = 0.25 * (clampv(G, mu, i, j, k) + clampv(G, mu, i, j + 1, k) +
+                                 clampv(G, mu, i, j, k + 1) + clampv(G, mu, i, j + 1, k + 1));
+            }
+}
+
+/* Velocity pass in place on F[9][N]: v = (beta v + dt b (div t)) / alpha. */
+static void vel_pass(const egrid *G, double *F, const double *P, const double *dmp, double dt)
+{
+    const i64 N = (i64)G->n[0] * G->n[1] * G->n[2];
+    const double *bx = P + 3 * N, *by = P + 4 * N, *bz = P + 5 * N;
+    double *vx = F + VX * N, *vy = F + VY * N, *vz = F + VZ * N;
+    const double *txx = F + TXX * N, *tyy = F + TYY * N, *tzz = F + TZZ * N;
+    const double *txy = F + TXY * N, *txz = F + TXZ * N, *tyz = F + TYZ * N;
+#pragma omp parallel for schedule(static)
+    for (i64 i = 0; i < G->n[0]; i++)
+        for (i64 j = 0; j < G->n[1]; j++)
+            for (i64 k = 0; k < G->n[2]; k++) {
+                i64 q = idx(G, i, j, k);
+                double al = 1.0 + dmp[q] * dt / 2.0, be = 1.0 - dmp[q] * dt / 2.0;
+                double fx = dst(G, txx, i, j, k, 0, 1) + dst(G, txy, i, j, k, 1, 0) +
+                            dst(G, txz, i, j, k, 2, 0);
+                double fy = dst(G, txy, i, j, k, 0, 0) + dst(G, tyy, i, j, k, 1, 1) +
+                            dst(G, tyz, i, j, k, 2, 0);
+                double fz = dst(G, txz, i, j, k, 0, 0) + dst(G, tyz, i, j, k, 1, 0) +
+                            dst(G, tzz, i, j, k, 2, 1);
+                vx[q] = (be * vx[q] + dt * bx[q] * fx) / al;
+                vy[q] = (be * vy[q] + dt * by[q] * fy) / al;
+                vz[q] = (be * vz[q] + dt * bz[q] * fz) / al;
+            }
+}
+
+/* Stress pass in place on F[9][N]:
+ * t = (beta t + dt (lambda tr(grad v) I + mu (grad v + grad v^T))) / alpha. */
+static void str_pass(const egrid *G, double *F, const double *P, const double *dmp, double dt)
+{
+    const i64 N = (i64)G->n[0] * G->n[1] * G->n[2];
+    const double *lam = P + N, *mu = P + 2 * N, *mxy = P + 6 * N, *mxz = P + 7 * N,
+                 *myz = P + 8 * N;
+    const double *vx = F + VX * N, *vy = F + VY * N, *vz = F + VZ * N;
+    double *txx = F + TXX * N, *tyy = F + TYY * N, *tzz = F + TZZ * N;
+    double *txy = F + TXY * N, *txz = F + TXZ * N, *tyz = F + TYZ * N;
+#pragma omp parallel for schedule(static)
+    for (i64 i = 0; i < G->n[0]; i++)
+        for (i64 j = 0; j < G->n[1]; j++)
+            for (i64 k = 0; k < G->n[2]; k++) {
+                i64 q = idx(G, i, j, k);
+                double al = 1.0 + dmp[q] * dt / 2.0, be = 1.0 - dmp[q] * dt / 2.0;
+                double exx = dst(G, vx, i, j, k, 0, 0), eyy = dst(G, vy, i, j, k, 1, 0),
+                       ezz = dst(G, vz, i, j, k, 2, 0);
+                double tr = exx + eyy + ezz;
+                txx[q] = (be * txx[q] + dt * (lam[q] * tr + 2.0 * mu[q] * exx)) / al;
+                tyy[q] = (be * tyy[q] + dt * (lam[q] * tr + 2.0 * mu[q] * eyy)) / al;
+                tzz[q] = (be * tzz[q] + dt * (lam[q] * tr + 2.0 * mu[q] * ezz)) / al;
+                double gxy = dst(G, vx, i, j, k, 1, 1) + dst(G, vy, i, j, k, 0, 1);
+                double gxz = dst(G, vx, i, j, k, 2, 1) + dst(G, vz, i, j, k, 0, 1);
+                double gyz = dst(G, vy, i, j, k, 2, 1) + dst(G, vz, i, j, k, 1, 1);
+                txy[q] = (be * txy[q] + dt * mxy[q] * gxy) / al;
+                txz[q] = (be * txz[q] + dt * mxz[q] * gxz) / al;
+                tyz[q] = (be * tyz[q] + dt * myz[q] * gyz) / al;
+            }
+}
+
+/*
+ * One velocity pass (which & 1) and/or one stress pass (which & 2), in that
+ * order, applied in place to a given state F[9][N] (vx vy vz txx tyy tzz txy
+ * txz tyz), with the forward's parameters and damping; for checking the two
+ * passes on their own against closed forms.
+ */
+int or_elastic_passes(const int *n, const double *h, int so, int nbl, double dt,
+                      const double *vp, const double *vs, const double *rho, double vmax_damp,
+                      int which, double *F)
+{
+    egrid G;
+    memcpy(G.n, n, sizeof(int) * 3);
+    memcpy(G.h, h, sizeof(double) * 3);
+    G.r = so / 2;
+    if (so < 2 || so > 16 || so % 2 || or_weights_d1_staggered(so, G.w)) return OR_EINVAL;
+    const i64 N = (i64)n[0] * n[1] * n[2];
+    double *P = calloc((size_t)10 * N, sizeof(double));
+    if (!P) return OR_ENOMEM;
+    double *dmp = P + 9 * N;
+    double vmax = vmax_damp;
+    if (!(vmax > 0.0)) {
+        vmax = 0.0;
+        for (i64 q = 0; q < N; q++)
+            if (vp[q] > vmax) vmax = vp[q];
+    }
+    or_damping(n, h, nbl, vmax, dmp);
+    set_params(&G, vp, vs, rho, P);
+    if (which & 1) vel_pass(&G, F, P, dmp, dt);
+    if (which & 2) str_pass(&G, F, P, dmp, dt);
+    free(P);
+    return OR_OK;
+}
+
 /*
  * Forward run from zero state. traces[2][nt][nrec]: vz then P (either block
  * zero-sized if traces is NULL). state[9][N] (optional): v^{nt-1/2} and
@@ -125,8 +245,8 @@ int or_elastic_forward(const int *n, const double *h, const double *o, int so, i
         free(F); free(Fold); free(P);
         return OR_ENOMEM;
     }
-    double *b = P, *lam = P + N, *mu = P + 2 * N, *bx = P + 3 * N, *by = P + 4 * N,
-           *bz = P + 5 * N, *mxy = P + 6 * N, *mxz = P + 7 * N, *myz = P + 8 * N, *dmp = P + 9 * N;
+    double *lam = P + N, *mu = P + 2 * N, *bx = P + 3 * N, *by = P + 4 * N, *bz = P + 5 * N,
+           *mxy = P + 6 * N, *mxz = P + 7 * N, *myz = P + 8 * N, *dmp = P + 9 * N;
     double vmax = vmax_damp;
     if (!(vmax > 0.0)) {
         vmax = 0.0;
@@ -134,25 +254,7 @@ int or_elastic_forward(const int *n, const double *h, const double *o, int so, i
             if (vp[q] > vmax) vmax = vp[q];
     }
     or_damping(n, h, nbl, vmax, dmp);
-    for (i64 q = 0; q < N; q++) {
-        b[q] = 1.0 / rho[q];
-        mu[q] = rho[q] * vs[q] * vs[q];
-        lam[q] = rho[q] * (vp[q] * vp[q] - 2.0 * vs[q] * vs[q]);
-    }
-    for (i64 i = 0; i < n[0]; i++)
-        for (i64 j = 0; j < n[1]; j++)
-            for (i64 k = 0; k < n[2]; k++) {
-                i64 q = idx(&G, i, j, k);
-                bx[q] = 0.5 * (clampv(&G, b, i, j, k) + clampv(&G, b, i + 1, j, k));
-                by[q] = 0.5 * (clampv(&G, b, i, j, k) + clampv(&G, b, i, j + 1, k));
-                bz[q] = 0.5 * (clampv(&G, b, i, j, k) + clampv(&G, b, i, j, k + 1));
-                mxy[q] = 0.25 * (clampv(&G, mu, i, j, k) + clampv(&G, mu, i + 1, j, k) +
-                                 clampv(&G, mu, i, j + 1, k) + clampv(&G, mu, i + 1, j + 1, k));
-                mxz[q] = 0.25 * (clampv(&G, mu, i, j, k) + clampv(&G, mu, i + 1, j, k) +
-                                 clampv(&G, mu, i, j, k + 1) + clampv(&G, mu, i + 1, j, k + 1));
-                myz[q] = 0.25 * (clampv(&G, mu, i, j, k) + clampv(&G, mu, i, j + 1, k) +
-                                 clampv(&G, mu, i, j, k + 1) + clampv(&G, mu, i, j + 1, k + 1));
-            }
+    set_params(&G, vp, vs, rho, P);
     double *vx = F + VX * N, *vy = F + VY * N, *vz = F + VZ * N;
     double *txx = F + TXX * N, *tyy = F + TYY * N, *tzz = F + TZZ * N;
     double *txy = F + TXY * N, *txz = F + TXZ * N, *tyz = F + TYZ * N;
@@ -174,43 +276,10 @@ int or_elastic_forward(const int *n, const double *h, const double *o, int so, i
         if (energy) memcpy(Fold, F + TXX * N, sizeof(double) * 6 * N);
         if (hist) memcpy(hist + ((i64)t * NF + TXX) * N, F + TXX * N, sizeof(double) * 6 * N);
         /* Velocity pass. */
-#pragma omp parallel for schedule(static)
-        for (i64 i = 0; i < n[0]; i++)
-            for (i64 j = 0; j < n[1]; j++)
-                for (i64 k = 0; k < n[2]; k++) {
-                    i64 q = idx(&G, i, j, k);
-                    double al = 1.0 + dmp[q] * dt / 2.0, be = 1.0 - dmp[q] * dt / 2.0;
-                    double fx = dst(&G, txx, i, j, k, 0, 1) + dst(&G, txy, i, j, k, 1, 0) +
-                                dst(&G, txz, i, j, k, 2, 0);
-                    double fy = dst(&G, txy, i, j, k, 0, 0) + dst(&G, tyy, i, j, k, 1, 1) +
-                                dst(&G, tyz, i, j, k, 2, 0);
-                    double fz = dst(&G, txz, i, j, k, 0, 0) + dst(&G, tyz, i, j, k, 1, 0) +
-                                dst(&G, tzz, i, j, k, 2, 1);
-                    vx[q] = (be * vx[q] + dt * bx[q] * fx) / al;
-                    vy[q] = (be * vy[q] + dt * by[q] * fy) / al;
-                    vz[q] = (be * vz[q] + dt * bz[q] * fz) / al;
-                }
+        vel_pass(&G, F, P, dmp, dt);
         if (hist) memcpy(hist + (i64)t * NF * N, F, sizeof(double) * 3 * N);
         /* Stress pass. */
-#pragma omp parallel for schedule(static)
-        for (i64 i = 0; i < n[0]; i++)
-            for (i64 j = 0; j < n[1]; j++)
-                for (i64 k = 0; k < n[2]; k++) {
-                    i64 q = idx(&G, i, j, k);
-                    double al = 1.0 + dmp[q] * dt / 2.0, be = 1.0 - dmp[q] * dt / 2.0;
-                    double exx = dst(&G, vx, i, j, k, 0, 0), eyy = dst(&G, vy, i, j, k, 1, 0),
-                           ezz = dst(&G, vz, i, j, k, 2, 0);
-                    double tr = exx + eyy + ezz;
-                    txx[q] = (be * txx[q] + dt * (lam[q] * tr + 2.0 * mu[q] * exx)) / al;
-                    tyy[q] = (be * tyy[q] + dt * (lam[q] * tr + 2.0 * mu[q] * eyy)) / al;
-                    tzz[q] = (be * tzz[q] + dt * (lam[q] * tr + 2.0 * mu[q] * ezz)) / al;
-                    double gxy = dst(&G, vx, i, j, k, 1, 1) + dst(&G, vy, i, j, k, 0, 1);
-                    double gxz = dst(&G, vx, i, j, k, 2, 1) + dst(&G, vz, i, j, k, 0, 1);
-                    double gyz = dst(&G, vy, i, j, k, 2, 1) + dst(&G, vz, i, j, k, 1, 1);
-                    txy[q] = (be * txy[q] + dt * mxy[q] * gxy) / al;
-                    txz[q] = (be * txz[q] + dt * mxz[q] * gxz) / al;
-                    tyz[q] = (be * tyz[q] + dt * myz[q] * gyz) / al;
-                }
+        str_pass(&G, F, P, dmp, dt);
         /* Explosive source into the normal stresses. */
         for (int s = 0; s < nsrc; s++) {
             int nodes[24];
@@ -324,8 +393,8 @@ int or_elastic_adjoint(const int *n, const double *h, const double *o, int so, i
         free(F); free(S); free(P);
         return OR_ENOMEM;
     }
-    double *b = P, *lam = P + N, *mu = P + 2 * N, *bx = P + 3 * N, *by = P + 4 * N,
-           *bz = P + 5 * N, *mxy = P + 6 * N, *mxz = P + 7 * N, *myz = P + 8 * N, *dmp = P + 9 * N;
+    double *lam = P + N, *mu = P + 2 * N, *bx = P + 3 * N, *by = P + 4 * N, *bz = P + 5 * N,
+           *mxy = P + 6 * N, *mxz = P + 7 * N, *myz = P + 8 * N, *dmp = P + 9 * N;
     double vmax = vmax_damp;
     if (!(vmax > 0.0)) {
         vmax = 0.0;
@@ -333,25 +402,7 @@ int or_elastic_adjoint(const int *n, const double *h, const double *o, int so, i
             if (vp[q] > vmax) vmax = vp[q];
     }
     or_damping(n, h, nbl, vmax, dmp);
-    for (i64 q = 0; q < N; q++) {
-        b[q] = 1.0 / rho[q];
-        mu[q] = rho[q] * vs[q] * vs[q];
-        lam[q] = rho[q] * (vp[q] * vp[q] - 2.0 * vs[q] * vs[q]);
-    }
-    for (i64 i = 0; i < n[0]; i++)
-        for (i64 j = 0; j < n[1]; j++)
-            for (i64 k = 0; k < n[2]; k++) {
-                i64 q = idx(&G, i, j, k);
-                bx[q] = 0.5 * (clampv(&G, b, i, j, k) + clampv(&G, b, i + 1, j, k));
-                by[q] = 0.5 * (clampv(&G, b, i, j, k) + clampv(&G, b, i, j + 1, k));
-                bz[q] = 0.5 * (clampv(&G, b, i, j, k) + clampv(&G, b, i, j, k + 1));
-                mxy[q] = 0.25 * (clampv(&G, mu, i, j, k) + clampv(&G, mu, i + 1, j, k) +
-                                 clampv(&G, mu, i, j + 1, k) + clampv(&G, mu, i + 1, j + 1, k));
-                mxz[q] = 0.25 * (clampv(&G, mu, i, j, k) + clampv(&G, mu, i + 1, j, k) +
-                                 clampv(&G, mu, i, j, k + 1) + clampv(&G, mu, i + 1, j, k + 1));
-                myz[q] = 0.25 * (clampv(&G, mu, i, j, k) + clampv(&G, mu, i, j + 1, k) +
-                                 clampv(&G, mu, i, j, k + 1) + clampv(&G, mu, i, j + 1, k + 1));
-            }
+    set_params(&G, vp, vs, rho, P);
     double *vx = F + VX * N, *vy = F + VY * N, *vz = F + VZ * N;
     double *txx = F + TXX * N, *tyy = F + TYY * N, *tzz = F + TZZ * N;
     double *txy = F + TXY * N, *txz = F + TXZ * N, *tyz = F + TYZ * N;

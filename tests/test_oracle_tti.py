@@ -1,7 +1,8 @@
 """Pins of the FP64 TTI oracle (Section III-B) against what the mathematics
 fixes: the isotropic limit, exactness of the rotated operator on quadratics,
-its symmetry and sign, the zero-source invariant, and the kinematics of an
-elliptically anisotropic medium."""
+its symmetry and sign, the zero-source invariant, the kinematics of an
+elliptically and of an anelliptically anisotropic medium (eps != delta, with
+an eps/delta-swap control), and the delta := min(delta, eps) clip."""
 import math
 
 import numpy as np
@@ -205,3 +206,121 @@ def test_tti_gradient_taylor(orc):
     ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
     assert all(3.5 < r < 4.6 for r in ratios), ratios
     assert abs(gd) > 4 * errs[0]
+
+
+# --------------------------------------------------------------------------
+# Anelliptic kinematics (eps != delta, Section III-B's anisotropy
+# parameters). For a plane wave with unit wavenumber at angle psi from the
+# symmetry axis, H0 -> -sin^2 psi and Hz -> -cos^2 psi, so the system's
+# matrix [[(1+2e) s2, sqrt(1+2d) c2], [sqrt(1+2d) s2, c2]] gives the squared
+# phase speed (in units of vp^2) as its larger eigenvalue
+#   lam = 1/2 [(1+2e) s2 + c2 + sqrt(((1+2e) s2 + c2)^2 - 8 (e - d) s2 c2)].
+# A point source's peak travels with the group velocity: magnitude
+# sqrt(v^2 + v'^2), direction psi + atan(v'/v), v' = dv/dpsi.
+# --------------------------------------------------------------------------
+def _phase_speed(psi, eps, dlt, vp):
+    s2, c2 = math.sin(psi) ** 2, math.cos(psi) ** 2
+    a = (1 + 2 * eps) * s2 + c2
+    return vp * math.sqrt(0.5 * (a + math.sqrt(a * a - 8 * (eps - dlt) * s2 * c2)))
+
+
+def _group(psi, eps, dlt, vp):
+    dp = 1e-6
+    v = _phase_speed(psi, eps, dlt, vp)
+    dv = (_phase_speed(psi + dp, eps, dlt, vp) - _phase_speed(psi - dp, eps, dlt, vp)) / (2 * dp)
+    return psi + math.atan2(dv, v), math.hypot(v, dv)
+
+
+def _group_speed_at(angle, eps, dlt, vp):
+    """Group speed of the quasi-P wave along the ray at ``angle`` from the
+    axis (the phase angle found by bisection on the group angle)."""
+    from scipy.optimize import brentq
+
+    if angle in (0.0, math.pi / 2):
+        return _phase_speed(angle, eps, dlt, vp)
+    psi = brentq(lambda p: _group(p, eps, dlt, vp)[0] - angle, 1e-4, math.pi / 2 - 1e-4,
+                 xtol=1e-12)
+    return _group(psi, eps, dlt, vp)[1]
+
+
+def _anelliptic_arrivals(orc, eps, dlt, psis, R, th=0.0, ph=0.0):
+    """Peak times of p at distance R along rays at angles ``psis`` from a
+    vertical (th = 0) symmetry axis, in the x-z plane."""
+    n = (60, 44, 60)
+    h = 10.0
+    vp = 1500.0
+    dt = W.cfl_dt(vp * math.sqrt(1 + 2 * max(eps, dlt)), h)
+    f0 = 12.0
+    nt = int(0.27 / dt)
+    s = _tti_shot(1, n, 8, nt, 8, eps, dlt, th, ph, vp=vp, nsrc=1, nrec=len(psis))
+    s.dt = dt
+    src = np.array([20.3, 22.0, 16.2]) * h
+    s.src_xyz = src[None, :]
+    s.src_wav = W.ricker(f0, nt, dt)[:, None]
+    s.rec_xyz = np.array([src + R * np.array([math.sin(p), 0.0, math.cos(p)]) for p in psis])
+    tr = orc.tti_forward(s)["traces"]
+    out = []
+    for k in range(len(psis)):
+        i = int(np.argmax(tr[:, k]))
+        y0, y1, y2 = tr[i - 1, k], tr[i, k], tr[i + 1, k]
+        out.append((i + 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)) * dt)
+    return np.array(out), 1.0 / f0, vp
+
+
+_EPS, _DLT = 0.25, 0.05
+_PSIS = [math.pi / 2, math.pi / 6, math.pi / 4, math.pi / 3]
+
+
+def _anelliptic_expected(R, vp, t0, eps=_EPS, dlt=_DLT):
+    return np.array([t0 + R / _group_speed_at(p, eps, dlt, vp) for p in _PSIS])
+
+
+def test_anelliptic_kinematics(orc):
+    """eps = 0.25, delta = 0.05, vertical axis: the peak arrives across the
+    axis at vp sqrt(1+2 eps), and at 30, 45 and 60 degrees at the group speed
+    of the dispersion relation above (not the elliptic one, which is 3.6%
+    faster at 45 degrees). Along the axis the speed is vp for any eps and
+    delta (the elliptic test covers it); there the slow quasi-S artifact of
+    the pseudo-acoustic system (the smaller eigenvalue, nonzero when eps >
+    delta) focuses along the axis and its side lobe overlaps the weak P
+    peak, so that ray is left out."""
+    R = 18.0 * 10.0
+    got, t0, vp = _anelliptic_arrivals(orc, _EPS, _DLT, _PSIS, R)
+    want = _anelliptic_expected(R, vp, t0)
+    assert abs(_group_speed_at(math.pi / 2, _EPS, _DLT, vp) - vp * math.sqrt(1.5)) < 1e-9
+    for k, psi in enumerate(_PSIS):
+        assert abs(got[k] - want[k]) <= 0.01 * (want[k] - t0), (psi, got[k], want[k])
+    # The elliptic medium with the same eps would be detectably faster at 45
+    # degrees, so the check above sees delta.
+    ell = t0 + R / _group_speed_at(math.pi / 4, _EPS, _EPS, vp)
+    assert abs(ell - want[2]) > 0.025 * (want[2] - t0)
+    assert abs(_group_speed_at(0.0, _EPS, _DLT, vp) - vp) < 1e-9
+
+
+def test_anelliptic_swapped_parameters_fail(orc):
+    """Control: the same medium with eps and delta swapped (the plausible
+    mistake of exchanging them in the coupling) misses the expected
+    arrivals by far more than the tolerance."""
+    R = 18.0 * 10.0
+    got, t0, vp = _anelliptic_arrivals(orc, _DLT, _EPS, _PSIS, R)
+    want = _anelliptic_expected(R, vp, t0)
+    assert abs(got[0] - want[0]) > 0.05 * (want[0] - t0)
+    assert max(abs(got[k] - want[k]) / (want[k] - t0) for k in range(1, 4)) > 0.02
+
+
+def test_delta_above_epsilon_is_clipped(orc):
+    """delta := min(delta, eps): a run whose delta exceeds eps everywhere is
+    bitwise the run with delta = eps, and differs from the run with the
+    drawn delta below eps."""
+    shape = (22, 24, 26)
+    rng = np.random.Generator(np.random.PCG64(5))
+    eps = W.smooth_field(rng, shape, 0.05, 0.3, 3.0)
+    th = W.smooth_field(rng, shape, -0.7, 0.7, 3.0)
+    ph = W.smooth_field(rng, shape, -2.0, 2.0, 3.0)
+    s = _tti_shot(12, shape, 8, 40, 4, eps, eps, th, ph)
+    a = orc.tti_forward(s)
+    b = orc.tti_forward(s, delta=eps + 0.1)
+    c = orc.tti_forward(s, delta=0.5 * eps)
+    for k in ("traces", "p_last", "r_last"):
+        assert np.array_equal(a[k], b[k]), k
+    assert _rel(c["p_last"], a["p_last"]) > 1e-3
