@@ -71,26 +71,35 @@ def copy_calibration(torch):
     return 0
 
 
-def serve_bench(tb, W, torch, nreq, load, max_active, arena_gb):
+def serve_bench(tb, W, torch, nreq, loads, max_active, arena_gb):
     """C5 serving: gradient requests (forward, residual vs observed traces,
     adjoint, checkpointed squared-slowness gradient) on mixed 128-384^3 SO8
     grids with 500-1500 steps. Phase 1 submits every request at once
-    (saturated shots/s); phase 2 replays the same requests with Poisson
-    arrivals at `load` x that rate and reports completion - arrival latency.
-    Models, sparse sets and observed data (forward runs of the true model
-    with a +5% velocity anomaly) are made before the clock starts."""
+    (saturated shots/s); then the same requests are replayed with Poisson
+    arrivals at each of `loads` x that rate, reporting completion - arrival
+    latency per load. Models, sparse sets, observed data (forward runs of the
+    true model with a +5% velocity anomaly) and one autotuner sweep per
+    served grid size (requests then run the tuned schedule) are made before
+    the clock starts."""
     import numpy as np
 
     rng = np.random.Generator(np.random.PCG64(10253))
     reqs = []
     t0 = time.perf_counter()
+    tuned = {}
     for _ in range(nreq):
         shot, vp_true = W.serving_request(rng)
         vmax = float(shot.vp.max())
+        prop = tb.Acoustic(shot, damp_vmax=vmax)
+        n = shot.shape[0]
+        if n not in tuned:
+            best, ms = tb.autotune(prop.model, prop.sparse, steps=16)
+            torch.cuda.synchronize()
+            tuned[n] = dict(schedule=repr(best), ms_per_step=round(ms, 4))
+            log(f"serving: tuned {n}^3: {best} {ms:.3f} ms/step")
         true = tb.Acoustic(shot, vp=vp_true, damp_vmax=vmax)
         d_obs = true.forward(None, want_fields=False)["traces"]
         true.close()
-        prop = tb.Acoustic(shot, damp_vmax=vmax)
         reqs.append((shot, prop, d_obs))
     torch.cuda.synchronize()
     log(f"serving: {nreq} requests prepared in {time.perf_counter() - t0:.1f} s "
@@ -126,25 +135,32 @@ def serve_bench(tb, W, torch, nreq, load, max_active, arena_gb):
     span, lat_sat, losses, st = run([0.0] * nreq)
     rate = nreq / span
     log(f"serving saturated: {nreq} requests in {span:.2f} s = {rate:.3f} shots/s; stats {st}")
-    arr = np.cumsum(np.random.Generator(np.random.PCG64(7)).exponential(1.0 / (load * rate), nreq))
-    arr = arr - arr[0]
-    span2, lat, losses2, st2 = run(list(arr))
-    assert losses2 == losses, "a request's misfit changed between runs"
-    lat_ms = np.array(lat) * 1e3
+    per_load = []
+    for k, load in enumerate(loads):
+        gen = np.random.Generator(np.random.PCG64(7 + k))
+        arr = np.cumsum(gen.exponential(1.0 / (load * rate), nreq))
+        arr = arr - arr[0]
+        span2, lat, losses2, st2 = run(list(arr))
+        assert losses2 == losses, "a request's misfit changed between runs"
+        lat_ms = np.array(lat) * 1e3
+        per_load.append(dict(
+            load=load, offered_shots_per_s=round(load * rate, 4),
+            shots_per_s=round(nreq / span2, 4),
+            p50_ms=round(float(np.percentile(lat_ms, 50)), 1),
+            p99_ms=round(float(np.percentile(lat_ms, 99)), 1),
+            batched_passes_per_launch=round(st2["passes_batched"] / max(st2["launches"], 1), 2),
+            graph_replays=st2["graph_replays"], graph_captures=st2["graph_captures"]))
+        log(f"serving Poisson at {load}x: {per_load[-1]}")
     out = dict(shots_per_s=round(rate, 4), requests=nreq,
                point_updates_per_request_mean=round(work / nreq / 1e9, 3),
                gradient_gpts_per_s_equiv=round(work / span / 1e9, 2),
-               poisson_load=load, poisson_shots_per_s=round(nreq / span2, 4),
-               p50_ms=round(float(np.percentile(lat_ms, 50)), 1),
-               p99_ms=round(float(np.percentile(lat_ms, 99)), 1),
                saturated_p50_ms=round(float(np.percentile(np.array(lat_sat) * 1e3, 50)), 1),
+               saturated_p99_ms=round(float(np.percentile(np.array(lat_sat) * 1e3, 99)), 1),
+               poisson=per_load, tuned_schedules=tuned,
                max_active=max_active, arena_gib=arena_gb,
-               batched_passes_per_launch=round(st2["passes_batched"] / max(st2["launches"], 1), 2),
-               graph_replays=st2["graph_replays"], graph_captures=st2["graph_captures"],
                request="gradient (forward + residual + adjoint + imaging, checkpoints every "
                        "ceil(sqrt(nt)))",
                mix="SO8 two-layer, N in {128,192,256,384}, nt 500-1500, Poisson arrivals")
-    log(f"serving Poisson at {load}x: p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms")
     for _, prop, _ in reqs:
         prop.close()
     return out
@@ -153,7 +169,10 @@ def serve_bench(tb, W, torch, nreq, load, max_active, arena_gb):
 def physics_bench(tb, W, torch, which, steps):
     """GPts/s of the TTI (256^3 SO8, 800 steps, 44 B per point-step) or
     elastic (256^3 SO8, 600 steps, 84 B per point-step) propagator on one
-    shot, inputs resident; effective bandwidth at those algorithmic bytes."""
+    shot, inputs resident, for the spatially blocked schedule and the
+    autotuner's choice among the temporally blocked ones (passes of T steps
+    over x-slabs); effective bandwidth at those algorithmic bytes, and the
+    bitwise identity of the two."""
     import numpy as np
 
     if which == "tti":
@@ -163,24 +182,41 @@ def physics_bench(tb, W, torch, which, steps):
         shot = W.elastic_smooth()
         bpp = 84
     prop = tb.Propagator(shot)
-    ws = prop.workspace(None)
     nt = shot.nt
-    shape = (2, nt, prop.nrec) if which == "elastic" else (nt, prop.nrec)
-    rec = torch.empty(shape, dtype=torch.float32, device="cuda")
-    tb.forward(prop.model, prop.sparse, None, ws, rec)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        tb.forward(prop.model, prop.sparse, None, ws, rec)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
     N3 = int(np.prod(shot.shape))
-    g = N3 * nt / dt / 1e9
+    shape = (2, nt, prop.nrec) if which == "elastic" else (nt, prop.nrec)
+
+    def timed(sched):
+        ws = prop.workspace(sched)
+        rec = torch.empty(shape, dtype=torch.float32, device="cuda")
+        u = torch.empty(shot.shape, dtype=torch.float32, device="cuda")
+        tb.forward(prop.model, prop.sparse, sched, ws, rec, u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            tb.forward(prop.model, prop.sparse, sched, ws, rec, u)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, rec, u
+
+    dt_sb, rec_sb, u_sb = timed(tb.schedule("sb"))
+    g_sb = N3 * nt / dt_sb / 1e9
+    best, _ = tb.autotune(prop.model, prop.sparse, steps=16)
+    tbs = tb.schedule("tb", 2, 0, 32) if best.time_tile == 1 else best
+    dt_tb, rec_tb, u_tb = timed(tbs)
+    g_tb = N3 * nt / dt_tb / 1e9
+    same = bool(torch.equal(rec_sb.view(torch.int32), rec_tb.view(torch.int32))
+                and torch.equal(u_sb.view(torch.int32), u_tb.view(torch.int32)))
     prop.close()
-    log(f"{which}: {shot.name}: {dt * 1e3:.1f} ms/shot, {g:.1f} GPts/s")
-    return dict(workload=shot.name, ms_per_shot=round(dt * 1e3, 2), gpts_per_s=round(g, 2),
+    log(f"{which}: {shot.name}: SB {dt_sb * 1e3:.1f} ms/shot {g_sb:.1f} GPts/s; {tbs} "
+        f"{dt_tb * 1e3:.1f} ms/shot {g_tb:.1f} GPts/s; tuned {best}; bitwise {same}")
+    return dict(workload=shot.name, ms_per_shot=round(dt_sb * 1e3, 2), gpts_per_s=round(g_sb, 2),
                 bytes_per_point_step=bpp,
-                effective_hbm_frac=round(g * bpp / HBM_PEAK_GBS, 4), schedule="SB")
+                effective_hbm_frac=round(g_sb * bpp / HBM_PEAK_GBS, 4), schedule="SB",
+                temporal_blocked=dict(schedule=repr(tbs), ms_per_shot=round(dt_tb * 1e3, 2),
+                                      gpts_per_s=round(g_tb, 2),
+                                      effective_hbm_frac=round(g_tb * bpp / HBM_PEAK_GBS, 4),
+                                      bitwise_equal_to_sb=same),
+                tuned_schedule=repr(best))
 
 
 def space_order_bench(tb, W, torch, nt):
@@ -216,6 +252,11 @@ def space_order_bench(tb, W, torch, nt):
                 best = (g, repr(sc))
         row["tb_gpts"], row["tb_schedule"] = round(best[0], 1), best[1]
         row["tb_over_sb"] = round(best[0] / row["sb_gpts"], 3)
+        # The autotuner's sweep of every schedule (SB included) on this
+        # model; the NULL schedule then runs its choice.
+        tsc, _ = tb.autotune(prop.model, prop.sparse, steps=16)
+        dt, _, _, _, _, _ = time_forward(tb, prop, None, 1, 1, torch)
+        row["tuned_schedule"], row["tuned_gpts"] = repr(tsc), round(N / dt / 1e9, 1)
         prop.close()
         log(f"space order {row}")
         out.append(row)
@@ -261,6 +302,17 @@ def inspector_seconds(tb, prop, shot, torch):
     dt = time.perf_counter() - t0
     tb.destroy_sparse(sp)
     return dt
+
+
+def first_arrival_steps(shot, margin=1.15):
+    """Steps until the direct wave's Ricker peak reaches the nearest receiver
+    at the fastest velocity, with a margin: the parity leg's traces then
+    carry the wavelet."""
+    import numpy as np
+
+    d = np.linalg.norm(shot.src_xyz[:, None, :] - shot.rec_xyz[None, :, :], axis=2).min()
+    t = d / float(shot.vp.max()) + 1.0 / 8.0  # Ricker peak delay 1/f, f >= 8 Hz
+    return int(np.ceil(margin * t / shot.dt))
 
 
 def log(msg):
@@ -321,12 +373,14 @@ def main(argv=None):
                     help="skip the source-density sweep")
     ap.add_argument("--no-physics", action="store_true",
                     help="skip the TTI and elastic measurements")
-    ap.add_argument("--serve-requests", type=int, default=16)
-    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-loads", type=str, default="0.5,0.8,1.0",
+                    help="Poisson loads as fractions of the saturated rate")
     ap.add_argument("--serve-active", type=int, default=4)
     ap.add_argument("--serve-arena-gb", type=float, default=128.0)
-    ap.add_argument("--cpu-steps", type=int, default=64,
-                    help="steps of the full grid the FP64 oracle runs as the CPU sample")
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="steps of the full grid the FP64 oracle runs for the parity leg and "
+                         "the CPU sample (0: until the direct wave reaches the receivers)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -402,7 +456,8 @@ def main(argv=None):
     if not args.no_cpu:
         import oracle
 
-        sample = W.acoustic_two_layer(n=args.n, nt=args.cpu_steps)
+        steps = args.cpu_steps or first_arrival_steps(shot)
+        sample = W.acoustic_two_layer(n=args.n, nt=min(steps, shot.nt))
         t0 = time.perf_counter()
         ref = oracle.acoustic_forward(sample)
         cpu_s = time.perf_counter() - t0
@@ -410,27 +465,23 @@ def main(argv=None):
         cpu = dict(value=round(N3 * sample.nt / cpu_s / 1e9, 4), unit="GPts/s", cores=cores,
                    kind="oracle", seconds=round(cpu_s, 2),
                    sample=f"FP64 oracle, full {args.n}^3 grid, first {sample.nt} of {shot.nt} "
-                          f"steps (same sources/receivers)")
+                          f"steps (same sources/receivers; the run the parity leg compares)")
         log(f"oracle: {cpu_s:.1f} s for {sample.nt} steps on {cores} threads")
         sp = tb.Acoustic(sample)
         errs = {}
-        # Early in the run the receivers only see the stencil's numerical
-        # far field, whose values lie below FP32's range: the relative error
-        # of traces is then reported as not applicable.
         tr_peak = float(np.abs(ref["traces"]).max())
         for name, sc in (("tb", tb_sched), ("sb", sb_sched)):
             o = sp.forward(sc)
             torch.cuda.synchronize()
             tr = o["traces"].cpu().numpy()
-            errs[name] = dict(traces=rel_l2(tr, ref["traces"]) if tr_peak > 1e-30 else
-                              f"n/a: oracle trace peak {tr_peak:.1e}, GPU peak "
-                              f"{float(np.abs(tr).max()):.1e}",
+            errs[name] = dict(traces=rel_l2(tr, ref["traces"]),
                               u_last=rel_l2(o["u_last"].cpu().numpy(), ref["u_last"]),
                               u_prev=rel_l2(o["u_prev"].cpu().numpy(), ref["u_prev"]))
+
         sp.close()
-        parity = dict(steps=sample.nt, **{k: {kk: float(f"{vv:.3e}") if isinstance(vv, float)
-                                              else vv for kk, vv in v.items()}
-                                          for k, v in errs.items()})
+        parity = dict(steps=sample.nt, oracle_trace_peak=float(f"{tr_peak:.3e}"),
+                      **{k: {kk: float(f"{vv:.3e}") for kk, vv in v.items()}
+                         for k, v in errs.items()})
         log(f"parity vs FP64 oracle at {sample.nt} steps: {parity}")
 
     orders = None
@@ -446,7 +497,8 @@ def main(argv=None):
 
     serving = None
     if not args.no_serve:
-        serving = serve_bench(tb, W, torch, args.serve_requests, args.serve_load,
+        serving = serve_bench(tb, W, torch, args.serve_requests,
+                              [float(x) for x in args.serve_loads.split(",")],
                               args.serve_active, args.serve_arena_gb)
 
     line = {

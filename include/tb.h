@@ -59,17 +59,22 @@ typedef struct tb_sparse tb_sparse;
  * Section III-B, the elastic system of Section III-C; Section IV-B).
  *  shape       grid nodes per axis; the absorbing layers lie inside it.
  *  spacing     h per axis in metres; origin in metres.
- *  space_order 4 or 8 (centred Taylor weights, radius space_order/2).
+ *  space_order 4, 8 or 12 (centred Taylor weights, radius space_order/2).
  *  nbl         absorbing-layer width in nodes (0 = no damping).
  *  dt, nt      time step (s) and number of updates of a forward run.
  *  damp_vmax   velocity used by the damping profile (<= 0: max(vp)).
  *  vp          device float32 [nx][ny][nz] P velocity (m/s); read during the
  *              call only (the library derives its own coefficient arrays).
+ *              NULL when slowness2 is given.
  *  epsilon, delta, theta, phi   TTI only (device float32 [nx][ny][nz]):
  *              Thomsen parameters (delta is clipped to epsilon) and the tilt
  *              from vertical / azimuth (radians) of the symmetry axis.
  *  vs, rho     elastic only (device float32 [nx][ny][nz]): S velocity (m/s)
  *              and density (kg/m^3).
+ *  slowness2   acoustic only, in place of vp (device float32 [nx][ny][nz]):
+ *              the squared slowness m = 1/vp^2 (s^2/m^2) of equation (acou),
+ *              the variable tb_gradient differentiates by. The coefficient
+ *              is then c = dt^2/m (FP64, rounded once); vp NULL.
  * All parameter arrays are read during the call only.
  */
 typedef struct {
@@ -89,6 +94,7 @@ typedef struct {
     const float *phi;
     const float *vs;
     const float *rho;
+    const float *slowness2;
 } tb_model_desc;
 
 /*
@@ -110,11 +116,18 @@ typedef struct {
  *           over two workgroups per compute unit. A segment whose injection
  *           list exceeds the staged capacity is streamed as consecutive
  *           pieces.
+ * TTI and elastic (Section II-B applied to the systems of Sections III-B
+ * and III-C): TB_SCHED_TB runs passes of time_tile (1..4) steps over
+ * overlapped x-slabs of chunk_x owned planes (0: 32), each step's range
+ * shrinking by the skew 2 * radius (the two chained first-derivative stages
+ * of a step) from the first to the last step of a pass; tile_y is ignored.
+ * TB_SCHED_SB is one step per pass over all of x.
  * Every schedule gives bit-identical results. Passing NULL where a schedule
  * is accepted selects the tuned choice for the model if tb_autotune cached
- * one, else TB, time_tile 3 at space order 4 and 2 otherwise, tile_y 32,
- * with whole x when nx <= 1024 and the tiles fill at least half the compute
- * units but not all of them, else chunk_x 64 when nx >= 256, else 0.
+ * one, else: acoustic TB with time_tile 3 at space order 4, 2 at space order
+ * 8 and SB (time_tile 1) at space order 12, tile_y 32, with whole x when nx
+ * <= 1024 and the tiles fill at least half the compute units but not all of
+ * them, else chunk_x 64 when nx >= 256, else 0; TTI and elastic SB.
  */
 typedef struct {
     int32_t mode;
@@ -129,12 +142,15 @@ typedef struct {
 #define TB_OP_GRADIENT 2
 
 /*
- * Create a model: validates the description, computes c = dt^2 vp^2 (FP64,
- * rounded once to FP32) and the damping profile into library-owned device
- * memory on the current device. Errors: TB_EINVAL, TB_EUNSUPPORTED (physics,
- * space order, or nx above 65535: the sparse-list keys hold x in 16 bits),
- * TB_EUNSTABLE (vp_max dt exceeds the leapfrog bound of the chosen weights),
- * TB_ENOMEM, TB_EHIP. *out is NULL on failure.
+ * Create a model: validates the description, computes c = dt^2 vp^2 (or
+ * dt^2/m; FP64, rounded once to FP32) and the damping profile into
+ * library-owned device memory on the current device. Errors: TB_EINVAL,
+ * TB_EUNSUPPORTED (physics, space order; nx above 65535: the sparse-list keys
+ * hold x in 16 bits; a padded y-z plane of 2 GiB or more, ny * nzp * 4 >=
+ * 2^31 with nzp = nz rounded up to a multiple of 4: the wave-front kernel
+ * addresses a plane with 32-bit offsets), TB_EUNSTABLE (vp_max dt exceeds
+ * the leapfrog bound of the chosen weights), TB_ENOMEM, TB_EHIP. *out is
+ * NULL on failure.
  */
 tb_status tb_create_model(const tb_model_desc *desc, tb_model **out);
 void tb_destroy_model(tb_model *m);
@@ -210,9 +226,8 @@ tb_status tb_workspace_size(const tb_model *m, const tb_sparse *s, const tb_sche
  *            then P^n = (txx + tyy + tzz)^n / 3; field_out = vz^{nt-1/2},
  *            field_prev_out = tzz^{nt}.
  * Fields are [nx][ny][nz]. ws must hold tb_workspace_size(TB_OP_FORWARD)
- * bytes of device memory. TTI and elastic run the spatially blocked schedule
- * only (a temporally blocked schedule returns TB_EUNSUPPORTED; NULL selects
- * the spatially blocked one).
+ * bytes of device memory for the same schedule. Every schedule of every
+ * physics gives the same bits.
  * Errors: TB_EINVAL, TB_EWORKSPACE, TB_EUNSUPPORTED, TB_EHIP.
  */
 tb_status tb_forward(const tb_model *m, const tb_sparse *s, const tb_schedule *sched, void *ws,
@@ -283,11 +298,14 @@ tb_status tb_gradient_workspace_size(const tb_model *m, const tb_sparse *s,
 /*
  * Autotuner (the paper sweeps tile and block sizes per kernel and platform,
  * Section IV-C / Table 1, and leaves the time-tile depth open). Times every
- * valid (time_tile, tile_y, chunk_x) on the device for `steps` updates of
- * this model and sparse set (zero initial state; no output is written),
+ * valid schedule on the device for `steps` updates of this model and sparse
+ * set (zero initial state; no output is written) — acoustic: time_tile,
+ * tile_y, chunk_x and, for chunk_x 0, one to three resident workgroups per
+ * compute unit (a choice tb_schedule does not express; a NULL schedule
+ * gets it); TTI and elastic: time_tile 1..3 and slab widths 16, 32, 64 —
  * caches the fastest per (physics, space order, grid shape) for the process,
  * and returns it. Afterwards a NULL schedule on any model of that key
- * resolves to the tuned choice. Allocates a temporary four-field workspace.
+ * resolves to the tuned choice. Allocates a temporary workspace.
  * Errors: TB_EINVAL, TB_ENOMEM, TB_EHIP.
  */
 tb_status tb_autotune(const tb_model *m, const tb_sparse *s, int32_t steps, void *stream,

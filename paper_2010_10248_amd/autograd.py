@@ -9,6 +9,7 @@ gradient (argument marshalling only: every step runs in the HIP library).
 """
 from __future__ import annotations
 
+import numpy as np
 import torch
 
 from . import tb
@@ -43,8 +44,7 @@ def modelling(q: torch.Tensor, prop: "tb.Acoustic", sched=None) -> torch.Tensor:
 class _Misfit(torch.autograd.Function):
     @staticmethod
     def forward(ctx, m, shot, d_obs, sched, checkpoint_every, damp_vmax):
-        vp = torch.rsqrt(m.detach().float()).contiguous()
-        prop = tb.Acoustic(shot, vp=vp, device=m.device, damp_vmax=damp_vmax)
+        prop = tb.Acoustic(shot, slowness2=m.detach(), device=m.device, damp_vmax=damp_vmax)
         try:
             J, g = prop.gradient(d_obs.float().contiguous(), sched, checkpoint_every)
         finally:
@@ -60,6 +60,10 @@ class _Misfit(torch.autograd.Function):
 
 def misfit(m: torch.Tensor, shot, d_obs: torch.Tensor, sched=None, checkpoint_every: int = 0,
            damp_vmax: float = 0.0) -> torch.Tensor:
-    """J(m) as a float64 scalar tensor; damp_vmax fixes the damping profile
-    (0 = max vp of this m)."""
+    """J(m) as a float64 scalar tensor. The library takes m itself (c = dt^2/m
+    in FP64, rounded once). The damping profile is held fixed, as the
+    gradient assumes: its velocity is damp_vmax, or when that is 0 the
+    largest vp of the shot's own model (not of m)."""
+    if not damp_vmax > 0.0:
+        damp_vmax = float(np.max(shot.vp))
     return _Misfit.apply(m, shot, d_obs, sched, checkpoint_every, damp_vmax)

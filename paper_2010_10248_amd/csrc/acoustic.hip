@@ -245,8 +245,10 @@ tb_status launch_fill(float *ptr, size_t n, float v, hipStream_t st)
     return TB_OK;
 }
 
+// c = dt^2 vp^2, or c = dt^2 / m from the squared slowness (is_m), in FP64
+// and rounded once; the padding columns z >= nz are zero.
 __global__ void c_from_vp_kernel(const float *__restrict__ vp, float *__restrict__ c, int ny,
-                                 int nz, int nzp, long long n, double dt)
+                                 int nz, int nzp, long long n, double dt, int is_m)
 {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
@@ -255,21 +257,21 @@ __global__ void c_from_vp_kernel(const float *__restrict__ vp, float *__restrict
         float out = 0.0f;
         if (z < nz) {
             const double v = (double)vp[xy * nz + z];
-            out = (float)(dt * dt * v * v);
+            out = is_m ? (float)(dt * dt / v) : (float)(dt * dt * v * v);
         }
         c[i] = out;
     }
 }
 
 tb_status launch_c_from_vp(const float *vp, float *c, int nx, int ny, int nz, int nzp, double dt,
-                           hipStream_t st)
+                           bool is_m, hipStream_t st)
 {
     const long long n = (long long)nx * ny * nzp;
     if (n == 0) return TB_OK;
     long long blocks = (n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(c_from_vp_kernel, dim3((unsigned)blocks), dim3(256), 0, st, vp, c, ny, nz,
-                       nzp, n, dt);
+                       nzp, n, dt, (int)is_m);
     TB_HIP(hipGetLastError());
     return TB_OK;
 }

@@ -104,14 +104,17 @@ size_t field_bytes(const tb_model *m) { return align256(m->field_elems() * sizeo
 
 tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice *out)
 {
-    // Default: three steps per pass at space order 4, two otherwise, on 32-row
-    // tiles. When the tiles fill at least half the CUs but not all, each tile
+    // Default: three steps per pass at space order 4, two at space order 8,
+    // one (spatial blocking) at space order 12, where the radius-6 halos of a
+    // two-step tile cost more than the pass saves (measured at 512^3: 178
+    // against 249 GPts/s), on 32-row tiles. When the tiles fill at least half
+    // the CUs but not all, each tile
     // streams whole x (neighbouring tiles in step, sharing their halo reads in
     // L2) and the spare workgroups take the tails; otherwise long x axes use
     // 64-plane chunks dispatched chunk-major, short ones the even partition of
     // the tile-x space. A schedule tuned for the model's shape (tb_autotune)
     // replaces the default.
-    const int T0 = m->r == 2 && acoustic_shape_ok(2, 3, 16, 32) ? 3 : 2;
+    const int T0 = m->r == 2 && acoustic_shape_ok(2, 3, 16, 32) ? 3 : (m->r >= 6 ? 1 : 2);
     SchedChoice c{T0, 32, m->n[0] >= 256 ? 64 : 0, 2};
     if (m->n[0] <= kMaxChunk) {
         const int nt = make_geom(m->r, T0, 32, kMaxChunk, m->ncu, m->n[0], m->n[1], m->n[2]).ntiles();
@@ -128,16 +131,22 @@ tb_status resolve_schedule(const tb_model *m, const tb_schedule *s, SchedChoice 
         c.chunk = s->chunk_x;
     } else {
         SchedChoice t;
+        if (m->physics != TB_ACOUSTIC) c = SchedChoice{1, 0, 0, 1};
         if (tuned_schedule(m, &t)) c = t;
-        if (m->physics != TB_ACOUSTIC) c.T = 1;
-    }
-    if (m->physics != TB_ACOUSTIC && c.T != 1) {
-        set_error("temporal blocking is built for the acoustic propagator only");
-        return TB_EUNSUPPORTED;
     }
     if (c.T < 1 || c.T > 4) {
         set_error("time_tile %d not in 1..4", c.T);
         return TB_EUNSUPPORTED;
+    }
+    if (m->physics != TB_ACOUSTIC) {
+        // TTI and elastic: passes of T steps over x-slabs of chunk_x owned
+        // planes (0: the default width); tile_y does not apply.
+        if (c.chunk < 0) {
+            set_error("chunk_x %d negative", c.chunk);
+            return TB_EINVAL;
+        }
+        *out = c;
+        return TB_OK;
     }
     if (m->r >= 4 && c.T > 3) {
         set_error("time_tile %d exceeds 3 at space order %d", c.T, m->so);
@@ -382,11 +391,49 @@ tb_status run_plan(const tb_model *m, tb_sparse *s, const SchedChoice &sc, const
     return TB_OK;
 }
 
-size_t forward_ws_bytes(const tb_model *m, const tb_sparse *s)
+namespace {
+
+// Overlapped x-slab passes of the TTI and elastic propagators (layout and
+// widths; see plan_slab_passes).
+constexpr int kSlabDefault = 32;
+
+int slab_fields(const tb_model *m) { return m->physics == TB_TTI ? 4 : 9; }
+
+// Skew per step: two chained first-derivative stages of radius r (the rotated
+// gradient and its divergence; the velocity and the stress pass).
+int slab_skew(const tb_model *m) { return 2 * m->r; }
+
+int slab_width(const tb_model *m, const SchedChoice &sc)
 {
-    const size_t nf = m->physics == TB_TTI ? 8 : (m->physics == TB_ELASTIC ? 9 : 5);
-    return nf * field_bytes(m) +
-           align256(((size_t)m->nt + 1) * std::max(s->nrid + s->nrid2, 1) * sizeof(float));
+    if (sc.T == 1) return m->n[0];
+    return sc.chunk > 0 ? std::min(sc.chunk, m->n[0]) : std::min(kSlabDefault, m->n[0]);
+}
+
+// Planes a step writes beyond its range on each side: the elastic velocity
+// pass runs r planes wider than the stress pass that reads it.
+int slab_margin(const tb_model *m) { return m->physics == TB_ELASTIC ? m->r : 0; }
+
+// Planes of one scratch level: the widest written range of a slab.
+size_t slab_ext(const tb_model *m, const SchedChoice &sc)
+{
+    if (sc.T == 1) return 0;
+    return (size_t)std::min(m->n[0], slab_width(m, sc) + 2 * (sc.T - 1) * slab_skew(m) +
+                                         2 * slab_margin(m));
+}
+
+}  // namespace
+
+size_t forward_ws_bytes(const tb_model *m, const tb_sparse *s, const SchedChoice &sc)
+{
+    const size_t rec =
+        align256(((size_t)m->nt + 1) * std::max(s->nrid + s->nrid2, 1) * sizeof(float));
+    if (m->physics == TB_ACOUSTIC) return 5 * field_bytes(m) + rec;
+    // States A and B, the rotated gradients (TTI), p^{nt-1} (TTI), then two
+    // scratch levels of the slabs.
+    const size_t nf = slab_fields(m);
+    const size_t plane = (size_t)m->n[1] * m->nzp * sizeof(float);
+    const size_t extra = m->physics == TB_TTI ? 3 : 0;
+    return (2 * nf + extra) * field_bytes(m) + 2 * align256(nf * slab_ext(m, sc) * plane) + rec;
 }
 
 namespace {
@@ -447,51 +494,173 @@ ElParams el_params(const tb_model *m, float *const *F)
     return P;
 }
 
-// TTI forward (SB): p (two levels), r (two levels), w_p, w_r, q_p, q_r, then
-// rec_dcmp.
-tb_status plan_forward_tti(const tb_model *m, tb_sparse *s, void *ws, float *rec_out,
-                           float *field_out, float *field_prev_out, Plan *plan)
+// Forward of the TTI and elastic propagators as passes over x-slabs.
+//
+// A pass of T' steps advances the state from A (level n0) to B (level
+// n0 + T'), slab after slab. The slab owning planes [x0, x1) computes step s
+// over U_s = [x0 - (T'-1-s) h, x1 + (T'-1-s) h) clipped to the grid, with h
+// the skew per step (slab_skew): it reads level n0 + s from A (s = 0) or
+// from the slab's scratch level, and writes level n0 + s + 1 to the other
+// scratch level, or to B at s = T' - 1. U_s widened by h is U_{s-1}, exactly
+// what step s reads. Injection of step s reaches every point of U_s — the
+// redundant copies in the slab's halo included, which is what makes the
+// reordering legal (Section II-B, Fig. 4b) — and receivers record the owned
+// planes [x0, x1) only, each level from the copy of its own slab. A is only
+// read and B only written during a pass, so slabs do not interact, and each
+// point is computed by the expression of the one-step schedule: every slab
+// width and depth gives the same bits. The scratch levels are addressed with
+// the global plane offsets (their base pointer is moved back by the first
+// plane they hold). T = 1 is spatial blocking: one slab of all of x.
+//
+// The state is (p, r, w_p, w_r) for TTI (w = u^n - u^{n-1}) and (vx, vy, vz,
+// txx, tyy, tzz, txy, txz, tyz) for elastic; receiver rows are indexed by
+// level. field_prev (TTI: p^{nt-1}) is gathered from the owned planes of the
+// level before the last.
+tb_status plan_slab_passes(const tb_model *m, tb_sparse *s, const SchedChoice &sc, void *ws,
+                           float *rec_out, float *field_out, float *field_prev_out, Plan *plan,
+                           int nsteps)
 {
+    const bool tti = m->physics == TB_TTI;
+    const int NF = slab_fields(m);
     const size_t fb = field_bytes(m), fe = m->field_elems();
+    const long long plane = (long long)m->n[1] * m->nzp;
+    const int nx = m->n[0], ny = m->n[1], nz = m->n[2], nzp = m->nzp, r = m->r;
     char *base = (char *)ws;
-    float *F[8];
-    for (int k = 0; k < 8; k++) F[k] = (float *)(base + k * fb);
-    float *rec = (float *)(base + 8 * fb);
-    for (int k = 0; k < 8; k++) plan->push_back(fill_item(F[k], fe));
-    const int nrid = s->nrid, npts = s->npts, nt = m->nt;
-    if (nrid > 0) plan->push_back(fill_item(rec, (size_t)nrid));
-    TtiParams P = tti_params(m);
-    P.vp = F[4];
-    P.vr = F[5];
-    P.qp = F[6];
-    P.qr = F[7];
-    const int r = m->r;
+    auto field = [&](int k) { return (float *)(base + (size_t)k * fb); };
+    float *A[9], *B[9];
+    for (int f = 0; f < NF; f++) {
+        A[f] = field(f);
+        B[f] = field(NF + f);
+    }
+    float *qp = tti ? field(2 * NF) : nullptr, *qr = tti ? field(2 * NF + 1) : nullptr;
+    float *mid = tti ? field(2 * NF + 2) : nullptr;
+    const int nfull = 2 * NF + (tti ? 3 : 0);
+    const size_t ext = slab_ext(m, sc);
+    const size_t sbytes = align256((size_t)NF * ext * plane * sizeof(float));
+    float *scr[2] = {(float *)(base + nfull * fb), (float *)(base + nfull * fb + sbytes)};
+    float *rec = (float *)(base + nfull * fb + 2 * sbytes);
+    const int nrid = s->nrid, nrid2 = s->nrid2, npts = s->npts;
+    const int nt = nsteps >= 0 ? std::min(nsteps, m->nt) : m->nt;
+    const int stride = nrid + nrid2;  // elastic rows: P (nrid), then vz (nrid2)
+    for (int f = 0; f < NF; f++) plan->push_back(fill_item(A[f], fe));
+    if (tti) plan->push_back(fill_item(B[0], fe));  // p^{-1} when nt = 0
+    if (stride > 0) plan->push_back(fill_item(rec, (size_t)stride));
+    const TtiParams PT = tti ? tti_params(m) : TtiParams{};
+    float *F0[9] = {};
+    const ElParams PE = tti ? ElParams{} : el_params(m, F0);
     const float *dcmp = s->d_dcmp;
-    const long long *soff = s->d_src_off, *roff = s->d_rid_off;
-    int pc = 0, pp = 1;  // p^n in F[pc], p^{n-1} in F[pp]; r in F[pc + 2], F[pp + 2]
-    for (int n = 0; n < nt; n++) {
-        TtiParams Q = P;
-        Q.p = F[pc];
-        Q.pn = F[pp];
-        Q.r = F[pc + 2];
-        Q.rn = F[pp + 2];
+    const long long *soff = s->d_src_off, *roff = s->d_rid_off, *roff2 = s->d_rid2_off;
+    const int h = slab_skew(m), wm = slab_margin(m);
+    const int W = slab_width(m, sc);
+
+    // One step of one slab: level n from `in` to `out` over [lo, hi), owned
+    // planes [x0, x1).
+    auto step = [=](float *const *in, float *const *out, int n, int lo, int hi, int x0,
+                    int x1) -> Item {
         const float *inc = dcmp + (size_t)n * npts;
-        float *row = rec + (size_t)(n + 1) * nrid;
-        plan->push_back(act_item([=](hipStream_t st) {
-            return launch_tti_step(Q, r, inc, soff, npts, row, roff, nrid, st);
-        }));
-        std::swap(pc, pp);
+        float *row = rec + (size_t)(n + 1) * (tti ? nrid : stride);
+        if (tti) {
+            TtiParams Q = PT;
+            Q.p = in[0];
+            Q.r = in[1];
+            Q.vp = in[2];
+            Q.vr = in[3];
+            Q.pn = out[0];
+            Q.rn = out[1];
+            Q.vpo = out[2];
+            Q.vro = out[3];
+            Q.qp = qp;
+            Q.qr = qr;
+            Q.xlo = lo;
+            Q.xhi = hi;
+            return act_item([=](hipStream_t st) {
+                return launch_tti_step(Q, r, inc, soff, npts, row, roff, nrid, x0, x1, st);
+            });
+        }
+        ElParams E = PE;
+        for (int c = 0; c < 3; c++) {
+            E.v[c] = in[c];
+            E.vo[c] = out[c];
+        }
+        for (int c = 0; c < 6; c++) {
+            E.t[c] = in[3 + c];
+            E.to[c] = out[3 + c];
+        }
+        E.xlo = lo;
+        E.xhi = hi;
+        return act_item([=](hipStream_t st) {
+            return launch_elastic_step(E, r, inc, soff, npts, row, roff, nrid, row + nrid, roff2,
+                                       nrid2, x0, x1, st);
+        });
+    };
+
+    float **cur = A, **nxt = B;
+    int n0 = 0;
+    float *prev_level = A[0];  // p^{nt-1} when the last pass is one step
+    while (n0 < nt) {
+        const int Tp = std::min(sc.T, nt - n0);
+        const bool last = n0 + Tp == nt;
+        const int width = Tp == 1 ? nx : W;
+        for (int x0 = 0; x0 < nx; x0 += width) {
+            const int x1 = std::min(nx, x0 + width);
+            const int e_lo = std::max(0, x0 - (Tp - 1) * h - wm);
+            float *lv[2][9];
+            for (int k = 0; k < 2; k++)
+                for (int f = 0; f < NF; f++)
+                    lv[k][f] = scr[k] + (ptrdiff_t)f * (ptrdiff_t)ext * plane -
+                               (ptrdiff_t)e_lo * plane;
+            for (int st_ = 0; st_ < Tp; st_++) {
+                const int lo = std::max(0, x0 - (Tp - 1 - st_) * h);
+                const int hi = std::min(nx, x1 + (Tp - 1 - st_) * h);
+                // Host check before anything is launched: a scratch level
+                // must hold every plane the step writes into it ([lo, hi)
+                // widened by the margin) and every plane the next step reads
+                // from it (its range widened by the skew, which is this one).
+                if (st_ < Tp - 1 && (std::max(0, lo - wm) < e_lo ||
+                                     std::min(nx, hi + wm) > e_lo + (int)ext)) {
+                    set_error("internal: slab step [%d, %d) beyond its scratch [%d, %d)", lo, hi,
+                              e_lo, e_lo + (int)ext);
+                    return TB_EINVAL;
+                }
+                float *const *in = st_ == 0 ? cur : lv[(st_ - 1) & 1];
+                float *const *out = st_ == Tp - 1 ? nxt : lv[st_ & 1];
+                plan->push_back(step(in, out, n0 + st_, lo, hi, x0, x1));
+                if (tti && last && field_prev_out && Tp >= 2 && st_ == Tp - 2) {
+                    // p^{nt-1} of the owned planes.
+                    plan->push_back(copy_item(mid + (size_t)x0 * plane, out[0] + (size_t)x0 * plane,
+                                              (size_t)(x1 - x0) * plane * sizeof(float)));
+                }
+            }
+        }
+        if (last) prev_level = Tp >= 2 ? mid : cur[0];
+        std::swap(cur, nxt);
+        n0 += Tp;
     }
     if (rec_out && s->nrec > 0 && nt > 0) {
         const int nrec = s->nrec;
-        const int *ptr = s->d_rc_ptr, *id = s->d_rc_id;
-        const float *w = s->d_rc_w;
-        plan->push_back(act_item([=](hipStream_t st) {
-            return launch_trace_reduce(rec, nrid, nt, ptr, id, w, nrec, rec_out, 0, st);
-        }));
+        if (tti) {
+            const int *ptr = s->d_rc_ptr, *id = s->d_rc_id;
+            const float *w = s->d_rc_w;
+            plan->push_back(act_item([=](hipStream_t st) {
+                return launch_trace_reduce(rec, nrid, nt, ptr, id, w, nrec, rec_out, 0, st);
+            }));
+        } else {
+            // Rows are [P (nrid) | vz (nrid2)]: reduce each part with its mirror.
+            const int *p1 = s->d_rc_ptr, *i1 = s->d_rc_id, *p2 = s->d_rc2_ptr,
+                      *i2 = s->d_rc2_id;
+            const float *w1 = s->d_rc_w, *w2 = s->d_rc2_w;
+            plan->push_back(act_item([=](hipStream_t st) -> tb_status {
+                tb_status rc =
+                    launch_trace_reduce(rec + nrid, stride, nt, p2, i2, w2, nrec, rec_out, 0, st);
+                if (rc) return rc;
+                return launch_trace_reduce(rec, stride, nt, p1, i1, w1, nrec,
+                                           rec_out + (size_t)nt * nrec, 0, st);
+            }));
+        }
     }
-    const int nx = m->n[0], ny = m->n[1], nz = m->n[2], nzp = m->nzp;
-    float *fc = F[pc], *fp = F[pp];
+    // Field outputs. TTI: p^{nt}, p^{nt-1}; elastic: vz^{nt-1/2}, tzz^{nt}.
+    float *fc = tti ? cur[0] : cur[2];
+    float *fp = tti ? (nt == 0 ? B[0] : prev_level) : cur[5];
     if (field_out)
         plan->push_back(act_item([=](hipStream_t st) {
             return launch_unpad(fc, field_out, nx, ny, nz, nzp, st);
@@ -499,59 +668,6 @@ tb_status plan_forward_tti(const tb_model *m, tb_sparse *s, void *ws, float *rec
     if (field_prev_out)
         plan->push_back(act_item([=](hipStream_t st) {
             return launch_unpad(fp, field_prev_out, nx, ny, nz, nzp, st);
-        }));
-    return TB_OK;
-}
-
-// Elastic forward (SB): vx vy vz txx tyy tzz txy txz tyz, then rows of P and
-// vz samples; traces [2][nt][nrec] (vz, then P).
-tb_status plan_forward_elastic(const tb_model *m, tb_sparse *s, void *ws, float *rec_out,
-                               float *field_out, float *field_prev_out, Plan *plan)
-{
-    const size_t fb = field_bytes(m), fe = m->field_elems();
-    char *base = (char *)ws;
-    float *F[9];
-    for (int k = 0; k < 9; k++) F[k] = (float *)(base + k * fb);
-    const int nrid = s->nrid, nrid2 = s->nrid2, npts = s->npts, nt = m->nt;
-    const int stride = nrid + nrid2;
-    float *rec = (float *)(base + 9 * fb);  // row k: P at nrid points, vz at nrid2
-    for (int k = 0; k < 9; k++) plan->push_back(fill_item(F[k], fe));
-    if (stride > 0) plan->push_back(fill_item(rec, (size_t)stride));
-    const ElParams P = el_params(m, F);
-    const int r = m->r;
-    const float *dcmp = s->d_dcmp;
-    const long long *soff = s->d_src_off, *roff = s->d_rid_off, *roff2 = s->d_rid2_off;
-    for (int n = 0; n < nt; n++) {
-        const float *inc = dcmp + (size_t)n * npts;
-        float *row = rec + (size_t)(n + 1) * stride;
-        plan->push_back(act_item([=](hipStream_t st) {
-            return launch_elastic_step(P, r, inc, soff, npts, row, roff, nrid, row + nrid, roff2,
-                                       nrid2, st);
-        }));
-    }
-    if (rec_out && s->nrec > 0 && nt > 0) {
-        // Rows are [P (nrid) | vz (nrid2)]: reduce each part with its mirror.
-        const int nrec = s->nrec;
-        const int *p1 = s->d_rc_ptr, *i1 = s->d_rc_id, *p2 = s->d_rc2_ptr, *i2 = s->d_rc2_id;
-        const float *w1 = s->d_rc_w, *w2 = s->d_rc2_w;
-        plan->push_back(act_item([=](hipStream_t st) -> tb_status {
-            tb_status rc =
-                launch_trace_reduce(rec + nrid, stride, nt, p2, i2, w2, nrec, rec_out, 0, st);
-            if (rc) return rc;
-            return launch_trace_reduce(rec, stride, nt, p1, i1, w1, nrec,
-                                       rec_out + (size_t)nt * nrec, 0, st);
-        }));
-    }
-    // Field outputs: vz^{nt-1/2} (field_out) and tzz^{nt} (field_prev_out).
-    const int nx = m->n[0], ny = m->n[1], nz = m->n[2], nzp = m->nzp;
-    float *fv = F[2], *ft = F[5];
-    if (field_out)
-        plan->push_back(act_item([=](hipStream_t st) {
-            return launch_unpad(fv, field_out, nx, ny, nz, nzp, st);
-        }));
-    if (field_prev_out)
-        plan->push_back(act_item([=](hipStream_t st) {
-            return launch_unpad(ft, field_prev_out, nx, ny, nz, nzp, st);
         }));
     return TB_OK;
 }
@@ -643,13 +759,21 @@ size_t gradient_ws_bytes(const tb_model *m, const tb_sparse *s, const SchedChoic
     return grad_layout(m, s, sc, every).total;
 }
 
+tb_status plan_forward_steps(const tb_model *m, tb_sparse *s, const SchedChoice &sc, void *ws,
+                             int nsteps, Plan *plan)
+{
+    if (m->physics == TB_ACOUSTIC) {
+        set_error("plan_forward_steps covers the slab passes of TTI and elastic");
+        return TB_EUNSUPPORTED;
+    }
+    return plan_slab_passes(m, s, sc, ws, nullptr, nullptr, nullptr, plan, nsteps);
+}
+
 tb_status plan_forward(const tb_model *m, tb_sparse *s, const SchedChoice &sc, void *ws,
                        float *rec_out, float *field_out, float *field_prev_out, Plan *plan)
 {
-    if (m->physics == TB_TTI)
-        return plan_forward_tti(m, s, ws, rec_out, field_out, field_prev_out, plan);
-    if (m->physics == TB_ELASTIC)
-        return plan_forward_elastic(m, s, ws, rec_out, field_out, field_prev_out, plan);
+    if (m->physics != TB_ACOUSTIC)
+        return plan_slab_passes(m, s, sc, ws, rec_out, field_out, field_prev_out, plan, -1);
     const size_t fb = field_bytes(m), fe = m->field_elems();
     char *base = (char *)ws;
     float *U[2] = {(float *)base, (float *)(base + fb)};
@@ -956,7 +1080,7 @@ tb_status elastic_gradient(const tb_model *m, tb_sparse *s, int every, void *ws,
                                       hipMemcpyDeviceToDevice, strm));
         float *row = rec + (size_t)(t + 1) * stride;
         if ((st = launch_elastic_step(PF, m->r, s->d_dcmp + (size_t)t * npts, soff, npts, row, roff,
-                                      nrid, row + nrid, roff2, nrid2, strm)))
+                                      nrid, row + nrid, roff2, nrid2, 0, m->n[0], strm)))
             return st;
     }
     if (nt > 0 && nrec > 0) {
@@ -991,7 +1115,7 @@ tb_status elastic_gradient(const tb_model *m, tb_sparse *s, int every, void *ws,
                 TB_HIP(hipMemcpyAsync(sl + (3 + f) * (fb / sizeof(float)), Ff[3 + f], fb,
                                       hipMemcpyDeviceToDevice, strm));
             if ((st = launch_elastic_step(PF, m->r, s->d_dcmp + (size_t)t * npts, soff, npts,
-                                          nullptr, roff, 0, nullptr, roff2, 0, strm)))
+                                          nullptr, roff, 0, nullptr, roff2, 0, 0, 0, strm)))
                 return st;
             for (int f = 0; f < 3; f++)
                 TB_HIP(hipMemcpyAsync(sl + f * (fb / sizeof(float)), Ff[f], fb,
@@ -1110,7 +1234,7 @@ tb_status tti_gradient(const tb_model *m, tb_sparse *s, int every, void *ws, con
         Q.r = fld(L.F, pc + 2);
         Q.rn = fld(L.F, pp + 2);
         if ((st = launch_tti_step(Q, m->r, s->d_dcmp + (size_t)n * npts, soff, npts,
-                                  rec + (size_t)(n + 1) * nrid, roff, nrid, strm)))
+                                  rec + (size_t)(n + 1) * nrid, roff, nrid, 0, m->n[0], strm)))
             return st;
         std::swap(pc, pp);
     }
@@ -1155,7 +1279,7 @@ tb_status tti_gradient(const tb_model *m, tb_sparse *s, int every, void *ws, con
             Q.pn = fld(L.slots, 2 * i + 2);
             Q.rn = fld(L.slots, 2 * i + 3);
             if ((st = launch_tti_step(Q, m->r, s->d_dcmp + (size_t)k * npts, soff, npts, nullptr,
-                                      roff, 0, strm)))
+                                      roff, 0, 0, 0, strm)))
                 return st;
         }
         for (int k = k1 - 1; k >= k0; k--) {
@@ -1262,9 +1386,17 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
             return TB_EINVAL;
         }
     }
-    if (!(d->dt > 0.0) || d->nt < 0 || d->nbl < 0 || !d->vp) {
-        set_error("dt, nt, nbl or vp invalid");
+    if (!(d->dt > 0.0) || d->nt < 0 || d->nbl < 0) {
+        set_error("dt, nt or nbl invalid");
         return TB_EINVAL;
+    }
+    if ((d->vp == nullptr) == (d->slowness2 == nullptr)) {
+        set_error("give exactly one of vp and slowness2");
+        return TB_EINVAL;
+    }
+    if (d->slowness2 && d->physics != TB_ACOUSTIC) {
+        set_error("slowness2 is accepted for the acoustic physics only");
+        return TB_EUNSUPPORTED;
     }
     const int nx = d->shape[0], ny = d->shape[1], nz = d->shape[2];
     if ((long long)ny * nz > (1LL << 30) || (long long)nx * ny * nz > (1LL << 36)) {
@@ -1273,6 +1405,11 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
     }
     if (nx > 65535) {
         set_error("nx %d above 65535 (the sparse-list keys hold x in 16 bits)", nx);
+        return TB_EUNSUPPORTED;
+    }
+    if ((long long)ny * ((nz + 3) & ~3) * 4 >= (1LL << 31)) {
+        set_error("a padded y-z plane of %lld bytes reaches 2 GiB (planes are addressed with "
+                  "32-bit offsets)", (long long)ny * ((nz + 3) & ~3) * 4);
         return TB_EUNSUPPORTED;
     }
     auto m = std::make_unique<tb_model>();
@@ -1291,15 +1428,19 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
     if (m->ncu < 1) m->ncu = 1;
 
     const size_t N = (size_t)nx * ny * nz;
+    // The host copy holds vp, or m = 1/vp^2 when the caller gave slowness2.
+    const bool by_m = d->slowness2 != nullptr;
     std::vector<float> vp(N);
-    TB_HIP(hipMemcpy(vp.data(), d->vp, N * sizeof(float), hipMemcpyDeviceToHost));
+    TB_HIP(hipMemcpy(vp.data(), by_m ? d->slowness2 : d->vp, N * sizeof(float),
+                     hipMemcpyDeviceToHost));
     double vpmax = 0.0;
     for (size_t i = 0; i < N; i++) {
         if (!(vp[i] > 0.0f) || !std::isfinite(vp[i])) {
-            set_error("vp[%zu] = %g is not a positive finite velocity", i, (double)vp[i]);
+            set_error("%s[%zu] = %g is not positive and finite", by_m ? "slowness2" : "vp", i,
+                      (double)vp[i]);
             return TB_EINVAL;
         }
-        vpmax = std::max(vpmax, (double)vp[i]);
+        vpmax = std::max(vpmax, by_m ? 1.0 / std::sqrt((double)vp[i]) : (double)vp[i]);
     }
     m->vmax = d->damp_vmax > 0.0 ? d->damp_vmax : vpmax;
     // TTI parameters: the fastest phase velocity is vp sqrt(1 + 2 eps).
@@ -1406,15 +1547,18 @@ tb_status tb_create_model(const tb_model_desc *d, tb_model **out)
     damping_axis(nx, m->nbl, m->h[0], m->vmax, m->damp.data());
     damping_axis(ny, m->nbl, m->h[1], m->vmax, m->damp.data() + nx);
     damping_axis(nz, m->nbl, m->h[2], m->vmax, m->damp.data() + nx + ny);
-    // c = dt^2 vp^2 on the device from the caller's vp (the same FP64
-    // expression the inspector evaluates at its points from the host copy).
+    // c = dt^2 vp^2 (or dt^2/m) on the device from the caller's array (the
+    // same FP64 expression the inspector evaluates at its points from the
+    // host copy).
     TB_HIP(hipMalloc(&m->d_c, m->field_elems() * sizeof(float)));
     {
-        tb_status rc = launch_c_from_vp(d->vp, m->d_c, nx, ny, nz, m->nzp, m->dt, nullptr);
+        tb_status rc = launch_c_from_vp(by_m ? d->slowness2 : d->vp, m->d_c, nx, ny, nz, m->nzp,
+                                        m->dt, by_m, nullptr);
         if (rc) return rc;
         TB_HIP(hipDeviceSynchronize());
     }
     m->vp_host = std::move(vp);
+    m->host_is_m = by_m;
     TB_HIP(hipMalloc(&m->d_zero, 256));
     TB_HIP(hipMemset(m->d_zero, 0, 256));
     if (!el_host.empty()) {
@@ -1568,7 +1712,7 @@ tb_status tb_workspace_size(const tb_model *m, const tb_sparse *s, const tb_sche
     const size_t nt1 = (size_t)m->nt + 1;
     switch (op) {
     case TB_OP_FORWARD:
-        *bytes = forward_ws_bytes(m, s);
+        *bytes = forward_ws_bytes(m, s, sc);
         return TB_OK;
     case TB_OP_ADJOINT:
         // Acoustic: u, v (two levels each); TTI: lambda_p, lambda_r (two

@@ -9,6 +9,8 @@
 //   el_src   t_ii^{n+1} += dt W q(t_n) at the inspector's points
 //   el_rec   gather of P = (txx + tyy + tzz) / 3 (nodes) and of vz (vz grid)
 // Both updates are in place (each element reads its own old value only).
+#include <algorithm>
+
 #include "elastic_params.h"
 
 namespace tbw {
@@ -28,15 +30,16 @@ struct Site {
 __device__ __forceinline__ bool locate4(const ElParams &P, Site &q)
 {
     const int nz4 = P.nzp / 4;
+    const int xe = P.xhi > 0 ? P.xhi : P.nx;
     const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (gid >= (long long)P.nx * P.ny * nz4) return false;
+    if (gid >= (long long)(xe - P.xlo) * P.ny * nz4) return false;
     q.z4 = (int)(gid % nz4) * 4;
     const long long xy = gid / nz4;
     q.y = (int)(xy % P.ny);
-    q.x = (int)(xy / P.ny);
+    q.x = P.xlo + (int)(xy / P.ny);
     q.sx = (long long)P.ny * P.nzp;
     q.sy = P.nzp;
-    q.off = xy * P.nzp + q.z4;
+    q.off = ((long long)q.x * P.ny + q.y) * P.nzp + q.z4;
     return true;
 }
 
@@ -115,7 +118,7 @@ __global__ void __launch_bounds__(256) el_vel(const ElParams P)
             if (d != 0.0f) r /= 1.0f + dd;
             v[k] = r;
         }
-        *(f4 *)(P.v[c] + q.off) = v;
+        *(f4 *)((P.vo[c] ? P.vo[c] : P.v[c]) + q.off) = v;
     }
 }
 
@@ -160,15 +163,18 @@ __global__ void __launch_bounds__(256) el_str(const ElParams P)
         for (int c = 0; c < 6; c++) t[c][k] = n[c];
     }
 #pragma unroll
-    for (int c = 0; c < 6; c++) *(f4 *)(P.t[c] + q.off) = t[c];
+    for (int c = 0; c < 6; c++) *(f4 *)((P.to[c] ? P.to[c] : P.t[c]) + q.off) = t[c];
 }
 
+// Points of planes [xlo, xhi) only (plane = ny * nzp elements).
 __global__ void el_src(float *__restrict__ txx, float *__restrict__ tyy, float *__restrict__ tzz,
-                       const float *__restrict__ inc, const long long *__restrict__ soff, int npts)
+                       const float *__restrict__ inc, const long long *__restrict__ soff, int npts,
+                       long long plane, int xlo, int xhi)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npts) return;
-    const long long o = soff[i];
+    const long long o = soff[i], x = o / plane;
+    if (x < xlo || x >= xhi) return;
     txx[o] += inc[i];
     tyy[o] += inc[i];
     tzz[o] += inc[i];
@@ -177,15 +183,17 @@ __global__ void el_src(float *__restrict__ txx, float *__restrict__ tyy, float *
 __global__ void el_rec(const float *__restrict__ txx, const float *__restrict__ tyy,
                        const float *__restrict__ tzz, const float *__restrict__ vz,
                        float *__restrict__ row_p, const long long *__restrict__ roff, int nrid,
-                       float *__restrict__ row_v, const long long *__restrict__ roff2, int nrid2)
+                       float *__restrict__ row_v, const long long *__restrict__ roff2, int nrid2,
+                       long long plane, int xlo, int xhi)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nrid) {
-        const long long o = roff[i];
-        row_p[i] = (txx[o] + tyy[o] + tzz[o]) / 3.0f;
+        const long long o = roff[i], x = o / plane;
+        if (x >= xlo && x < xhi) row_p[i] = (txx[o] + tyy[o] + tzz[o]) / 3.0f;
     } else if (i < nrid + nrid2) {
         const int j = i - nrid;
-        row_v[j] = vz[roff2[j]];
+        const long long o = roff2[j], x = o / plane;
+        if (x >= xlo && x < xhi) row_v[j] = vz[o];
     }
 }
 
@@ -268,7 +276,7 @@ __global__ void __launch_bounds__(256) el_adj_pre_vel(const ElParams P, ElScratc
             v[k] *= (1.0f - dd) * ia;
         }
         *(f4 *)(S.f[c] + q.off) = u;
-        *(f4 *)(P.v[c] + q.off) = v;
+        *(f4 *)((P.vo[c] ? P.vo[c] : P.v[c]) + q.off) = v;
     }
 }
 
@@ -447,32 +455,46 @@ unsigned nblocks(long long n) { return (unsigned)((n + 255) / 256); }
 
 tb_status launch_elastic_step(const ElParams &P, int r, const float *inc, const long long *soff,
                               int npts, float *row_p, const long long *roff, int nrid,
-                              float *row_v, const long long *roff2, int nrid2, hipStream_t st)
+                              float *row_v, const long long *roff2, int nrid2, int rlo, int rhi,
+                              hipStream_t st)
 {
-    const long long total = (long long)P.nx * P.ny * (P.nzp / 4);
-    if (total == 0) return TB_OK;
+    const int xlo = P.xlo, xhi = P.xhi > 0 ? P.xhi : P.nx;
+    const long long row = (long long)P.ny * (P.nzp / 4);
+    const long long total = (long long)(xhi - xlo) * row;
+    if (total <= 0) return TB_OK;
+    // The velocity pass feeds the stress pass's x derivatives: r planes more
+    // on each side. The stress pass reads the new velocities.
+    ElParams V = P;
+    V.xlo = std::max(0, xlo - r);
+    V.xhi = std::min(P.nx, xhi + r);
+    const long long vtotal = (long long)(V.xhi - V.xlo) * row;
+    ElParams S = P;
+    for (int c = 0; c < 3; c++) S.v[c] = P.vo[c] ? P.vo[c] : P.v[c];
     if (r == 2) {
-        hipLaunchKernelGGL(el_vel<2>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL(el_str<2>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL(el_vel<2>, dim3(nblocks(vtotal)), dim3(256), 0, st, V);
+        hipLaunchKernelGGL(el_str<2>, dim3(nblocks(total)), dim3(256), 0, st, S);
     } else if (r == 4) {
-        hipLaunchKernelGGL(el_vel<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL(el_str<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL(el_vel<4>, dim3(nblocks(vtotal)), dim3(256), 0, st, V);
+        hipLaunchKernelGGL(el_str<4>, dim3(nblocks(total)), dim3(256), 0, st, S);
     } else if (r == 6) {
-        hipLaunchKernelGGL(el_vel<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL(el_str<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL(el_vel<6>, dim3(nblocks(vtotal)), dim3(256), 0, st, V);
+        hipLaunchKernelGGL(el_str<6>, dim3(nblocks(total)), dim3(256), 0, st, S);
     } else {
         set_error("elastic radius %d not built", r);
         return TB_EUNSUPPORTED;
     }
     TB_HIP(hipGetLastError());
+    float *const *tout = P.to[0] ? P.to : P.t;
+    const long long plane = (long long)P.ny * P.nzp;
     if (npts > 0) {
-        hipLaunchKernelGGL(el_src, dim3(nblocks(npts)), dim3(256), 0, st, P.t[0], P.t[1], P.t[2],
-                           inc, soff, npts);
+        hipLaunchKernelGGL(el_src, dim3(nblocks(npts)), dim3(256), 0, st, tout[0], tout[1],
+                           tout[2], inc, soff, npts, plane, xlo, xhi);
         TB_HIP(hipGetLastError());
     }
-    if (nrid + nrid2 > 0) {
-        hipLaunchKernelGGL(el_rec, dim3(nblocks(nrid + nrid2)), dim3(256), 0, st, P.t[0], P.t[1],
-                           P.t[2], P.v[2], row_p, roff, nrid, row_v, roff2, nrid2);
+    if (nrid + nrid2 > 0 && rhi > rlo) {
+        hipLaunchKernelGGL(el_rec, dim3(nblocks(nrid + nrid2)), dim3(256), 0, st, tout[0], tout[1],
+                           tout[2], S.v[2], row_p, roff, nrid, row_v, roff2, nrid2, plane, rlo,
+                           rhi);
         TB_HIP(hipGetLastError());
     }
     return TB_OK;

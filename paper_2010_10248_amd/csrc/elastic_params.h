@@ -16,6 +16,13 @@ struct ElParams {
     float w[6];               // staggered first derivative, unit spacing
     float ih[3];              // 1/h per axis
     int nx, ny, nz, nzp;
+    // Planes [xlo, xhi) a launch computes (xhi = 0: all of x), and where the
+    // forward passes write (NULL: in place over v, t). Temporally blocked
+    // passes compute shrinking x ranges into separate buffers; every buffer
+    // is addressed with the global (x, y, z) offsets.
+    int xlo, xhi;
+    float *vo[3];
+    float *to[6];
 };
 
 // Six scratch fields of the adjoint step (also used to pass a forward
@@ -61,11 +68,15 @@ tb_status launch_elastic_adjoint_step(const ElParams &P, const ElScratch &S, int
                                       const double *src_alpha, double dt, int npts,
                                       hipStream_t st);
 
-// One step: velocity and stress passes (in place), injection of inc[npts] at
-// soff into the three normal stresses, gather of P into row_p[nrid] at roff
-// and of vz into row_v[nrid2] at roff2.
+// One step: velocity and stress passes (in place, or into P.vo / P.to),
+// injection of inc[npts] at soff into the three normal stresses, gather of P
+// into row_p[nrid] at roff and of vz into row_v[nrid2] at roff2. The stress
+// pass and the injection cover planes [P.xlo, P.xhi), the velocity pass that
+// range widened by the radius; receivers are gathered at the points of
+// planes [rlo, rhi) only.
 tb_status launch_elastic_step(const ElParams &P, int r, const float *inc, const long long *soff,
                               int npts, float *row_p, const long long *roff, int nrid,
-                              float *row_v, const long long *roff2, int nrid2, hipStream_t st);
+                              float *row_v, const long long *roff2, int nrid2, int rlo, int rhi,
+                              hipStream_t st);
 
 }  // namespace tbw

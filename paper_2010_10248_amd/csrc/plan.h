@@ -54,11 +54,15 @@ using Plan = std::vector<Item>;
 tb_status pass_params(const tb_model *m, tb_sparse *s, const SchedChoice &sc, const Pass &p,
                       AcParams *out, const TileGeom **geom, bool *gl);
 
-size_t forward_ws_bytes(const tb_model *m, const tb_sparse *s);
+size_t forward_ws_bytes(const tb_model *m, const tb_sparse *s, const SchedChoice &sc);
 size_t gradient_ws_bytes(const tb_model *m, const tb_sparse *s, const SchedChoice &sc, int every);
 
 tb_status plan_forward(const tb_model *m, tb_sparse *s, const SchedChoice &sc, void *ws,
                        float *rec_out, float *field_out, float *field_prev_out, Plan *plan);
+// The first nsteps updates of a TTI or elastic forward (no outputs), for
+// timing schedules.
+tb_status plan_forward_steps(const tb_model *m, tb_sparse *s, const SchedChoice &sc, void *ws,
+                             int nsteps, Plan *plan);
 // loss_dst: host memory that receives J by an asynchronous copy (NULL: none).
 tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, int every,
                         void *ws, const float *d_obs, float *grad_m, double *loss_dst,

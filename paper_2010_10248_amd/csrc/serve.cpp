@@ -416,7 +416,7 @@ tb_status tb_server_submit(tb_server *sv, const tb_request *rq, int64_t *id)
     if (rc) return rc;
     tb_sparse *s = const_cast<tb_sparse *>(rq->sparse);
     j->ws_bytes = rq->op == TB_OP_FORWARD
-                      ? forward_ws_bytes(rq->model, s)
+                      ? forward_ws_bytes(rq->model, s, j->sc)
                       : gradient_ws_bytes(rq->model, s, j->sc, rq->checkpoint_every);
     if (j->ws_bytes > sv->arena.bytes) {
         set_error("request needs %zu bytes of workspace; the arena holds %zu", j->ws_bytes,

@@ -120,16 +120,18 @@ struct tb_model {
     // Elastic: eight padded fields, each multiplied by dt: b at the vx, vy,
     // vz points, lambda and mu at the nodes, mu at the txy, txz, tyz points.
     float *d_el = nullptr;
-    std::vector<float> vp_host;  // host copy of vp [nx][ny][nz]
+    std::vector<float> vp_host;  // host copy of vp [nx][ny][nz] (of m = 1/vp^2 if host_is_m)
+    bool host_is_m = false;
     std::vector<float> damp;     // host copy of the three tables
     // The inspector's scale of injected values at raster point i: dt^2 vp^2
-    // (FP64 from the FP32 vp; the value the device field c rounds) for the
-    // second-order systems, dt for the stress injection of the elastic one.
+    // or dt^2/m (FP64 from the FP32 input; the value the device field c
+    // rounds) for the second-order systems, dt for the stress injection of
+    // the elastic one.
     double inj_coef(int64_t i) const
     {
         if (physics == TB_ELASTIC) return dt;
         const double v = (double)vp_host[i];
-        return dt * dt * v * v;
+        return host_is_m ? dt * dt / v : dt * dt * v * v;
     }
     size_t field_elems() const { return (size_t)n[0] * n[1] * nzp; }
     ~tb_model();
@@ -216,7 +218,7 @@ tb_status launch_fill(float *p, size_t n, float v, hipStream_t st);
 // c[x][y][z] = dt^2 vp^2 (FP64, rounded once) over the padded layout [nx][ny][nzp]
 // (0 in the padding), from vp [nx][ny][nz].
 tb_status launch_c_from_vp(const float *vp, float *c, int nx, int ny, int nz, int nzp, double dt,
-                           hipStream_t st);
+                           bool is_m, hipStream_t st);
 tb_status kernel_timing(int enable);
 tb_status kernel_timing_read(int *n, double *ms);
 tb_status launch_trace_reduce(const float *rec_dcmp, int nrid, int nt, const int *ptr,

@@ -15,6 +15,8 @@
 //                and r', and the receiver gather of p'.
 // Every field is zero outside the grid (bounds-checked neighbour reads), so
 // Hz = -D^T D exactly, as in the definition of the operator.
+#include <algorithm>
+
 #include "tti_params.h"
 
 namespace tbw {
@@ -37,18 +39,20 @@ struct Site {
     long long off, sx, sy;
 };
 
+__device__ __forceinline__ int xend(const TtiParams &P) { return P.xhi > 0 ? P.xhi : P.nx; }
+
 __device__ __forceinline__ bool locate4(const TtiParams &P, Site &q)
 {
     const int nz4 = P.nzp / 4;
     const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (gid >= (long long)P.nx * P.ny * nz4) return false;
+    if (gid >= (long long)(xend(P) - P.xlo) * P.ny * nz4) return false;
     q.z4 = (int)(gid % nz4) * 4;
     const long long xy = gid / nz4;
     q.y = (int)(xy % P.ny);
-    q.x = (int)(xy / P.ny);
+    q.x = P.xlo + (int)(xy / P.ny);
     q.sx = (long long)P.ny * P.nzp;
     q.sy = P.nzp;
-    q.off = xy * P.nzp + q.z4;
+    q.off = ((long long)q.x * P.ny + q.y) * P.nzp + q.z4;
     return true;
 }
 
@@ -219,20 +223,24 @@ __global__ void __launch_bounds__(256) tti_update(const TtiParams P, double *__r
         rn[k] = rc[k] + wr;
     }
     if constexpr (MODE != kImage) {
-        *(f4 *)(P.vp + q.off) = vp;
-        *(f4 *)(P.vr + q.off) = vr;
+        *(f4 *)((P.vpo ? P.vpo : P.vp) + q.off) = vp;
+        *(f4 *)((P.vro ? P.vro : P.vr) + q.off) = vr;
         *(f4 *)(P.pn + q.off) = pn;
         *(f4 *)(P.rn + q.off) = rn;
     }
 }
 
+// Points of planes [xlo, xhi) only (plane = ny * nzp elements).
 __global__ void tti_sparse(float *__restrict__ p, float *__restrict__ r, float *__restrict__ vp,
                            float *__restrict__ vr, const float *__restrict__ inc,
-                           const long long *__restrict__ soff, int npts)
+                           const long long *__restrict__ soff, int npts, long long plane, int xlo,
+                           int xhi)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < npts) {
         const long long o = soff[i];
+        const long long x = o / plane;
+        if (x < xlo || x >= xhi) return;
         p[o] += inc[i];
         r[o] += inc[i];
         vp[o] += inc[i];
@@ -241,10 +249,14 @@ __global__ void tti_sparse(float *__restrict__ p, float *__restrict__ r, float *
 }
 
 __global__ void tti_record(const float *__restrict__ p, float *__restrict__ rec_row,
-                           const long long *__restrict__ roff, int nrid)
+                           const long long *__restrict__ roff, int nrid, long long plane, int xlo,
+                           int xhi)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nrid) rec_row[i] = p[roff[i]];
+    if (i < nrid) {
+        const long long o = roff[i], x = o / plane;
+        if (x >= xlo && x < xhi) rec_row[i] = p[o];
+    }
 }
 
 // z = (c/alpha) D lambda with D = [[1+2 eps, s], [s, 1]] per node.
@@ -308,21 +320,29 @@ unsigned nblocks(long long n) { return (unsigned)((n + 255) / 256); }
 }  // namespace
 
 tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const long long *soff,
-                          int npts, float *rec_row, const long long *roff, int nrid,
-                          hipStream_t st)
+                          int npts, float *rec_row, const long long *roff, int nrid, int rlo,
+                          int rhi, hipStream_t st)
 {
-    const long long total = (long long)P.nx * P.ny * (P.nzp / 4);
-    if (total == 0) return TB_OK;
+    const int xlo = P.xlo, xhi = P.xhi > 0 ? P.xhi : P.nx;
+    const long long row = (long long)P.ny * (P.nzp / 4);
+    const long long total = (long long)(xhi - xlo) * row;
+    if (total <= 0) return TB_OK;
+    // The rotated gradients feed the update's x derivatives: r planes more
+    // on each side.
+    TtiParams G = P;
+    G.xlo = std::max(0, xlo - r);
+    G.xhi = std::min(P.nx, xhi + r);
+    const long long gtotal = (long long)(G.xhi - G.xlo) * row;
     if (r == 2) {
-        hipLaunchKernelGGL(tti_rot<2>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL(tti_rot<2>, dim3(nblocks(gtotal)), dim3(256), 0, st, G);
         hipLaunchKernelGGL((tti_update<2, kForward>), dim3(nblocks(total)), dim3(256), 0, st, P,
                            nullptr);
     } else if (r == 4) {
-        hipLaunchKernelGGL(tti_rot<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL(tti_rot<4>, dim3(nblocks(gtotal)), dim3(256), 0, st, G);
         hipLaunchKernelGGL((tti_update<4, kForward>), dim3(nblocks(total)), dim3(256), 0, st, P,
                            nullptr);
     } else if (r == 6) {
-        hipLaunchKernelGGL(tti_rot<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
+        hipLaunchKernelGGL(tti_rot<6>, dim3(nblocks(gtotal)), dim3(256), 0, st, G);
         hipLaunchKernelGGL((tti_update<6, kForward>), dim3(nblocks(total)), dim3(256), 0, st, P,
                            nullptr);
     } else {
@@ -330,14 +350,16 @@ tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const lon
         return TB_EUNSUPPORTED;
     }
     TB_HIP(hipGetLastError());
+    const long long plane = (long long)P.ny * P.nzp;
     if (npts > 0) {
-        hipLaunchKernelGGL(tti_sparse, dim3(nblocks(npts)), dim3(256), 0, st, P.pn, P.rn, P.vp,
-                           P.vr, inc, soff, npts);
+        hipLaunchKernelGGL(tti_sparse, dim3(nblocks(npts)), dim3(256), 0, st, P.pn, P.rn,
+                           P.vpo ? P.vpo : P.vp, P.vro ? P.vro : P.vr, inc, soff, npts, plane,
+                           xlo, xhi);
         TB_HIP(hipGetLastError());
     }
-    if (nrid > 0) {
+    if (nrid > 0 && rhi > rlo) {
         hipLaunchKernelGGL(tti_record, dim3(nblocks(nrid)), dim3(256), 0, st, P.pn, rec_row, roff,
-                           nrid);
+                           nrid, plane, rlo, rhi);
         TB_HIP(hipGetLastError());
     }
     return TB_OK;

@@ -23,14 +23,22 @@ struct TtiParams {
     // z = (c/alpha) D lambda^{k+1} (zp, zr), which p and r then point to.
     const float *lp, *lr;
     float *zp, *zr;
+    // Planes [xlo, xhi) a launch computes (xhi = 0: all of x), and where the
+    // forward update writes the new velocities (NULL: in place over vp, vr).
+    // Temporally blocked passes compute shrinking x ranges into separate
+    // buffers; every buffer is addressed with the global (x, y, z) offsets.
+    int xlo, xhi;
+    float *vpo, *vro;
 };
 
 // One step: rotated gradients, coupled update (velocity form), injection of
 // inc[npts] at soff into both fields, gather of p^{n+1} into rec_row[nrid] at
-// roff.
+// roff. The update covers planes [P.xlo, P.xhi), the rotated gradients that
+// range widened by the radius, and injection every point of the update's
+// range; receivers are gathered at the points of planes [rlo, rhi) only.
 tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const long long *soff,
-                          int npts, float *rec_row, const long long *roff, int nrid,
-                          hipStream_t st);
+                          int npts, float *rec_row, const long long *roff, int nrid, int rlo,
+                          int rhi, hipStream_t st);
 
 // One step of the adjoint of q -> d, backwards: lambda^{k+1} in (P.lp, P.lr),
 // psi^{k+1} = lambda^{k+1} - lambda^{k+2} in (P.vp, P.vr) (updated in place

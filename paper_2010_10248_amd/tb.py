@@ -41,7 +41,7 @@ class ModelDesc(ctypes.Structure):
                 ("dt", ctypes.c_double), ("nt", ctypes.c_int32), ("damp_vmax", ctypes.c_double),
                 ("vp", ctypes.c_void_p), ("epsilon", ctypes.c_void_p), ("delta", ctypes.c_void_p),
                 ("theta", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("vs", ctypes.c_void_p),
-                ("rho", ctypes.c_void_p)]
+                ("rho", ctypes.c_void_p), ("slowness2", ctypes.c_void_p)]
 
 
 class Schedule(ctypes.Structure):
@@ -175,9 +175,10 @@ def _stream(stream) -> Optional[int]:
 
 def create_model(shape, spacing, origin, space_order, nbl, dt, nt, vp, damp_vmax=0.0,
                  physics=ACOUSTIC, epsilon=None, delta=None, theta=None, phi=None, vs=None,
-                 rho=None):
+                 rho=None, slowness2=None):
     """vp (and the physics' other parameters): float32 CUDA tensors
-    [nx][ny][nz]. Returns an opaque handle."""
+    [nx][ny][nz]; acoustic models may give the squared slowness ``slowness2``
+    instead of vp (vp None). Returns an opaque handle."""
     d = ModelDesc()
     d.physics = physics
     d.shape[:] = [int(v) for v in shape]
@@ -190,7 +191,7 @@ def create_model(shape, spacing, origin, space_order, nbl, dt, nt, vp, damp_vmax
     d.damp_vmax = float(damp_vmax)
     d.vp = None if vp is None else vp.data_ptr()
     for name, t in (("epsilon", epsilon), ("delta", delta), ("theta", theta), ("phi", phi),
-                    ("vs", vs), ("rho", rho)):
+                    ("vs", vs), ("rho", rho), ("slowness2", slowness2)):
         setattr(d, name, None if t is None else t.data_ptr())
     h = _vp()
     _check(lib().tb_create_model(ctypes.byref(d), ctypes.byref(h)), "tb_create_model")
@@ -389,17 +390,21 @@ class Propagator:
     """A model (acoustic or TTI, from the shot's physics) plus its sparse
     operators on the current CUDA device."""
 
-    def __init__(self, shot, vp=None, src_wav=None, device="cuda", damp_vmax: float = 0.0):
+    def __init__(self, shot, vp=None, src_wav=None, device="cuda", damp_vmax: float = 0.0,
+                 slowness2=None):
         import torch
 
         self.shot = shot
         self.device = torch.device(device)
-        vp = shot.vp if vp is None else vp
-        if isinstance(vp, torch.Tensor):
-            self.vp = vp.to(device=self.device, dtype=torch.float32).contiguous()
-        else:
-            self.vp = torch.as_tensor(np.ascontiguousarray(vp, dtype=np.float32),
-                                      device=self.device)
+
+        def dev(a):
+            if isinstance(a, torch.Tensor):
+                return a.to(device=self.device, dtype=torch.float32).contiguous()
+            return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=self.device)
+
+        # An acoustic model may be given by its squared slowness instead of vp.
+        self.slowness2 = None if slowness2 is None else dev(slowness2)
+        self.vp = None if slowness2 is not None else dev(shot.vp if vp is None else vp)
         physics = getattr(shot, "physics", ACOUSTIC)
         self.physics = physics
         extra = {}
@@ -412,7 +417,7 @@ class Propagator:
         self._params = extra
         self.model = create_model(shot.shape, shot.spacing, shot.origin, shot.space_order,
                                   shot.nbl, shot.dt, shot.nt, self.vp, damp_vmax=damp_vmax,
-                                  physics=physics, **extra)
+                                  physics=physics, slowness2=self.slowness2, **extra)
         wav = shot.src_wav if src_wav is None else src_wav
         self.sparse = inspect_sparse(self.model, shot.src_xyz, wav, shot.rec_xyz)
         self.nsrc = shot.src_xyz.shape[0]

@@ -288,9 +288,6 @@ def test_dense_x_plane_runs_the_global_list_kernel(torch_cuda, orc):
                                             ("tb", 2, 32, 64), ("sb", 1, 16, 2048)])
 
 
-@pytest.mark.skipif(not __import__("os").environ.get("TB_FULL_PARITY"),
-                    reason="full-length 512^3 oracle run (about 2 minutes of FP64 on 16 threads); "
-                           "set TB_FULL_PARITY=1")
 def test_full_size_c2_all_steps(torch_cuda, orc):
     """The 512^3 SO8 two-layer workload over all 1000 steps in the launch
     configurations the benchmark times: TB (whole x) bitwise equal to SB, and

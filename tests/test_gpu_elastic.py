@@ -58,8 +58,11 @@ def test_elastic_zero_source_and_unsupported_paths(torch_cuda):
     out = prop.forward(None)
     for k in ("traces", "u_last", "u_prev"):
         assert torch.count_nonzero(out[k]) == 0, k
+    out = prop.forward(tb.schedule("tb", 2, 0, 8))
+    for k in ("traces", "u_last", "u_prev"):
+        assert torch.count_nonzero(out[k]) == 0, k
     with pytest.raises(tb.TbError) as e:
-        prop.forward(tb.schedule("tb", 2, 32))
+        prop.forward(tb.schedule("tb", 5, 0, 8))
     assert e.value.status == tb.EUNSUPPORTED
     qh = prop.adjoint(torch.zeros((2, s.nt, s.rec_xyz.shape[0]), device="cuda"))
     assert torch.count_nonzero(qh) == 0
@@ -95,41 +98,65 @@ def test_elastic_adjoint_dot_product_and_oracle(torch_cuda, orc, so, n):
     prop.close()
 
 
-def test_elastic_full_size_first_steps(torch_cuda, orc):
-    """The 256^3 SO8 elastic workload: the first 4 steps against the oracle
-    on the full grid (vz and tzz fields)."""
+def test_elastic_full_size_100_steps(torch_cuda, orc):
+    """The 256^3 SO8 elastic workload on the full grid for 100 steps against
+    the oracle: vz and P traces and the final vz and tzz fields. The
+    recipe's receiver line is 650 m from the source, so a second line of 24
+    receivers through the source (the recipe unchanged otherwise) gives
+    traces that carry the wavelet."""
     from paper_2010_10248_amd import tb
 
-    s = W.elastic_smooth(nt=4)
+    s = W.elastic_smooth(nt=100)
+    h = np.array(s.spacing)
+    x0 = s.src_xyz[0]
+    near = x0 + np.outer(np.linspace(-12.3, 12.7, 24), [1.0, 0.0, 0.0]) * h
+    s.rec_xyz = np.concatenate([s.rec_xyz, near + np.array([0.0, 0.37, -0.41]) * h])
+    print("elastic 256^3 100 steps: running the oracle", flush=True)
     ref = orc.elastic_forward(s)
     out = tb.Propagator(s).forward(None)
-    e = (_rel(out["u_last"].cpu().numpy(), ref["vz_field"]),
-         _rel(out["u_prev"].cpu().numpy(), ref["tzz"]))
-    print(f"elastic 256^3 first 4 steps: {e}", flush=True)
-    assert max(e) <= TOL
+    tr = out["traces"].cpu().numpy()
+    assert np.abs(ref["p"][:, 256:]).max() > 1e-3 * np.abs(ref["tzz"]).max()
+    e = dict(vz=_rel(tr[0], ref["vz"]), p=_rel(tr[1], ref["p"]),
+             vz_field=_rel(out["u_last"].cpu().numpy(), ref["vz_field"]),
+             tzz_field=_rel(out["u_prev"].cpu().numpy(), ref["tzz"]))
+    print(f"elastic 256^3 100 steps: {e}", flush=True)
+    assert all(v <= TOL for v in e.values()), e
 
 
 def test_elastic_long_run(torch_cuda, orc):
-    """600 steps on a reduced grid against the oracle: traces over the whole
-    record by relative L2. On this small absorbing grid the wavefield has
-    decayed 150-600x by the last step, so the final fields are compared with
-    the field scale of the energetic phase (step 100): the FP32 rounding error
-    is a fixed fraction of that scale, not of the decayed remainder."""
+    """600 steps on a reduced grid without absorbing layers (the energy of
+    the scheme is conserved, so the final fields are as energetic as the
+    wavefield after the source): traces and final fields by relative L2
+    against the oracle."""
     from paper_2010_10248_amd import tb
 
-    s = W.elastic_smooth(seed=10, n=(36, 40, 44), so=8, nt=600, nbl=6, nrec=16, sigma=4.0)
+    s = W.elastic_smooth(seed=10, n=(36, 40, 44), so=8, nt=600, nbl=0, nrec=16, sigma=4.0)
     ref = orc.elastic_forward(s)
-    early = orc.elastic_forward(W.elastic_smooth(seed=10, n=(36, 40, 44), so=8, nt=100, nbl=6,
-                                                 nrec=16, sigma=4.0))
     out = tb.Propagator(s).forward(None)
     tr = out["traces"].cpu().numpy()
-    dv = np.linalg.norm(out["u_last"].cpu().numpy() - ref["vz_field"])
-    dt = np.linalg.norm(out["u_prev"].cpu().numpy() - ref["tzz"])
     e = dict(vz=_rel(tr[0], ref["vz"]), p=_rel(tr[1], ref["p"]),
-             vz_field=float(dv / np.linalg.norm(early["vz_field"])),
-             tzz_field=float(dt / np.linalg.norm(early["tzz"])))
+             vz_field=_rel(out["u_last"].cpu().numpy(), ref["vz_field"]),
+             tzz_field=_rel(out["u_prev"].cpu().numpy(), ref["tzz"]))
     print(f"elastic 600 steps: {e}", flush=True)
     assert all(v <= TOL for v in e.values()), e
+
+
+def test_elastic_long_run_damped(torch_cuda, orc):
+    """With absorbing layers the wavefield decays; traces over all 600 steps
+    and the fields at step 200, while still energetic, by relative L2."""
+    from paper_2010_10248_amd import tb
+
+    for nt in (200, 600):
+        s = W.elastic_smooth(seed=10, n=(36, 40, 44), so=8, nt=nt, nbl=6, nrec=16, sigma=4.0)
+        ref = orc.elastic_forward(s)
+        out = tb.Propagator(s).forward(None)
+        tr = out["traces"].cpu().numpy()
+        e = dict(vz=_rel(tr[0], ref["vz"]), p=_rel(tr[1], ref["p"]))
+        if nt == 200:
+            e.update(vz_field=_rel(out["u_last"].cpu().numpy(), ref["vz_field"]),
+                     tzz_field=_rel(out["u_prev"].cpu().numpy(), ref["tzz"]))
+        print(f"elastic damped {nt} steps: {e}", flush=True)
+        assert all(v <= TOL for v in e.values()), e
 
 
 @pytest.mark.parametrize("so,data", [(8, "zero"), (8, "perturbed"), (4, "zero")])
@@ -174,4 +201,36 @@ def test_elastic_gradient_matches_oracle(torch_cuda, orc, so, data):
             base = g
         else:
             assert np.array_equal(g.view(np.uint32), base.view(np.uint32)), every
+    prop.close()
+
+
+@pytest.mark.parametrize("so,n,nt", [(8, (61, 30, 34), 47), (4, (45, 28, 31), 41),
+                                     (12, (70, 26, 29), 23)])
+def test_elastic_temporal_blocking_bitwise_and_parity(torch_cuda, orc, so, n, nt):
+    """Passes of T steps over x-slabs (the velocity and stress passes of each
+    step in one wave-front, skewed by the sum of their radii; T = 2, 3, 4,
+    uneven slab widths, nt not a multiple of T) give the one-step
+    schedule's bits, with the source on a slab seam and the receivers along
+    x across every seam; parity of the first against the oracle."""
+    import torch
+
+    from paper_2010_10248_amd import tb
+
+    s = W.elastic_smooth(seed=180 + so, n=n, so=so, nt=nt, nbl=5, nrec=30, sigma=3.0)
+    h = np.array(s.spacing)
+    s.src_xyz[0, 0] = 26.0 * h[0]
+    prop = tb.Propagator(s)
+    base = prop.forward(tb.schedule("sb"))
+    ref = orc.elastic_forward(s)
+    tr = base["traces"].cpu().numpy()
+    e = dict(vz=_rel(tr[0], ref["vz"]), p=_rel(tr[1], ref["p"]),
+             vz_field=_rel(base["u_last"].cpu().numpy(), ref["vz_field"]),
+             tzz_field=_rel(base["u_prev"].cpu().numpy(), ref["tzz"]))
+    print(f"elastic SO{so} {n} nt={nt}: {e}", flush=True)
+    assert np.abs(ref["p"]).max() > 0
+    assert all(v <= TOL for v in e.values()), e
+    for T, w in ((2, 8), (2, 13), (3, 13), (4, 8), (2, 1), (3, 0), (2, 4096)):
+        out = prop.forward(tb.schedule("tb", T, 0, w))
+        for k in ("traces", "u_last", "u_prev"):
+            assert torch.equal(out[k].view(torch.int32), base[k].view(torch.int32)), (T, w, k)
     prop.close()
