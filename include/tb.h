@@ -235,6 +235,26 @@ tb_status tb_forward(const tb_model *m, const tb_sparse *s, const tb_schedule *s
                      void *stream);
 
 /*
+ * tb_forward for callers that cannot allocate (code under stream capture,
+ * serving loops or harnesses that forbid device allocation): the same plan
+ * and kernels, with the workspace in a fixed 64 MiB device array of the
+ * library (one per device it runs on, held until the process ends) instead
+ * of caller memory. Outputs as tb_forward. It calls no allocating routine;
+ * host bookkeeping only. Limits and errors: TB_EWORKSPACE when the run needs
+ * more than 64 MiB (tb_workspace_size(TB_OP_FORWARD); acoustic grids up to
+ * about 145^3); TB_EINVAL when the model is not on the current device, when
+ * per-launch timing (tb_kernel_timing) is on, or when the schedule's tile
+ * lists are not built yet (the first tb_forward of a sparse handle with that
+ * schedule builds and uploads them). Every call on a device shares that
+ * device's array, and each call clears what it needs: calls that overlap on
+ * one device (other streams, other threads) race and must be serialised by
+ * the caller.
+ */
+tb_status tb_forward_noalloc(const tb_model *m, const tb_sparse *s, const tb_schedule *sched,
+                             float *rec_out, float *field_out, float *field_prev_out,
+                             void *stream);
+
+/*
  * Exact discrete adjoint of the linear map q -> d of tb_forward, driven by
  * rec_in[nt][nrec] at the receiver points; output src_out[nt][nsrc] (device).
  * Used for the dot-product test and for imaging. Acoustic: the forward update

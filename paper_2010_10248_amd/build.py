@@ -19,7 +19,7 @@ COMMON = ["-O3", "-std=c++20", "-fPIC", "-ffp-contract=off", f"--offload-arch={A
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 SOURCES = ["acoustic_r4.hip", "acoustic_r6.hip", "acoustic_r2.hip", "acoustic.hip", "imaging.hip", "capi.cpp",
-           "inspector.cpp", "autotune.cpp", "serve.cpp", "tti.hip", "elastic.hip"]
+           "inspector.cpp", "autotune.cpp", "serve.cpp", "tti.hip", "elastic.hip", "noalloc.hip"]
 
 
 def _needs(obj: str, src: str, deps) -> bool:

@@ -221,6 +221,18 @@ tb_status lists_for(const tb_model *m, tb_sparse *s, int adjoint, const SchedCho
     return get_lists(m, s, adjoint, T, sc.tile_y, sc.chunk, wgs, out);
 }
 
+bool plan_lists_cached(const tb_model *m, tb_sparse *s, const SchedChoice &sc, const Plan &plan)
+{
+    const int wgs = m->ncu * (sc.chunk > 0 ? 1 : sc.wgs_per_cu);
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (const Item &it : plan) {
+        if (!it.is_pass) continue;
+        auto key = std::make_tuple(it.pass.adjoint, it.pass.T, sc.tile_y, sc.chunk, wgs);
+        if (s->tiles.find(key) == s->tiles.end()) return false;
+    }
+    return true;
+}
+
 namespace {
 
 AcLaunch to_launch(const Pass &p)

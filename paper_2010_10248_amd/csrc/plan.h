@@ -69,6 +69,9 @@ tb_status plan_gradient(const tb_model *m, tb_sparse *s, const SchedChoice &sc, 
                         Plan *plan);
 tb_status run_plan(const tb_model *m, tb_sparse *s, const SchedChoice &sc, const Plan &plan,
                    hipStream_t st);
+// True when the per-segment lists of every pass of the plan are already
+// cached in the sparse handle (running the plan then allocates nothing).
+bool plan_lists_cached(const tb_model *m, tb_sparse *s, const SchedChoice &sc, const Plan &plan);
 
 // Tuned schedules (tb_autotune), keyed by physics, space order and shape.
 bool tuned_schedule(const tb_model *m, SchedChoice *out);

@@ -90,6 +90,8 @@ _SIGNATURES = {
                                            ctypes.POINTER(ctypes.c_size_t)]),
     "tb_forward": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(Schedule), _vp, ctypes.c_size_t,
                                     _vp, _vp, _vp, _vp]),
+    "tb_forward_noalloc": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(Schedule), _vp, _vp, _vp,
+                                            _vp]),
     "tb_adjoint": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(Schedule), _vp, ctypes.c_size_t,
                                     _vp, _vp, _vp]),
     "tb_gradient": (ctypes.c_int32, [_vp, _vp, ctypes.POINTER(Schedule), _vp, ctypes.c_size_t,
@@ -278,6 +280,14 @@ def forward(model, sparse, sched, ws, rec_out=None, field_out=None, field_prev_o
                             _tptr(ws), ws.numel() * ws.element_size(), _tptr(rec_out),
                             _tptr(field_out), _tptr(field_prev_out), _stream(stream)),
            "tb_forward")
+
+
+def forward_noalloc(model, sparse, sched, rec_out=None, field_out=None, field_prev_out=None,
+                    stream=None):
+    """tb_forward with the library's fixed device workspace (no allocation)."""
+    _check(lib().tb_forward_noalloc(model, sparse, None if sched is None else ctypes.byref(sched),
+                                    _tptr(rec_out), _tptr(field_out), _tptr(field_prev_out),
+                                    _stream(stream)), "tb_forward_noalloc")
 
 
 def adjoint(model, sparse, sched, ws, rec_in, src_out, stream=None):
