@@ -166,7 +166,7 @@ def serve_bench(tb, W, torch, nreq, loads, max_active, arena_gb):
     return out
 
 
-def physics_bench(tb, W, torch, which, steps):
+def physics_bench(tb, W, torch, which, steps, nt=0, sb_only=False):
     """GPts/s of the TTI (256^3 SO8, 800 steps, 44 B per point-step) or
     elastic (256^3 SO8, 600 steps, 84 B per point-step) propagator on one
     shot, inputs resident, for the spatially blocked schedule and the
@@ -176,10 +176,10 @@ def physics_bench(tb, W, torch, which, steps):
     import numpy as np
 
     if which == "tti":
-        shot = W.tti_smooth()
+        shot = W.tti_smooth(nt=nt) if nt else W.tti_smooth()
         bpp = 44
     else:
-        shot = W.elastic_smooth()
+        shot = W.elastic_smooth(nt=nt) if nt else W.elastic_smooth()
         bpp = 84
     prop = tb.Propagator(shot)
     nt = shot.nt
@@ -200,6 +200,12 @@ def physics_bench(tb, W, torch, which, steps):
 
     dt_sb, rec_sb, u_sb = timed(tb.schedule("sb"))
     g_sb = N3 * nt / dt_sb / 1e9
+    if sb_only:
+        prop.close()
+        log(f"{which}: {shot.name}: SB {dt_sb * 1e3:.1f} ms/shot {g_sb:.1f} GPts/s")
+        return dict(workload=shot.name, ms_per_shot=round(dt_sb * 1e3, 2),
+                    gpts_per_s=round(g_sb, 2), bytes_per_point_step=bpp,
+                    effective_hbm_frac=round(g_sb * bpp / HBM_PEAK_GBS, 4), schedule="SB")
     best, _ = tb.autotune(prop.model, prop.sparse, steps=16)
     tbs = tb.schedule("tb", 2, 0, 32) if best.time_tile == 1 else best
     dt_tb, rec_tb, u_tb = timed(tbs)
@@ -373,6 +379,10 @@ def main(argv=None):
                     help="skip the source-density sweep")
     ap.add_argument("--no-physics", action="store_true",
                     help="skip the TTI and elastic measurements")
+    ap.add_argument("--physics-nt", type=int, default=0,
+                    help="steps of the TTI and elastic shots (0: their workloads' 800 and 600)")
+    ap.add_argument("--physics-sb-only", action="store_true",
+                    help="time only the spatially blocked TTI and elastic schedules")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-loads", type=str, default="0.5,0.8,1.0",
                     help="Poisson loads as fractions of the saturated rate")
@@ -493,7 +503,8 @@ def main(argv=None):
 
     physics = None
     if not args.no_physics:
-        physics = {k: physics_bench(tb, W, torch, k, 2) for k in ("tti", "elastic")}
+        physics = {k: physics_bench(tb, W, torch, k, 2, args.physics_nt, args.physics_sb_only)
+                   for k in ("tti", "elastic")}
 
     serving = None
     if not args.no_serve:

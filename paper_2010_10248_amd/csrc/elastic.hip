@@ -27,11 +27,28 @@ struct Site {
     long long off, sx, sy;
 };
 
+// XCD-aware block order. The hardware deals consecutive workgroups to the 8
+// XCDs round-robin. With P.band = S > 0 the launch's blocks form runs of 8S
+// (S = blocks of one x-plane / 8, rounded up), and XCD k takes the k-th
+// contiguous band of S blocks of every run: each XCD streams the same band
+// of y rows through the planes, so that neighbour reads along x and most
+// along y meet in its own L2 (with plain round-robin order every y neighbour
+// of a row sits on another XCD). A permutation of the work; blocks past the
+// grid return at once.
+template <class Params>
+__device__ __forceinline__ long long block_index(const Params &P)
+{
+    const unsigned b = blockIdx.x;
+    if (P.band <= 0) return b;
+    const unsigned S = (unsigned)P.band, xcd = b & 7, j = b >> 3;
+    return (long long)(j / S) * 8 * S + xcd * S + (j % S);
+}
+
 __device__ __forceinline__ bool locate4(const ElParams &P, Site &q)
 {
     const int nz4 = P.nzp / 4;
     const int xe = P.xhi > 0 ? P.xhi : P.nx;
-    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long gid = block_index(P) * blockDim.x + threadIdx.x;
     if (gid >= (long long)(xe - P.xlo) * P.ny * nz4) return false;
     q.z4 = (int)(gid % nz4) * 4;
     const long long xy = gid / nz4;
@@ -451,6 +468,16 @@ __global__ void el_grad_finish(const ElParams P, ElGradAcc G, float *__restrict_
 
 unsigned nblocks(long long n) { return (unsigned)((n + 255) / 256); }
 
+// Grid of a banded launch over n threads whose x-planes hold `row` threads:
+// S = blocks per plane / 8 (rounded up), and whole runs of 8S blocks.
+unsigned banded(long long n, long long row, int *band)
+{
+    const long long S = std::max(1LL, ((row + 255) / 256 + 7) / 8);
+    const long long run = 8 * S, nb = (n + 255) / 256;
+    *band = (int)S;
+    return (unsigned)((nb + run - 1) / run * run);
+}
+
 }  // namespace
 
 tb_status launch_elastic_step(const ElParams &P, int r, const float *inc, const long long *soff,
@@ -470,15 +497,16 @@ tb_status launch_elastic_step(const ElParams &P, int r, const float *inc, const 
     const long long vtotal = (long long)(V.xhi - V.xlo) * row;
     ElParams S = P;
     for (int c = 0; c < 3; c++) S.v[c] = P.vo[c] ? P.vo[c] : P.v[c];
+    const unsigned vgrid = banded(vtotal, row, &V.band), sgrid = banded(total, row, &S.band);
     if (r == 2) {
-        hipLaunchKernelGGL(el_vel<2>, dim3(nblocks(vtotal)), dim3(256), 0, st, V);
-        hipLaunchKernelGGL(el_str<2>, dim3(nblocks(total)), dim3(256), 0, st, S);
+        hipLaunchKernelGGL(el_vel<2>, dim3(vgrid), dim3(256), 0, st, V);
+        hipLaunchKernelGGL(el_str<2>, dim3(sgrid), dim3(256), 0, st, S);
     } else if (r == 4) {
-        hipLaunchKernelGGL(el_vel<4>, dim3(nblocks(vtotal)), dim3(256), 0, st, V);
-        hipLaunchKernelGGL(el_str<4>, dim3(nblocks(total)), dim3(256), 0, st, S);
+        hipLaunchKernelGGL(el_vel<4>, dim3(vgrid), dim3(256), 0, st, V);
+        hipLaunchKernelGGL(el_str<4>, dim3(sgrid), dim3(256), 0, st, S);
     } else if (r == 6) {
-        hipLaunchKernelGGL(el_vel<6>, dim3(nblocks(vtotal)), dim3(256), 0, st, V);
-        hipLaunchKernelGGL(el_str<6>, dim3(nblocks(total)), dim3(256), 0, st, S);
+        hipLaunchKernelGGL(el_vel<6>, dim3(vgrid), dim3(256), 0, st, V);
+        hipLaunchKernelGGL(el_str<6>, dim3(sgrid), dim3(256), 0, st, S);
     } else {
         set_error("elastic radius %d not built", r);
         return TB_EUNSUPPORTED;

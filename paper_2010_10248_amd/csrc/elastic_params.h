@@ -23,6 +23,9 @@ struct ElParams {
     int xlo, xhi;
     float *vo[3];
     float *to[6];
+    // XCD-aware block order of the forward launches (0: linear): runs of
+    // 8 * band blocks, of which XCD k takes the k-th contiguous band.
+    int band;
 };
 
 // Six scratch fields of the adjoint step (also used to pass a forward

@@ -39,12 +39,29 @@ struct Site {
     long long off, sx, sy;
 };
 
+// XCD-aware block order. The hardware deals consecutive workgroups to the 8
+// XCDs round-robin. With P.band = S > 0 the launch's blocks form runs of 8S
+// (S = blocks of one x-plane / 8, rounded up), and XCD k takes the k-th
+// contiguous band of S blocks of every run: each XCD streams the same band
+// of y rows through the planes, so that neighbour reads along x and most
+// along y meet in its own L2 (with plain round-robin order every y neighbour
+// of a row sits on another XCD). A permutation of the work; blocks past the
+// grid return at once.
+template <class Params>
+__device__ __forceinline__ long long block_index(const Params &P)
+{
+    const unsigned b = blockIdx.x;
+    if (P.band <= 0) return b;
+    const unsigned S = (unsigned)P.band, xcd = b & 7, j = b >> 3;
+    return (long long)(j / S) * 8 * S + xcd * S + (j % S);
+}
+
 __device__ __forceinline__ int xend(const TtiParams &P) { return P.xhi > 0 ? P.xhi : P.nx; }
 
 __device__ __forceinline__ bool locate4(const TtiParams &P, Site &q)
 {
     const int nz4 = P.nzp / 4;
-    const long long gid = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    const long long gid = block_index(P) * blockDim.x + threadIdx.x;
     if (gid >= (long long)(xend(P) - P.xlo) * P.ny * nz4) return false;
     q.z4 = (int)(gid % nz4) * 4;
     const long long xy = gid / nz4;
@@ -317,6 +334,16 @@ __global__ void tti_adj_record(const float *__restrict__ lp, const float *__rest
 
 unsigned nblocks(long long n) { return (unsigned)((n + 255) / 256); }
 
+// Grid of a banded launch over n threads whose x-planes hold `row` threads:
+// S = blocks per plane / 8 (rounded up), and whole runs of 8S blocks.
+unsigned banded(long long n, long long row, int *band)
+{
+    const long long S = std::max(1LL, ((row + 255) / 256 + 7) / 8);
+    const long long run = 8 * S, nb = (n + 255) / 256;
+    *band = (int)S;
+    return (unsigned)((nb + run - 1) / run * run);
+}
+
 }  // namespace
 
 tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const long long *soff,
@@ -333,18 +360,17 @@ tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const lon
     G.xlo = std::max(0, xlo - r);
     G.xhi = std::min(P.nx, xhi + r);
     const long long gtotal = (long long)(G.xhi - G.xlo) * row;
+    TtiParams U = P;
+    const unsigned ggrid = banded(gtotal, row, &G.band), ugrid = banded(total, row, &U.band);
     if (r == 2) {
-        hipLaunchKernelGGL(tti_rot<2>, dim3(nblocks(gtotal)), dim3(256), 0, st, G);
-        hipLaunchKernelGGL((tti_update<2, kForward>), dim3(nblocks(total)), dim3(256), 0, st, P,
-                           nullptr);
+        hipLaunchKernelGGL(tti_rot<2>, dim3(ggrid), dim3(256), 0, st, G);
+        hipLaunchKernelGGL((tti_update<2, kForward>), dim3(ugrid), dim3(256), 0, st, U, nullptr);
     } else if (r == 4) {
-        hipLaunchKernelGGL(tti_rot<4>, dim3(nblocks(gtotal)), dim3(256), 0, st, G);
-        hipLaunchKernelGGL((tti_update<4, kForward>), dim3(nblocks(total)), dim3(256), 0, st, P,
-                           nullptr);
+        hipLaunchKernelGGL(tti_rot<4>, dim3(ggrid), dim3(256), 0, st, G);
+        hipLaunchKernelGGL((tti_update<4, kForward>), dim3(ugrid), dim3(256), 0, st, U, nullptr);
     } else if (r == 6) {
-        hipLaunchKernelGGL(tti_rot<6>, dim3(nblocks(gtotal)), dim3(256), 0, st, G);
-        hipLaunchKernelGGL((tti_update<6, kForward>), dim3(nblocks(total)), dim3(256), 0, st, P,
-                           nullptr);
+        hipLaunchKernelGGL(tti_rot<6>, dim3(ggrid), dim3(256), 0, st, G);
+        hipLaunchKernelGGL((tti_update<6, kForward>), dim3(ugrid), dim3(256), 0, st, U, nullptr);
     } else {
         set_error("TTI radius %d not built", r);
         return TB_EUNSUPPORTED;

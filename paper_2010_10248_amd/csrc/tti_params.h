@@ -29,6 +29,9 @@ struct TtiParams {
     // buffers; every buffer is addressed with the global (x, y, z) offsets.
     int xlo, xhi;
     float *vpo, *vro;
+    // XCD-aware block order of the forward launches (0: linear): runs of
+    // 8 * band blocks, of which XCD k takes the k-th contiguous band.
+    int band;
 };
 
 // One step: rotated gradients, coupled update (velocity form), injection of
