@@ -564,13 +564,32 @@ tb_status plan_slab_passes(const tb_model *m, tb_sparse *s, const SchedChoice &s
     const long long *soff = s->d_src_off, *roff = s->d_rid_off, *roff2 = s->d_rid2_off;
     const int h = slab_skew(m), wm = slab_margin(m);
     const int W = slab_width(m, sc);
+    // x of every source and receiver point (sorted): a slab step whose range
+    // holds none skips the injection or the gather launch.
+    const long long nyz = (long long)m->n[1] * m->n[2];
+    auto xs_of = [&](const std::vector<int64_t> &nodes) {
+        std::vector<int> xs;
+        for (int64_t r : nodes) xs.push_back((int)(r / nyz));
+        std::sort(xs.begin(), xs.end());
+        return xs;
+    };
+    const std::vector<int> sx = xs_of(s->src_nodes), rx = xs_of(s->rid_nodes),
+                           rx2 = xs_of(s->rid2_nodes);
+    auto any_in = [](const std::vector<int> &xs, int lo, int hi) {
+        auto it = std::lower_bound(xs.begin(), xs.end(), lo);
+        return it != xs.end() && *it < hi;
+    };
 
     // One step of one slab: level n from `in` to `out` over [lo, hi), owned
     // planes [x0, x1).
-    auto step = [=](float *const *in, float *const *out, int n, int lo, int hi, int x0,
+    auto step = [&](float *const *in, float *const *out, int n, int lo, int hi, int x0,
                     int x1) -> Item {
         const float *inc = dcmp + (size_t)n * npts;
         float *row = rec + (size_t)(n + 1) * (tti ? nrid : stride);
+        // Launch counts of the sparse kernels (0: no point in the range).
+        const int ninj = any_in(sx, lo, hi) ? npts : 0;
+        const bool rec_here = any_in(rx, x0, x1) || any_in(rx2, x0, x1);
+        const int rlo = rec_here ? x0 : 0, rhi = rec_here ? x1 : 0;
         if (tti) {
             TtiParams Q = PT;
             Q.p = in[0];
@@ -586,7 +605,7 @@ tb_status plan_slab_passes(const tb_model *m, tb_sparse *s, const SchedChoice &s
             Q.xlo = lo;
             Q.xhi = hi;
             return act_item([=](hipStream_t st) {
-                return launch_tti_step(Q, r, inc, soff, npts, row, roff, nrid, x0, x1, st);
+                return launch_tti_step(Q, r, inc, soff, ninj, row, roff, nrid, rlo, rhi, st);
             });
         }
         ElParams E = PE;
@@ -601,8 +620,8 @@ tb_status plan_slab_passes(const tb_model *m, tb_sparse *s, const SchedChoice &s
         E.xlo = lo;
         E.xhi = hi;
         return act_item([=](hipStream_t st) {
-            return launch_elastic_step(E, r, inc, soff, npts, row, roff, nrid, row + nrid, roff2,
-                                       nrid2, x0, x1, st);
+            return launch_elastic_step(E, r, inc, soff, ninj, row, roff, nrid, row + nrid, roff2,
+                                       nrid2, rlo, rhi, st);
         });
     };
 

@@ -185,8 +185,11 @@ def test_adjoint_dot_product_and_oracle(torch_cuda, orc, so):
     q = rng.standard_normal(s.src_wav.shape)
     dp = rng.standard_normal((s.nt, s.rec_xyz.shape[0]))
     prop = tb.Acoustic(s, src_wav=q)
-    for sc in (tb.schedule("sb"), tb.schedule("tb", 2, 32), tb.schedule("tb", 2, 16, 20),
-               tb.schedule("tb", 2, 32, 2048)):
+    scheds = [tb.schedule("sb"), tb.schedule("tb", 2, 32), tb.schedule("tb", 2, 16, 20),
+              tb.schedule("tb", 2, 32, 2048), None]
+    if so == 4:  # three steps per pass (the space-order-4 default) and four
+        scheds += [tb.schedule("tb", 3, 32), tb.schedule("tb", 4, 16, 20)]
+    for sc in scheds:
         _say(f"adjoint so{so} {sc}")
         Fq = prop.forward(sc)["traces"].double().cpu().numpy()
         FTd = prop.adjoint(torch.as_tensor(dp.astype(np.float32), device="cuda"), sc)

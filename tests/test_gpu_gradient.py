@@ -71,10 +71,14 @@ def test_gradient_matches_oracle_and_is_schedule_independent(torch_cuda, orc, so
     prop = tb.Acoustic(shot, damp_vmax=vmax)
     d = torch.as_tensor(dobs.astype(np.float32), device="cuda")
     base = None
-    for sc, every in ((tb.schedule("sb"), 0), (tb.schedule("tb", 2, 32), 0),
-                      (tb.schedule("tb", 2, 32), 1), (tb.schedule("tb", 2, 16, 9), 7),
-                      (tb.schedule("tb", 2, 0, 0), 5), (tb.schedule("sb"), 70),
-                      (tb.schedule("tb", 2, 32, 2048), 3)):
+    cases = [(tb.schedule("sb"), 0), (tb.schedule("tb", 2, 32), 0),
+             (tb.schedule("tb", 2, 32), 1), (tb.schedule("tb", 2, 16, 9), 7),
+             (tb.schedule("tb", 2, 0, 0), 5), (tb.schedule("sb"), 70),
+             (tb.schedule("tb", 2, 32, 2048), 3), (None, 7)]
+    if so == 4:  # depth 3 (the default there) with spacings that are not multiples of it
+        cases += [(tb.schedule("tb", 3, 32), 7), (tb.schedule("tb", 3, 32, 2048), 0),
+                  (tb.schedule("tb", 4, 16), 5)]
+    for sc, every in cases:
         _say(f"gradient so{so} {data} {sc} checkpoint_every={every}")
         J, g = prop.gradient(d, sc, every)
         g = g.cpu().numpy()
