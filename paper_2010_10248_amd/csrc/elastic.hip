@@ -109,16 +109,97 @@ __device__ __forceinline__ f4 dstg(const float *__restrict__ f, const ElParams &
     return s;
 }
 
+// Forward passes on 2-D tiles: a workgroup takes 16 y rows x 64 z (16 lanes
+// of 4 z) of one x-plane. The three fields each pass differentiates along y
+// are staged in LDS with R rows of halo on each side (zero outside the grid),
+// so a y neighbour costs an LDS read instead of a vector load; x and z
+// neighbours are read as before. The per-point expressions and their order
+// are those of the one-point form, so the values are the same bits.
+constexpr int kTY = 16, kTZ = 16;  // tile rows, tile lanes (4 z each)
+
+struct TileSite {
+    Site q;
+    int ty, tz, y0;
+    bool valid;
+};
+
+// Tile of this workgroup in the banded block order over the planes [xlo,
+// xhi); false (for the whole workgroup) past the grid.
+__device__ __forceinline__ bool tile_site(const ElParams &P, TileSite &t)
+{
+    const int nz4 = P.nzp / 4;
+    const int nty = (P.ny + kTY - 1) / kTY, ntz = (nz4 + kTZ - 1) / kTZ;
+    const long long tpp = (long long)nty * ntz;
+    const int xe = P.xhi > 0 ? P.xhi : P.nx;
+    const long long L = block_index(P);
+    if (L >= (long long)(xe - P.xlo) * tpp) return false;
+    const int x = P.xlo + (int)(L / tpp);
+    const int tl = (int)(L % tpp);
+    t.ty = threadIdx.x / kTZ;
+    t.tz = threadIdx.x % kTZ;
+    t.y0 = (tl / ntz) * kTY;
+    const int y = t.y0 + t.ty, z4 = ((tl % ntz) * kTZ + t.tz) * 4;
+    t.valid = y < P.ny && z4 < P.nzp;
+    t.q.x = x;
+    t.q.y = y;
+    t.q.z4 = z4;
+    t.q.sx = (long long)P.ny * P.nzp;
+    t.q.sy = P.nzp;
+    t.q.off = ((long long)x * P.ny + y) * P.nzp + z4;
+    return true;
+}
+
+// Rows y0-R .. y0+16+R-1 of field f at this tile's x and z columns into
+// L[0 .. 16+2R) (row y0 + i - R at L[i]).
+template <int R>
+__device__ __forceinline__ void stage_rows(f4 (*L)[kTZ], const float *f, const ElParams &P,
+                                           const TileSite &t)
+{
+    const bool zin = t.q.z4 < P.nzp;
+    L[t.ty + R][t.tz] = ld4(f, t.q.off, t.valid);
+    if ((int)threadIdx.x < 2 * R * kTZ) {
+        const int hr = threadIdx.x / kTZ;
+        const int row = hr < R ? hr : kTY + hr;
+        const int yy = t.y0 + row - R;
+        const bool ok = zin && yy >= 0 && yy < P.ny;
+        L[row][t.tz] = ld4(f, ((long long)t.q.x * P.ny + yy) * P.nzp + t.q.z4, ok);
+    }
+}
+
+// The y derivative of dstg<R, 1, FWD> from the staged rows.
+template <int R, bool FWD>
+__device__ __forceinline__ f4 dy_lds(const f4 (*L)[kTZ], const ElParams &P, const TileSite &t)
+{
+    f4 s = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int m = 0; m < R; m++) {
+        const int up = FWD ? m + 1 : m, dn = FWD ? -m : -m - 1;
+        const f4 fu = L[t.ty + R + up][t.tz], fd = L[t.ty + R + dn][t.tz];
+#pragma unroll
+        for (int k = 0; k < 4; k++) s[k] = __builtin_fmaf(P.w[m], fu[k] - fd[k], s[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) s[k] *= P.ih[1];
+    return s;
+}
+
 template <int R>
 __global__ void __launch_bounds__(256) el_vel(const ElParams P)
 {
-    Site q;
-    if (!locate4(P, q)) return;
-    const f4 fx = dstg<R, 0, true>(P.t[0], P, q) + dstg<R, 1, false>(P.t[3], P, q) +
+    __shared__ f4 L[3][kTY + 2 * R][kTZ];
+    TileSite t;
+    if (!tile_site(P, t)) return;
+    stage_rows<R>(L[0], P.t[3], P, t);
+    stage_rows<R>(L[1], P.t[1], P, t);
+    stage_rows<R>(L[2], P.t[5], P, t);
+    __syncthreads();
+    if (!t.valid) return;
+    const Site &q = t.q;
+    const f4 fx = dstg<R, 0, true>(P.t[0], P, q) + dy_lds<R, false>(L[0], P, t) +
                   dstg<R, 2, false>(P.t[4], P, q);
-    const f4 fy = dstg<R, 0, false>(P.t[3], P, q) + dstg<R, 1, true>(P.t[1], P, q) +
+    const f4 fy = dstg<R, 0, false>(P.t[3], P, q) + dy_lds<R, true>(L[1], P, t) +
                   dstg<R, 2, false>(P.t[5], P, q);
-    const f4 fz = dstg<R, 0, false>(P.t[4], P, q) + dstg<R, 1, false>(P.t[5], P, q) +
+    const f4 fz = dstg<R, 0, false>(P.t[4], P, q) + dy_lds<R, false>(L[2], P, t) +
                   dstg<R, 2, true>(P.t[2], P, q);
     const f4 f3[3] = {fx, fy, fz};
     const float dxy = P.dx[q.x] + P.dy[q.y];
@@ -142,14 +223,21 @@ __global__ void __launch_bounds__(256) el_vel(const ElParams P)
 template <int R>
 __global__ void __launch_bounds__(256) el_str(const ElParams P)
 {
-    Site q;
-    if (!locate4(P, q)) return;
+    __shared__ f4 L[3][kTY + 2 * R][kTZ];
+    TileSite ts;
+    if (!tile_site(P, ts)) return;
+    stage_rows<R>(L[0], P.v[0], P, ts);
+    stage_rows<R>(L[1], P.v[1], P, ts);
+    stage_rows<R>(L[2], P.v[2], P, ts);
+    __syncthreads();
+    if (!ts.valid) return;
+    const Site &q = ts.q;
     const f4 exx = dstg<R, 0, false>(P.v[0], P, q);
-    const f4 eyy = dstg<R, 1, false>(P.v[1], P, q);
+    const f4 eyy = dy_lds<R, false>(L[1], P, ts);
     const f4 ezz = dstg<R, 2, false>(P.v[2], P, q);
-    const f4 gxy = dstg<R, 1, true>(P.v[0], P, q) + dstg<R, 0, true>(P.v[1], P, q);
+    const f4 gxy = dy_lds<R, true>(L[0], P, ts) + dstg<R, 0, true>(P.v[1], P, q);
     const f4 gxz = dstg<R, 2, true>(P.v[0], P, q) + dstg<R, 0, true>(P.v[2], P, q);
-    const f4 gyz = dstg<R, 2, true>(P.v[1], P, q) + dstg<R, 1, true>(P.v[2], P, q);
+    const f4 gyz = dstg<R, 2, true>(P.v[1], P, q) + dy_lds<R, true>(L[2], P, ts);
     const f4 lam = ld4(P.lam, q.off, true), mu = ld4(P.mu, q.off, true);
     const f4 m0 = ld4(P.ms[0], q.off, true), m1 = ld4(P.ms[1], q.off, true),
              m2 = ld4(P.ms[2], q.off, true);
@@ -183,7 +271,6 @@ __global__ void __launch_bounds__(256) el_str(const ElParams P)
     for (int c = 0; c < 6; c++) *(f4 *)((P.to[c] ? P.to[c] : P.t[c]) + q.off) = t[c];
 }
 
-// Points of planes [xlo, xhi) only (plane = ny * nzp elements).
 __global__ void el_src(float *__restrict__ txx, float *__restrict__ tyy, float *__restrict__ tzz,
                        const float *__restrict__ inc, const long long *__restrict__ soff, int npts,
                        long long plane, int xlo, int xhi)
@@ -468,12 +555,14 @@ __global__ void el_grad_finish(const ElParams P, ElGradAcc G, float *__restrict_
 
 unsigned nblocks(long long n) { return (unsigned)((n + 255) / 256); }
 
-// Grid of a banded launch over n threads whose x-planes hold `row` threads:
-// S = blocks per plane / 8 (rounded up), and whole runs of 8S blocks.
-unsigned banded(long long n, long long row, int *band)
+// Grid of a tiled launch over `planes` x-planes (16 x 64 tiles, one per
+// workgroup), banded: S = tiles of one plane / 8 (rounded up), whole runs of
+// 8S workgroups.
+unsigned tiled(int planes, int ny, int nz4, int *band)
 {
-    const long long S = std::max(1LL, ((row + 255) / 256 + 7) / 8);
-    const long long run = 8 * S, nb = (n + 255) / 256;
+    const long long tpp = (long long)((ny + kTY - 1) / kTY) * ((nz4 + kTZ - 1) / kTZ);
+    const long long S = std::max(1LL, (tpp + 7) / 8);
+    const long long run = 8 * S, nb = (long long)planes * tpp;
     *band = (int)S;
     return (unsigned)((nb + run - 1) / run * run);
 }
@@ -497,7 +586,9 @@ tb_status launch_elastic_step(const ElParams &P, int r, const float *inc, const 
     const long long vtotal = (long long)(V.xhi - V.xlo) * row;
     ElParams S = P;
     for (int c = 0; c < 3; c++) S.v[c] = P.vo[c] ? P.vo[c] : P.v[c];
-    const unsigned vgrid = banded(vtotal, row, &V.band), sgrid = banded(total, row, &S.band);
+    (void)vtotal;
+    const unsigned vgrid = tiled(V.xhi - V.xlo, P.ny, P.nzp / 4, &V.band),
+                   sgrid = tiled(xhi - xlo, P.ny, P.nzp / 4, &S.band);
     if (r == 2) {
         hipLaunchKernelGGL(el_vel<2>, dim3(vgrid), dim3(256), 0, st, V);
         hipLaunchKernelGGL(el_str<2>, dim3(sgrid), dim3(256), 0, st, S);
