@@ -105,17 +105,132 @@ __device__ __forceinline__ f4 d1xy(const float *f, const TtiParams &P, const Sit
     return s;
 }
 
+// 2-D tiles of the rotated-gradient and update kernels: a workgroup takes
+// 16 y rows x 64 z (16 lanes of 4 z) of one x-plane. The fields (or the
+// products of two fields) a kernel differentiates along y or z are staged in
+// LDS with R rows and ZB z of halo on each side (zero outside the grid), so
+// a y or z neighbour costs an LDS read instead of a vector load; x
+// neighbours are read as before. Values and operation order are those of the
+// one-point form, so the results are the same bits.
+constexpr int kTY = 16, kTZ = 16;
+
+template <int R>
+struct TileLds {
+    static constexpr int H = zspan<R>() / 4;
+    f4 a[kTY + 2 * R][kTZ + 2 * H];
+};
+
+struct TileSite {
+    Site q;
+    int ty, tz, y0, c0;
+    bool valid;
+};
+
+__device__ __forceinline__ bool tile_site(const TtiParams &P, TileSite &t)
+{
+    const int nz4 = P.nzp / 4;
+    const int nty = (P.ny + kTY - 1) / kTY, ntz = (nz4 + kTZ - 1) / kTZ;
+    const long long tpp = (long long)nty * ntz;
+    const long long L = block_index(P);
+    if (L >= (long long)(xend(P) - P.xlo) * tpp) return false;
+    const int x = P.xlo + (int)(L / tpp);
+    const int tl = (int)(L % tpp);
+    t.ty = threadIdx.x / kTZ;
+    t.tz = threadIdx.x % kTZ;
+    t.y0 = (tl / ntz) * kTY;
+    t.c0 = (tl % ntz) * kTZ;
+    const int y = t.y0 + t.ty, z4 = (t.c0 + t.tz) * 4;
+    t.valid = y < P.ny && z4 < P.nzp;
+    t.q.x = x;
+    t.q.y = y;
+    t.q.z4 = z4;
+    t.q.sx = (long long)P.ny * P.nzp;
+    t.q.sy = P.nzp;
+    t.q.off = ((long long)x * P.ny + y) * P.nzp + z4;
+    return true;
+}
+
+// f (times g when g is set) at this tile's x: its own points, plus (YH) R
+// rows above and below and (ZH) ZB z before and after. a[i][j] holds row
+// y0 + i - R, float4 column c0 + j - H.
+template <int R, bool YH, bool ZH>
+__device__ __forceinline__ void stage(TileLds<R> &L, const float *f, const float *g,
+                                      const TtiParams &P, const TileSite &t)
+{
+    constexpr int H = TileLds<R>::H;
+    const long long plane = (long long)t.q.x * P.ny;
+    auto at = [&](int y, int c) {
+        const bool ok = y >= 0 && y < P.ny && c >= 0 && 4 * c < P.nzp;
+        const long long o = (plane + y) * P.nzp + 4 * c;
+        const f4 a = ld4(f, o, ok);
+        if (!g) return a;
+        const f4 b = ld4(g, o, ok);
+        return f4{a[0] * b[0], a[1] * b[1], a[2] * b[2], a[3] * b[3]};
+    };
+    const int tid = threadIdx.x;
+    L.a[t.ty + R][t.tz + H] = at(t.y0 + t.ty, t.c0 + t.tz);
+    if constexpr (YH) {
+        if (tid < 2 * R * kTZ) {
+            const int hr = tid / kTZ, row = hr < R ? hr : kTY + hr;
+            L.a[row][t.tz + H] = at(t.y0 + row - R, t.c0 + t.tz);
+        }
+    }
+    if constexpr (ZH) {
+        if (tid < 2 * H * kTY) {
+            const int row = tid / (2 * H), hc = tid % (2 * H);
+            const int col = hc < H ? hc : kTZ + hc;
+            L.a[row + R][col] = at(t.y0 + row, t.c0 + col - H);
+        }
+    }
+}
+
+// Staged row y + m (m in [-R, R]) and the z window of the tile site (the
+// values zwin reads).
+template <int R>
+__device__ __forceinline__ f4 yrow(const TileLds<R> &L, const TileSite &t, int m)
+{
+    return L.a[t.ty + R + m][t.tz + TileLds<R>::H];
+}
+
+template <int R>
+__device__ __forceinline__ void zwin_lds(const TileLds<R> &L, const TileSite &t, float *w)
+{
+    constexpr int H = TileLds<R>::H, ZB = 4 * H;
+#pragma unroll
+    for (int o = -H; o <= H; o++) {
+        const f4 a = L.a[t.ty + R][t.tz + H + o];
+#pragma unroll
+        for (int k = 0; k < 4; k++) w[ZB + 4 * o + k] = a[k];
+    }
+}
+
 template <int R>
 __global__ void __launch_bounds__(256) tti_rot(const TtiParams P)
 {
-    Site q;
-    if (!locate4(P, q)) return;
+    __shared__ TileLds<R> L[2];  // p, r along y
+    TileSite t;
+    if (!tile_site(P, t)) return;
+    stage<R, true, false>(L[0], P.p, nullptr, P, t);
+    stage<R, true, false>(L[1], P.r, nullptr, P, t);
+    __syncthreads();
+    if (!t.valid) return;
+    const Site &q = t.q;
     constexpr int ZB = zspan<R>();
     float zp[4 + 2 * ZB], zr[4 + 2 * ZB];
     zwin<ZB>(P.p, q, P.nzp, zp);
     zwin<ZB>(P.r, q, P.nzp, zr);
-    const f4 gpx = d1xy<R>(P.p, P, q, 0), gpy = d1xy<R>(P.p, P, q, 1);
-    const f4 grx = d1xy<R>(P.r, P, q, 0), gry = d1xy<R>(P.r, P, q, 1);
+    const f4 gpx = d1xy<R>(P.p, P, q, 0), grx = d1xy<R>(P.r, P, q, 0);
+    f4 gpy = f4{0.f, 0.f, 0.f, 0.f}, gry = gpy;
+#pragma unroll
+    for (int m = 1; m <= R; m++) {
+        const f4 pu = yrow<R>(L[0], t, m), pd = yrow<R>(L[0], t, -m);
+        const f4 ru = yrow<R>(L[1], t, m), rd = yrow<R>(L[1], t, -m);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            gpy[k] = __builtin_fmaf(P.w1[m - 1], pu[k] - pd[k], gpy[k]);
+            gry[k] = __builtin_fmaf(P.w1[m - 1], ru[k] - rd[k], gry[k]);
+        }
+    }
     const f4 ax = ld4(P.ax, q.off, true), ay = ld4(P.ay, q.off, true), az = ld4(P.az, q.off, true);
     f4 qp, qr;
 #pragma unroll
@@ -144,43 +259,55 @@ template <int R, int MODE>
 __global__ void __launch_bounds__(256) tti_update(const TtiParams P, double *__restrict__ g)
 {
     constexpr bool ADJ = MODE == kAdjoint;
-    Site q;
-    if (!locate4(P, q)) return;
+    // p, a_y q_p and a_y q_r along y.
+    __shared__ TileLds<R> L[3];
+    TileSite t;
+    if (!tile_site(P, t)) return;
+    stage<R, true, false>(L[0], P.p, nullptr, P, t);
+    stage<R, true, false>(L[1], P.ay, P.qp, P, t);
+    stage<R, true, false>(L[2], P.ay, P.qr, P, t);
+    __syncthreads();
+    if (!t.valid) return;
+    const Site &q = t.q;
     constexpr int ZB = zspan<R>();
-    float zp[4 + 2 * ZB];
+    float zp[4 + 2 * ZB], zaz[4 + 2 * ZB], zqp[4 + 2 * ZB], zqr[4 + 2 * ZB];
     zwin<ZB>(P.p, q, P.nzp, zp);
-    // Products a_z q along z for the z part of Hz.
-    float zaz[4 + 2 * ZB], zqp[4 + 2 * ZB], zqr[4 + 2 * ZB];
     zwin<ZB>(P.az, q, P.nzp, zaz);
     zwin<ZB>(P.qp, q, P.nzp, zqp);
     zwin<ZB>(P.qr, q, P.nzp, zqr);
     f4 lx = f4{0.f, 0.f, 0.f, 0.f}, ly = lx, hpx = lx, hpy = lx, hrx = lx, hry = lx;
     const f4 pc = ld4(P.p, q.off, true);
-    // One offset per iteration: unrolled, the compiler hoists all 64 neighbour
-    // loads (256 VGPRs, one wave per SIMD); rolled, the kernel runs 3 waves
-    // per SIMD and the step is 15% faster.
+    // x neighbours from memory, one offset per iteration (rolled, the kernel
+    // keeps 3 waves per SIMD); y neighbours from LDS.
 #pragma unroll 1
     for (int m = 1; m <= R; m++) {
-        const bool xp = q.x + m < P.nx, xm = q.x - m >= 0, yp = q.y + m < P.ny, ym = q.y - m >= 0;
-        const long long ox = m * q.sx, oy = m * q.sy;
+        const bool xp = q.x + m < P.nx, xm = q.x - m >= 0;
+        const long long ox = m * q.sx;
         const f4 pxp = ld4(P.p, q.off + ox, xp), pxm = ld4(P.p, q.off - ox, xm);
-        const f4 pyp = ld4(P.p, q.off + oy, yp), pym = ld4(P.p, q.off - oy, ym);
         const f4 axp = ld4(P.ax, q.off + ox, xp), axm = ld4(P.ax, q.off - ox, xm);
-        const f4 ayp = ld4(P.ay, q.off + oy, yp), aym = ld4(P.ay, q.off - oy, ym);
         const f4 qpxp = ld4(P.qp, q.off + ox, xp), qpxm = ld4(P.qp, q.off - ox, xm);
-        const f4 qpyp = ld4(P.qp, q.off + oy, yp), qpym = ld4(P.qp, q.off - oy, ym);
         const f4 qrxp = ld4(P.qr, q.off + ox, xp), qrxm = ld4(P.qr, q.off - ox, xm);
-        const f4 qryp = ld4(P.qr, q.off + oy, yp), qrym = ld4(P.qr, q.off - oy, ym);
         const float w1 = P.w1[m - 1], w2 = P.w2[m];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const float p2 = 2.0f * pc[k];
             lx[k] = __builtin_fmaf(w2, (pxp[k] + pxm[k]) - p2, lx[k]);
-            ly[k] = __builtin_fmaf(w2, (pyp[k] + pym[k]) - p2, ly[k]);
             hpx[k] = __builtin_fmaf(w1, axp[k] * qpxp[k] - axm[k] * qpxm[k], hpx[k]);
-            hpy[k] = __builtin_fmaf(w1, ayp[k] * qpyp[k] - aym[k] * qpym[k], hpy[k]);
             hrx[k] = __builtin_fmaf(w1, axp[k] * qrxp[k] - axm[k] * qrxm[k], hrx[k]);
-            hry[k] = __builtin_fmaf(w1, ayp[k] * qryp[k] - aym[k] * qrym[k], hry[k]);
+        }
+    }
+#pragma unroll 2
+    for (int m = 1; m <= R; m++) {
+        const f4 pyp = yrow<R>(L[0], t, m), pym = yrow<R>(L[0], t, -m);
+        const f4 tpp = yrow<R>(L[1], t, m), tpm = yrow<R>(L[1], t, -m);
+        const f4 trp = yrow<R>(L[2], t, m), trm = yrow<R>(L[2], t, -m);
+        const float w1 = P.w1[m - 1], w2 = P.w2[m];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const float p2 = 2.0f * pc[k];
+            ly[k] = __builtin_fmaf(w2, (pyp[k] + pym[k]) - p2, ly[k]);
+            hpy[k] = __builtin_fmaf(w1, tpp[k] - tpm[k], hpy[k]);
+            hry[k] = __builtin_fmaf(w1, trp[k] - trm[k], hry[k]);
         }
     }
     const f4 zero = f4{0.f, 0.f, 0.f, 0.f};
@@ -334,12 +461,14 @@ __global__ void tti_adj_record(const float *__restrict__ lp, const float *__rest
 
 unsigned nblocks(long long n) { return (unsigned)((n + 255) / 256); }
 
-// Grid of a banded launch over n threads whose x-planes hold `row` threads:
-// S = blocks per plane / 8 (rounded up), and whole runs of 8S blocks.
-unsigned banded(long long n, long long row, int *band)
+// Grid of a tiled launch over `planes` x-planes (16 x 64 tiles, one per
+// workgroup), banded: S = tiles of one plane / 8 (rounded up), whole runs of
+// 8S workgroups.
+unsigned tiled(int planes, int ny, int nz4, int *band)
 {
-    const long long S = std::max(1LL, ((row + 255) / 256 + 7) / 8);
-    const long long run = 8 * S, nb = (n + 255) / 256;
+    const long long tpp = (long long)((ny + kTY - 1) / kTY) * ((nz4 + kTZ - 1) / kTZ);
+    const long long S = std::max(1LL, (tpp + 7) / 8);
+    const long long run = 8 * S, nb = (long long)planes * tpp;
     *band = (int)S;
     return (unsigned)((nb + run - 1) / run * run);
 }
@@ -361,7 +490,9 @@ tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const lon
     G.xhi = std::min(P.nx, xhi + r);
     const long long gtotal = (long long)(G.xhi - G.xlo) * row;
     TtiParams U = P;
-    const unsigned ggrid = banded(gtotal, row, &G.band), ugrid = banded(total, row, &U.band);
+    (void)gtotal;
+    const unsigned ggrid = tiled(G.xhi - G.xlo, P.ny, P.nzp / 4, &G.band),
+                   ugrid = tiled(xhi - xlo, P.ny, P.nzp / 4, &U.band);
     if (r == 2) {
         hipLaunchKernelGGL(tti_rot<2>, dim3(ggrid), dim3(256), 0, st, G);
         hipLaunchKernelGGL((tti_update<2, kForward>), dim3(ugrid), dim3(256), 0, st, U, nullptr);
@@ -404,17 +535,19 @@ tb_status launch_tti_adjoint_step(const TtiParams &P, int r, const float *inc,
         TB_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(tti_adj_mix, dim3(nblocks(total)), dim3(256), 0, st, P);
+    TtiParams Q = P;
+    const unsigned tgrid = tiled(P.nx, P.ny, P.nzp / 4, &Q.band);
     if (r == 2) {
-        hipLaunchKernelGGL(tti_rot<2>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL((tti_update<2, kAdjoint>), dim3(nblocks(total)), dim3(256), 0, st, P,
+        hipLaunchKernelGGL(tti_rot<2>, dim3(tgrid), dim3(256), 0, st, Q);
+        hipLaunchKernelGGL((tti_update<2, kAdjoint>), dim3(tgrid), dim3(256), 0, st, Q,
                            nullptr);
     } else if (r == 4) {
-        hipLaunchKernelGGL(tti_rot<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL((tti_update<4, kAdjoint>), dim3(nblocks(total)), dim3(256), 0, st, P,
+        hipLaunchKernelGGL(tti_rot<4>, dim3(tgrid), dim3(256), 0, st, Q);
+        hipLaunchKernelGGL((tti_update<4, kAdjoint>), dim3(tgrid), dim3(256), 0, st, Q,
                            nullptr);
     } else if (r == 6) {
-        hipLaunchKernelGGL(tti_rot<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL((tti_update<6, kAdjoint>), dim3(nblocks(total)), dim3(256), 0, st, P,
+        hipLaunchKernelGGL(tti_rot<6>, dim3(tgrid), dim3(256), 0, st, Q);
+        hipLaunchKernelGGL((tti_update<6, kAdjoint>), dim3(tgrid), dim3(256), 0, st, Q,
                            nullptr);
     } else {
         set_error("TTI radius %d not built", r);
@@ -433,15 +566,17 @@ tb_status launch_tti_image(const TtiParams &P, int r, double *g, hipStream_t st)
 {
     const long long total = (long long)P.nx * P.ny * (P.nzp / 4);
     if (total == 0) return TB_OK;
+    TtiParams Q = P;
+    const unsigned tgrid = tiled(P.nx, P.ny, P.nzp / 4, &Q.band);
     if (r == 2) {
-        hipLaunchKernelGGL(tti_rot<2>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL((tti_update<2, kImage>), dim3(nblocks(total)), dim3(256), 0, st, P, g);
+        hipLaunchKernelGGL(tti_rot<2>, dim3(tgrid), dim3(256), 0, st, Q);
+        hipLaunchKernelGGL((tti_update<2, kImage>), dim3(tgrid), dim3(256), 0, st, Q, g);
     } else if (r == 4) {
-        hipLaunchKernelGGL(tti_rot<4>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL((tti_update<4, kImage>), dim3(nblocks(total)), dim3(256), 0, st, P, g);
+        hipLaunchKernelGGL(tti_rot<4>, dim3(tgrid), dim3(256), 0, st, Q);
+        hipLaunchKernelGGL((tti_update<4, kImage>), dim3(tgrid), dim3(256), 0, st, Q, g);
     } else if (r == 6) {
-        hipLaunchKernelGGL(tti_rot<6>, dim3(nblocks(total)), dim3(256), 0, st, P);
-        hipLaunchKernelGGL((tti_update<6, kImage>), dim3(nblocks(total)), dim3(256), 0, st, P, g);
+        hipLaunchKernelGGL(tti_rot<6>, dim3(tgrid), dim3(256), 0, st, Q);
+        hipLaunchKernelGGL((tti_update<6, kImage>), dim3(tgrid), dim3(256), 0, st, Q, g);
     } else {
         set_error("TTI radius %d not built", r);
         return TB_EUNSUPPORTED;
