@@ -57,6 +57,29 @@ def measured_traffic(sched_repr):
         return None
 
 
+PHYS_COUNTERS = os.path.join(ROOT, "profiles", "tti_elastic_256_so8_counters.md")
+
+
+def physics_traffic(which):
+    """HBM bytes per step of the TTI or elastic kernels from the committed
+    counter summary, or None when it was taken on other kernel sources."""
+    try:
+        text = open(PHYS_COUNTERS).read()
+    except OSError:
+        return None
+    kv = dict(re.findall(r"^- (\w+): `?([^`\n]+)`?$", text, re.M))
+    src = os.path.join(ROOT, "paper_2010_10248_amd", "csrc",
+                       "tti.hip" if which == "tti" else "elastic.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    if kv.get(f"{which}_sha") != sha:
+        return None
+    try:
+        return float(kv[f"{which}_hbm_bytes_per_step"])
+    except (KeyError, ValueError):
+        return None
+
+
 def copy_calibration(torch):
     """Five device-to-device copies of 1 GiB: the counters of this plain copy
     kernel scale FETCH_SIZE / WRITE_SIZE to bytes."""
@@ -200,6 +223,14 @@ def physics_bench(tb, W, torch, which, steps, nt=0, sb_only=False):
 
     dt_sb, rec_sb, u_sb = timed(tb.schedule("sb"))
     g_sb = N3 * nt / dt_sb / 1e9
+    # Roofline of the spatially blocked step at the metric's algorithmic bytes
+    # (shot time, so injection, gathers and launch gaps count against it).
+    traffic = physics_traffic(which)
+    roof = dict(bound="hbm", achieved=round(g_sb * bpp, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(g_sb * bpp / HBM_PEAK_GBS, 4),
+                traffic=round(traffic) if traffic is not None else None,
+                traffic_unit="HBM bytes per step (calibrated FETCH_SIZE + WRITE_SIZE)",
+                algorithmic_bytes_per_step=bpp * N3)
     if sb_only:
         prop.close()
         log(f"{which}: {shot.name}: SB {dt_sb * 1e3:.1f} ms/shot {g_sb:.1f} GPts/s")
@@ -218,6 +249,7 @@ def physics_bench(tb, W, torch, which, steps, nt=0, sb_only=False):
     return dict(workload=shot.name, ms_per_shot=round(dt_sb * 1e3, 2), gpts_per_s=round(g_sb, 2),
                 bytes_per_point_step=bpp,
                 effective_hbm_frac=round(g_sb * bpp / HBM_PEAK_GBS, 4), schedule="SB",
+                roofline=roof,
                 temporal_blocked=dict(schedule=repr(tbs), ms_per_shot=round(dt_tb * 1e3, 2),
                                       gpts_per_s=round(g_tb, 2),
                                       effective_hbm_frac=round(g_tb * bpp / HBM_PEAK_GBS, 4),
