@@ -17,12 +17,14 @@
 // Hz = -D^T D exactly, as in the definition of the operator.
 #include <algorithm>
 
+#include "acoustic_kernel.h"  // buffer, DPP and barrier helpers (tbw::wf)
 #include "tti_params.h"
 
 namespace tbw {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+using wf::f4v;
 
 // Each thread takes 4 consecutive z (float4 accesses); neighbours along x and
 // y are float4 loads, neighbours along z come from the window [z4-ZB,
@@ -374,6 +376,469 @@ __global__ void __launch_bounds__(256) tti_update(const TtiParams P, double *__r
     }
 }
 
+// ---------------------------------------------------------------------------
+// Streaming forward kernels (radius 2 and 4). A workgroup of 256 threads
+// owns a 16-row x 32-z tile (16 lanes of 2 z per row) and streams a chunk of
+// x planes. Each thread keeps the (2R+1)-plane x windows of its column in
+// registers (slot k holds plane j - R + k for the centre plane j, shifted by
+// one slot per tick), publishes the centre plane's y-differentiated values
+// to double-buffered LDS together with R halo rows on each side loaded from
+// memory, and takes z neighbours from the adjacent lanes of its 16-lane row
+// by DPP, the row's edge lanes supplying the tile's outer z values. All
+// field traffic uses buffer instructions with per-plane descriptors built on
+// the scalar unit: lanes outside the grid carry an offset past the plane
+// (loads give 0, stores are dropped), and planes outside [0, nx), or outside
+// the chunk for the centre-plane inputs, get an empty descriptor. The inputs
+// a tick starts with are loaded during the previous tick. Two z per lane
+// keep the windows, the next tick's inputs and the current terms within the
+// registers of three waves per SIMD. Per point the operations and their
+// order are those of tti_rot / tti_update above (with contraction off, a
+// product formed once and reused rounds the same), so the streaming and
+// tiled kernels give the same bits.
+constexpr int kSY = 16, kSZ = 16;  // tile rows, lanes per row
+
+// PL consecutive z per lane (2 or 4) as one vector.
+template <int PL>
+struct VecOf;
+template <>
+struct VecOf<2> {
+    typedef float type __attribute__((ext_vector_type(2)));
+    typedef unsigned bits __attribute__((ext_vector_type(2)));
+};
+template <>
+struct VecOf<4> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    typedef unsigned bits __attribute__((ext_vector_type(4)));
+};
+template <int PL>
+using vec = typename VecOf<PL>::type;
+
+template <int PL, int POLICY = wf::kTemporal>
+__device__ __forceinline__ vec<PL> vload(wf::rsrc_t r, unsigned off)
+{
+    if constexpr (PL == 2)
+        return __builtin_bit_cast(vec<2>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, POLICY));
+    else
+        return __builtin_bit_cast(vec<4>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, POLICY));
+}
+template <int PL>
+__device__ __forceinline__ void vstore(wf::rsrc_t r, unsigned off, vec<PL> v)
+{
+    if constexpr (PL == 2)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(typename VecOf<2>::bits, v), r,
+                                              (int)off, 0, wf::kStreaming);
+    else
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(typename VecOf<4>::bits, v), r,
+                                               (int)off, 0, wf::kStreaming);
+}
+// Lane l takes lane l -+ 1 or 2 of its 16-lane row; lanes whose source lies
+// outside the row keep `edge` (vshift) or take 0 (vshift0).
+template <int CTRL, int PL>
+__device__ __forceinline__ vec<PL> vshift(vec<PL> edge, vec<PL> v)
+{
+    vec<PL> o;
+#pragma unroll
+    for (int k = 0; k < PL; k++) o[k] = wf::lane_shift<CTRL>(edge[k], v[k]);
+    return o;
+}
+template <int CTRL, int PL>
+__device__ __forceinline__ vec<PL> vshift0(vec<PL> v)
+{
+    vec<PL> o;
+#pragma unroll
+    for (int k = 0; k < PL; k++) o[k] = wf::lane_shift0<CTRL>(v[k]);
+    return o;
+}
+
+// z neighbours of the PL own points: w[4 + k + m] is point k's neighbour at
+// offset m (|m| <= R <= 4). With 4 z per lane the float4s of lanes l-1, l,
+// l+1 cover that; with 2 z per lane the pairs of lanes l-2 .. l+2 (l-1 ..
+// l+1 at radius 2). rg: the tile's outer values held by the edge lanes (4 z
+// per lane: lane 0 the float4 before the tile, lane 15 the one after; 2 z
+// per lane: lanes 0 and 1 the pair 4 z before their own, lanes 14 and 15 the
+// pair 4 after, or lanes 0 and 15 the pair 2 away at radius 2).
+template <int R, int PL>
+__device__ __forceinline__ void zwin(vec<PL> rg, vec<PL> v, float *w)
+{
+    if constexpr (PL == 4) {
+        const vec<4> l1 = vshift<wf::kDppRowShr1, 4>(rg, v), r1 = vshift<wf::kDppRowShl1, 4>(rg, v);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            w[k] = l1[k];
+            w[4 + k] = v[k];
+            w[8 + k] = r1[k];
+        }
+    } else {
+        vec<2> l1, r1;
+        if constexpr (R <= 2) {
+            l1 = vshift<wf::kDppRowShr1, 2>(rg, v);
+            r1 = vshift<wf::kDppRowShl1, 2>(rg, v);
+        } else {
+            // Lane 0's left pair is lane 1's outer pair, lane 15's right
+            // pair lane 14's.
+            l1 = vshift<wf::kDppRowShr1, 2>(vshift0<wf::kDppRowShl1, 2>(rg), v);
+            r1 = vshift<wf::kDppRowShl1, 2>(vshift0<wf::kDppRowShr1, 2>(rg), v);
+            const vec<2> l2 = vshift<wf::kDppRowShr2, 2>(rg, v), r2 = vshift<wf::kDppRowShl2, 2>(rg, v);
+            w[0] = l2[0];
+            w[1] = l2[1];
+            w[8] = r2[0];
+            w[9] = r2[1];
+        }
+        w[2] = l1[0];
+        w[3] = l1[1];
+        w[4] = v[0];
+        w[5] = v[1];
+        w[6] = r1[0];
+        w[7] = r1[1];
+    }
+}
+
+// Centred first derivative (unit weights w1) of the PL points along z.
+template <int R, int PL>
+__device__ __forceinline__ vec<PL> d1z(const TtiParams &P, const float *w)
+{
+    vec<PL> g;
+#pragma unroll
+    for (int k = 0; k < PL; k++) {
+        float a = 0.0f;
+#pragma unroll
+        for (int m = 1; m <= R; m++) a = __builtin_fmaf(P.w1[m - 1], w[4 + k + m] - w[4 + k - m], a);
+        g[k] = a;
+    }
+    return g;
+}
+
+// Work item and lane geometry of a streaming launch (tiles of 16 rows x
+// 16 PL z).
+struct SSite {
+    int xa, xb;        // chunk planes [xa, xb)
+    int row, zl, y, z;
+    unsigned off;      // own points in the plane (kNoLane outside the grid)
+    unsigned off_yr;   // y halo row of threads < 2R*16 (whole waves)
+    unsigned off_rg;   // outer z values of the edge lanes
+    int yr_lds;        // LDS row of the y halo value
+    bool yring;
+};
+
+template <int R, int PL>
+__device__ __forceinline__ bool ssite(const TtiParams &P, SSite &s)
+{
+    constexpr int ZW = PL * kSZ;
+    const int ntz = (P.nzp + ZW - 1) / ZW;
+    const int ntiles = ((P.ny + kSY - 1) / kSY) * ntz;
+    const int nwg = ntiles * P.nchunks;
+    // XCD-aware order: the hardware deals consecutive workgroups to the 8
+    // XCDs round-robin; XCD k takes the k-th contiguous run of the
+    // chunk-major work list, so each XCD streams whole x ranges of
+    // neighbouring tiles in step and their halo rows meet in its L2.
+    const int b = blockIdx.x, q8 = nwg >> 3, r8 = nwg & 7, xcd = b & 7;
+    const int wi = xcd * q8 + min(xcd, r8) + (b >> 3);
+    const int chunk = wi / ntiles, tile = wi % ntiles;
+    s.xa = P.xlo + chunk * P.chunk;
+    s.xb = min(s.xa + P.chunk, P.xhi > 0 ? P.xhi : P.nx);
+    const int tid = threadIdx.x;
+    s.row = tid / kSZ;
+    s.zl = tid % kSZ;
+    const int y0 = (tile / ntz) * kSY, z0 = (tile % ntz) * ZW;
+    s.y = y0 + s.row;
+    s.z = z0 + PL * s.zl;
+    const bool yin = s.y < P.ny, zin = s.z < P.nzp;
+    s.off = (yin && zin) ? (unsigned)((s.y * P.nzp + s.z) * 4) : wf::kNoLane;
+    s.yring = tid < 2 * R * kSZ;
+    const int yr = s.row < R ? y0 - R + s.row : y0 + kSY + s.row - R;
+    const bool yrok = s.yring && yr >= 0 && yr < P.ny && zin;
+    s.off_yr = yrok ? (unsigned)((yr * P.nzp + s.z) * 4) : wf::kNoLane;
+    s.yr_lds = s.row < R ? s.row : kSY + s.row;
+    constexpr int ZO = PL == 4 || R <= 2 ? PL : 4;  // distance of the outer values
+    const bool edge = ZO == PL ? (s.zl == 0 || s.zl == kSZ - 1) : (s.zl < 2 || s.zl >= kSZ - 2);
+    const int zr = s.zl < kSZ / 2 ? s.z - ZO : s.z + ZO;
+    const bool rgok = edge && yin && zr >= 0 && zr < P.nzp;
+    s.off_rg = rgok ? (unsigned)((s.y * P.nzp + zr) * 4) : wf::kNoLane;
+    return s.xa < s.xb;
+}
+
+template <class V>
+__device__ __forceinline__ V vmul(V a, V b)
+{
+    return a * b;  // elementwise, rounded per element (contraction is off)
+}
+
+// Descriptor of plane x of a field; empty unless ok and 0 <= x < nx.
+__device__ __forceinline__ wf::rsrc_t plane_of(const float *f, const TtiParams &P, int x, bool ok)
+{
+    const bool in = ok && x >= 0 && x < P.nx;
+    const long long sx = (long long)P.ny * P.nzp;
+    return wf::make_rsrc(f + (in ? (long long)x * sx : 0), in ? (unsigned)(sx * 4) : 0u);
+}
+
+template <int R, int PL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+tti_rot_s(const TtiParams P)
+{
+    static_assert(R == 2 || R == 4, "streaming kernels cover radius 2 and 4");
+    using V = vec<PL>;
+    constexpr int U = 2 * R + 1, LR = kSY + 2 * R, CTR = R;
+    __shared__ V sh[2][2][LR][kSZ];  // p, r along y
+    SSite s;
+    if (!ssite<R, PL>(P, s)) return;
+    struct In {
+        V p, r;            // window plane i
+        V ax, ay, az;      // centre plane j = i - R
+        V yp, yr, gp, gr;  // halo values at j
+    };
+    const int i0 = s.xa - R, ilast = s.xb - 1 + R;
+    auto fetch = [&](int i, In &f) {
+        const int j = i - R;
+        const bool c = j >= s.xa && j < s.xb, w = i <= ilast;
+        f.p = vload<PL>(plane_of(P.p, P, i, w), s.off);
+        f.r = vload<PL>(plane_of(P.r, P, i, w), s.off);
+        f.ax = vload<PL, wf::kStreaming>(plane_of(P.ax, P, j, c), s.off);
+        f.ay = vload<PL, wf::kStreaming>(plane_of(P.ay, P, j, c), s.off);
+        f.az = vload<PL, wf::kStreaming>(plane_of(P.az, P, j, c), s.off);
+        const wf::rsrc_t pj = plane_of(P.p, P, j, c), rj = plane_of(P.r, P, j, c);
+        f.yp = vload<PL>(pj, s.off_yr);
+        f.yr = vload<PL>(rj, s.off_yr);
+        f.gp = vload<PL>(pj, s.off_rg);
+        f.gr = vload<PL>(rj, s.off_rg);
+    };
+    const V zero = V{};
+    V wp[U], wr[U];  // x windows, slot k = plane j - R + k
+#pragma unroll
+    for (int k = 0; k < U; k++) wp[k] = wr[k] = zero;
+    In pf;
+    fetch(i0, pf);
+    int tick = 0;
+    for (int i = i0; i <= ilast; i++) {
+        const In cur = pf;
+#pragma unroll
+        for (int k = 0; k + 1 < U; k++) {
+            wp[k] = wp[k + 1];
+            wr[k] = wr[k + 1];
+        }
+        wp[U - 1] = cur.p;
+        wr[U - 1] = cur.r;
+        const int j = i - R;
+        const bool out = j >= s.xa;
+        const int buf = tick & 1;
+        V gpz, grz;
+        if (out) {
+            sh[buf][0][s.row + R][s.zl] = wp[CTR];
+            sh[buf][1][s.row + R][s.zl] = wr[CTR];
+            if (s.yring) {
+                sh[buf][0][s.yr_lds][s.zl] = cur.yp;
+                sh[buf][1][s.yr_lds][s.zl] = cur.yr;
+            }
+            float zp[12], zr[12];
+            zwin<R, PL>(cur.gp, wp[CTR], zp);
+            zwin<R, PL>(cur.gr, wr[CTR], zr);
+            gpz = d1z<R, PL>(P, zp);
+            grz = d1z<R, PL>(P, zr);
+        }
+        const V ax = cur.ax, ay = cur.ay, az = cur.az;
+        fetch(i + 1, pf);
+        if (out) {
+            wf::lds_barrier();
+            V gpx = zero, grx = zero, gpy = zero, gry = zero;
+#pragma unroll
+            for (int m = 1; m <= R; m++) {
+#pragma unroll
+                for (int k = 0; k < PL; k++) {
+                    gpx[k] = __builtin_fmaf(P.w1[m - 1], wp[CTR + m][k] - wp[CTR - m][k], gpx[k]);
+                    grx[k] = __builtin_fmaf(P.w1[m - 1], wr[CTR + m][k] - wr[CTR - m][k], grx[k]);
+                }
+            }
+#pragma unroll
+            for (int m = 1; m <= R; m++) {
+                const V pu = sh[buf][0][s.row + R + m][s.zl], pd = sh[buf][0][s.row + R - m][s.zl];
+                const V ru = sh[buf][1][s.row + R + m][s.zl], rd = sh[buf][1][s.row + R - m][s.zl];
+#pragma unroll
+                for (int k = 0; k < PL; k++) {
+                    gpy[k] = __builtin_fmaf(P.w1[m - 1], pu[k] - pd[k], gpy[k]);
+                    gry[k] = __builtin_fmaf(P.w1[m - 1], ru[k] - rd[k], gry[k]);
+                }
+            }
+            V qp, qr;
+#pragma unroll
+            for (int k = 0; k < PL; k++) {
+                qp[k] = ax[k] * (gpx[k] * P.ih[0]) + ay[k] * (gpy[k] * P.ih[1]) + az[k] * (gpz[k] * P.ih[2]);
+                qr[k] = ax[k] * (grx[k] * P.ih[0]) + ay[k] * (gry[k] * P.ih[1]) + az[k] * (grz[k] * P.ih[2]);
+            }
+            vstore<PL>(plane_of(P.qp, P, j, true), s.off, qp);
+            vstore<PL>(plane_of(P.qr, P, j, true), s.off, qr);
+            tick++;
+        }
+    }
+}
+
+template <int R, int PL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+tti_update_s(const TtiParams P)
+{
+    static_assert(R == 2 || R == 4, "streaming kernels cover radius 2 and 4");
+    using V = vec<PL>;
+    constexpr int U = 2 * R + 1, LR = kSY + 2 * R, CTR = R;
+    __shared__ V sh[2][3][LR][kSZ];  // p, a_y q_p, a_y q_r along y
+    SSite s;
+    if (!ssite<R, PL>(P, s)) return;
+    const bool yin = s.y < P.ny;
+    const float dyv = yin ? P.dy[s.y] : 0.0f;
+    float dzv[PL];
+#pragma unroll
+    for (int k = 0; k < PL; k++) dzv[k] = s.z + k < P.nz ? P.dz[s.z + k] : 0.0f;
+    // Inputs loaded a tick ahead (those the tick starts with); the update's
+    // own centre inputs (r, w_p, w_r, 1+2e, s, c) are loaded as the tick
+    // starts, for use at its end.
+    struct In {
+        V p, ax, qp, qr;       // window plane i
+        V ay, az, cqp, cqr;    // centre plane j = i - R
+        V yp, yay, yqp, yqr;   // y halo at j
+        V gp, gaz, gqp, gqr;   // outer z pair at j
+    };
+    float *const vpo = P.vpo ? P.vpo : P.vp;
+    float *const vro = P.vro ? P.vro : P.vr;
+    const int i0 = s.xa - R, ilast = s.xb - 1 + R;
+    auto fetch = [&](int i, In &f) {
+        const int j = i - R;
+        const bool c = j >= s.xa && j < s.xb, w = i <= ilast;
+        f.p = vload<PL>(plane_of(P.p, P, i, w), s.off);
+        f.ax = vload<PL>(plane_of(P.ax, P, i, w), s.off);
+        f.qp = vload<PL>(plane_of(P.qp, P, i, w), s.off);
+        f.qr = vload<PL>(plane_of(P.qr, P, i, w), s.off);
+        const wf::rsrc_t pj = plane_of(P.p, P, j, c), ayj = plane_of(P.ay, P, j, c),
+                         azj = plane_of(P.az, P, j, c), qpj = plane_of(P.qp, P, j, c),
+                         qrj = plane_of(P.qr, P, j, c);
+        f.ay = vload<PL>(ayj, s.off);
+        f.az = vload<PL>(azj, s.off);
+        f.cqp = vload<PL>(qpj, s.off);
+        f.cqr = vload<PL>(qrj, s.off);
+        f.yp = vload<PL>(pj, s.off_yr);
+        f.yay = vload<PL>(ayj, s.off_yr);
+        f.yqp = vload<PL>(qpj, s.off_yr);
+        f.yqr = vload<PL>(qrj, s.off_yr);
+        f.gp = vload<PL>(pj, s.off_rg);
+        f.gaz = vload<PL>(azj, s.off_rg);
+        f.gqp = vload<PL>(qpj, s.off_rg);
+        f.gqr = vload<PL>(qrj, s.off_rg);
+    };
+    const V zero = V{};
+    V wp[U], wpx[U], wrx[U];  // p, a_x q_p, a_x q_r along x
+#pragma unroll
+    for (int k = 0; k < U; k++) wp[k] = wpx[k] = wrx[k] = zero;
+    In pf;
+    fetch(i0, pf);
+    int tick = 0;
+    for (int i = i0; i <= ilast; i++) {
+        const In cur = pf;
+#pragma unroll
+        for (int k = 0; k + 1 < U; k++) {
+            wp[k] = wp[k + 1];
+            wpx[k] = wpx[k + 1];
+            wrx[k] = wrx[k + 1];
+        }
+        wp[U - 1] = cur.p;
+        wpx[U - 1] = vmul(cur.ax, cur.qp);
+        wrx[U - 1] = vmul(cur.ax, cur.qr);
+        const int j = i - R;
+        const bool out = j >= s.xa;
+        // First half (no LDS reads): publish the centre plane and take the z
+        // terms from the adjacent lanes; the next tick's inputs are requested
+        // once this tick's are consumed.
+        V rc, vpc, vrc, e1, sd, cc, lz, hpz, hrz;
+        const int buf = tick & 1;
+        const V pc = wp[CTR];
+        if (out) {
+            rc = vload<PL, wf::kStreaming>(plane_of(P.r, P, j, true), s.off);
+            vpc = vload<PL, wf::kStreaming>(plane_of(P.vp, P, j, true), s.off);
+            vrc = vload<PL, wf::kStreaming>(plane_of(P.vr, P, j, true), s.off);
+            e1 = vload<PL, wf::kStreaming>(plane_of(P.e1, P, j, true), s.off);
+            sd = vload<PL, wf::kStreaming>(plane_of(P.sd, P, j, true), s.off);
+            cc = vload<PL, wf::kStreaming>(plane_of(P.c, P, j, true), s.off);
+            sh[buf][0][s.row + R][s.zl] = pc;
+            sh[buf][1][s.row + R][s.zl] = vmul(cur.ay, cur.cqp);
+            sh[buf][2][s.row + R][s.zl] = vmul(cur.ay, cur.cqr);
+            if (s.yring) {
+                sh[buf][0][s.yr_lds][s.zl] = cur.yp;
+                sh[buf][1][s.yr_lds][s.zl] = vmul(cur.yay, cur.yqp);
+                sh[buf][2][s.yr_lds][s.zl] = vmul(cur.yay, cur.yqr);
+            }
+            float zp[12], zqp[12], zqr[12];
+            zwin<R, PL>(cur.gp, pc, zp);
+            zwin<R, PL>(vmul(cur.gaz, cur.gqp), vmul(cur.az, cur.cqp), zqp);
+            zwin<R, PL>(vmul(cur.gaz, cur.gqr), vmul(cur.az, cur.cqr), zqr);
+#pragma unroll
+            for (int k = 0; k < PL; k++) {
+                const float p2 = 2.0f * pc[k];
+                float l = 0.0f;
+#pragma unroll
+                for (int m = 1; m <= R; m++)
+                    l = __builtin_fmaf(P.w2[m], (zp[4 + k + m] + zp[4 + k - m]) - p2, l);
+                lz[k] = l;
+            }
+            hpz = d1z<R, PL>(P, zqp);
+            hrz = d1z<R, PL>(P, zqr);
+        }
+        fetch(i + 1, pf);
+        if (out) {
+            wf::lds_barrier();
+            V lx = zero, ly = zero, hpx = zero, hpy = zero, hrx = zero, hry = zero;
+#pragma unroll
+            for (int m = 1; m <= R; m++) {
+                const float w1 = P.w1[m - 1], w2 = P.w2[m];
+#pragma unroll
+                for (int k = 0; k < PL; k++) {
+                    const float p2 = 2.0f * pc[k];
+                    lx[k] = __builtin_fmaf(w2, (wp[CTR + m][k] + wp[CTR - m][k]) - p2, lx[k]);
+                    hpx[k] = __builtin_fmaf(w1, wpx[CTR + m][k] - wpx[CTR - m][k], hpx[k]);
+                    hrx[k] = __builtin_fmaf(w1, wrx[CTR + m][k] - wrx[CTR - m][k], hrx[k]);
+                }
+            }
+#pragma unroll
+            for (int m = 1; m <= R; m++) {
+                const V pyp = sh[buf][0][s.row + R + m][s.zl], pym = sh[buf][0][s.row + R - m][s.zl];
+                const V tpp = sh[buf][1][s.row + R + m][s.zl], tpm = sh[buf][1][s.row + R - m][s.zl];
+                const V trp = sh[buf][2][s.row + R + m][s.zl], trm = sh[buf][2][s.row + R - m][s.zl];
+                const float w1 = P.w1[m - 1], w2 = P.w2[m];
+#pragma unroll
+                for (int k = 0; k < PL; k++) {
+                    const float p2 = 2.0f * pc[k];
+                    ly[k] = __builtin_fmaf(w2, (pyp[k] + pym[k]) - p2, ly[k]);
+                    hpy[k] = __builtin_fmaf(w1, tpp[k] - tpm[k], hpy[k]);
+                    hry[k] = __builtin_fmaf(w1, trp[k] - trm[k], hry[k]);
+                }
+            }
+            const float dxy = P.dx[j] + dyv;
+            V vp = vpc, vr = vrc, pn, rn;
+#pragma unroll
+            for (int k = 0; k < PL; k++) {
+                const float lap = lx[k] * P.ih2[0] + ly[k] * P.ih2[1] + lz[k] * P.ih2[2];
+                const float hzp = hpx[k] * P.ih[0] + hpy[k] * P.ih[1] + hpz[k] * P.ih[2];
+                const float hzr = hrx[k] * P.ih[0] + hry[k] * P.ih[1] + hrz[k] * P.ih[2];
+                const float h0p = lap - hzp;
+                const float d = dxy + dzv[k];
+                const float dd = d * P.hdt;
+                const float beta = 1.0f - dd;
+                const float rhs_p = __builtin_fmaf(e1[k], h0p, sd[k] * hzr);
+                const float rhs_r = __builtin_fmaf(sd[k], h0p, hzr);
+                float wpn = __builtin_fmaf(cc[k], rhs_p, beta * vp[k]);
+                float wrn = __builtin_fmaf(cc[k], rhs_r, beta * vr[k]);
+                if (d != 0.0f) {
+                    wpn = wpn / (1.0f + dd);
+                    wrn = wrn / (1.0f + dd);
+                }
+                vp[k] = wpn;
+                vr[k] = wrn;
+                pn[k] = pc[k] + wpn;
+                rn[k] = rc[k] + wrn;
+            }
+            vstore<PL>(plane_of(vpo, P, j, true), s.off, vp);
+            vstore<PL>(plane_of(vro, P, j, true), s.off, vr);
+            vstore<PL>(plane_of(P.pn, P, j, true), s.off, pn);
+            vstore<PL>(plane_of(P.rn, P, j, true), s.off, rn);
+            tick++;
+        }
+    }
+}
+
 // Points of planes [xlo, xhi) only (plane = ny * nzp elements).
 __global__ void tti_sparse(float *__restrict__ p, float *__restrict__ r, float *__restrict__ vp,
                            float *__restrict__ vr, const float *__restrict__ inc,
@@ -473,6 +938,20 @@ unsigned tiled(int planes, int ny, int nz4, int *band)
     return (unsigned)((nb + run - 1) / run * run);
 }
 
+// Grid of a streaming launch over `planes` planes: the tiles of a plane
+// times the chunks of x, about two workgroups per CU with at least 16 planes
+// per chunk (each chunk re-reads 2R planes of halo).
+unsigned streamed(int planes, int ny, int nzp, int pl, int *chunk, int *nchunks)
+{
+    const int zw = pl * kSZ;
+    const int ntiles = ((ny + kSY - 1) / kSY) * ((nzp + zw - 1) / zw);
+    const int want = std::max(1, 512 / ntiles);
+    const int ch = std::min(planes, std::max(16, (planes + want - 1) / want));
+    *chunk = ch;
+    *nchunks = (planes + ch - 1) / ch;
+    return (unsigned)(ntiles * *nchunks);
+}
+
 }  // namespace
 
 tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const long long *soff,
@@ -488,18 +967,22 @@ tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const lon
     TtiParams G = P;
     G.xlo = std::max(0, xlo - r);
     G.xhi = std::min(P.nx, xhi + r);
-    const long long gtotal = (long long)(G.xhi - G.xlo) * row;
     TtiParams U = P;
-    (void)gtotal;
-    const unsigned ggrid = tiled(G.xhi - G.xlo, P.ny, P.nzp / 4, &G.band),
-                   ugrid = tiled(xhi - xlo, P.ny, P.nzp / 4, &U.band);
-    if (r == 2) {
-        hipLaunchKernelGGL(tti_rot<2>, dim3(ggrid), dim3(256), 0, st, G);
-        hipLaunchKernelGGL((tti_update<2, kForward>), dim3(ugrid), dim3(256), 0, st, U, nullptr);
-    } else if (r == 4) {
-        hipLaunchKernelGGL(tti_rot<4>, dim3(ggrid), dim3(256), 0, st, G);
-        hipLaunchKernelGGL((tti_update<4, kForward>), dim3(ugrid), dim3(256), 0, st, U, nullptr);
+    if (r == 2 || r == 4) {
+        // The rotated gradient takes 4 z per lane, the update 2 (its three x
+        // windows and the next tick's inputs then fit three waves per SIMD).
+        const unsigned gs = streamed(G.xhi - G.xlo, P.ny, P.nzp, 4, &G.chunk, &G.nchunks),
+                       us = streamed(xhi - xlo, P.ny, P.nzp, 2, &U.chunk, &U.nchunks);
+        if (r == 2) {
+            hipLaunchKernelGGL((tti_rot_s<2, 4>), dim3(gs), dim3(256), 0, st, G);
+            hipLaunchKernelGGL((tti_update_s<2, 2>), dim3(us), dim3(256), 0, st, U);
+        } else {
+            hipLaunchKernelGGL((tti_rot_s<4, 4>), dim3(gs), dim3(256), 0, st, G);
+            hipLaunchKernelGGL((tti_update_s<4, 2>), dim3(us), dim3(256), 0, st, U);
+        }
     } else if (r == 6) {
+        const unsigned ggrid = tiled(G.xhi - G.xlo, P.ny, P.nzp / 4, &G.band),
+                       ugrid = tiled(xhi - xlo, P.ny, P.nzp / 4, &U.band);
         hipLaunchKernelGGL(tti_rot<6>, dim3(ggrid), dim3(256), 0, st, G);
         hipLaunchKernelGGL((tti_update<6, kForward>), dim3(ugrid), dim3(256), 0, st, U, nullptr);
     } else {

@@ -32,6 +32,8 @@ struct TtiParams {
     // XCD-aware block order of the forward launches (0: linear): runs of
     // 8 * band blocks, of which XCD k takes the k-th contiguous band.
     int band;
+    // Streaming launches: planes per workgroup and chunks per tile.
+    int chunk, nchunks;
 };
 
 // One step: rotated gradients, coupled update (velocity form), injection of
