@@ -678,6 +678,10 @@ tti_update_s(const TtiParams P)
     using V = vec<PL>;
     constexpr int U = 2 * R + 1, LR = kSY + 2 * R, CTR = R;
     __shared__ V sh[2][3][LR][kSZ];  // p, a_y q_p, a_y q_r along y
+    // q_p, q_r of the newest plane wait R ticks for their turn as the centre
+    // plane in a thread-private LDS delay line (each thread reads back only
+    // its own values): re-reading them from memory would miss L2 by then.
+    __shared__ V qd[R + 1][2][kSY * kSZ];
     SSite s;
     if (!ssite<R, PL>(P, s)) return;
     const bool yin = s.y < P.ny;
@@ -690,7 +694,7 @@ tti_update_s(const TtiParams P)
     // starts, for use at its end.
     struct In {
         V p, ax, qp, qr;       // window plane i
-        V ay, az, cqp, cqr;    // centre plane j = i - R
+        V ay, az;              // centre plane j = i - R
         V yp, yay, yqp, yqr;   // y halo at j
         V gp, gaz, gqp, gqr;   // outer z pair at j
     };
@@ -709,8 +713,6 @@ tti_update_s(const TtiParams P)
                          qrj = plane_of(P.qr, P, j, c);
         f.ay = vload<PL>(ayj, s.off);
         f.az = vload<PL>(azj, s.off);
-        f.cqp = vload<PL>(qpj, s.off);
-        f.cqr = vload<PL>(qrj, s.off);
         f.yp = vload<PL>(pj, s.off_yr);
         f.yay = vload<PL>(ayj, s.off_yr);
         f.yqp = vload<PL>(qpj, s.off_yr);
@@ -726,9 +728,14 @@ tti_update_s(const TtiParams P)
     for (int k = 0; k < U; k++) wp[k] = wpx[k] = wrx[k] = zero;
     In pf;
     fetch(i0, pf);
-    int tick = 0;
+    const int tid = threadIdx.x;
+    int tick = 0, qs = 0;  // qs: delay-line slot of plane i, (i - i0) mod (R + 1)
     for (int i = i0; i <= ilast; i++) {
         const In cur = pf;
+        qd[qs][0][tid] = cur.qp;
+        qd[qs][1][tid] = cur.qr;
+        const int qc = qs == R ? 0 : qs + 1;  // slot of plane i - R
+        qs = qc;
 #pragma unroll
         for (int k = 0; k + 1 < U; k++) {
             wp[k] = wp[k + 1];
@@ -747,6 +754,7 @@ tti_update_s(const TtiParams P)
         const int buf = tick & 1;
         const V pc = wp[CTR];
         if (out) {
+            const V cqp = qd[qc][0][tid], cqr = qd[qc][1][tid];
             rc = vload<PL, wf::kStreaming>(plane_of(P.r, P, j, true), s.off);
             vpc = vload<PL, wf::kStreaming>(plane_of(P.vp, P, j, true), s.off);
             vrc = vload<PL, wf::kStreaming>(plane_of(P.vr, P, j, true), s.off);
@@ -754,8 +762,8 @@ tti_update_s(const TtiParams P)
             sd = vload<PL, wf::kStreaming>(plane_of(P.sd, P, j, true), s.off);
             cc = vload<PL, wf::kStreaming>(plane_of(P.c, P, j, true), s.off);
             sh[buf][0][s.row + R][s.zl] = pc;
-            sh[buf][1][s.row + R][s.zl] = vmul(cur.ay, cur.cqp);
-            sh[buf][2][s.row + R][s.zl] = vmul(cur.ay, cur.cqr);
+            sh[buf][1][s.row + R][s.zl] = vmul(cur.ay, cqp);
+            sh[buf][2][s.row + R][s.zl] = vmul(cur.ay, cqr);
             if (s.yring) {
                 sh[buf][0][s.yr_lds][s.zl] = cur.yp;
                 sh[buf][1][s.yr_lds][s.zl] = vmul(cur.yay, cur.yqp);
@@ -763,8 +771,8 @@ tti_update_s(const TtiParams P)
             }
             float zp[12], zqp[12], zqr[12];
             zwin<R, PL>(cur.gp, pc, zp);
-            zwin<R, PL>(vmul(cur.gaz, cur.gqp), vmul(cur.az, cur.cqp), zqp);
-            zwin<R, PL>(vmul(cur.gaz, cur.gqr), vmul(cur.az, cur.cqr), zqr);
+            zwin<R, PL>(vmul(cur.gaz, cur.gqp), vmul(cur.az, cqp), zqp);
+            zwin<R, PL>(vmul(cur.gaz, cur.gqr), vmul(cur.az, cqr), zqr);
 #pragma unroll
             for (int k = 0; k < PL; k++) {
                 const float p2 = 2.0f * pc[k];
