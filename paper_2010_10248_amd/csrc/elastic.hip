@@ -12,6 +12,7 @@
 #include <algorithm>
 
 #include "elastic_params.h"
+#include "stream_kernel.h"
 
 namespace tbw {
 namespace {
@@ -269,6 +270,294 @@ __global__ void __launch_bounds__(256) el_str(const ElParams P)
     }
 #pragma unroll
     for (int c = 0; c < 6; c++) *(f4 *)((P.to[c] ? P.to[c] : P.t[c]) + q.off) = t[c];
+}
+
+// ---------------------------------------------------------------------------
+// Streaming forward passes (radius 2 and 4; building blocks in
+// stream_kernel.h). Slot k of an x window holds plane j - R + k for the
+// centre plane j (a staggered derivative reads slots R - R .. R + R), shifted
+// by one slot per tick; the inputs a tick starts with are loaded during the
+// previous tick. Per point the operations and their order are those of
+// el_vel / el_str above, so the streaming and tiled passes give the same
+// bits.
+using namespace st;
+
+// Staggered first derivatives (unit weights w, scaled by 1/h) of the PL
+// points: along x from a window, along y from staged LDS rows, along z from
+// the lane window of zlanes. FWD as in dstg.
+template <int R, int PL, bool FWD>
+__device__ __forceinline__ vec<PL> sdx(const ElParams &P, const vec<PL> *win)
+{
+    vec<PL> s = vec<PL>{};
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        const int up = FWD ? m + 1 : m, dn = FWD ? -m : -m - 1;
+#pragma unroll
+        for (int k = 0; k < PL; k++) s[k] = __builtin_fmaf(P.w[m], win[R + up][k] - win[R + dn][k], s[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < PL; k++) s[k] *= P.ih[0];
+    return s;
+}
+template <int R, int PL, bool FWD>
+__device__ __forceinline__ vec<PL> sdy(const ElParams &P, const vec<PL> (*L)[kSZ], const SSite &s)
+{
+    vec<PL> a = vec<PL>{};
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        const int up = FWD ? m + 1 : m, dn = FWD ? -m : -m - 1;
+        const vec<PL> fu = L[s.row + R + up][s.zl], fd = L[s.row + R + dn][s.zl];
+#pragma unroll
+        for (int k = 0; k < PL; k++) a[k] = __builtin_fmaf(P.w[m], fu[k] - fd[k], a[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < PL; k++) a[k] *= P.ih[1];
+    return a;
+}
+template <int R, int PL, bool FWD>
+__device__ __forceinline__ vec<PL> sdz(const ElParams &P, const float *w)
+{
+    vec<PL> a;
+#pragma unroll
+    for (int k = 0; k < PL; k++) {
+        float t = 0.0f;
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const int up = FWD ? m + 1 : m, dn = FWD ? -m : -m - 1;
+            t = __builtin_fmaf(P.w[m], w[4 + k + up] - w[4 + k + dn], t);
+        }
+        a[k] = t * P.ih[2];
+    }
+    return a;
+}
+
+template <int R, int PL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+el_vel_s(const ElParams P)
+{
+    static_assert(R == 2 || R == 4, "streaming passes cover radius 2 and 4");
+    using V = vec<PL>;
+    constexpr int U = 2 * R + 1, LR = kSY + 2 * R, CTR = R;
+    __shared__ V sh[2][3][LR][kSZ];  // txy, tyy, tyz along y
+    SSite s;
+    if (!ssite<R, PL>(P, s)) return;
+    const float dyv = s.y < P.ny ? P.dy[s.y] : 0.0f;
+    float dzv[PL];
+#pragma unroll
+    for (int k = 0; k < PL; k++) dzv[k] = s.z + k < P.nz ? P.dz[s.z + k] : 0.0f;
+    struct In {
+        V xx, xy, xz;     // txx, txy, txz at the window plane i
+        V yy, yz, zz;     // tyy, tyz, tzz at the centre plane j = i - R
+        V hxy, hyy, hyz;  // y halo at j
+        V gxz, gyz, gzz;  // outer z values at j
+    };
+    const int i0 = s.xa - R, ilast = s.xb - 1 + R;
+    auto fetch = [&](int i, In &f) {
+        const int j = i - R;
+        const bool c = j >= s.xa && j < s.xb, w = i <= ilast;
+        f.xx = vload<PL>(plane_of(P.t[0], P, i, w), s.off);
+        f.xy = vload<PL>(plane_of(P.t[3], P, i, w), s.off);
+        f.xz = vload<PL>(plane_of(P.t[4], P, i, w), s.off);
+        const wf::rsrc_t xyj = plane_of(P.t[3], P, j, c), yyj = plane_of(P.t[1], P, j, c),
+                         yzj = plane_of(P.t[5], P, j, c), xzj = plane_of(P.t[4], P, j, c),
+                         zzj = plane_of(P.t[2], P, j, c);
+        f.yy = vload<PL>(yyj, s.off);
+        f.yz = vload<PL>(yzj, s.off);
+        f.zz = vload<PL>(zzj, s.off);
+        f.hxy = vload<PL>(xyj, s.off_yr);
+        f.hyy = vload<PL>(yyj, s.off_yr);
+        f.hyz = vload<PL>(yzj, s.off_yr);
+        f.gxz = vload<PL>(xzj, s.off_rg);
+        f.gyz = vload<PL>(yzj, s.off_rg);
+        f.gzz = vload<PL>(zzj, s.off_rg);
+    };
+    const V zero = V{};
+    V wxx[U], wxy[U], wxz[U];
+#pragma unroll
+    for (int k = 0; k < U; k++) wxx[k] = wxy[k] = wxz[k] = zero;
+    In pf;
+    fetch(i0, pf);
+    int tick = 0;
+    for (int i = i0; i <= ilast; i++) {
+        const In cur = pf;
+#pragma unroll
+        for (int k = 0; k + 1 < U; k++) {
+            wxx[k] = wxx[k + 1];
+            wxy[k] = wxy[k + 1];
+            wxz[k] = wxz[k + 1];
+        }
+        wxx[U - 1] = cur.xx;
+        wxy[U - 1] = cur.xy;
+        wxz[U - 1] = cur.xz;
+        const int j = i - R;
+        const bool out = j >= s.xa;
+        const int buf = tick & 1;
+        V vo[3], bq[3], dz[3];
+        if (out) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                vo[c] = vload<PL, wf::kStreaming>(plane_of(P.v[c], P, j, true), s.off);
+                bq[c] = vload<PL, wf::kStreaming>(plane_of(P.bq[c], P, j, true), s.off);
+            }
+            sh[buf][0][s.row + R][s.zl] = wxy[CTR];
+            sh[buf][1][s.row + R][s.zl] = cur.yy;
+            sh[buf][2][s.row + R][s.zl] = cur.yz;
+            if (s.yring) {
+                sh[buf][0][s.yr_lds][s.zl] = cur.hxy;
+                sh[buf][1][s.yr_lds][s.zl] = cur.hyy;
+                sh[buf][2][s.yr_lds][s.zl] = cur.hyz;
+            }
+            float w[12];
+            zlanes<R, PL>(cur.gxz, wxz[CTR], w);
+            dz[0] = sdz<R, PL, false>(P, w);
+            zlanes<R, PL>(cur.gyz, cur.yz, w);
+            dz[1] = sdz<R, PL, false>(P, w);
+            zlanes<R, PL>(cur.gzz, cur.zz, w);
+            dz[2] = sdz<R, PL, true>(P, w);
+        }
+        fetch(i + 1, pf);
+        if (out) {
+            wf::lds_barrier();
+            V f3[3];
+            f3[0] = sdx<R, PL, true>(P, wxx) + sdy<R, PL, false>(P, sh[buf][0], s) + dz[0];
+            f3[1] = sdx<R, PL, false>(P, wxy) + sdy<R, PL, true>(P, sh[buf][1], s) + dz[1];
+            f3[2] = sdx<R, PL, false>(P, wxz) + sdy<R, PL, false>(P, sh[buf][2], s) + dz[2];
+            const float dxy = P.dx[j] + dyv;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                V v = vo[c];
+#pragma unroll
+                for (int k = 0; k < PL; k++) {
+                    const float d = dxy + dzv[k];
+                    const float dd = d * P.hdt;
+                    float r = __builtin_fmaf(1.0f - dd, v[k], bq[c][k] * f3[c][k]);
+                    if (d != 0.0f) r /= 1.0f + dd;
+                    v[k] = r;
+                }
+                vstore<PL>(plane_of(P.vo[c] ? P.vo[c] : P.v[c], P, j, true), s.off, v);
+            }
+            tick++;
+        }
+    }
+}
+
+template <int R, int PL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+el_str_s(const ElParams P)
+{
+    static_assert(R == 2 || R == 4, "streaming passes cover radius 2 and 4");
+    using V = vec<PL>;
+    constexpr int U = 2 * R + 1, LR = kSY + 2 * R, CTR = R;
+    __shared__ V sh[2][3][LR][kSZ];  // vx, vy, vz along y
+    SSite s;
+    if (!ssite<R, PL>(P, s)) return;
+    const float dyv = s.y < P.ny ? P.dy[s.y] : 0.0f;
+    float dzv[PL];
+#pragma unroll
+    for (int k = 0; k < PL; k++) dzv[k] = s.z + k < P.nz ? P.dz[s.z + k] : 0.0f;
+    struct In {
+        V x, y, z;     // vx, vy, vz at the window plane i
+        V hx, hy, hz;  // y halo at the centre plane j = i - R
+        V gx, gy, gz;  // outer z values at j
+    };
+    const int i0 = s.xa - R, ilast = s.xb - 1 + R;
+    auto fetch = [&](int i, In &f) {
+        const int j = i - R;
+        const bool c = j >= s.xa && j < s.xb, w = i <= ilast;
+        f.x = vload<PL>(plane_of(P.v[0], P, i, w), s.off);
+        f.y = vload<PL>(plane_of(P.v[1], P, i, w), s.off);
+        f.z = vload<PL>(plane_of(P.v[2], P, i, w), s.off);
+        const wf::rsrc_t xj = plane_of(P.v[0], P, j, c), yj = plane_of(P.v[1], P, j, c),
+                         zj = plane_of(P.v[2], P, j, c);
+        f.hx = vload<PL>(xj, s.off_yr);
+        f.hy = vload<PL>(yj, s.off_yr);
+        f.hz = vload<PL>(zj, s.off_yr);
+        f.gx = vload<PL>(xj, s.off_rg);
+        f.gy = vload<PL>(yj, s.off_rg);
+        f.gz = vload<PL>(zj, s.off_rg);
+    };
+    const V zero = V{};
+    V wx[U], wy[U], wz[U];
+#pragma unroll
+    for (int k = 0; k < U; k++) wx[k] = wy[k] = wz[k] = zero;
+    In pf;
+    fetch(i0, pf);
+    int tick = 0;
+    for (int i = i0; i <= ilast; i++) {
+        const In cur = pf;
+#pragma unroll
+        for (int k = 0; k + 1 < U; k++) {
+            wx[k] = wx[k + 1];
+            wy[k] = wy[k + 1];
+            wz[k] = wz[k + 1];
+        }
+        wx[U - 1] = cur.x;
+        wy[U - 1] = cur.y;
+        wz[U - 1] = cur.z;
+        const int j = i - R;
+        const bool out = j >= s.xa;
+        const int buf = tick & 1;
+        V lam, mu, ms[3], t[6], ezz, zxz, zyz;
+        if (out) {
+            const wf::rsrc_t lj = plane_of(P.lam, P, j, true), mj = plane_of(P.mu, P, j, true);
+            lam = vload<PL, wf::kStreaming>(lj, s.off);
+            mu = vload<PL, wf::kStreaming>(mj, s.off);
+#pragma unroll
+            for (int c = 0; c < 3; c++) ms[c] = vload<PL, wf::kStreaming>(plane_of(P.ms[c], P, j, true), s.off);
+#pragma unroll
+            for (int c = 0; c < 6; c++) t[c] = vload<PL, wf::kStreaming>(plane_of(P.t[c], P, j, true), s.off);
+            sh[buf][0][s.row + R][s.zl] = wx[CTR];
+            sh[buf][1][s.row + R][s.zl] = wy[CTR];
+            sh[buf][2][s.row + R][s.zl] = wz[CTR];
+            if (s.yring) {
+                sh[buf][0][s.yr_lds][s.zl] = cur.hx;
+                sh[buf][1][s.yr_lds][s.zl] = cur.hy;
+                sh[buf][2][s.yr_lds][s.zl] = cur.hz;
+            }
+            float w[12];
+            zlanes<R, PL>(cur.gz, wz[CTR], w);
+            ezz = sdz<R, PL, false>(P, w);
+            zlanes<R, PL>(cur.gx, wx[CTR], w);
+            zxz = sdz<R, PL, true>(P, w);
+            zlanes<R, PL>(cur.gy, wy[CTR], w);
+            zyz = sdz<R, PL, true>(P, w);
+        }
+        fetch(i + 1, pf);
+        if (out) {
+            wf::lds_barrier();
+            const V exx = sdx<R, PL, false>(P, wx);
+            const V eyy = sdy<R, PL, false>(P, sh[buf][1], s);
+            const V gxy = sdy<R, PL, true>(P, sh[buf][0], s) + sdx<R, PL, true>(P, wy);
+            const V gxz = zxz + sdx<R, PL, true>(P, wz);
+            const V gyz = zyz + sdy<R, PL, true>(P, sh[buf][2], s);
+            const float dxy = P.dx[j] + dyv;
+#pragma unroll
+            for (int k = 0; k < PL; k++) {
+                const float d = dxy + dzv[k];
+                const float dd = d * P.hdt;
+                const float beta = 1.0f - dd;
+                const float tr = exx[k] + eyy[k] + ezz[k];
+                const float mu2 = 2.0f * mu[k];
+                float n[6];
+                n[0] = __builtin_fmaf(beta, t[0][k], __builtin_fmaf(lam[k], tr, mu2 * exx[k]));
+                n[1] = __builtin_fmaf(beta, t[1][k], __builtin_fmaf(lam[k], tr, mu2 * eyy[k]));
+                n[2] = __builtin_fmaf(beta, t[2][k], __builtin_fmaf(lam[k], tr, mu2 * ezz[k]));
+                n[3] = __builtin_fmaf(beta, t[3][k], ms[0][k] * gxy[k]);
+                n[4] = __builtin_fmaf(beta, t[4][k], ms[1][k] * gxz[k]);
+                n[5] = __builtin_fmaf(beta, t[5][k], ms[2][k] * gyz[k]);
+                if (d != 0.0f) {
+#pragma unroll
+                    for (int c = 0; c < 6; c++) n[c] /= 1.0f + dd;
+                }
+#pragma unroll
+                for (int c = 0; c < 6; c++) t[c][k] = n[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 6; c++)
+                vstore<PL>(plane_of(P.to[c] ? P.to[c] : P.t[c], P, j, true), s.off, t[c]);
+            tick++;
+        }
+    }
 }
 
 __global__ void el_src(float *__restrict__ txx, float *__restrict__ tyy, float *__restrict__ tzz,
@@ -587,15 +876,20 @@ tb_status launch_elastic_step(const ElParams &P, int r, const float *inc, const 
     ElParams S = P;
     for (int c = 0; c < 3; c++) S.v[c] = P.vo[c] ? P.vo[c] : P.v[c];
     (void)vtotal;
-    const unsigned vgrid = tiled(V.xhi - V.xlo, P.ny, P.nzp / 4, &V.band),
-                   sgrid = tiled(xhi - xlo, P.ny, P.nzp / 4, &S.band);
-    if (r == 2) {
-        hipLaunchKernelGGL(el_vel<2>, dim3(vgrid), dim3(256), 0, st, V);
-        hipLaunchKernelGGL(el_str<2>, dim3(sgrid), dim3(256), 0, st, S);
-    } else if (r == 4) {
-        hipLaunchKernelGGL(el_vel<4>, dim3(vgrid), dim3(256), 0, st, V);
-        hipLaunchKernelGGL(el_str<4>, dim3(sgrid), dim3(256), 0, st, S);
+    if (r == 2 || r == 4) {
+        constexpr int VPL = 2, SPL = 2;  // z per lane of the two passes
+        const unsigned vs = streamed(V.xhi - V.xlo, P.ny, P.nzp, VPL, &V.chunk, &V.nchunks),
+                       ss = streamed(xhi - xlo, P.ny, P.nzp, SPL, &S.chunk, &S.nchunks);
+        if (r == 2) {
+            hipLaunchKernelGGL((el_vel_s<2, VPL>), dim3(vs), dim3(256), 0, st, V);
+            hipLaunchKernelGGL((el_str_s<2, SPL>), dim3(ss), dim3(256), 0, st, S);
+        } else {
+            hipLaunchKernelGGL((el_vel_s<4, VPL>), dim3(vs), dim3(256), 0, st, V);
+            hipLaunchKernelGGL((el_str_s<4, SPL>), dim3(ss), dim3(256), 0, st, S);
+        }
     } else if (r == 6) {
+        const unsigned vgrid = tiled(V.xhi - V.xlo, P.ny, P.nzp / 4, &V.band),
+                       sgrid = tiled(xhi - xlo, P.ny, P.nzp / 4, &S.band);
         hipLaunchKernelGGL(el_vel<6>, dim3(vgrid), dim3(256), 0, st, V);
         hipLaunchKernelGGL(el_str<6>, dim3(sgrid), dim3(256), 0, st, S);
     } else {

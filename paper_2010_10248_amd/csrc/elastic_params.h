@@ -26,6 +26,8 @@ struct ElParams {
     // XCD-aware block order of the forward launches (0: linear): runs of
     // 8 * band blocks, of which XCD k takes the k-th contiguous band.
     int band;
+    // Streaming launches: planes per workgroup and chunks per tile.
+    int chunk, nchunks;
 };
 
 // Six scratch fields of the adjoint step (also used to pass a forward
