@@ -355,12 +355,13 @@ el_vel_s(const ElParams P)
     auto fetch = [&](int i, In &f) {
         const int j = i - R;
         const bool c = j >= s.xa && j < s.xb, w = i <= ilast;
-        f.xx = vload<PL>(plane_of(P.t[0], P, i, w), s.off);
-        f.xy = vload<PL>(plane_of(P.t[3], P, i, w), s.off);
-        f.xz = vload<PL>(plane_of(P.t[4], P, i, w), s.off);
-        const wf::rsrc_t xyj = plane_of(P.t[3], P, j, c), yyj = plane_of(P.t[1], P, j, c),
-                         yzj = plane_of(P.t[5], P, j, c), xzj = plane_of(P.t[4], P, j, c),
-                         zzj = plane_of(P.t[2], P, j, c);
+        const PlaneRef xw = plane(P, i, w), xc = plane(P, j, c);
+        f.xx = vload<PL>(at(P.t[0], xw), s.off);
+        f.xy = vload<PL>(at(P.t[3], xw), s.off);
+        f.xz = vload<PL>(at(P.t[4], xw), s.off);
+        const wf::rsrc_t xyj = at(P.t[3], xc), yyj = at(P.t[1], xc),
+                         yzj = at(P.t[5], xc), xzj = at(P.t[4], xc),
+                         zzj = at(P.t[2], xc);
         f.yy = vload<PL>(yyj, s.off);
         f.yz = vload<PL>(yzj, s.off);
         f.zz = vload<PL>(zzj, s.off);
@@ -391,13 +392,14 @@ el_vel_s(const ElParams P)
         wxz[U - 1] = cur.xz;
         const int j = i - R;
         const bool out = j >= s.xa;
+        const PlaneRef xj = plane(P, j, true);
         const int buf = tick & 1;
         V vo[3], bq[3], dz[3];
         if (out) {
 #pragma unroll
             for (int c = 0; c < 3; c++) {
-                vo[c] = vload<PL, wf::kStreaming>(plane_of(P.v[c], P, j, true), s.off);
-                bq[c] = vload<PL, wf::kStreaming>(plane_of(P.bq[c], P, j, true), s.off);
+                vo[c] = vload<PL, wf::kStreaming>(at(P.v[c], xj), s.off);
+                bq[c] = vload<PL, wf::kStreaming>(at(P.bq[c], xj), s.off);
             }
             sh[buf][0][s.row + R][s.zl] = wxy[CTR];
             sh[buf][1][s.row + R][s.zl] = cur.yy;
@@ -434,7 +436,7 @@ el_vel_s(const ElParams P)
                     if (d != 0.0f) r /= 1.0f + dd;
                     v[k] = r;
                 }
-                vstore<PL>(plane_of(P.vo[c] ? P.vo[c] : P.v[c], P, j, true), s.off, v);
+                vstore<PL>(at(P.vo[c] ? P.vo[c] : P.v[c], xj), s.off, v);
             }
             tick++;
         }
@@ -464,17 +466,17 @@ el_str_s(const ElParams P)
     auto fetch = [&](int i, In &f) {
         const int j = i - R;
         const bool c = j >= s.xa && j < s.xb, w = i <= ilast;
-        f.x = vload<PL>(plane_of(P.v[0], P, i, w), s.off);
-        f.y = vload<PL>(plane_of(P.v[1], P, i, w), s.off);
-        f.z = vload<PL>(plane_of(P.v[2], P, i, w), s.off);
-        const wf::rsrc_t xj = plane_of(P.v[0], P, j, c), yj = plane_of(P.v[1], P, j, c),
-                         zj = plane_of(P.v[2], P, j, c);
-        f.hx = vload<PL>(xj, s.off_yr);
-        f.hy = vload<PL>(yj, s.off_yr);
-        f.hz = vload<PL>(zj, s.off_yr);
-        f.gx = vload<PL>(xj, s.off_rg);
-        f.gy = vload<PL>(yj, s.off_rg);
-        f.gz = vload<PL>(zj, s.off_rg);
+        const PlaneRef xw = plane(P, i, w), xc = plane(P, j, c);
+        f.x = vload<PL>(at(P.v[0], xw), s.off);
+        f.y = vload<PL>(at(P.v[1], xw), s.off);
+        f.z = vload<PL>(at(P.v[2], xw), s.off);
+        const wf::rsrc_t dvx = at(P.v[0], xc), dvy = at(P.v[1], xc), dvz = at(P.v[2], xc);
+        f.hx = vload<PL>(dvx, s.off_yr);
+        f.hy = vload<PL>(dvy, s.off_yr);
+        f.hz = vload<PL>(dvz, s.off_yr);
+        f.gx = vload<PL>(dvx, s.off_rg);
+        f.gy = vload<PL>(dvy, s.off_rg);
+        f.gz = vload<PL>(dvz, s.off_rg);
     };
     const V zero = V{};
     V wx[U], wy[U], wz[U];
@@ -496,16 +498,17 @@ el_str_s(const ElParams P)
         wz[U - 1] = cur.z;
         const int j = i - R;
         const bool out = j >= s.xa;
+        const PlaneRef xj = plane(P, j, true);
         const int buf = tick & 1;
         V lam, mu, ms[3], t[6], ezz, zxz, zyz;
         if (out) {
-            const wf::rsrc_t lj = plane_of(P.lam, P, j, true), mj = plane_of(P.mu, P, j, true);
+            const wf::rsrc_t lj = at(P.lam, xj), mj = at(P.mu, xj);
             lam = vload<PL, wf::kStreaming>(lj, s.off);
             mu = vload<PL, wf::kStreaming>(mj, s.off);
 #pragma unroll
-            for (int c = 0; c < 3; c++) ms[c] = vload<PL, wf::kStreaming>(plane_of(P.ms[c], P, j, true), s.off);
+            for (int c = 0; c < 3; c++) ms[c] = vload<PL, wf::kStreaming>(at(P.ms[c], xj), s.off);
 #pragma unroll
-            for (int c = 0; c < 6; c++) t[c] = vload<PL, wf::kStreaming>(plane_of(P.t[c], P, j, true), s.off);
+            for (int c = 0; c < 6; c++) t[c] = vload<PL, wf::kStreaming>(at(P.t[c], xj), s.off);
             sh[buf][0][s.row + R][s.zl] = wx[CTR];
             sh[buf][1][s.row + R][s.zl] = wy[CTR];
             sh[buf][2][s.row + R][s.zl] = wz[CTR];
@@ -554,7 +557,7 @@ el_str_s(const ElParams P)
             }
 #pragma unroll
             for (int c = 0; c < 6; c++)
-                vstore<PL>(plane_of(P.to[c] ? P.to[c] : P.t[c], P, j, true), s.off, t[c]);
+                vstore<PL>(at(P.to[c] ? P.to[c] : P.t[c], xj), s.off, t[c]);
             tick++;
         }
     }

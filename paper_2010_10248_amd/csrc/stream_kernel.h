@@ -173,13 +173,23 @@ __device__ __forceinline__ V vmul(V a, V b)
     return a * b;  // elementwise, rounded per element (contraction is off)
 }
 
-// Descriptor of plane x of a field; empty unless ok and 0 <= x < nx.
+// Byte offset of plane x and its size (0 unless ok and 0 <= x < nx),
+// computed once per plane and tick; at() forms a field's descriptor from it
+// with one 64-bit add, so that empty planes read 0 without a branch.
+struct PlaneRef {
+    long long off;
+    unsigned bytes;
+};
 template <class Params>
-__device__ __forceinline__ wf::rsrc_t plane_of(const float *f, const Params &P, int x, bool ok)
+__device__ __forceinline__ PlaneRef plane(const Params &P, int x, bool ok)
 {
     const bool in = ok && x >= 0 && x < P.nx;
-    const long long sx = (long long)P.ny * P.nzp;
-    return wf::make_rsrc(f + (in ? (long long)x * sx : 0), in ? (unsigned)(sx * 4) : 0u);
+    const long long pb = (long long)P.ny * P.nzp * 4;
+    return PlaneRef{in ? (long long)x * pb : 0, in ? (unsigned)pb : 0u};
+}
+__device__ __forceinline__ wf::rsrc_t at(const float *f, PlaneRef r)
+{
+    return wf::make_rsrc((const char *)f + r.off, r.bytes);
 }
 
 // Grid of a streaming launch over `planes` planes: the tiles of a plane

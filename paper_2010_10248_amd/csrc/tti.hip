@@ -420,12 +420,13 @@ tti_rot_s(const TtiParams P)
     auto fetch = [&](int i, In &f) {
         const int j = i - R;
         const bool c = j >= s.xa && j < s.xb, w = i <= ilast;
-        f.p = vload<PL>(plane_of(P.p, P, i, w), s.off);
-        f.r = vload<PL>(plane_of(P.r, P, i, w), s.off);
-        f.ax = vload<PL, wf::kStreaming>(plane_of(P.ax, P, j, c), s.off);
-        f.ay = vload<PL, wf::kStreaming>(plane_of(P.ay, P, j, c), s.off);
-        f.az = vload<PL, wf::kStreaming>(plane_of(P.az, P, j, c), s.off);
-        const wf::rsrc_t pj = plane_of(P.p, P, j, c), rj = plane_of(P.r, P, j, c);
+        const PlaneRef xw = plane(P, i, w), xc = plane(P, j, c);
+        f.p = vload<PL>(at(P.p, xw), s.off);
+        f.r = vload<PL>(at(P.r, xw), s.off);
+        f.ax = vload<PL, wf::kStreaming>(at(P.ax, xc), s.off);
+        f.ay = vload<PL, wf::kStreaming>(at(P.ay, xc), s.off);
+        f.az = vload<PL, wf::kStreaming>(at(P.az, xc), s.off);
+        const wf::rsrc_t pj = at(P.p, xc), rj = at(P.r, xc);
         f.yp = vload<PL>(pj, s.off_yr);
         f.yr = vload<PL>(rj, s.off_yr);
         f.gp = vload<PL>(pj, s.off_rg);
@@ -449,6 +450,7 @@ tti_rot_s(const TtiParams P)
         wr[U - 1] = cur.r;
         const int j = i - R;
         const bool out = j >= s.xa;
+        const PlaneRef xj = plane(P, j, true);
         const int buf = tick & 1;
         V gpz, grz;
         if (out) {
@@ -493,8 +495,8 @@ tti_rot_s(const TtiParams P)
                 qp[k] = ax[k] * (gpx[k] * P.ih[0]) + ay[k] * (gpy[k] * P.ih[1]) + az[k] * (gpz[k] * P.ih[2]);
                 qr[k] = ax[k] * (grx[k] * P.ih[0]) + ay[k] * (gry[k] * P.ih[1]) + az[k] * (grz[k] * P.ih[2]);
             }
-            vstore<PL>(plane_of(P.qp, P, j, true), s.off, qp);
-            vstore<PL>(plane_of(P.qr, P, j, true), s.off, qr);
+            vstore<PL>(at(P.qp, xj), s.off, qp);
+            vstore<PL>(at(P.qr, xj), s.off, qr);
             tick++;
         }
     }
@@ -512,8 +514,17 @@ tti_update_s(const TtiParams P)
     // plane in a thread-private LDS delay line (each thread reads back only
     // its own values): re-reading them from memory would miss L2 by then.
     __shared__ V qd[R + 1][2][kSY * kSZ];
+    // The same for the halo values of p, q_p, q_r (the y halo rows and the
+    // tile's outer z values): they are loaded with the neighbouring tiles'
+    // own loads of the newest plane, while those lines are in L2, and wait R
+    // ticks for the centre.
+    constexpr int NE = R <= 2 ? 2 : 4;  // edge lanes per row
+    __shared__ V yd[R + 1][3][2 * R * kSZ];
+    __shared__ V zd[R + 1][3][kSY * NE];
     SSite s;
     if (!ssite<R, PL>(P, s)) return;
+    const bool edge = NE == 2 ? (s.zl == 0 || s.zl == kSZ - 1) : (s.zl < 2 || s.zl >= kSZ - 2);
+    const int ze = s.row * NE + (s.zl < kSZ / 2 ? s.zl : s.zl - kSZ + NE);
     const bool yin = s.y < P.ny;
     const float dyv = yin ? P.dy[s.y] : 0.0f;
     float dzv[PL];
@@ -525,8 +536,9 @@ tti_update_s(const TtiParams P)
     struct In {
         V p, ax, qp, qr;       // window plane i
         V ay, az;              // centre plane j = i - R
-        V yp, yay, yqp, yqr;   // y halo at j
-        V gp, gaz, gqp, gqr;   // outer z pair at j
+        V yp, yqp, yqr;        // y halo at i
+        V gp, gqp, gqr;        // outer z values at i
+        V yay, gaz;            // y halo and outer z values at j
     };
     float *const vpo = P.vpo ? P.vpo : P.vp;
     float *const vro = P.vro ? P.vro : P.vr;
@@ -534,23 +546,26 @@ tti_update_s(const TtiParams P)
     auto fetch = [&](int i, In &f) {
         const int j = i - R;
         const bool c = j >= s.xa && j < s.xb, w = i <= ilast;
-        f.p = vload<PL>(plane_of(P.p, P, i, w), s.off);
-        f.ax = vload<PL>(plane_of(P.ax, P, i, w), s.off);
-        f.qp = vload<PL>(plane_of(P.qp, P, i, w), s.off);
-        f.qr = vload<PL>(plane_of(P.qr, P, i, w), s.off);
-        const wf::rsrc_t pj = plane_of(P.p, P, j, c), ayj = plane_of(P.ay, P, j, c),
-                         azj = plane_of(P.az, P, j, c), qpj = plane_of(P.qp, P, j, c),
-                         qrj = plane_of(P.qr, P, j, c);
+        const PlaneRef xw = plane(P, i, w), xc = plane(P, j, c);
+        f.p = vload<PL>(at(P.p, xw), s.off);
+        f.ax = vload<PL>(at(P.ax, xw), s.off);
+        f.qp = vload<PL>(at(P.qp, xw), s.off);
+        f.qr = vload<PL>(at(P.qr, xw), s.off);
+        const bool h = i >= s.xa && i < s.xb;  // plane i is a centre later
+        const PlaneRef xh = plane(P, i, h);
+        const wf::rsrc_t pi = at(P.p, xh), qpi = at(P.qp, xh),
+                         qri = at(P.qr, xh), ayj = at(P.ay, xc),
+                         azj = at(P.az, xc);
         f.ay = vload<PL>(ayj, s.off);
         f.az = vload<PL>(azj, s.off);
-        f.yp = vload<PL>(pj, s.off_yr);
+        f.yp = vload<PL>(pi, s.off_yr);
+        f.yqp = vload<PL>(qpi, s.off_yr);
+        f.yqr = vload<PL>(qri, s.off_yr);
+        f.gp = vload<PL>(pi, s.off_rg);
+        f.gqp = vload<PL>(qpi, s.off_rg);
+        f.gqr = vload<PL>(qri, s.off_rg);
         f.yay = vload<PL>(ayj, s.off_yr);
-        f.yqp = vload<PL>(qpj, s.off_yr);
-        f.yqr = vload<PL>(qrj, s.off_yr);
-        f.gp = vload<PL>(pj, s.off_rg);
         f.gaz = vload<PL>(azj, s.off_rg);
-        f.gqp = vload<PL>(qpj, s.off_rg);
-        f.gqr = vload<PL>(qrj, s.off_rg);
     };
     const V zero = V{};
     V wp[U], wpx[U], wrx[U];  // p, a_x q_p, a_x q_r along x
@@ -564,6 +579,16 @@ tti_update_s(const TtiParams P)
         const In cur = pf;
         qd[qs][0][tid] = cur.qp;
         qd[qs][1][tid] = cur.qr;
+        if (s.yring) {
+            yd[qs][0][tid] = cur.yp;
+            yd[qs][1][tid] = cur.yqp;
+            yd[qs][2][tid] = cur.yqr;
+        }
+        if (edge) {
+            zd[qs][0][ze] = cur.gp;
+            zd[qs][1][ze] = cur.gqp;
+            zd[qs][2][ze] = cur.gqr;
+        }
         const int qc = qs == R ? 0 : qs + 1;  // slot of plane i - R
         qs = qc;
 #pragma unroll
@@ -577,6 +602,7 @@ tti_update_s(const TtiParams P)
         wrx[U - 1] = vmul(cur.ax, cur.qr);
         const int j = i - R;
         const bool out = j >= s.xa;
+        const PlaneRef xj = plane(P, j, true);
         // First half (no LDS reads): publish the centre plane and take the z
         // terms from the adjacent lanes; the next tick's inputs are requested
         // once this tick's are consumed.
@@ -585,24 +611,30 @@ tti_update_s(const TtiParams P)
         const V pc = wp[CTR];
         if (out) {
             const V cqp = qd[qc][0][tid], cqr = qd[qc][1][tid];
-            rc = vload<PL, wf::kStreaming>(plane_of(P.r, P, j, true), s.off);
-            vpc = vload<PL, wf::kStreaming>(plane_of(P.vp, P, j, true), s.off);
-            vrc = vload<PL, wf::kStreaming>(plane_of(P.vr, P, j, true), s.off);
-            e1 = vload<PL, wf::kStreaming>(plane_of(P.e1, P, j, true), s.off);
-            sd = vload<PL, wf::kStreaming>(plane_of(P.sd, P, j, true), s.off);
-            cc = vload<PL, wf::kStreaming>(plane_of(P.c, P, j, true), s.off);
+            rc = vload<PL, wf::kStreaming>(at(P.r, xj), s.off);
+            vpc = vload<PL, wf::kStreaming>(at(P.vp, xj), s.off);
+            vrc = vload<PL, wf::kStreaming>(at(P.vr, xj), s.off);
+            e1 = vload<PL, wf::kStreaming>(at(P.e1, xj), s.off);
+            sd = vload<PL, wf::kStreaming>(at(P.sd, xj), s.off);
+            cc = vload<PL, wf::kStreaming>(at(P.c, xj), s.off);
             sh[buf][0][s.row + R][s.zl] = pc;
             sh[buf][1][s.row + R][s.zl] = vmul(cur.ay, cqp);
             sh[buf][2][s.row + R][s.zl] = vmul(cur.ay, cqr);
             if (s.yring) {
-                sh[buf][0][s.yr_lds][s.zl] = cur.yp;
-                sh[buf][1][s.yr_lds][s.zl] = vmul(cur.yay, cur.yqp);
-                sh[buf][2][s.yr_lds][s.zl] = vmul(cur.yay, cur.yqr);
+                sh[buf][0][s.yr_lds][s.zl] = yd[qc][0][tid];
+                sh[buf][1][s.yr_lds][s.zl] = vmul(cur.yay, yd[qc][1][tid]);
+                sh[buf][2][s.yr_lds][s.zl] = vmul(cur.yay, yd[qc][2][tid]);
+            }
+            V gp = zero, gqp = zero, gqr = zero;
+            if (edge) {
+                gp = zd[qc][0][ze];
+                gqp = zd[qc][1][ze];
+                gqr = zd[qc][2][ze];
             }
             float zp[12], zqp[12], zqr[12];
-            zlanes<R, PL>(cur.gp, pc, zp);
-            zlanes<R, PL>(vmul(cur.gaz, cur.gqp), vmul(cur.az, cqp), zqp);
-            zlanes<R, PL>(vmul(cur.gaz, cur.gqr), vmul(cur.az, cqr), zqr);
+            zlanes<R, PL>(gp, pc, zp);
+            zlanes<R, PL>(vmul(cur.gaz, gqp), vmul(cur.az, cqp), zqp);
+            zlanes<R, PL>(vmul(cur.gaz, gqr), vmul(cur.az, cqr), zqr);
 #pragma unroll
             for (int k = 0; k < PL; k++) {
                 const float p2 = 2.0f * pc[k];
@@ -668,10 +700,10 @@ tti_update_s(const TtiParams P)
                 pn[k] = pc[k] + wpn;
                 rn[k] = rc[k] + wrn;
             }
-            vstore<PL>(plane_of(vpo, P, j, true), s.off, vp);
-            vstore<PL>(plane_of(vro, P, j, true), s.off, vr);
-            vstore<PL>(plane_of(P.pn, P, j, true), s.off, pn);
-            vstore<PL>(plane_of(P.rn, P, j, true), s.off, rn);
+            vstore<PL>(at(vpo, xj), s.off, vp);
+            vstore<PL>(at(vro, xj), s.off, vr);
+            vstore<PL>(at(P.pn, xj), s.off, pn);
+            vstore<PL>(at(P.rn, xj), s.off, rn);
             tick++;
         }
     }
