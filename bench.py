@@ -60,6 +60,16 @@ def measured_traffic(sched_repr):
 PHYS_COUNTERS = os.path.join(ROOT, "profiles", "tti_elastic_256_so8_counters.md")
 
 
+def physics_sha(which):
+    """sha256 prefix of the sources the TTI or elastic forward kernels are
+    compiled from (the physics file and the streaming building blocks)."""
+    h = hashlib.sha256()
+    for name in ("tti.hip" if which == "tti" else "elastic.hip", "stream_kernel.h"):
+        with open(os.path.join(ROOT, "paper_2010_10248_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def physics_traffic(which):
     """HBM bytes per step of the TTI or elastic kernels from the committed
     counter summary, or None when it was taken on other kernel sources."""
@@ -68,10 +78,7 @@ def physics_traffic(which):
     except OSError:
         return None
     kv = dict(re.findall(r"^- (\w+): `?([^`\n]+)`?$", text, re.M))
-    src = os.path.join(ROOT, "paper_2010_10248_amd", "csrc",
-                       "tti.hip" if which == "tti" else "elastic.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    sha = physics_sha(which)
     if kv.get(f"{which}_sha") != sha:
         return None
     try:
