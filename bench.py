@@ -60,6 +60,18 @@ def measured_traffic(sched_repr):
 PHYS_COUNTERS = os.path.join(ROOT, "profiles", "tti_elastic_256_so8_counters.md")
 
 
+def host_cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def physics_sha(which):
     """sha256 prefix of the sources the TTI or elastic forward kernels are
     compiled from (the physics file and the streaming building blocks)."""
@@ -512,7 +524,7 @@ def main(argv=None):
         cpu_s = time.perf_counter() - t0
         cores = oracle.num_threads()
         cpu = dict(value=round(N3 * sample.nt / cpu_s / 1e9, 4), unit="GPts/s", cores=cores,
-                   kind="oracle", seconds=round(cpu_s, 2),
+                   kind="oracle", cpu_model=host_cpu_model(), seconds=round(cpu_s, 2),
                    sample=f"FP64 oracle, full {args.n}^3 grid, first {sample.nt} of {shot.nt} "
                           f"steps (same sources/receivers; the run the parity leg compares)")
         log(f"oracle: {cpu_s:.1f} s for {sample.nt} steps on {cores} threads")
