@@ -339,8 +339,16 @@ el_vel_s(const ElParams P)
     using V = vec<PL>;
     constexpr int U = 2 * R + 1, LR = kSY + 2 * R, CTR = R;
     __shared__ V sh[2][3][LR][kSZ];  // txy, tyy, tyz along y
+    // The halo values of the x-windowed txy (y halo rows) and txz (outer z
+    // values) are loaded with the neighbouring tiles' own loads of the newest
+    // plane, while those lines are in L2, and wait R ticks for the centre in
+    // thread-private LDS delay lines; tyy, tyz, tzz are read at the centre
+    // plane by their owners too, so their halo values load with those.
+    __shared__ V yd[R + 1][2 * R * kSZ];
+    __shared__ V zd[R + 1][kSY * edge_lanes<R, PL>()];
     SSite s;
     if (!ssite<R, PL>(P, s)) return;
+    const int tid = threadIdx.x;
     const float dyv = s.y < P.ny ? P.dy[s.y] : 0.0f;
     float dzv[PL];
 #pragma unroll
@@ -348,8 +356,9 @@ el_vel_s(const ElParams P)
     struct In {
         V xx, xy, xz;     // txx, txy, txz at the window plane i
         V yy, yz, zz;     // tyy, tyz, tzz at the centre plane j = i - R
-        V hxy, hyy, hyz;  // y halo at j
-        V gxz, gyz, gzz;  // outer z values at j
+        V hxy, gxz;       // y halo of txy and outer z values of txz at i
+        V hyy, hyz;       // y halo at j
+        V gyz, gzz;       // outer z values at j
     };
     const int i0 = s.xa - R, ilast = s.xb - 1 + R;
     auto fetch = [&](int i, In &f) {
@@ -359,16 +368,15 @@ el_vel_s(const ElParams P)
         f.xx = vload<PL>(at(P.t[0], xw), s.off);
         f.xy = vload<PL>(at(P.t[3], xw), s.off);
         f.xz = vload<PL>(at(P.t[4], xw), s.off);
-        const wf::rsrc_t xyj = at(P.t[3], xc), yyj = at(P.t[1], xc),
-                         yzj = at(P.t[5], xc), xzj = at(P.t[4], xc),
-                         zzj = at(P.t[2], xc);
+        const PlaneRef xh = plane(P, i, i >= s.xa && i < s.xb);  // a centre later
+        const wf::rsrc_t yyj = at(P.t[1], xc), yzj = at(P.t[5], xc), zzj = at(P.t[2], xc);
         f.yy = vload<PL>(yyj, s.off);
         f.yz = vload<PL>(yzj, s.off);
         f.zz = vload<PL>(zzj, s.off);
-        f.hxy = vload<PL>(xyj, s.off_yr);
+        f.hxy = vload<PL>(at(P.t[3], xh), s.off_yr);
         f.hyy = vload<PL>(yyj, s.off_yr);
         f.hyz = vload<PL>(yzj, s.off_yr);
-        f.gxz = vload<PL>(xzj, s.off_rg);
+        f.gxz = vload<PL>(at(P.t[4], xh), s.off_rg);
         f.gyz = vload<PL>(yzj, s.off_rg);
         f.gzz = vload<PL>(zzj, s.off_rg);
     };
@@ -378,9 +386,13 @@ el_vel_s(const ElParams P)
     for (int k = 0; k < U; k++) wxx[k] = wxy[k] = wxz[k] = zero;
     In pf;
     fetch(i0, pf);
-    int tick = 0;
+    int tick = 0, hs = 0;  // hs: delay slot of plane i, (i - i0) mod (R + 1)
     for (int i = i0; i <= ilast; i++) {
         const In cur = pf;
+        if (s.yring) yd[hs][tid] = cur.hxy;
+        if (s.edge) zd[hs][s.ze] = cur.gxz;
+        const int hc = hs == R ? 0 : hs + 1;  // slot of plane i - R
+        hs = hc;
 #pragma unroll
         for (int k = 0; k + 1 < U; k++) {
             wxx[k] = wxx[k + 1];
@@ -405,12 +417,12 @@ el_vel_s(const ElParams P)
             sh[buf][1][s.row + R][s.zl] = cur.yy;
             sh[buf][2][s.row + R][s.zl] = cur.yz;
             if (s.yring) {
-                sh[buf][0][s.yr_lds][s.zl] = cur.hxy;
+                sh[buf][0][s.yr_lds][s.zl] = yd[hc][tid];
                 sh[buf][1][s.yr_lds][s.zl] = cur.hyy;
                 sh[buf][2][s.yr_lds][s.zl] = cur.hyz;
             }
             float w[12];
-            zlanes<R, PL>(cur.gxz, wxz[CTR], w);
+            zlanes<R, PL>(s.edge ? zd[hc][s.ze] : zero, wxz[CTR], w);
             dz[0] = sdz<R, PL, false>(P, w);
             zlanes<R, PL>(cur.gyz, cur.yz, w);
             dz[1] = sdz<R, PL, false>(P, w);
@@ -451,16 +463,23 @@ el_str_s(const ElParams P)
     using V = vec<PL>;
     constexpr int U = 2 * R + 1, LR = kSY + 2 * R, CTR = R;
     __shared__ V sh[2][3][LR][kSZ];  // vx, vy, vz along y
+    // The halo values of vx, vy, vz (y halo rows, outer z values) are loaded
+    // with the neighbouring tiles' own loads of the newest plane, while those
+    // lines are in L2, and wait R ticks for the centre in thread-private LDS
+    // delay lines.
+    __shared__ V yd[R + 1][3][2 * R * kSZ];
+    __shared__ V zd[R + 1][3][kSY * edge_lanes<R, PL>()];
     SSite s;
     if (!ssite<R, PL>(P, s)) return;
+    const int tid = threadIdx.x;
     const float dyv = s.y < P.ny ? P.dy[s.y] : 0.0f;
     float dzv[PL];
 #pragma unroll
     for (int k = 0; k < PL; k++) dzv[k] = s.z + k < P.nz ? P.dz[s.z + k] : 0.0f;
     struct In {
         V x, y, z;     // vx, vy, vz at the window plane i
-        V hx, hy, hz;  // y halo at the centre plane j = i - R
-        V gx, gy, gz;  // outer z values at j
+        V hx, hy, hz;  // y halo at plane i
+        V gx, gy, gz;  // outer z values at plane i
     };
     const int i0 = s.xa - R, ilast = s.xb - 1 + R;
     auto fetch = [&](int i, In &f) {
@@ -470,7 +489,8 @@ el_str_s(const ElParams P)
         f.x = vload<PL>(at(P.v[0], xw), s.off);
         f.y = vload<PL>(at(P.v[1], xw), s.off);
         f.z = vload<PL>(at(P.v[2], xw), s.off);
-        const wf::rsrc_t dvx = at(P.v[0], xc), dvy = at(P.v[1], xc), dvz = at(P.v[2], xc);
+        const PlaneRef xh = plane(P, i, i >= s.xa && i < s.xb);  // a centre later
+        const wf::rsrc_t dvx = at(P.v[0], xh), dvy = at(P.v[1], xh), dvz = at(P.v[2], xh);
         f.hx = vload<PL>(dvx, s.off_yr);
         f.hy = vload<PL>(dvy, s.off_yr);
         f.hz = vload<PL>(dvz, s.off_yr);
@@ -484,9 +504,21 @@ el_str_s(const ElParams P)
     for (int k = 0; k < U; k++) wx[k] = wy[k] = wz[k] = zero;
     In pf;
     fetch(i0, pf);
-    int tick = 0;
+    int tick = 0, hs = 0;  // hs: delay slot of plane i, (i - i0) mod (R + 1)
     for (int i = i0; i <= ilast; i++) {
         const In cur = pf;
+        if (s.yring) {
+            yd[hs][0][tid] = cur.hx;
+            yd[hs][1][tid] = cur.hy;
+            yd[hs][2][tid] = cur.hz;
+        }
+        if (s.edge) {
+            zd[hs][0][s.ze] = cur.gx;
+            zd[hs][1][s.ze] = cur.gy;
+            zd[hs][2][s.ze] = cur.gz;
+        }
+        const int hc = hs == R ? 0 : hs + 1;  // slot of plane i - R
+        hs = hc;
 #pragma unroll
         for (int k = 0; k + 1 < U; k++) {
             wx[k] = wx[k + 1];
@@ -513,16 +545,22 @@ el_str_s(const ElParams P)
             sh[buf][1][s.row + R][s.zl] = wy[CTR];
             sh[buf][2][s.row + R][s.zl] = wz[CTR];
             if (s.yring) {
-                sh[buf][0][s.yr_lds][s.zl] = cur.hx;
-                sh[buf][1][s.yr_lds][s.zl] = cur.hy;
-                sh[buf][2][s.yr_lds][s.zl] = cur.hz;
+                sh[buf][0][s.yr_lds][s.zl] = yd[hc][0][tid];
+                sh[buf][1][s.yr_lds][s.zl] = yd[hc][1][tid];
+                sh[buf][2][s.yr_lds][s.zl] = yd[hc][2][tid];
+            }
+            V gx = zero, gy = zero, gz = zero;
+            if (s.edge) {
+                gx = zd[hc][0][s.ze];
+                gy = zd[hc][1][s.ze];
+                gz = zd[hc][2][s.ze];
             }
             float w[12];
-            zlanes<R, PL>(cur.gz, wz[CTR], w);
+            zlanes<R, PL>(gz, wz[CTR], w);
             ezz = sdz<R, PL, false>(P, w);
-            zlanes<R, PL>(cur.gx, wx[CTR], w);
+            zlanes<R, PL>(gx, wx[CTR], w);
             zxz = sdz<R, PL, true>(P, w);
-            zlanes<R, PL>(cur.gy, wy[CTR], w);
+            zlanes<R, PL>(gy, wy[CTR], w);
             zyz = sdz<R, PL, true>(P, w);
         }
         fetch(i + 1, pf);

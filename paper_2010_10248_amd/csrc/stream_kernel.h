@@ -128,7 +128,17 @@ struct SSite {
     unsigned off_rg;   // outer z values of the edge lanes
     int yr_lds;        // LDS row of the y halo value
     bool yring;
+    bool edge;         // lane holds outer z values
+    int ze;            // its index among the tile's edge lanes (row-major)
 };
+
+// Edge lanes per row: lanes 0 and 15, or lanes 0, 1, 14 and 15 (2 z per lane
+// beyond radius 2).
+template <int R, int PL>
+constexpr int edge_lanes()
+{
+    return PL == 4 || R <= 2 ? 2 : 4;
+}
 
 template <int R, int PL, class Params>
 __device__ __forceinline__ bool ssite(const Params &P, SSite &s)
@@ -160,9 +170,11 @@ __device__ __forceinline__ bool ssite(const Params &P, SSite &s)
     s.off_yr = yrok ? (unsigned)((yr * P.nzp + s.z) * 4) : wf::kNoLane;
     s.yr_lds = s.row < R ? s.row : kSY + s.row;
     constexpr int ZO = PL == 4 || R <= 2 ? PL : 4;  // distance of the outer values
-    const bool edge = ZO == PL ? (s.zl == 0 || s.zl == kSZ - 1) : (s.zl < 2 || s.zl >= kSZ - 2);
+    constexpr int NE = edge_lanes<R, PL>();
+    s.edge = s.zl < NE / 2 || s.zl >= kSZ - NE / 2;
+    s.ze = s.row * NE + (s.zl < kSZ / 2 ? s.zl : s.zl - kSZ + NE);
     const int zr = s.zl < kSZ / 2 ? s.z - ZO : s.z + ZO;
-    const bool rgok = edge && yin && zr >= 0 && zr < P.nzp;
+    const bool rgok = s.edge && yin && zr >= 0 && zr < P.nzp;
     s.off_rg = rgok ? (unsigned)((s.y * P.nzp + zr) * 4) : wf::kNoLane;
     return s.xa < s.xb;
 }

@@ -518,13 +518,12 @@ tti_update_s(const TtiParams P)
     // tile's outer z values): they are loaded with the neighbouring tiles'
     // own loads of the newest plane, while those lines are in L2, and wait R
     // ticks for the centre.
-    constexpr int NE = R <= 2 ? 2 : 4;  // edge lanes per row
     __shared__ V yd[R + 1][3][2 * R * kSZ];
-    __shared__ V zd[R + 1][3][kSY * NE];
+    __shared__ V zd[R + 1][3][kSY * edge_lanes<R, PL>()];
     SSite s;
     if (!ssite<R, PL>(P, s)) return;
-    const bool edge = NE == 2 ? (s.zl == 0 || s.zl == kSZ - 1) : (s.zl < 2 || s.zl >= kSZ - 2);
-    const int ze = s.row * NE + (s.zl < kSZ / 2 ? s.zl : s.zl - kSZ + NE);
+    const bool edge = s.edge;
+    const int ze = s.ze;
     const bool yin = s.y < P.ny;
     const float dyv = yin ? P.dy[s.y] : 0.0f;
     float dzv[PL];
