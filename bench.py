@@ -113,7 +113,7 @@ def copy_calibration(torch):
     return 0
 
 
-def serve_bench(tb, W, torch, nreq, loads, max_active, arena_gb):
+def serve_bench(tb, W, torch, nreq, loads, max_active, arena_gb, mix="tuned"):
     """C5 serving: gradient requests (forward, residual vs observed traces,
     adjoint, checkpointed squared-slowness gradient) on mixed 128-384^3 SO8
     grids with 500-1500 steps. Phase 1 submits every request at once
@@ -122,13 +122,17 @@ def serve_bench(tb, W, torch, nreq, loads, max_active, arena_gb):
     latency per load. Models, sparse sets, observed data (forward runs of the
     true model with a +5% velocity anomaly) and one autotuner sweep per
     served grid size (requests then run the tuned schedule) are made before
-    the clock starts."""
+    the clock starts. mix = "shared": sizes whose tuned kernel shape (steps
+    per pass, tile rows) differs from the most common one among the served
+    sizes run that shape instead, so that their passes batch with the
+    others'."""
     import numpy as np
 
     rng = np.random.Generator(np.random.PCG64(10253))
     reqs = []
     t0 = time.perf_counter()
     tuned = {}
+    best_of = {}
     for _ in range(nreq):
         shot, vp_true = W.serving_request(rng)
         vmax = float(shot.vp.max())
@@ -138,6 +142,7 @@ def serve_bench(tb, W, torch, nreq, loads, max_active, arena_gb):
             best, ms = tb.autotune(prop.model, prop.sparse, steps=16)
             torch.cuda.synchronize()
             tuned[n] = dict(schedule=repr(best), ms_per_step=round(ms, 4))
+            best_of[n] = best
             log(f"serving: tuned {n}^3: {best} {ms:.3f} ms/step")
         true = tb.Acoustic(shot, vp=vp_true, damp_vmax=vmax)
         d_obs = true.forward(None, want_fields=False)["traces"]
@@ -147,6 +152,19 @@ def serve_bench(tb, W, torch, nreq, loads, max_active, arena_gb):
     log(f"serving: {nreq} requests prepared in {time.perf_counter() - t0:.1f} s "
         f"(sizes {sorted(r[0].shape[0] for r in reqs)}, nt {sorted(r[0].nt for r in reqs)})")
     work = sum(int(np.prod(r[0].shape)) * r[0].nt for r in reqs)
+
+    def shape(sc):  # what the server batches on: steps per pass, tile rows
+        return (1 if sc.mode == tb.SCHED_SB else sc.time_tile, sc.tile_y or 32)
+
+    sched_of = {n: None for n in best_of}  # None: the tuned choice
+    if mix == "shared":
+        shapes = [shape(best_of[r[0].shape[0]]) for r in reqs]
+        major = max(set(shapes), key=lambda v: (shapes.count(v), v))
+        for n, sc in best_of.items():
+            if shape(sc) != major:
+                sched_of[n] = tb.schedule("sb" if major[0] == 1 else "tb", major[0], major[1], 0)
+                tuned[n]["served_schedule"] = repr(sched_of[n])
+                log(f"serving: {n}^3 runs the shared shape {sched_of[n]}")
 
     def run(arrivals):
         sv = tb.Server(arena_bytes=int(arena_gb * 2**30), max_active=max_active, graphs=True)
@@ -160,7 +178,8 @@ def serve_bench(tb, W, torch, nreq, loads, max_active, arena_gb):
             now = time.perf_counter() - start
             while nxt < nreq and arrivals[nxt] <= now:
                 shot, prop, d_obs = reqs[nxt]
-                rid_of[sv.submit_gradient(prop, d_obs, grads[nxt])] = nxt
+                rid_of[sv.submit_gradient(prop, d_obs, grads[nxt],
+                                          sched_of[shot.shape[0]])] = nxt
                 nxt += 1
             act, queued = sv.step()
             for rid, J in sv.poll():
@@ -198,7 +217,9 @@ def serve_bench(tb, W, torch, nreq, loads, max_active, arena_gb):
                gradient_gpts_per_s_equiv=round(work / span / 1e9, 2),
                saturated_p50_ms=round(float(np.percentile(np.array(lat_sat) * 1e3, 50)), 1),
                saturated_p99_ms=round(float(np.percentile(np.array(lat_sat) * 1e3, 99)), 1),
-               poisson=per_load, tuned_schedules=tuned,
+               poisson=per_load, tuned_schedules=tuned, served_schedules=mix,
+               saturated_batched_passes_per_launch=round(
+                   st["passes_batched"] / max(st["launches"], 1), 2),
                max_active=max_active, arena_gib=arena_gb,
                request="gradient (forward + residual + adjoint + imaging, checkpoints every "
                        "ceil(sqrt(nt)))",
@@ -435,6 +456,9 @@ def main(argv=None):
     ap.add_argument("--physics-sb-only", action="store_true",
                     help="time only the spatially blocked TTI and elastic schedules")
     ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-mix", choices=("tuned", "shared"), default="shared",
+                    help="served schedules: each size's tuned choice, or the most common tuned "
+                         "kernel shape for every size (so that all passes can batch)")
     ap.add_argument("--serve-loads", type=str, default="0.5,0.8,1.0",
                     help="Poisson loads as fractions of the saturated rate")
     ap.add_argument("--serve-active", type=int, default=4)
@@ -561,7 +585,7 @@ def main(argv=None):
     if not args.no_serve:
         serving = serve_bench(tb, W, torch, args.serve_requests,
                               [float(x) for x in args.serve_loads.split(",")],
-                              args.serve_active, args.serve_arena_gb)
+                              args.serve_active, args.serve_arena_gb, args.serve_mix)
 
     line = {
         "metric": METRIC,
