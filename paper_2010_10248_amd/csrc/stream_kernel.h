@@ -57,22 +57,25 @@ __device__ __forceinline__ void vstore(wf::rsrc_t r, unsigned off, vec<PL> v)
                                                (int)off, 0, wf::kStreaming);
 }
 // Lane l takes lane l -+ 1 or 2 of its 16-lane row; lanes whose source lies
-// outside the row keep `edge` (vshift) or take 0 (vshift0).
+// outside the row keep `edge` (vshift) or take 0 (vshift0). One DPP move per
+// component, written out (as the acoustic kernel's row_shift): moves over
+// vector elements indexed in a loop have been merged into one by the
+// compiler.
 template <int CTRL, int PL>
 __device__ __forceinline__ vec<PL> vshift(vec<PL> edge, vec<PL> v)
 {
-    vec<PL> o;
-#pragma unroll
-    for (int k = 0; k < PL; k++) o[k] = wf::lane_shift<CTRL>(edge[k], v[k]);
-    return o;
+    if constexpr (PL == 4)
+        return wf::row_shift<CTRL>(edge, v);
+    else
+        return vec<2>{wf::lane_shift<CTRL>(edge.x, v.x), wf::lane_shift<CTRL>(edge.y, v.y)};
 }
 template <int CTRL, int PL>
 __device__ __forceinline__ vec<PL> vshift0(vec<PL> v)
 {
-    vec<PL> o;
-#pragma unroll
-    for (int k = 0; k < PL; k++) o[k] = wf::lane_shift0<CTRL>(v[k]);
-    return o;
+    if constexpr (PL == 4)
+        return wf::row_shift0<CTRL>(v);
+    else
+        return vec<2>{wf::lane_shift0<CTRL>(v.x), wf::lane_shift0<CTRL>(v.y)};
 }
 
 // z neighbours of the PL own points: w[4 + k + m] is point k's neighbour at
