@@ -455,6 +455,7 @@ TtiParams tti_params(const tb_model *m)
 {
     const size_t fe = m->field_elems();
     TtiParams P{};
+    P.ncu = m->ncu;
     P.ax = m->d_tti;
     P.ay = m->d_tti + fe;
     P.az = m->d_tti + 2 * fe;
@@ -486,6 +487,7 @@ ElParams el_params(const tb_model *m, float *const *F)
 {
     const size_t fe = m->field_elems();
     ElParams P{};
+    P.ncu = m->ncu;
     for (int k = 0; k < 3; k++) P.v[k] = F[k];
     for (int k = 0; k < 6; k++) P.t[k] = F[3 + k];
     for (int k = 0; k < 3; k++) P.bq[k] = m->d_el + k * fe;

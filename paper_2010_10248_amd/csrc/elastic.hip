@@ -919,8 +919,8 @@ tb_status launch_elastic_step(const ElParams &P, int r, const float *inc, const 
     (void)vtotal;
     if (r == 2 || r == 4) {
         constexpr int VPL = 2, SPL = 2;  // z per lane of the two passes
-        const unsigned vs = streamed(V.xhi - V.xlo, P.ny, P.nzp, VPL, &V.chunk, &V.nchunks),
-                       ss = streamed(xhi - xlo, P.ny, P.nzp, SPL, &S.chunk, &S.nchunks);
+        const unsigned vs = streamed(V.xhi - V.xlo, P.ny, P.nzp, VPL, P.ncu, &V.chunk, &V.nchunks),
+                       ss = streamed(xhi - xlo, P.ny, P.nzp, SPL, P.ncu, &S.chunk, &S.nchunks);
         if (r == 2) {
             hipLaunchKernelGGL((el_vel_s<2, VPL>), dim3(vs), dim3(256), 0, st, V);
             hipLaunchKernelGGL((el_str_s<2, SPL>), dim3(ss), dim3(256), 0, st, S);

@@ -26,8 +26,10 @@ struct ElParams {
     // XCD-aware block order of the forward launches (0: linear): runs of
     // 8 * band blocks, of which XCD k takes the k-th contiguous band.
     int band;
-    // Streaming launches: planes per workgroup and chunks per tile.
+    // Streaming launches: planes per workgroup and chunks per tile (set by
+    // the launch), and the device's compute units (set with the model).
     int chunk, nchunks;
+    int ncu;
 };
 
 // Six scratch fields of the adjoint step (also used to pass a forward

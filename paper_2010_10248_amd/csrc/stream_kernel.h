@@ -208,13 +208,13 @@ __device__ __forceinline__ wf::rsrc_t at(const float *f, PlaneRef r)
 }
 
 // Grid of a streaming launch over `planes` planes: the tiles of a plane
-// times the chunks of x, about two workgroups per CU with at least 16 planes
-// per chunk (each chunk re-reads 2R planes of halo).
-inline unsigned streamed(int planes, int ny, int nzp, int pl, int *chunk, int *nchunks)
+// times the chunks of x, about two workgroups per CU (ncu compute units)
+// with at least 16 planes per chunk (each chunk re-reads 2R planes of halo).
+inline unsigned streamed(int planes, int ny, int nzp, int pl, int ncu, int *chunk, int *nchunks)
 {
     const int zw = pl * kSZ;
     const int ntiles = ((ny + kSY - 1) / kSY) * ((nzp + zw - 1) / zw);
-    const int want = std::max(1, 512 / ntiles);
+    const int want = std::max(1, 2 * std::max(1, ncu) / ntiles);
     const int ch = std::min(planes, std::max(16, (planes + want - 1) / want));
     *chunk = ch;
     *nchunks = (planes + ch - 1) / ch;

@@ -826,8 +826,8 @@ tb_status launch_tti_step(const TtiParams &P, int r, const float *inc, const lon
     if (r == 2 || r == 4) {
         // The rotated gradient takes 4 z per lane, the update 2 (its three x
         // windows and the next tick's inputs then fit three waves per SIMD).
-        const unsigned gs = streamed(G.xhi - G.xlo, P.ny, P.nzp, 4, &G.chunk, &G.nchunks),
-                       us = streamed(xhi - xlo, P.ny, P.nzp, 2, &U.chunk, &U.nchunks);
+        const unsigned gs = streamed(G.xhi - G.xlo, P.ny, P.nzp, 4, P.ncu, &G.chunk, &G.nchunks),
+                       us = streamed(xhi - xlo, P.ny, P.nzp, 2, P.ncu, &U.chunk, &U.nchunks);
         if (r == 2) {
             hipLaunchKernelGGL((tti_rot_s<2, 4>), dim3(gs), dim3(256), 0, st, G);
             hipLaunchKernelGGL((tti_update_s<2, 2>), dim3(us), dim3(256), 0, st, U);
