@@ -72,13 +72,23 @@ def host_cpu_model():
     return None
 
 
+def code_text(path):
+    """A C++ source without its comments, trailing blanks and empty lines, so
+    that editing a comment does not detach a measurement from the code."""
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
+
+
 def physics_sha(which):
-    """sha256 prefix of the sources the TTI or elastic forward kernels are
-    compiled from (the physics file and the streaming building blocks)."""
+    """sha256 prefix of the code (comments dropped) the TTI or elastic forward
+    kernels are compiled from: the physics file and the streaming building
+    blocks."""
     h = hashlib.sha256()
     for name in ("tti.hip" if which == "tti" else "elastic.hip", "stream_kernel.h"):
-        with open(os.path.join(ROOT, "paper_2010_10248_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        h.update(code_text(os.path.join(ROOT, "paper_2010_10248_amd", "csrc", name)).encode())
     return h.hexdigest()[:16]
 
 

@@ -9,6 +9,9 @@
 //   el_src   t_ii^{n+1} += dt W q(t_n) at the inspector's points
 //   el_rec   gather of P = (txx + tyy + tzz) / 3 (nodes) and of vz (vz grid)
 // Both updates are in place (each element reads its own old value only).
+// The forward step at radius 2 and 4 runs the x-streaming forms of the two
+// passes (el_vel_s, el_str_s; same per-point operations); radius 6 runs the
+// tiled ones.
 #include <algorithm>
 
 #include "elastic_params.h"

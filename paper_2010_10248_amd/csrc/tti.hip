@@ -15,6 +15,9 @@
 //                and r', and the receiver gather of p'.
 // Every field is zero outside the grid (bounds-checked neighbour reads), so
 // Hz = -D^T D exactly, as in the definition of the operator.
+// The forward step at radius 2 and 4 runs the x-streaming forms of the two
+// kernels (tti_rot_s, tti_update_s; same per-point operations); radius 6 and
+// the adjoint and imaging modes run the tiled ones.
 #include <algorithm>
 
 #include "stream_kernel.h"
